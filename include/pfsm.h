@@ -1,0 +1,148 @@
+/*
+ * libpfsm -- partitioned folded spectrum method (PFSM) subspace
+ * diagonalisation on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Briggs, Kelley, Bernholc, "Parallel implementation of electronic
+ * structure eigensolver using a partitioned folded spectrum method"
+ * (arXiv:1502.07806).  Given a real symmetric A (Eq. 3) and the previous
+ * eigenvectors V_prev, one call
+ *   1. forms the operator in the previous basis, At = V_prev^T A V_prev
+ *      (the matrix elements of Eq. 12);
+ *   2. splits the eigen-index range into slices, one per partition, and
+ *      diagonalises an overlapping diagonal submatrix of At around each slice
+ *      (Methodology: submatrices of order M, slice inside its submatrix,
+ *      Fig. 1);
+ *   3. pads the selected submatrix eigenvectors with zeros to start vectors
+ *      and uses the submatrix eigenvalues as shifts;
+ *   4. applies folded-spectrum iterations x <- x - alpha (At - eps I)^q x
+ *      (Eq. 11 for q = 2; q = 1 is the one-product variant);
+ *   5. orthonormalises all vectors (Gram-Schmidt in column order, computed as
+ *      Cholesky-QR: S = X^T X = L L^T, X <- X L^{-T});
+ *   6. returns Rayleigh quotients as eigenvalues (ascending) and the vectors
+ *      rotated back, V = V_prev X.
+ *
+ * Conventions (LAPACK style, as the paper's "calling interface similar to the
+ * standard eigensolvers" suggests): column-major storage with leading
+ * dimensions; eigenvectors are columns; eigenvalues ascending; every device
+ * pointer refers to memory on the current HIP device; the caller owns every
+ * buffer it passes.  The `stream` arguments are hipStream_t values (NULL =
+ * the default stream).
+ *
+ * Errors: the return value reports synchronous argument / resource errors
+ * only.  Conditions found on the device are written to *dInfo (int32, device
+ * memory, cleared by the call itself):
+ *      0  success
+ *    k>0  the overlap matrix is not positive definite at column k (the start
+ *         vectors do not span: a randomly mixed, non-diagonally-dominant input
+ *         as the Methodology section warns, or duplicated previous vectors)
+ *     -1  a non-finite eigenvalue (non-finite input propagates to it)
+ *     -3  a submatrix eigensolver did not converge within its sweep limit
+ * The first condition found wins.
+ */
+#ifndef PFSM_H
+#define PFSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pfsm_status {
+  PFSM_OK = 0,
+  PFSM_INVALID_ARG = 1,
+  PFSM_NOT_SUPPORTED = 2,
+  PFSM_OOM = 3,
+  PFSM_HIP_ERROR = 4,
+  PFSM_WORKSPACE_TOO_SMALL = 5
+} pfsm_status;
+
+typedef enum pfsm_precision {
+  PFSM_PREC_FP64 = 0,       /* every product in FP64 on matrix cores */
+  PFSM_PREC_MIXED_BF16 = 1  /* BF16-split products with FP32 accumulation for the bulk,
+                               FP64 submatrix eigensolver, Cholesky and final
+                               Rayleigh-Ritz refinement against A */
+} pfsm_precision;
+
+typedef enum pfsm_shift_mode {
+  PFSM_SHIFT_FIXED = 0,    /* eps = submatrix eigenvalue, held fixed (Methodology) */
+  PFSM_SHIFT_RAYLEIGH = 1  /* eps = Rayleigh quotient refreshed before every iteration */
+} pfsm_shift_mode;
+
+/* Plan descriptor.  All pointers are host pointers, read during plan creation only. */
+typedef struct pfsm_desc {
+  int64_t n;                   /* matrix order, >= 1 */
+  int32_t num_parts;           /* number of slices P, 1 <= P <= n */
+  const int64_t* part_offsets; /* P+1 ascending slice boundaries, [0] = 0, [P] = n, no empty slice */
+  int64_t halo;                /* rows added on each side of a slice to form its submatrix
+                                  (order M_p = min(n, m_p + 2 halo)); < 0: half of the largest slice */
+  int32_t iterations;          /* folded-spectrum iterations, >= 0 */
+  int32_t fs_power;            /* q: 2 (Eq. 11) or 1 */
+  double alpha;                /* step length; <= 0: 1 / rho^q, rho = Gershgorin width of At (Eqs. 8-11) */
+  int32_t shift_mode;          /* pfsm_shift_mode */
+  int32_t precision;           /* pfsm_precision */
+  int32_t max_sweeps;          /* submatrix Jacobi sweep limit; <= 0: 10 */
+  int32_t reserved;            /* must be 0 */
+} pfsm_desc;
+
+typedef struct pfsm_plan pfsm_plan;
+
+/* Validate the descriptor and build the partition/submatrix tables.
+ * Allocates the plan (host) and a small device table on the current device.
+ * Errors: INVALID_ARG (bad sizes/offsets/options), HIP_ERROR, OOM. */
+pfsm_status pfsm_plan_create(pfsm_plan** plan, const pfsm_desc* desc);
+
+/* Bytes of device workspace pfsm_solve / pfsm_backward need for this plan. */
+pfsm_status pfsm_workspace_size(const pfsm_plan* plan, size_t* bytes);
+
+/* One PFSM step (Methodology; Eqs. 3, 11, 12).
+ *   dA      n x n symmetric (both triangles read; not symmetrised), lda >= n
+ *   dVprev  n x n previous eigenvectors, columns ordered by ascending previous
+ *           eigenvalue, ldv >= n
+ *   dLambda n eigenvalues out (ascending)
+ *   dVout   n x n eigenvectors out, ldvo >= n; must not overlap dA or dVprev
+ *   dWork   device workspace of at least pfsm_workspace_size bytes, 256-byte aligned
+ *   dInfo   device int32 status word (see above)
+ * The call only enqueues work on `stream`: it does not allocate, synchronise
+ * or read device memory on the host.  Inputs are not modified.
+ * Errors: INVALID_ARG (null pointer, bad leading dimension, aliasing),
+ * WORKSPACE_TOO_SMALL, HIP_ERROR (launch failure). */
+pfsm_status pfsm_solve(pfsm_plan* plan, const double* dA, int64_t lda, const double* dVprev, int64_t ldv,
+                       double* dLambda, double* dVout, int64_t ldvo, void* dWork, size_t work_bytes,
+                       int32_t* dInfo, void* stream);
+
+/* Reverse-mode gradient of a symmetric eigendecomposition A = V diag(lambda) V^T
+ * (eigen-adjoint: dA = sym(V (diag(gLambda) + F o (V^T gV)) V^T), F_ij =
+ * d/(d^2 + eta^2), d = lambda_j - lambda_i, F_ii = 0; the Lorentzian keeps an
+ * exactly degenerate pair finite).
+ *   dLambda, dV   forward outputs (n, n x n with ldv)
+ *   dGradLambda   dL/dlambda (n) or NULL (zero)
+ *   dGradV        dL/dV (n x n, ldg) or NULL (zero)
+ *   dGradA        output n x n symmetric, ldga >= n; must not overlap the inputs
+ * Errors: INVALID_ARG, WORKSPACE_TOO_SMALL, HIP_ERROR. */
+pfsm_status pfsm_backward(pfsm_plan* plan, const double* dLambda, const double* dV, int64_t ldv,
+                          const double* dGradLambda, const double* dGradV, int64_t ldg, double eta,
+                          double* dGradA, int64_t ldga, void* dWork, size_t work_bytes, int32_t* dInfo,
+                          void* stream);
+
+/* Release the plan and its device table (synchronises the device first). */
+void pfsm_plan_destroy(pfsm_plan* plan);
+
+/* Static string for a status code. */
+const char* pfsm_status_string(pfsm_status status);
+
+/* Diagnostics for tests and benchmarks (not part of the method):
+ * out[0] = ||A V - V diag(lambda)||_F / ||A||_F, out[1] = ||V^T V - I||_F,
+ * computed in FP64 on the device; out is a device array of 2 doubles.
+ * Uses the plan's workspace (the result of a previous solve must already be
+ * in dLambda / dV, which must not lie inside the workspace). */
+pfsm_status pfsm_diagnostics(pfsm_plan* plan, const double* dA, int64_t lda, const double* dLambda,
+                             const double* dV, int64_t ldv, double* dOut, void* dWork, size_t work_bytes,
+                             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFSM_H */

@@ -1,0 +1,6 @@
+"""MI355X-native partitioned folded spectrum method (PFSM) subspace diagonalisation.
+
+The compute path is libpfsm.so (hand-written HIP kernels for gfx950) behind
+the C ABI declared in include/pfsm.h; this package is its Python binding.
+"""
+from .binding import Plan, PFSMFunction, load_library, solve, LIB_PATH  # noqa: F401

@@ -1,0 +1,217 @@
+"""ctypes binding of libpfsm (argument marshalling only).
+
+Every step of the method runs inside libpfsm's HIP kernels; this module only
+converts torch tensors into device pointers, leading dimensions and the
+current HIP stream.  It raises if the library is missing: there is no
+fallback implementation.
+
+Layout: the library is column-major.  A torch tensor V whose strides are
+(1, ld) is passed as is; any other layout is copied into column-major order
+first.  Returned eigenvector matrices are column-major views (V.stride() ==
+(1, n)); V[:, j] is the j-th eigenvector.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpfsm.so")
+
+PFSM_PREC = {"fp64": 0, "mixed_bf16": 1}
+PFSM_SHIFT = {"fixed": 0, "rayleigh": 1}
+INFO_TEXT = {0: "ok", -1: "non-finite eigenvalue", -3: "submatrix eigensolver did not converge"}
+
+
+class PfsmDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("num_parts", ctypes.c_int32),
+        ("part_offsets", ctypes.POINTER(ctypes.c_int64)),
+        ("halo", ctypes.c_int64),
+        ("iterations", ctypes.c_int32),
+        ("fs_power", ctypes.c_int32),
+        ("alpha", ctypes.c_double),
+        ("shift_mode", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("max_sweeps", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpfsm.so; raises RuntimeError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libpfsm.so not found at %s: build it with "
+                           "`python -m paper_1502_07806_amd.build_lib` (no fallback exists)" % path)
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    lib.pfsm_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PfsmDesc)]
+    lib.pfsm_plan_create.restype = ctypes.c_int
+    lib.pfsm_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.pfsm_workspace_size.restype = ctypes.c_int
+    lib.pfsm_solve.argtypes = [vp, vp, i64, vp, i64, vp, vp, i64, vp, sz, vp, vp]
+    lib.pfsm_solve.restype = ctypes.c_int
+    lib.pfsm_backward.argtypes = [vp, vp, vp, i64, vp, vp, i64, dbl, vp, i64, vp, sz, vp, vp]
+    lib.pfsm_backward.restype = ctypes.c_int
+    lib.pfsm_diagnostics.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, sz, vp]
+    lib.pfsm_diagnostics.restype = ctypes.c_int
+    lib.pfsm_plan_destroy.argtypes = [vp]
+    lib.pfsm_plan_destroy.restype = None
+    lib.pfsm_status_string.argtypes = [ctypes.c_int]
+    lib.pfsm_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise RuntimeError(load_library().pfsm_status_string(status).decode())
+
+
+def _colmajor(t: torch.Tensor) -> Tuple[torch.Tensor, int]:
+    """Column-major view/copy of a 2-D float64 CUDA tensor and its leading dimension."""
+    if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 2:
+        raise ValueError("expected a 2-D float64 GPU tensor")
+    n0, n1 = t.shape
+    if t.stride(0) == 1 and t.stride(1) >= max(1, n0):
+        return t, t.stride(1)
+    c = t.t().contiguous().t()
+    return c, max(1, n0)
+
+
+def _stream_handle() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """A PFSM plan: partition layout, submatrix policy and iteration options for order n."""
+
+    def __init__(self, n: int, part_offsets: Sequence[int], halo: int = -1, iterations: int = 3,
+                 fs_power: int = 2, alpha: float = 0.0, shift_mode: str = "fixed", precision: str = "fp64",
+                 max_sweeps: int = 0):
+        lib = load_library()
+        offs = (ctypes.c_int64 * len(part_offsets))(*[int(x) for x in part_offsets])
+        d = PfsmDesc(int(n), len(part_offsets) - 1, offs, int(halo), int(iterations), int(fs_power), float(alpha),
+                     PFSM_SHIFT[shift_mode], PFSM_PREC[precision], int(max_sweeps), 0)
+        h = ctypes.c_void_p()
+        _check(lib.pfsm_plan_create(ctypes.byref(h), ctypes.byref(d)))
+        self._h = h
+        self.n = int(n)
+        self.part_offsets = [int(x) for x in part_offsets]
+        self.precision = precision
+        sz = ctypes.c_size_t()
+        _check(lib.pfsm_workspace_size(h, ctypes.byref(sz)))
+        self.workspace_bytes = int(sz.value)
+        self._work = None
+        self._info = None
+
+    def _workspace(self, device) -> torch.Tensor:
+        if self._work is None or self._work.device != device:
+            self._work = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+            self._info = torch.zeros(1, dtype=torch.int32, device=device)
+        return self._work
+
+    @property
+    def info(self) -> torch.Tensor:
+        return self._info
+
+    def solve(self, A: torch.Tensor, V_prev: torch.Tensor, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
+              check: bool = True):
+        n = self.n
+        if A.shape != (n, n) or V_prev.shape != (n, n):
+            raise ValueError("A and V_prev must be %d x %d" % (n, n))
+        Ac, lda = _colmajor(A)  # A is symmetric: row-major storage of A is A^T = A as well
+        Vc, ldv = _colmajor(V_prev)
+        work = self._workspace(A.device)
+        if out is None:
+            lam = torch.empty(n, dtype=torch.float64, device=A.device)
+            Vout = torch.empty((n, n), dtype=torch.float64, device=A.device).t()
+        else:
+            lam, Vout = out
+        if Vout.stride(0) != 1:
+            raise ValueError("out V must be column-major (stride(0) == 1)")
+        _check(load_library().pfsm_solve(self._h, Ac.data_ptr(), lda, Vc.data_ptr(), ldv, lam.data_ptr(),
+                                          Vout.data_ptr(), Vout.stride(1), work.data_ptr(), self.workspace_bytes,
+                                          self._info.data_ptr(), _stream_handle()))
+        if check:
+            self.check()
+        return lam, Vout
+
+    def check(self):
+        """Synchronise and raise if the device reported a failure."""
+        code = int(self._info.item())
+        if code != 0:
+            text = INFO_TEXT.get(code, "overlap matrix not positive definite at column %d" % code)
+            raise RuntimeError("pfsm device info %d: %s" % (code, text))
+
+    def backward(self, lam: torch.Tensor, V: torch.Tensor, grad_lam: Optional[torch.Tensor],
+                 grad_V: Optional[torch.Tensor], eta: float = 1e-8) -> torch.Tensor:
+        n = self.n
+        Vc, ldv = _colmajor(V)
+        work = self._workspace(V.device)
+        gl = grad_lam.contiguous() if grad_lam is not None else None
+        if grad_V is not None:
+            gVc, ldg = _colmajor(grad_V)
+        else:
+            gVc, ldg = None, n
+        gA = torch.empty((n, n), dtype=torch.float64, device=V.device).t()
+        _check(load_library().pfsm_backward(self._h, lam.contiguous().data_ptr(), Vc.data_ptr(), ldv,
+                                             gl.data_ptr() if gl is not None else None,
+                                             gVc.data_ptr() if gVc is not None else None, ldg, float(eta),
+                                             gA.data_ptr(), n, work.data_ptr(), self.workspace_bytes,
+                                             self._info.data_ptr(), _stream_handle()))
+        return gA
+
+    def diagnostics(self, A: torch.Tensor, lam: torch.Tensor, V: torch.Tensor) -> Tuple[float, float]:
+        """(||AV - V diag(lam)||_F / ||A||_F, ||V^T V - I||_F), computed on the device in FP64."""
+        Ac, lda = _colmajor(A)
+        Vc, ldv = _colmajor(V)
+        work = self._workspace(A.device)
+        out = torch.empty(2, dtype=torch.float64, device=A.device)
+        _check(load_library().pfsm_diagnostics(self._h, Ac.data_ptr(), lda, lam.contiguous().data_ptr(),
+                                                Vc.data_ptr(), ldv, out.data_ptr(), work.data_ptr(),
+                                                self.workspace_bytes, _stream_handle()))
+        o = out.cpu()
+        return float(o[0]), float(o[1])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.pfsm_plan_destroy(h)
+            self._h = None
+
+
+def solve(A: torch.Tensor, V_prev: torch.Tensor, plan: Plan, check: bool = True):
+    """(lam, V) = PFSM step for (A, V_prev) with `plan`."""
+    return plan.solve(A, V_prev, check=check)
+
+
+class PFSMFunction(torch.autograd.Function):
+    """(lam, V) = PFSMFunction.apply(A, V_prev, plan, eta); gradient flows to A only.
+
+    The backward pass is the eigen-adjoint of A = V diag(lam) V^T computed by
+    libpfsm (pfsm_backward); V_prev and the plan get no gradient."""
+
+    @staticmethod
+    def forward(ctx, A, V_prev, plan: Plan, eta: float = 1e-8):
+        lam, V = plan.solve(A, V_prev)
+        ctx.plan = plan
+        ctx.eta = eta
+        ctx.save_for_backward(lam, V)
+        return lam, V
+
+    @staticmethod
+    def backward(ctx, grad_lam, grad_V):
+        lam, V = ctx.saved_tensors
+        gA = ctx.plan.backward(lam, V, grad_lam, grad_V, ctx.eta)
+        return gA, None, None, None

@@ -1,0 +1,32 @@
+// Batched submatrix eigensolver interface (internal to libpfsm).
+#pragma once
+#include "common.h"
+
+namespace pfsm {
+
+constexpr int EIGH_B = 32;                 // column-block width; pair problems are 2b x 2b
+constexpr double EIGH_PAD_DIAG = 1e200;    // decoupled padding eigenvalue (sorts last)
+constexpr int PFSM_INFO_EIGH_NOCONV = -3;  // a submatrix needed rotations in its last sweep
+
+struct EighBatch {
+  int P;                   // number of submatrices
+  int Mp;                  // padded order (multiple of 2b), common to all
+  int nb;                  // Mp / b (even)
+  int inner_max_sweeps;    // sweeps of the in-LDS pair solver
+  double* Bw;              // [P][Mp][Mp] working matrices (column-major)
+  double* Uw;              // [P][Mp][Mp] accumulated eigenvectors
+  double* Rw;              // [P][nb/2][2b][2b] pair rotations of the current round
+  int* rflag;              // [P][nb/2] 1 if the pair's rotation is not the identity
+  int* state;              // [P][2] {done, rotated-this-sweep}
+  int* sel;                // [P][Mp] ascending rank -> local index
+  const int64_t* wstart;   // [P] first row/column of the submatrix in At
+  const int32_t* wsize;    // [P] order M_p
+  const int32_t* offset;   // [P] rank of the slice's first eigenpair inside the submatrix
+  const int64_t* part_start;  // [P] first global column of the slice
+  int* info;               // device info word (first error wins)
+};
+
+hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, int max_sweeps, hipStream_t s);
+hipError_t embed_start_vectors(const EighBatch& e, double* X, int64_t ldx, double* eps, int64_t n, hipStream_t s);
+
+}  // namespace pfsm

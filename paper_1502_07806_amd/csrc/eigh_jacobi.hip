@@ -1,0 +1,367 @@
+// Batched FP64 eigensolver for the PFSM submatrices (block Jacobi).
+//
+// Each submatrix B_p (order M_p <= Mp) is padded to Mp = multiple of 2b with
+// decoupled diagonal entries PAD_DIAG (which sort above every true
+// eigenvalue), and diagonalised by a two-sided block-cyclic Jacobi method:
+//
+//   for each sweep, for each round of a round-robin tournament over the
+//   nb = Mp/b column blocks:
+//     solve   (one workgroup per block pair (I,J)): the 2b x 2b matrix
+//             [B_II B_IJ; B_JI B_JJ] is diagonalised in LDS by a scalar
+//             parallel-order cyclic Jacobi, giving an orthogonal R_IJ;
+//     apply   (one workgroup per 2b x 2b tile): B <- J^T B J and U <- U J
+//             with J = diag of the R's, as small MFMA products in LDS.
+//
+// A sweep in which no pair needed a rotation marks the submatrix converged;
+// later kernels of that submatrix return immediately.  The rotation
+// threshold is relative: |b_pq| > 2^-53 sqrt(|b_pp b_qq|).
+#include "common.h"
+#include "eigh.h"
+
+namespace pfsm {
+namespace {
+
+constexpr int NT = 256;
+constexpr int B2 = 2 * EIGH_B;   // 64: order of a pair problem / apply tile
+constexpr int LS = B2 + 1;       // LDS row stride
+constexpr double TOL = 1.1102230246251565e-16;  // 2^-53
+constexpr double TINY = 1e-300;
+
+// Circle-method tournament: position -> block index in round r (n even).
+__device__ __host__ inline int rr_index(int pos, int r, int n) {
+  if (pos == 0) return 0;
+  return ((pos - 1 + r) % (n - 1)) + 1;
+}
+__device__ inline void pair_blocks(int k, int r, int nb, int& I, int& J) {
+  int a = rr_index(k, r, nb), b = rr_index(nb - 1 - k, r, nb);
+  I = min(a, b);
+  J = max(a, b);
+}
+// global index (within the padded submatrix) of local index t in [0, 2b) of pair (I, J)
+__device__ inline int pair_idx(int t, int I, int J) { return t < EIGH_B ? I * EIGH_B + t : J * EIGH_B + (t - EIGH_B); }
+
+// ------------------------------------------------------------------ gather
+__global__ void gather_windows(EighBatch e, const double* __restrict__ At, int64_t ldat) {
+  const int p = blockIdx.y;
+  const int Mp = e.Mp;
+  const int64_t w0 = e.wstart[p];
+  const int M = e.wsize[p];
+  double* B = e.Bw + (int64_t)p * Mp * Mp;
+  double* U = e.Uw + (int64_t)p * Mp * Mp;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)Mp * Mp;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int r = (int)(idx % Mp), c = (int)(idx / Mp);
+    double v;
+    if (r < M && c < M) v = At[(w0 + r) + (w0 + c) * ldat];
+    else v = (r == c) ? EIGH_PAD_DIAG : 0.0;
+    B[idx] = v;
+    U[idx] = (r == c) ? 1.0 : 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    e.state[2 * p] = 0;      // done flag
+    e.state[2 * p + 1] = 0;  // rotations in current sweep
+  }
+}
+
+// Start of a sweep: a submatrix whose previous sweep needed no rotation is done.
+__global__ void sweep_begin(EighBatch e, int sweep) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= e.P) return;
+  if (sweep > 0 && e.state[2 * p + 1] == 0) e.state[2 * p] = 1;
+  e.state[2 * p + 1] = 0;
+}
+
+// ------------------------------------------------------------------ pair solve
+__global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
+  const int npairs = e.nb / 2;
+  const int p = blockIdx.x / npairs, k = blockIdx.x % npairs;
+  int* flagR = e.rflag + (int64_t)p * npairs + k;
+  if (e.state[2 * p]) { if (threadIdx.x == 0) *flagR = 0; return; }
+  __shared__ double S[B2][LS];
+  __shared__ double R[B2][LS];
+  __shared__ double cs_c[B2 / 2], cs_s[B2 / 2];
+  __shared__ int pp[B2 / 2], qq[B2 / 2];
+  __shared__ int any_rot, sweep_rot;
+  const int Mp = e.Mp;
+  int I, J;
+  pair_blocks(k, round, e.nb, I, J);
+  const double* B = e.Bw + (int64_t)p * Mp * Mp;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < B2 * B2; idx += NT) {
+    int r = idx % B2, c = idx / B2;
+    S[r][c] = B[pair_idx(r, I, J) + (int64_t)pair_idx(c, I, J) * Mp];
+    R[r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  if (tid == 0) any_rot = 0;
+  __syncthreads();
+  // Is any rotation needed at all?
+  int need = 0;
+  for (int idx = tid; idx < B2 * B2; idx += NT) {
+    int r = idx % B2, c = idx / B2;
+    if (r < c) {
+      double a = fabs(S[r][c]);
+      if (a > TINY && a > TOL * sqrt(fabs(S[r][r]) * fabs(S[c][c]))) need = 1;
+    }
+  }
+  if (need) any_rot = 1;
+  __syncthreads();
+  if (!any_rot) { if (tid == 0) *flagR = 0; return; }
+
+  for (int sweep = 0; sweep < e.inner_max_sweeps; ++sweep) {
+    if (tid == 0) sweep_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < B2 - 1; ++r) {
+      if (tid < B2 / 2) {
+        int a = rr_index(tid, r, B2), b = rr_index(B2 - 1 - tid, r, B2);
+        int pi = min(a, b), qi = max(a, b);
+        double apq = S[pi][qi], app = S[pi][pi], aqq = S[qi][qi];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > TINY && fabs(apq) > TOL * sqrt(fabs(app) * fabs(aqq))) {
+          double tau = (aqq - app) / (2.0 * apq);
+          double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          sweep_rot = 1;
+        }
+        cs_c[tid] = c; cs_s[tid] = s; pp[tid] = pi; qq[tid] = qi;
+      }
+      __syncthreads();
+      // S <- J^T S J on every 2x2 block (pair k1 rows, pair k2 cols), k1 <= k2;
+      // the transposed block is written from the same values so S stays exactly symmetric.
+      for (int idx = tid; idx < (B2 / 2) * (B2 / 2); idx += NT) {
+        int k1 = idx % (B2 / 2), k2 = idx / (B2 / 2);
+        if (k1 > k2) continue;
+        int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+        double c1 = cs_c[k1], s1 = cs_s[k1], c2 = cs_c[k2], s2 = cs_s[k2];
+        double x_pp = S[p1][p2], x_pq = S[p1][q2], x_qp = S[q1][p2], x_qq = S[q1][q2];
+        // rows: p' = c p - s q ; q' = s p + c q
+        double y_pp = c1 * x_pp - s1 * x_qp, y_pq = c1 * x_pq - s1 * x_qq;
+        double y_qp = s1 * x_pp + c1 * x_qp, y_qq = s1 * x_pq + c1 * x_qq;
+        // cols: p' = c p - s q ; q' = s p + c q
+        double z_pp = c2 * y_pp - s2 * y_pq, z_pq = s2 * y_pp + c2 * y_pq;
+        double z_qp = c2 * y_qp - s2 * y_qq, z_qq = s2 * y_qp + c2 * y_qq;
+        if (k1 == k2) {
+          if (s1 != 0.0) { z_pq = 0.0; z_qp = 0.0; }
+          S[p1][p1] = z_pp; S[q1][q1] = z_qq; S[p1][q1] = z_pq; S[q1][p1] = z_qp;
+        } else {
+          S[p1][p2] = z_pp; S[p1][q2] = z_pq; S[q1][p2] = z_qp; S[q1][q2] = z_qq;
+          S[p2][p1] = z_pp; S[q2][p1] = z_pq; S[p2][q1] = z_qp; S[q2][q1] = z_qq;
+        }
+      }
+      // R <- R J
+      for (int idx = tid; idx < B2 * (B2 / 2); idx += NT) {
+        int i = idx % B2, kk = idx / B2;
+        int pc = pp[kk], qc = qq[kk];
+        double c = cs_c[kk], s = cs_s[kk];
+        double rp = R[i][pc], rq = R[i][qc];
+        R[i][pc] = c * rp - s * rq;
+        R[i][qc] = s * rp + c * rq;
+      }
+      __syncthreads();
+    }
+    if (!sweep_rot) break;
+  }
+  double* Rg = e.Rw + ((int64_t)p * npairs + k) * B2 * B2;
+  for (int idx = tid; idx < B2 * B2; idx += NT) {
+    int r = idx % B2, c = idx / B2;
+    Rg[idx] = R[r][c];
+  }
+  if (tid == 0) {
+    *flagR = 1;
+    atomicOr(&e.state[2 * p + 1], 1);
+  }
+}
+
+// 64x64x64 product in LDS with FP64 MFMA: Z = op(X) * Y, op(X) = X or X^T.
+// Wave w owns rows [32*(w&1), +32) and columns [32*(w>>1), +32).
+template <bool TX>
+__device__ inline void mm64(const double (*X)[LS], const double (*Y)[LS], v4d acc[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int i0 = (wave & 1) * 32, j0 = (wave >> 1) * 32;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k = 0; k < B2; k += 4) {
+    double af[2], bf[2];
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib) {
+      int i = i0 + ib * 16 + l16;
+      af[ib] = TX ? X[k + lq][i] : X[i][k + lq];
+    }
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) bf[jb] = Y[k + lq][j0 + jb * 16 + l16];
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+        acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[jb], af[ib], acc[ib][jb], 0, 0, 0);
+  }
+}
+__device__ inline void store_acc(double (*Z)[LS], v4d acc[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int i0 = (wave & 1) * 32, j0 = (wave >> 1) * 32;
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Z[i0 + ib * 16 + l16][j0 + jb * 16 + lq + 4 * r] = acc[ib][jb][r];
+}
+
+// ------------------------------------------------------------------ apply
+// Work items per submatrix: npairs(npairs+1)/2 tiles (k1 <= k2) of B, each also
+// written transposed into (k2, k1) so B stays exactly symmetric, then
+// (Mp/2b)*npairs tiles of U.
+__global__ __launch_bounds__(NT) void pair_apply(EighBatch e, int round) {
+  const int npairs = e.nb / 2;
+  const int nrc = e.Mp / B2;
+  const int ntri = npairs * (npairs + 1) / 2;
+  const int per = ntri + nrc * npairs;
+  const int p = blockIdx.x / per, w = blockIdx.x % per;
+  if (e.state[2 * p]) return;
+  const int Mp = e.Mp;
+  const int* fl = e.rflag + (int64_t)p * npairs;
+  const double* Rbase = e.Rw + (int64_t)p * npairs * B2 * B2;
+  __shared__ double T[B2][LS];
+  __shared__ double X[B2][LS];
+  __shared__ double Y[B2][LS];
+  const int tid = threadIdx.x;
+  v4d acc[2][2];
+  if (w < ntri) {
+    int k2 = 0;
+    while ((k2 + 1) * (k2 + 2) / 2 <= w) ++k2;
+    const int k1 = w - k2 * (k2 + 1) / 2;
+    const int f1 = fl[k1], f2 = fl[k2];
+    if (!f1 && !f2) return;
+    int I1, J1, I2, J2;
+    pair_blocks(k1, round, e.nb, I1, J1);
+    pair_blocks(k2, round, e.nb, I2, J2);
+    double* B = e.Bw + (int64_t)p * Mp * Mp;
+    const double* R1 = Rbase + (int64_t)k1 * B2 * B2;
+    const double* R2 = Rbase + (int64_t)k2 * B2 * B2;
+    for (int idx = tid; idx < B2 * B2; idx += NT) {
+      int r = idx % B2, c = idx / B2;
+      T[r][c] = B[pair_idx(r, I1, J1) + (int64_t)pair_idx(c, I2, J2) * Mp];
+      X[r][c] = f1 ? R1[idx] : (r == c ? 1.0 : 0.0);
+      Y[r][c] = f2 ? R2[idx] : (r == c ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    mm64<true>(X, T, acc);  // R1^T T
+    __syncthreads();
+    store_acc(T, acc);
+    __syncthreads();
+    mm64<false>(T, Y, acc);  // (R1^T T) R2
+    __syncthreads();
+    store_acc(T, acc);
+    __syncthreads();
+    for (int idx = tid; idx < B2 * B2; idx += NT) {
+      int r = idx % B2, c = idx / B2;
+      int gr = pair_idx(r, I1, J1), gc = pair_idx(c, I2, J2);
+      double v = T[r][c];
+      B[gr + (int64_t)gc * Mp] = v;
+      if (k1 != k2) B[gc + (int64_t)gr * Mp] = v;
+    }
+  } else {
+    const int ww = w - ntri;
+    const int rc = ww % nrc, k2 = ww / nrc;
+    if (!fl[k2]) return;
+    int I2, J2;
+    pair_blocks(k2, round, e.nb, I2, J2);
+    double* U = e.Uw + (int64_t)p * Mp * Mp;
+    const double* R2 = Rbase + (int64_t)k2 * B2 * B2;
+    for (int idx = tid; idx < B2 * B2; idx += NT) {
+      int r = idx % B2, c = idx / B2;
+      T[r][c] = U[(rc * B2 + r) + (int64_t)pair_idx(c, I2, J2) * Mp];
+      Y[r][c] = R2[idx];
+    }
+    __syncthreads();
+    mm64<false>(T, Y, acc);
+    __syncthreads();
+    store_acc(T, acc);
+    __syncthreads();
+    for (int idx = tid; idx < B2 * B2; idx += NT) {
+      int r = idx % B2, c = idx / B2;
+      U[(rc * B2 + r) + (int64_t)pair_idx(c, I2, J2) * Mp] = T[r][c];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ select + embed
+// Ascending rank of each diagonal entry (stable), then the slice's ranks
+// [offset, offset + size) become start vectors X0 (zero outside the
+// submatrix rows) and shifts eps.  One workgroup per submatrix for ranking.
+__global__ __launch_bounds__(NT) void rank_select(EighBatch e) {
+  const int p = blockIdx.x;
+  const int Mp = e.Mp;
+  const double* B = e.Bw + (int64_t)p * Mp * Mp;
+  int* sel = e.sel + (int64_t)p * Mp;
+  extern __shared__ double dsh[];
+  for (int i = threadIdx.x; i < Mp; i += NT) dsh[i] = B[i + (int64_t)i * Mp];
+  __syncthreads();
+  for (int i = threadIdx.x; i < Mp; i += NT) {
+    double di = dsh[i];
+    int rank = 0;
+    for (int j = 0; j < Mp; ++j) {
+      double dj = dsh[j];
+      rank += (dj < di) || (dj == di && j < i);
+    }
+    sel[rank] = i;  // rank -> local index
+  }
+  // not converged: the last sweep still rotated and no sweep was rotation-free
+  if (threadIdx.x == 0 && e.state[2 * p] == 0 && e.state[2 * p + 1] != 0 && e.info)
+    atomicCAS(e.info, 0, PFSM_INFO_EIGH_NOCONV);
+}
+
+__global__ void embed_x0(EighBatch e, double* __restrict__ X, int64_t ldx, double* __restrict__ eps, int64_t n) {
+  // one workgroup per column c of X0
+  const int64_t c = blockIdx.x;
+  // find partition of column c (part offsets are ascending, P small)
+  int p = 0;
+  while (p + 1 < e.P && e.part_start[p + 1] <= c) ++p;
+  const int64_t s = e.part_start[p];
+  const int64_t w0 = e.wstart[p];
+  const int M = e.wsize[p];
+  const int Mp = e.Mp;
+  const int li = e.sel[(int64_t)p * Mp + e.offset[p] + (int)(c - s)];
+  const double* U = e.Uw + (int64_t)p * Mp * Mp + (int64_t)li * Mp;
+  for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+    double v = 0.0;
+    if (r >= w0 && r < w0 + M) v = U[r - w0];
+    X[r + c * ldx] = v;
+  }
+  if (threadIdx.x == 0) {
+    const double* B = e.Bw + (int64_t)p * Mp * Mp;
+    eps[c] = B[li + (int64_t)li * Mp];
+  }
+}
+
+}  // namespace
+
+hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, int max_sweeps, hipStream_t s) {
+  const int npairs = e.nb / 2;
+  const int nrc = e.Mp / B2;
+  {
+    dim3 grid((unsigned)std::min<int64_t>(((int64_t)e.Mp * e.Mp + 255) / 256, 1024), e.P);
+    hipLaunchKernelGGL(gather_windows, grid, dim3(256), 0, s, e, At, ldat);
+  }
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    hipLaunchKernelGGL(sweep_begin, dim3((e.P + 63) / 64), dim3(64), 0, s, e, sw);
+    for (int r = 0; r < e.nb - 1; ++r) {
+      hipLaunchKernelGGL(pair_solve, dim3(e.P * npairs), dim3(NT), 0, s, e, r);
+      hipLaunchKernelGGL(pair_apply, dim3(e.P * (npairs * (npairs + 1) / 2 + nrc * npairs)), dim3(NT), 0, s, e, r);
+    }
+  }
+  hipLaunchKernelGGL(rank_select, dim3(e.P), dim3(NT), e.Mp * sizeof(double), s, e);
+  return hipGetLastError();
+}
+
+hipError_t embed_start_vectors(const EighBatch& e, double* X, int64_t ldx, double* eps, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(embed_x0, dim3((unsigned)n), dim3(256), 0, s, e, X, ldx, eps, n);
+  return hipGetLastError();
+}
+
+}  // namespace pfsm

@@ -1,0 +1,18 @@
+#pragma once
+#include "common.h"
+namespace pfsm {
+hipError_t fill_i32(int* p, int64_t count, int value, hipStream_t s);
+hipError_t gershgorin_alpha(const double* At, int64_t n, int64_t ld, int q, double user_alpha,
+                            double* part_lo, double* part_hi, double* scal, hipStream_t s);
+hipError_t rq_reduce(const double* part, int tiles_m, int64_t n, const double* den, double* out, hipStream_t s);
+hipError_t col_norm2(const double* X, int64_t m, int64_t n, int64_t ldx, double* out, hipStream_t s);
+hipError_t finalize_order(const double* lam_u, const double* X, int64_t n, int64_t ldx, double* Xp, int64_t ldxp,
+                          double* lam_out, int* rank, double* sgn, int* info, hipStream_t s);
+hipError_t adjoint_middle(double* T, int64_t ldt, int64_t n, const double* lam, const double* glam, double eta,
+                          bool have_t, hipStream_t s);
+hipError_t symmetrize(double* C, int64_t n, int64_t ldc, hipStream_t s);
+hipError_t scale_cols(const double* V, int64_t n, int64_t ldv, const double* d, double* out, int64_t ldo, hipStream_t s);
+hipError_t diag_sums(const double* A, int64_t lda, const double* AV, int64_t ldav, const double* V, int64_t ldv,
+                     const double* lam, const double* G, int64_t ldg, int64_t n, double* part, double* out,
+                     hipStream_t s);
+}  // namespace pfsm

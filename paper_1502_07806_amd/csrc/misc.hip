@@ -1,0 +1,342 @@
+// Bandwidth-bound helper kernels of the PFSM step: Gershgorin interval and
+// step length, Rayleigh-quotient reduction, sign convention + stable ordering
+// + column permutation, the eigen-adjoint middle factor, symmetrisation and
+// diagnostic norms.  One workgroup per column wherever a column is reduced,
+// so every read is a contiguous column segment.
+#include "common.h"
+#include "misc.h"
+#include <cfloat>
+
+namespace pfsm {
+namespace {
+
+constexpr int NT = 256;
+
+__device__ inline double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int w = 0; w < nw; ++w) t += sh[w];  // fixed order: deterministic
+  return t;
+}
+
+__global__ void k_fill_i32(int* p, int64_t count, int value) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// Column j of the symmetric At: radius sum_{i != j} |At_ij| (= row radius by symmetry).
+__global__ __launch_bounds__(NT) void k_gersh_col(const double* At, int64_t n, int64_t ld, double* lo, double* hi) {
+  __shared__ double sh[NT / 64];
+  const int64_t j = blockIdx.x;
+  const double* c = At + j * ld;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) s += fabs(c[i]);
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    double d = c[j];
+    double r = s - fabs(d);
+    lo[j] = d - r;
+    hi[j] = d + r;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_gersh_final(const double* lo, const double* hi, int64_t n, int q,
+                                                     double user_alpha, double* scal) {
+  __shared__ double slo[NT], shi[NT];
+  double a = DBL_MAX, b = -DBL_MAX;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    a = fmin(a, lo[i]);
+    b = fmax(b, hi[i]);
+  }
+  slo[threadIdx.x] = a;
+  shi[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + w]);
+      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double rho = shi[0] - slo[0];
+    double alpha;
+    if (user_alpha > 0.0) alpha = user_alpha;
+    else alpha = rho > 0.0 ? 1.0 / (q == 2 ? rho * rho : rho) : 0.0;
+    scal[0] = alpha;
+    scal[1] = slo[0];
+    scal[2] = shi[0];
+  }
+}
+
+__global__ void k_rq_reduce(const double* part, int tiles_m, int64_t n, const double* den, double* out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int t = 0; t < tiles_m; ++t) s += part[(int64_t)t * n + j];
+  if (den) s /= den[j];
+  out[j] = s;
+}
+
+__global__ __launch_bounds__(NT) void k_col_norm2(const double* X, int64_t m, int64_t ldx, double* out) {
+  __shared__ double sh[NT / 64];
+  const int64_t j = blockIdx.x;
+  const double* c = X + j * ldx;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += NT) s += c[i] * c[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+// Sign convention: the largest-magnitude entry of each column is positive
+// (ties: lowest row).  One workgroup per column.
+__global__ __launch_bounds__(NT) void k_col_sign(const double* X, int64_t n, int64_t ldx, double* sgn) {
+  __shared__ double sv[NT];
+  __shared__ int64_t si[NT];
+  const int64_t j = blockIdx.x;
+  const double* c = X + j * ldx;
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    double a = fabs(c[i]);
+    if (a > best) { best = a; bi = i; }  // strided scan: first maximum per thread
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      double a = sv[threadIdx.x + w];
+      int64_t ai = si[threadIdx.x + w];
+      if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && ai < si[threadIdx.x])) {
+        sv[threadIdx.x] = a;
+        si[threadIdx.x] = ai;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sgn[j] = (c[si[0]] < 0.0) ? -1.0 : 1.0;
+}
+
+// Stable ascending rank: #{k : l_k < l_j} + #{k < j : l_k == l_j}.
+__global__ __launch_bounds__(NT) void k_rank(const double* lam, int64_t n, int* rank, double* lam_out, int* info) {
+  __shared__ double tile[NT];
+  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const double lj = j < n ? lam[j] : 0.0;
+  int64_t r = 0;
+  for (int64_t base = 0; base < n; base += NT) {
+    __syncthreads();
+    if (base + threadIdx.x < n) tile[threadIdx.x] = lam[base + threadIdx.x];
+    __syncthreads();
+    const int cnt = (int)min<int64_t>(NT, n - base);
+    for (int t = 0; t < cnt; ++t) {
+      double lk = tile[t];
+      r += (lk < lj) || (lk == lj && base + t < j);
+    }
+  }
+  if (j < n) {
+    if (!isfinite(lj)) {
+      atomicCAS(info, 0, -1);
+      r = j;  // keep a valid permutation slot for non-finite values
+    }
+    if (r >= n) r = n - 1;
+    rank[j] = (int)r;
+    lam_out[r] = lj;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_permute(const double* X, int64_t n, int64_t ldx, const int* rank,
+                                                  const double* sgn, double* Xp, int64_t ldxp) {
+  const int64_t j = blockIdx.x;
+  const double s = sgn[j];
+  const double* src = X + j * ldx;
+  double* dst = Xp + (int64_t)rank[j] * ldxp;
+  for (int64_t i = threadIdx.x; i < n; i += NT) dst[i] = s * src[i];
+}
+
+// M = diag(glam) + F o T, F_ij = d / (d^2 + eta^2), d = lam_j - lam_i, F_ii = 0.
+__global__ void k_adjoint_middle(double* T, int64_t ldt, int64_t n, const double* lam, const double* glam,
+                                 double eta, int have_t) {
+  const int64_t j = blockIdx.y;
+  const double lj = lam[j];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    if (i == j) {
+      v = glam ? glam[j] : 0.0;
+    } else if (have_t) {
+      double d = lj - lam[i];
+      v = d / (d * d + eta * eta) * T[i + j * ldt];
+    }
+    T[i + j * ldt] = v;
+  }
+}
+
+// C <- (C + C^T) / 2, tile-pair at a time through LDS.
+__global__ void k_symmetrize(double* C, int64_t n, int64_t ldc) {
+  __shared__ double a[32][33], b[32][33];
+  const int64_t bi = blockIdx.x, bj = blockIdx.y;
+  if (bi < bj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    int64_t gi = bi * 32 + tx, gj = bj * 32 + r;
+    a[r][tx] = (gi < n && gj < n) ? C[gi + gj * ldc] : 0.0;   // a[c][r] = C(bi*32+r', bj*32+c')
+    int64_t hi = bj * 32 + tx, hj = bi * 32 + r;
+    b[r][tx] = (hi < n && hj < n) ? C[hi + hj * ldc] : 0.0;
+  }
+  __syncthreads();
+  // a[c][r] holds C(bi*32 + r, bj*32 + c); b[c][r] holds C(bj*32 + r, bi*32 + c)
+  for (int r = ty; r < 32; r += 8) {
+    int64_t gi = bi * 32 + tx, gj = bj * 32 + r;
+    double v = 0.5 * (a[r][tx] + b[tx][r]);
+    if (gi < n && gj < n) C[gi + gj * ldc] = v;
+  }
+  if (bi != bj) {
+    for (int r = ty; r < 32; r += 8) {
+      int64_t hi = bj * 32 + tx, hj = bi * 32 + r;
+      double v = 0.5 * (b[r][tx] + a[tx][r]);
+      if (hi < n && hj < n) C[hi + hj * ldc] = v;
+    }
+  }
+}
+
+__global__ void k_mirror_lower(double* C, int64_t n, int64_t ldc) {
+  __shared__ double a[32][33];
+  const int64_t bi = blockIdx.x, bj = blockIdx.y;  // destination tile (bi < bj: strictly upper)
+  if (bi > bj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // read source tile (bj, bi) (lower) coalesced
+  for (int r = ty; r < 32; r += 8) {
+    int64_t gi = bj * 32 + tx, gj = bi * 32 + r;
+    a[r][tx] = (gi < n && gj < n) ? C[gi + gj * ldc] : 0.0;  // a[c][r] = C(bj*32 + r, bi*32 + c)
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    int64_t gi = bi * 32 + tx, gj = bj * 32 + r;  // destination (row gi, col gj) = C(gj, gi)
+    if (gi < n && gj < n && gi < gj) C[gi + gj * ldc] = a[tx][r];
+  }
+}
+
+__global__ void k_scale_cols(const double* V, int64_t n, int64_t ldv, const double* d, double* out, int64_t ldo) {
+  const int64_t j = blockIdx.y;
+  const double s = d ? d[j] : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i + j * ldo] = s * V[i + j * ldv];
+}
+
+// Column partial sums for the diagnostics: part[0][j] = ||AV_j - lam_j V_j||^2,
+// part[1][j] = ||A_j||^2, part[2][j] = ||G_j - e_j||^2 (G = V^T V).
+__global__ __launch_bounds__(NT) void k_diag_cols(const double* A, int64_t lda, const double* AV, int64_t ldav,
+                                                   const double* V, int64_t ldv, const double* lam, const double* G,
+                                                   int64_t ldg, int64_t n, double* part) {
+  __shared__ double sh[NT / 64];
+  const int64_t j = blockIdx.x;
+  const double lj = lam[j];
+  double r = 0.0, a = 0.0, o = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    double t = AV[i + j * ldav] - lj * V[i + j * ldv];
+    r += t * t;
+    double x = A[i + j * lda];
+    a += x * x;
+    double g = G[i + j * ldg] - (i == j ? 1.0 : 0.0);
+    o += g * g;
+  }
+  r = block_sum(r, sh);
+  a = block_sum(a, sh);
+  o = block_sum(o, sh);
+  if (threadIdx.x == 0) {
+    part[j] = r;
+    part[n + j] = a;
+    part[2 * n + j] = o;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_diag_final(const double* part, int64_t n, double* out) {
+  __shared__ double sh[NT / 64];
+  double r = 0.0, a = 0.0, o = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    r += part[i];
+    a += part[n + i];
+    o += part[2 * n + i];
+  }
+  r = block_sum(r, sh);
+  a = block_sum(a, sh);
+  o = block_sum(o, sh);
+  if (threadIdx.x == 0) {
+    out[0] = sqrt(r) / sqrt(a);
+    out[1] = sqrt(o);
+  }
+}
+
+}  // namespace
+
+hipError_t fill_i32(int* p, int64_t count, int value, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 1024))),
+                     dim3(256), 0, s, p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t mirror_lower(double* C, int64_t n, int64_t ldc, hipStream_t s) {
+  unsigned t = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(k_mirror_lower, dim3(t, t), dim3(256), 0, s, C, n, ldc);
+  return hipGetLastError();
+}
+
+hipError_t gershgorin_alpha(const double* At, int64_t n, int64_t ld, int q, double user_alpha, double* part_lo,
+                            double* part_hi, double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_gersh_col, dim3((unsigned)n), dim3(NT), 0, s, At, n, ld, part_lo, part_hi);
+  hipLaunchKernelGGL(k_gersh_final, dim3(1), dim3(NT), 0, s, part_lo, part_hi, n, q, user_alpha, scal);
+  return hipGetLastError();
+}
+
+hipError_t rq_reduce(const double* part, int tiles_m, int64_t n, const double* den, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rq_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, tiles_m, n, den, out);
+  return hipGetLastError();
+}
+
+hipError_t col_norm2(const double* X, int64_t m, int64_t n, int64_t ldx, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_norm2, dim3((unsigned)n), dim3(NT), 0, s, X, m, ldx, out);
+  return hipGetLastError();
+}
+
+hipError_t finalize_order(const double* lam_u, const double* X, int64_t n, int64_t ldx, double* Xp, int64_t ldxp,
+                          double* lam_out, int* rank, double* sgn, int* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_sign, dim3((unsigned)n), dim3(NT), 0, s, X, n, ldx, sgn);
+  hipLaunchKernelGGL(k_rank, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, lam_u, n, rank, lam_out, info);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)n), dim3(NT), 0, s, X, n, ldx, rank, sgn, Xp, ldxp);
+  return hipGetLastError();
+}
+
+hipError_t adjoint_middle(double* T, int64_t ldt, int64_t n, const double* lam, const double* glam, double eta,
+                          bool have_t, hipStream_t s) {
+  dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 64), (unsigned)n);
+  hipLaunchKernelGGL(k_adjoint_middle, grid, dim3(256), 0, s, T, ldt, n, lam, glam, eta, have_t ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t symmetrize(double* C, int64_t n, int64_t ldc, hipStream_t s) {
+  unsigned t = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(k_symmetrize, dim3(t, t), dim3(256), 0, s, C, n, ldc);
+  return hipGetLastError();
+}
+
+hipError_t scale_cols(const double* V, int64_t n, int64_t ldv, const double* d, double* out, int64_t ldo,
+                      hipStream_t s) {
+  dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 64), (unsigned)n);
+  hipLaunchKernelGGL(k_scale_cols, grid, dim3(256), 0, s, V, n, ldv, d, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t diag_sums(const double* A, int64_t lda, const double* AV, int64_t ldav, const double* V, int64_t ldv,
+                     const double* lam, const double* G, int64_t ldg, int64_t n, double* part, double* out,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_cols, dim3((unsigned)n), dim3(NT), 0, s, A, lda, AV, ldav, V, ldv, lam, G, ldg, n, part);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(NT), 0, s, part, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace pfsm

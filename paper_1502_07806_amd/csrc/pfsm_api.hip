@@ -1,0 +1,389 @@
+// C ABI of libpfsm: plan construction (partition / submatrix tables, step
+// layout, workspace carving) and the enqueue sequence of one PFSM step.
+#include "../../include/pfsm.h"
+#include "common.h"
+#include "eigh.h"
+#include "chol.h"
+#include "misc.h"
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+using namespace pfsm;
+
+struct pfsm_plan {
+  int64_t n = 0;
+  int P = 0;
+  int64_t halo = 0;
+  int iterations = 0, q = 2, shift_mode = 0, precision = 0, max_sweeps = 10;
+  double alpha = 0.0;
+  std::vector<int64_t> part_start, wstart;
+  std::vector<int32_t> part_size, wsize, offset;
+  std::vector<int32_t> krange;  // [tiles_n][2] K range of the first folded-spectrum product
+  int Mp = 0, nb = 0;
+  int device = 0;
+  // device table
+  void* dtab = nullptr;
+  int64_t* d_wstart = nullptr;
+  int32_t* d_wsize = nullptr;
+  int32_t* d_offset = nullptr;
+  int64_t* d_part_start = nullptr;
+  int32_t* d_krange = nullptr;
+  // workspace layout (byte offsets)
+  size_t o_At, o_b0, o_b1, o_Bw, o_Uw, o_Rw, o_rflag, o_state, o_sel, o_T, o_part, o_eps, o_lamu, o_sgn, o_rank,
+      o_scal, o_glo, o_ghi, o_den, total;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + bbytes && pb < pa + abytes;
+}
+
+pfsm_status hip_status(hipError_t e) { return e == hipSuccess ? PFSM_OK : PFSM_HIP_ERROR; }
+
+#define PFSM_TRY(expr)                          \
+  do {                                          \
+    hipError_t _e = (expr);                     \
+    if (_e != hipSuccess) return PFSM_HIP_ERROR; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* pfsm_status_string(pfsm_status s) {
+  switch (s) {
+    case PFSM_OK: return "PFSM_OK";
+    case PFSM_INVALID_ARG: return "PFSM_INVALID_ARG: invalid argument";
+    case PFSM_NOT_SUPPORTED: return "PFSM_NOT_SUPPORTED: option not supported";
+    case PFSM_OOM: return "PFSM_OOM: out of memory";
+    case PFSM_HIP_ERROR: return "PFSM_HIP_ERROR: HIP runtime error";
+    case PFSM_WORKSPACE_TOO_SMALL: return "PFSM_WORKSPACE_TOO_SMALL: workspace smaller than pfsm_workspace_size";
+  }
+  return "PFSM: unknown status";
+}
+
+pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
+  if (!out || !d) return PFSM_INVALID_ARG;
+  *out = nullptr;
+  if (d->n < 1 || d->n > (int64_t)1 << 20) return PFSM_INVALID_ARG;
+  if (d->num_parts < 1 || d->num_parts > d->n || !d->part_offsets) return PFSM_INVALID_ARG;
+  if (d->iterations < 0 || d->iterations > 1000) return PFSM_INVALID_ARG;
+  if (d->fs_power != 1 && d->fs_power != 2) return PFSM_INVALID_ARG;
+  if (d->shift_mode != PFSM_SHIFT_FIXED && d->shift_mode != PFSM_SHIFT_RAYLEIGH) return PFSM_INVALID_ARG;
+  if (d->precision != PFSM_PREC_FP64 && d->precision != PFSM_PREC_MIXED_BF16) return PFSM_INVALID_ARG;
+  if (d->reserved != 0) return PFSM_INVALID_ARG;
+  if (!(d->alpha == d->alpha)) return PFSM_INVALID_ARG;  // NaN
+  const int64_t n = d->n;
+  const int P = d->num_parts;
+  if (d->part_offsets[0] != 0 || d->part_offsets[P] != n) return PFSM_INVALID_ARG;
+  int64_t mmax = 0;
+  for (int p = 0; p < P; ++p) {
+    int64_t m = d->part_offsets[p + 1] - d->part_offsets[p];
+    if (m < 1) return PFSM_INVALID_ARG;
+    mmax = std::max(mmax, m);
+  }
+  if (d->precision == PFSM_PREC_MIXED_BF16) return PFSM_NOT_SUPPORTED;  // enabled with the mixed kernels
+
+  pfsm_plan* pl = new (std::nothrow) pfsm_plan();
+  if (!pl) return PFSM_OOM;
+  pl->n = n;
+  pl->P = P;
+  pl->halo = d->halo < 0 ? mmax / 2 : d->halo;
+  pl->iterations = d->iterations;
+  pl->q = d->fs_power;
+  pl->alpha = d->alpha;
+  pl->shift_mode = d->shift_mode;
+  pl->precision = d->precision;
+  pl->max_sweeps = d->max_sweeps > 0 ? d->max_sweeps : 10;
+  int Mmax = 0;
+  for (int p = 0; p < P; ++p) {
+    int64_t s = d->part_offsets[p], m = d->part_offsets[p + 1] - s;
+    int64_t M = std::min<int64_t>(n, m + 2 * pl->halo);
+    int64_t w = std::min<int64_t>(std::max<int64_t>(s - pl->halo, 0), n - M);
+    pl->part_start.push_back(s);
+    pl->part_size.push_back((int32_t)m);
+    pl->wstart.push_back(w);
+    pl->wsize.push_back((int32_t)M);
+    pl->offset.push_back((int32_t)(s - w));
+    Mmax = std::max<int>(Mmax, (int)M);
+  }
+  const int B2 = 2 * EIGH_B;
+  pl->Mp = (Mmax + B2 - 1) / B2 * B2;
+  pl->nb = pl->Mp / EIGH_B;
+  // K range of each 128-column tile in the first product At * X0: the union of
+  // the submatrix row ranges of the slices the tile touches, widened to BK.
+  const int64_t tiles_n = (n + GEMM_BN - 1) / GEMM_BN;
+  for (int64_t t = 0; t < tiles_n; ++t) {
+    int64_t c0 = t * GEMM_BN, c1 = std::min<int64_t>(n, c0 + GEMM_BN);
+    int64_t lo = n, hi = 0;
+    for (int p = 0; p < P; ++p) {
+      int64_t s = pl->part_start[p], e = s + pl->part_size[p];
+      if (e <= c0 || s >= c1) continue;
+      lo = std::min(lo, pl->wstart[p]);
+      hi = std::max(hi, pl->wstart[p] + pl->wsize[p]);
+    }
+    lo = lo / GEMM_BK * GEMM_BK;
+    hi = std::min<int64_t>(n, (hi + GEMM_BK - 1) / GEMM_BK * GEMM_BK);
+    pl->krange.push_back((int32_t)lo);
+    pl->krange.push_back((int32_t)hi);
+  }
+  // device table
+  size_t tb = 0;
+  size_t o_ws = tb; tb = align256(tb + P * sizeof(int64_t));
+  size_t o_wz = tb; tb = align256(tb + P * sizeof(int32_t));
+  size_t o_of = tb; tb = align256(tb + P * sizeof(int32_t));
+  size_t o_ps = tb; tb = align256(tb + P * sizeof(int64_t));
+  size_t o_kr = tb; tb = align256(tb + pl->krange.size() * sizeof(int32_t));
+  if (hipGetDevice(&pl->device) != hipSuccess || hipMalloc(&pl->dtab, tb) != hipSuccess) {
+    delete pl;
+    return PFSM_HIP_ERROR;
+  }
+  char* base = (char*)pl->dtab;
+  pl->d_wstart = (int64_t*)(base + o_ws);
+  pl->d_wsize = (int32_t*)(base + o_wz);
+  pl->d_offset = (int32_t*)(base + o_of);
+  pl->d_part_start = (int64_t*)(base + o_ps);
+  pl->d_krange = (int32_t*)(base + o_kr);
+  bool ok = hipMemcpy(pl->d_wstart, pl->wstart.data(), P * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(pl->d_wsize, pl->wsize.data(), P * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(pl->d_offset, pl->offset.data(), P * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(pl->d_part_start, pl->part_start.data(), P * sizeof(int64_t), hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            hipMemcpy(pl->d_krange, pl->krange.data(), pl->krange.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    hipFree(pl->dtab);
+    delete pl;
+    return PFSM_HIP_ERROR;
+  }
+  // workspace layout
+  const size_t N2 = (size_t)n * n * sizeof(double);
+  const int tiles_m = (int)((n + GEMM_BM - 1) / GEMM_BM);
+  const size_t Mp2 = (size_t)pl->Mp * pl->Mp * sizeof(double);
+  size_t w = 0;
+  pl->o_At = w; w = align256(w + N2);
+  pl->o_b0 = w; w = align256(w + N2);
+  pl->o_b1 = w; w = align256(w + N2);
+  pl->o_Bw = w; w = align256(w + P * Mp2);
+  pl->o_Uw = w; w = align256(w + P * Mp2);
+  pl->o_Rw = w; w = align256(w + (size_t)P * (pl->nb / 2) * B2 * B2 * sizeof(double));
+  pl->o_rflag = w; w = align256(w + (size_t)P * (pl->nb / 2) * sizeof(int));
+  pl->o_state = w; w = align256(w + (size_t)P * 2 * sizeof(int));
+  pl->o_sel = w; w = align256(w + (size_t)P * pl->Mp * sizeof(int));
+  pl->o_T = w; w = align256(w + (size_t)((n + CHOL_NB - 1) / CHOL_NB) * CHOL_NB * CHOL_NB * sizeof(double));
+  pl->o_part = w; w = align256(w + (size_t)std::max<int64_t>(tiles_m, 3) * n * sizeof(double));
+  pl->o_eps = w; w = align256(w + n * sizeof(double));
+  pl->o_lamu = w; w = align256(w + n * sizeof(double));
+  pl->o_sgn = w; w = align256(w + n * sizeof(double));
+  pl->o_rank = w; w = align256(w + n * sizeof(int));
+  pl->o_scal = w; w = align256(w + 8 * sizeof(double));
+  pl->o_glo = w; w = align256(w + n * sizeof(double));
+  pl->o_ghi = w; w = align256(w + n * sizeof(double));
+  pl->o_den = w; w = align256(w + n * sizeof(double));
+  pl->total = w;
+  *out = pl;
+  return PFSM_OK;
+}
+
+pfsm_status pfsm_workspace_size(const pfsm_plan* pl, size_t* bytes) {
+  if (!pl || !bytes) return PFSM_INVALID_ARG;
+  *bytes = pl->total;
+  return PFSM_OK;
+}
+
+void pfsm_plan_destroy(pfsm_plan* pl) {
+  if (!pl) return;
+  if (pl->dtab) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(pl->dtab);
+  }
+  delete pl;
+}
+
+pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv, double* dLam,
+                       double* dVout, int64_t ldvo, void* dWork, size_t work_bytes, int32_t* dInfo, void* stream) {
+  if (!pl || !dA || !dV || !dLam || !dVout || !dWork || !dInfo) return PFSM_INVALID_ARG;
+  const int64_t n = pl->n;
+  if (lda < n || ldv < n || ldvo < n) return PFSM_INVALID_ARG;
+  if (((uintptr_t)dWork) % 256 != 0) return PFSM_INVALID_ARG;
+  if (work_bytes < pl->total) return PFSM_WORKSPACE_TOO_SMALL;
+  const size_t bA = (size_t)(lda * (n - 1) + n) * sizeof(double);
+  const size_t bV = (size_t)(ldv * (n - 1) + n) * sizeof(double);
+  const size_t bVo = (size_t)(ldvo * (n - 1) + n) * sizeof(double);
+  if (overlaps(dVout, bVo, dA, bA) || overlaps(dVout, bVo, dV, bV)) return PFSM_INVALID_ARG;
+  if (overlaps(dVout, bVo, dWork, pl->total) || overlaps(dLam, n * sizeof(double), dWork, pl->total) ||
+      overlaps(dLam, n * sizeof(double), dVout, bVo))
+    return PFSM_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  char* W = (char*)dWork;
+  double* At = (double*)(W + pl->o_At);
+  double* buf0 = (double*)(W + pl->o_b0);
+  double* buf1 = (double*)(W + pl->o_b1);
+  double* eps = (double*)(W + pl->o_eps);
+  double* lamu = (double*)(W + pl->o_lamu);
+  double* part = (double*)(W + pl->o_part);
+  double* scal = (double*)(W + pl->o_scal);
+  const int tiles_m = (int)((n + GEMM_BM - 1) / GEMM_BM);
+  int* info = (int*)dInfo;
+
+  PFSM_TRY(fill_i32(info, 1, 0, s));
+
+  // (1) operator in the previous basis: W = A V, At = V^T W (lower tiles, mirrored).
+  {
+    GemmArgs g = {};
+    g.M = n; g.N = n; g.K = n;
+    g.A = dA; g.lda = lda; g.B = dV; g.ldb = ldv; g.C = buf0; g.ldc = n;
+    g.alpha = 1.0;
+    PFSM_TRY(gemm_f64(false, false, EPI_STORE, g, s));
+    GemmArgs h = {};
+    h.M = n; h.N = n; h.K = n;
+    h.A = dV; h.lda = ldv; h.B = buf0; h.ldb = n; h.C = At; h.ldc = n;
+    h.alpha = 1.0; h.lower_only = 1;
+    PFSM_TRY(gemm_f64(true, false, EPI_STORE, h, s));
+    PFSM_TRY(mirror_lower(At, n, n, s));
+  }
+  // (2) step length from the Gershgorin interval (or the caller's alpha).
+  PFSM_TRY(gershgorin_alpha(At, n, n, pl->q, pl->alpha, (double*)(W + pl->o_glo), (double*)(W + pl->o_ghi), scal, s));
+
+  // (3) submatrix eigenproblems, (4) zero-padded start vectors and shifts.
+  EighBatch e = {};
+  e.P = pl->P; e.Mp = pl->Mp; e.nb = pl->nb; e.inner_max_sweeps = 30;
+  e.Bw = (double*)(W + pl->o_Bw); e.Uw = (double*)(W + pl->o_Uw); e.Rw = (double*)(W + pl->o_Rw);
+  e.rflag = (int*)(W + pl->o_rflag); e.state = (int*)(W + pl->o_state); e.sel = (int*)(W + pl->o_sel);
+  e.wstart = pl->d_wstart; e.wsize = pl->d_wsize; e.offset = pl->d_offset; e.part_start = pl->d_part_start;
+  e.info = info;
+  PFSM_TRY(eigh_batched_run(e, At, n, pl->max_sweeps, s));
+  double* X = buf1;
+  double* Wt = buf0;
+  PFSM_TRY(embed_start_vectors(e, X, n, eps, n, s));
+
+  // (5) folded-spectrum iterations.
+  for (int it = 0; it < pl->iterations; ++it) {
+    const int32_t* kr = (it == 0 && pl->shift_mode == PFSM_SHIFT_FIXED) ? pl->d_krange : nullptr;
+    if (pl->shift_mode == PFSM_SHIFT_RAYLEIGH) {
+      GemmArgs r = {};
+      r.M = n; r.N = n; r.K = n; r.A = At; r.lda = n; r.B = X; r.ldb = n; r.D = X; r.ldd = n; r.part = part;
+      r.alpha = 1.0;
+      PFSM_TRY(gemm_f64(false, false, EPI_RQ, r, s));
+      PFSM_TRY(col_norm2(X, n, n, n, (double*)(W + pl->o_den), s));
+      PFSM_TRY(rq_reduce(part, tiles_m, n, (double*)(W + pl->o_den), eps, s));
+    }
+    if (pl->q == 2) {
+      GemmArgs g = {};
+      g.M = n; g.N = n; g.K = n; g.A = At; g.lda = n; g.B = X; g.ldb = n; g.C = Wt; g.ldc = n;
+      g.eps = eps; g.krange = kr;
+      PFSM_TRY(gemm_f64(false, false, EPI_SHIFT, g, s));  // Y = (At - eps) X
+      GemmArgs h = {};
+      h.M = n; h.N = n; h.K = n; h.A = At; h.lda = n; h.B = Wt; h.ldb = n; h.C = X; h.ldc = n;
+      h.D = X; h.ldd = n; h.eps = eps; h.alpha_dev = scal;
+      PFSM_TRY(gemm_f64(false, false, EPI_FSUPD, h, s));  // X <- X - a (At - eps) Y  (in place: reads only Y)
+    } else {
+      GemmArgs g = {};
+      g.M = n; g.N = n; g.K = n; g.A = At; g.lda = n; g.B = X; g.ldb = n; g.C = Wt; g.ldc = n;
+      g.D = X; g.ldd = n; g.eps = eps; g.alpha_dev = scal; g.krange = kr;
+      PFSM_TRY(gemm_f64(false, false, EPI_FSUPD, g, s));  // X' = X - a (At - eps) X
+      std::swap(X, Wt);
+    }
+  }
+
+  // (6) Cholesky-QR: S = X^T X (lower tiles), S = L L^T, X <- X L^{-T}.
+  double* S = Wt;
+  {
+    GemmArgs g = {};
+    g.M = n; g.N = n; g.K = n; g.A = X; g.lda = n; g.B = X; g.ldb = n; g.C = S; g.ldc = n;
+    g.alpha = 1.0; g.lower_only = 1;
+    PFSM_TRY(gemm_f64(true, false, EPI_STORE, g, s));
+    PFSM_TRY(cholesky_qr(S, n, X, n, n, n, (double*)(W + pl->o_T), info, s));
+  }
+  // (7) Rayleigh quotients x_j^T At x_j.
+  {
+    GemmArgs r = {};
+    r.M = n; r.N = n; r.K = n; r.A = At; r.lda = n; r.B = X; r.ldb = n; r.D = X; r.ldd = n; r.part = part;
+    r.alpha = 1.0;
+    PFSM_TRY(gemm_f64(false, false, EPI_RQ, r, s));
+    PFSM_TRY(rq_reduce(part, tiles_m, n, nullptr, lamu, s));
+  }
+  // (8) sign convention, ascending order, back-rotation V_out = V X_perm.
+  double* Xp = S;
+  PFSM_TRY(finalize_order(lamu, X, n, n, Xp, n, dLam, (int*)(W + pl->o_rank), (double*)(W + pl->o_sgn), info, s));
+  {
+    GemmArgs g = {};
+    g.M = n; g.N = n; g.K = n; g.A = dV; g.lda = ldv; g.B = Xp; g.ldb = n; g.C = dVout; g.ldc = ldvo;
+    g.alpha = 1.0;
+    PFSM_TRY(gemm_f64(false, false, EPI_STORE, g, s));
+  }
+  return hip_status(hipGetLastError());
+}
+
+pfsm_status pfsm_backward(pfsm_plan* pl, const double* dLam, const double* dV, int64_t ldv, const double* gLam,
+                          const double* gV, int64_t ldg, double eta, double* dGradA, int64_t ldga, void* dWork,
+                          size_t work_bytes, int32_t* dInfo, void* stream) {
+  if (!pl || !dLam || !dV || !dGradA || !dWork || !dInfo) return PFSM_INVALID_ARG;
+  const int64_t n = pl->n;
+  if (ldv < n || ldga < n || (gV && ldg < n)) return PFSM_INVALID_ARG;
+  if (!(eta >= 0.0)) return PFSM_INVALID_ARG;
+  if (((uintptr_t)dWork) % 256 != 0) return PFSM_INVALID_ARG;
+  if (work_bytes < pl->total) return PFSM_WORKSPACE_TOO_SMALL;
+  const size_t bG = (size_t)(ldga * (n - 1) + n) * sizeof(double);
+  const size_t bV = (size_t)(ldv * (n - 1) + n) * sizeof(double);
+  if (overlaps(dGradA, bG, dV, bV) || overlaps(dGradA, bG, dWork, pl->total) ||
+      overlaps(dGradA, bG, dLam, n * sizeof(double)))
+    return PFSM_INVALID_ARG;
+  if (gV && overlaps(dGradA, bG, gV, (size_t)(ldg * (n - 1) + n) * sizeof(double))) return PFSM_INVALID_ARG;
+  if (gLam && overlaps(dGradA, bG, gLam, n * sizeof(double))) return PFSM_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  char* W = (char*)dWork;
+  double* T = (double*)(W + pl->o_b0);
+  double* G = (double*)(W + pl->o_b1);
+  PFSM_TRY(fill_i32((int*)dInfo, 1, 0, s));
+  if (gV) {
+    GemmArgs g = {};
+    g.M = n; g.N = n; g.K = n; g.A = dV; g.lda = ldv; g.B = gV; g.ldb = ldg; g.C = T; g.ldc = n; g.alpha = 1.0;
+    PFSM_TRY(gemm_f64(true, false, EPI_STORE, g, s));  // T = V^T gV
+  }
+  PFSM_TRY(adjoint_middle(T, n, n, dLam, gLam, eta, gV != nullptr, s));  // M = diag(glam) + F o T
+  {
+    GemmArgs g = {};
+    g.M = n; g.N = n; g.K = n; g.A = dV; g.lda = ldv; g.B = T; g.ldb = n; g.C = G; g.ldc = n; g.alpha = 1.0;
+    PFSM_TRY(gemm_f64(false, false, EPI_STORE, g, s));  // G = V M
+    GemmArgs h = {};
+    h.M = n; h.N = n; h.K = n; h.A = G; h.lda = n; h.B = dV; h.ldb = ldv; h.C = dGradA; h.ldc = ldga; h.alpha = 1.0;
+    PFSM_TRY(gemm_f64(false, true, EPI_STORE, h, s));  // dA = G V^T
+  }
+  PFSM_TRY(symmetrize(dGradA, n, ldga, s));
+  return hip_status(hipGetLastError());
+}
+
+pfsm_status pfsm_diagnostics(pfsm_plan* pl, const double* dA, int64_t lda, const double* dLam, const double* dV,
+                             int64_t ldv, double* dOut, void* dWork, size_t work_bytes, void* stream) {
+  if (!pl || !dA || !dLam || !dV || !dOut || !dWork) return PFSM_INVALID_ARG;
+  const int64_t n = pl->n;
+  if (lda < n || ldv < n) return PFSM_INVALID_ARG;
+  if (((uintptr_t)dWork) % 256 != 0) return PFSM_INVALID_ARG;
+  if (work_bytes < pl->total) return PFSM_WORKSPACE_TOO_SMALL;
+  const size_t bV = (size_t)(ldv * (n - 1) + n) * sizeof(double);
+  if (overlaps(dV, bV, dWork, pl->total) || overlaps(dLam, n * sizeof(double), dWork, pl->total))
+    return PFSM_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  char* W = (char*)dWork;
+  double* AV = (double*)(W + pl->o_b0);
+  double* G = (double*)(W + pl->o_b1);
+  double* part = (double*)(W + pl->o_part);
+  GemmArgs g = {};
+  g.M = n; g.N = n; g.K = n; g.A = dA; g.lda = lda; g.B = dV; g.ldb = ldv; g.C = AV; g.ldc = n; g.alpha = 1.0;
+  PFSM_TRY(gemm_f64(false, false, EPI_STORE, g, s));
+  GemmArgs h = {};
+  h.M = n; h.N = n; h.K = n; h.A = dV; h.lda = ldv; h.B = dV; h.ldb = ldv; h.C = G; h.ldc = n; h.alpha = 1.0;
+  PFSM_TRY(gemm_f64(true, false, EPI_STORE, h, s));
+  PFSM_TRY(diag_sums(dA, lda, AV, n, dV, ldv, dLam, G, n, n, part, dOut, s));
+  return hip_status(hipGetLastError());
+}
+
+}  // extern "C"
