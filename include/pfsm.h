@@ -141,6 +141,23 @@ pfsm_status pfsm_diagnostics(pfsm_plan* plan, const double* dA, int64_t lda, con
                              const double* dV, int64_t ldv, double* dOut, void* dWork, size_t work_bytes,
                              void* stream);
 
+/* Stage timing for benchmarks (instrumentation, off by default).
+ * pfsm_timing_begin creates max_solves x PFSM_TIMING_BOUNDS HIP events (on the
+ * plan's device) and makes the next max_solves calls of pfsm_solve record an
+ * event at each stage boundary on their stream.  pfsm_timing_read
+ * synchronises those events and writes, for each recorded solve s and stage k,
+ * the elapsed milliseconds between boundary k and k+1 to ms[s * (PFSM_TIMING_BOUNDS-1) + k]
+ * (unused stages read 0).  Stage order: 0 basis change, 1 step length, 2
+ * submatrix eigensolver + start vectors, 3 + 2i shifted product of iteration i,
+ * 4 + 2i folded-spectrum update of iteration i (i < iterations, at most 8),
+ * 19 overlap, 20 Cholesky-QR, 21 Rayleigh quotients, 22 ordering, 23
+ * back-rotation, 24 refinement (mixed precision).  pfsm_timing_end releases the events.
+ * Errors: INVALID_ARG, HIP_ERROR. */
+#define PFSM_TIMING_BOUNDS 26
+pfsm_status pfsm_timing_begin(pfsm_plan* plan, int32_t max_solves);
+pfsm_status pfsm_timing_read(pfsm_plan* plan, float* ms, int32_t capacity, int32_t* solves_recorded);
+pfsm_status pfsm_timing_end(pfsm_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,12 @@ def load_library(path: str = LIB_PATH):
     lib.pfsm_diagnostics.restype = ctypes.c_int
     lib.pfsm_plan_destroy.argtypes = [vp]
     lib.pfsm_plan_destroy.restype = None
+    lib.pfsm_timing_begin.argtypes = [vp, i32]
+    lib.pfsm_timing_begin.restype = ctypes.c_int
+    lib.pfsm_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
+    lib.pfsm_timing_read.restype = ctypes.c_int
+    lib.pfsm_timing_end.argtypes = [vp]
+    lib.pfsm_timing_end.restype = ctypes.c_int
     lib.pfsm_status_string.argtypes = [ctypes.c_int]
     lib.pfsm_status_string.restype = ctypes.c_char_p
     _lib = lib
@@ -183,6 +189,30 @@ class Plan:
                                                 self.workspace_bytes, _stream_handle()))
         o = out.cpu()
         return float(o[0]), float(o[1])
+
+    # -- stage timing (instrumentation for benchmarks)
+    TIMING_BOUNDS = 26
+    STAGES = (["basis_change", "step_length", "submatrix_eigh"]
+              + [x for i in range(8) for x in ("fs_shift_%d" % i, "fs_update_%d" % i)]
+              + ["overlap", "cholesky_qr", "rayleigh", "ordering", "back_rotation", "refinement"])
+
+    def timing_begin(self, max_solves: int):
+        _check(load_library().pfsm_timing_begin(self._h, int(max_solves)))
+
+    def timing_read(self):
+        """List (one entry per recorded solve) of {stage: milliseconds}."""
+        per = self.TIMING_BOUNDS - 1
+        cap = 4096 * per
+        buf = (ctypes.c_float * cap)()
+        cnt = ctypes.c_int32()
+        _check(load_library().pfsm_timing_read(self._h, buf, cap, ctypes.byref(cnt)))
+        out = []
+        for sv in range(cnt.value):
+            out.append({name: float(buf[sv * per + k]) for k, name in enumerate(self.STAGES)})
+        return out
+
+    def timing_end(self):
+        _check(load_library().pfsm_timing_end(self._h))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -24,6 +24,7 @@ struct EighBatch {
   const int32_t* offset;   // [P] rank of the slice's first eigenpair inside the submatrix
   const int64_t* part_start;  // [P] first global column of the slice
   int* info;               // device info word (first error wins)
+  const double* scal;      // device scalars; scal[1], scal[2] = Gershgorin interval of the full matrix
 };
 
 hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, int max_sweeps, hipStream_t s);

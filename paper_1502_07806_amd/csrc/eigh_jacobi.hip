@@ -13,10 +13,15 @@
 //             with J = diag of the R's, as small MFMA products in LDS.
 //
 // A sweep in which no pair needed a rotation marks the submatrix converged;
-// later kernels of that submatrix return immediately.  The rotation
-// threshold is relative: |b_pq| > 2^-53 sqrt(|b_pp b_qq|).
+// later kernels of that submatrix return immediately.  A pair (p, q) is
+// rotated when |b_pq| > 2^-53 sqrt(|b_pp b_qq|) (relative accuracy) and
+// |b_pq| > 256 * 2^-53 * ||B|| (rounding floor of the block products, with
+// ||B|| bounded by the Gershgorin interval of the full matrix).  Without the
+// floor, the rounding error of the MFMA block updates would keep rotating
+// exactly degenerate pairs forever.
 #include "common.h"
 #include "eigh.h"
+#include "order_key.h"
 
 namespace pfsm {
 namespace {
@@ -26,6 +31,15 @@ constexpr int B2 = 2 * EIGH_B;   // 64: order of a pair problem / apply tile
 constexpr int LS = B2 + 1;       // LDS row stride
 constexpr double TOL = 1.1102230246251565e-16;  // 2^-53
 constexpr double TINY = 1e-300;
+constexpr double NOISE = 256.0 * TOL;
+
+__device__ inline double noise_floor(const EighBatch& e) {
+  return NOISE * fmax(fmax(fabs(e.scal[1]), fabs(e.scal[2])), TINY);
+}
+__device__ inline bool must_rotate(double apq, double app, double aqq, double floor_abs) {
+  double a = fabs(apq);
+  return a > floor_abs && a > TOL * sqrt(fabs(app) * fabs(aqq));
+}
 
 // Circle-method tournament: position -> block index in round r (n even).
 __device__ __host__ inline int rr_index(int pos, int r, int n) {
@@ -95,13 +109,11 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   if (tid == 0) any_rot = 0;
   __syncthreads();
   // Is any rotation needed at all?
+  const double fl = noise_floor(e);
   int need = 0;
   for (int idx = tid; idx < B2 * B2; idx += NT) {
     int r = idx % B2, c = idx / B2;
-    if (r < c) {
-      double a = fabs(S[r][c]);
-      if (a > TINY && a > TOL * sqrt(fabs(S[r][r]) * fabs(S[c][c]))) need = 1;
-    }
+    if (r < c && must_rotate(S[r][c], S[r][r], S[c][c], fl)) need = 1;
   }
   if (need) any_rot = 1;
   __syncthreads();
@@ -116,7 +128,7 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
         int pi = min(a, b), qi = max(a, b);
         double apq = S[pi][qi], app = S[pi][pi], aqq = S[qi][qi];
         double c = 1.0, s = 0.0;
-        if (fabs(apq) > TINY && fabs(apq) > TOL * sqrt(fabs(app) * fabs(aqq))) {
+        if (must_rotate(apq, app, aqq, fl)) {
           double tau = (aqq - app) / (2.0 * apq);
           double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
@@ -305,11 +317,8 @@ __global__ __launch_bounds__(NT) void rank_select(EighBatch e) {
   for (int i = threadIdx.x; i < Mp; i += NT) {
     double di = dsh[i];
     int rank = 0;
-    for (int j = 0; j < Mp; ++j) {
-      double dj = dsh[j];
-      rank += (dj < di) || (dj == di && j < i);
-    }
-    sel[rank] = i;  // rank -> local index
+    for (int j = 0; j < Mp; ++j) rank += order_before(dsh[j], j, di, i);
+    sel[rank] = i;  // rank -> local index; ranks are a permutation even with NaN
   }
   // not converged: the last sweep still rotated and no sweep was rotation-free
   if (threadIdx.x == 0 && e.state[2 * p] == 0 && e.state[2 * p + 1] != 0 && e.info)
@@ -326,7 +335,8 @@ __global__ void embed_x0(EighBatch e, double* __restrict__ X, int64_t ldx, doubl
   const int64_t w0 = e.wstart[p];
   const int M = e.wsize[p];
   const int Mp = e.Mp;
-  const int li = e.sel[(int64_t)p * Mp + e.offset[p] + (int)(c - s)];
+  int li = e.sel[(int64_t)p * Mp + e.offset[p] + (int)(c - s)];
+  li = min(max(li, 0), Mp - 1);
   const double* U = e.Uw + (int64_t)p * Mp * Mp + (int64_t)li * Mp;
   for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
     double v = 0.0;

@@ -3,7 +3,7 @@
 namespace pfsm {
 hipError_t fill_i32(int* p, int64_t count, int value, hipStream_t s);
 hipError_t gershgorin_alpha(const double* At, int64_t n, int64_t ld, int q, double user_alpha,
-                            double* part_lo, double* part_hi, double* scal, hipStream_t s);
+                            double* part_lo, double* part_hi, double* scal, int* info, hipStream_t s);
 hipError_t rq_reduce(const double* part, int tiles_m, int64_t n, const double* den, double* out, hipStream_t s);
 hipError_t col_norm2(const double* X, int64_t m, int64_t n, int64_t ldx, double* out, hipStream_t s);
 hipError_t finalize_order(const double* lam_u, const double* X, int64_t n, int64_t ldx, double* Xp, int64_t ldxp,

@@ -5,6 +5,7 @@
 // so every read is a contiguous column segment.
 #include "common.h"
 #include "misc.h"
+#include "order_key.h"
 #include <cfloat>
 
 namespace pfsm {
@@ -46,20 +47,23 @@ __global__ __launch_bounds__(NT) void k_gersh_col(const double* At, int64_t n, i
 }
 
 __global__ __launch_bounds__(NT) void k_gersh_final(const double* lo, const double* hi, int64_t n, int q,
-                                                     double user_alpha, double* scal) {
+                                                     double user_alpha, double* scal, int* info) {
   __shared__ double slo[NT], shi[NT];
   double a = DBL_MAX, b = -DBL_MAX;
   for (int64_t i = threadIdx.x; i < n; i += NT) {
-    a = fmin(a, lo[i]);
-    b = fmax(b, hi[i]);
+    double x = lo[i], y = hi[i];
+    a = (x != x) ? x : fmin(a, x);  // keep NaN visible (fmin would drop it)
+    b = (y != y) ? y : fmax(b, y);
+    if (a != a || b != b) { a = b = __builtin_nan(""); break; }
   }
   slo[threadIdx.x] = a;
   shi[threadIdx.x] = b;
   __syncthreads();
   for (int w = NT / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
-      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + w]);
-      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + w]);
+      double a2 = slo[threadIdx.x + w], b2 = shi[threadIdx.x + w];
+      slo[threadIdx.x] = (a2 != a2) ? a2 : fmin(slo[threadIdx.x], a2);
+      shi[threadIdx.x] = (b2 != b2) ? b2 : fmax(shi[threadIdx.x], b2);
     }
     __syncthreads();
   }
@@ -71,6 +75,8 @@ __global__ __launch_bounds__(NT) void k_gersh_final(const double* lo, const doub
     scal[0] = alpha;
     scal[1] = slo[0];
     scal[2] = shi[0];
+    // A non-finite entry of A or V_prev spreads over every entry of At.
+    if (info && !(isfinite(slo[0]) && isfinite(shi[0]))) atomicCAS(info, 0, -1);
   }
 }
 
@@ -134,18 +140,11 @@ __global__ __launch_bounds__(NT) void k_rank(const double* lam, int64_t n, int* 
     if (base + threadIdx.x < n) tile[threadIdx.x] = lam[base + threadIdx.x];
     __syncthreads();
     const int cnt = (int)min<int64_t>(NT, n - base);
-    for (int t = 0; t < cnt; ++t) {
-      double lk = tile[t];
-      r += (lk < lj) || (lk == lj && base + t < j);
-    }
+    for (int t = 0; t < cnt; ++t) r += order_before(tile[t], base + t, lj, j);
   }
   if (j < n) {
-    if (!isfinite(lj)) {
-      atomicCAS(info, 0, -1);
-      r = j;  // keep a valid permutation slot for non-finite values
-    }
-    if (r >= n) r = n - 1;
-    rank[j] = (int)r;
+    if (!isfinite(lj)) atomicCAS(info, 0, -1);
+    rank[j] = (int)r;  // a permutation of 0..n-1 for any input (NaN sorts last)
     lam_out[r] = lj;
   }
 }
@@ -287,9 +286,9 @@ hipError_t mirror_lower(double* C, int64_t n, int64_t ldc, hipStream_t s) {
 }
 
 hipError_t gershgorin_alpha(const double* At, int64_t n, int64_t ld, int q, double user_alpha, double* part_lo,
-                            double* part_hi, double* scal, hipStream_t s) {
+                            double* part_hi, double* scal, int* info, hipStream_t s) {
   hipLaunchKernelGGL(k_gersh_col, dim3((unsigned)n), dim3(NT), 0, s, At, n, ld, part_lo, part_hi);
-  hipLaunchKernelGGL(k_gersh_final, dim3(1), dim3(NT), 0, s, part_lo, part_hi, n, q, user_alpha, scal);
+  hipLaunchKernelGGL(k_gersh_final, dim3(1), dim3(NT), 0, s, part_lo, part_hi, n, q, user_alpha, scal, info);
   return hipGetLastError();
 }
 

@@ -31,6 +31,9 @@ struct pfsm_plan {
   int64_t* d_part_start = nullptr;
   int32_t* d_krange = nullptr;
   // workspace layout (byte offsets)
+  // stage timing
+  std::vector<hipEvent_t> tev;
+  int t_max = 0, t_count = 0;
   size_t o_At, o_b0, o_b1, o_Bw, o_Uw, o_Rw, o_rflag, o_state, o_sel, o_T, o_part, o_eps, o_lamu, o_sgn, o_rank,
       o_scal, o_glo, o_ghi, o_den, total;
 };
@@ -46,6 +49,25 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
 }
 
 pfsm_status hip_status(hipError_t e) { return e == hipSuccess ? PFSM_OK : PFSM_HIP_ERROR; }
+
+// Records the boundary event k of the current timed solve (no-op when timing is off).
+struct StageClock {
+  pfsm_plan* pl;
+  hipStream_t s;
+  int slot;
+  int last = -1;
+  StageClock(pfsm_plan* p, hipStream_t st) : pl(p), s(st), slot(-1) {
+    if (pl->t_max > 0 && pl->t_count < pl->t_max) slot = pl->t_count++;
+  }
+  // Boundaries skipped since the previous mark are recorded here too, so the
+  // stages they delimit read zero.
+  void mark(int k) {
+    if (slot < 0) return;
+    for (int j = last + 1; j <= k && j < PFSM_TIMING_BOUNDS; ++j)
+      (void)hipEventRecord(pl->tev[(size_t)slot * PFSM_TIMING_BOUNDS + j], s);
+    if (k > last) last = k;
+  }
+};
 
 #define PFSM_TRY(expr)                          \
   do {                                          \
@@ -200,6 +222,7 @@ pfsm_status pfsm_workspace_size(const pfsm_plan* pl, size_t* bytes) {
 
 void pfsm_plan_destroy(pfsm_plan* pl) {
   if (!pl) return;
+  pfsm_timing_end(pl);
   if (pl->dtab) {
     (void)hipDeviceSynchronize();
     (void)hipFree(pl->dtab);
@@ -233,7 +256,9 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
   const int tiles_m = (int)((n + GEMM_BM - 1) / GEMM_BM);
   int* info = (int*)dInfo;
 
+  StageClock clk(pl, s);
   PFSM_TRY(fill_i32(info, 1, 0, s));
+  clk.mark(0);
 
   // (1) operator in the previous basis: W = A V, At = V^T W (lower tiles, mirrored).
   {
@@ -249,8 +274,10 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
     PFSM_TRY(gemm_f64(true, false, EPI_STORE, h, s));
     PFSM_TRY(mirror_lower(At, n, n, s));
   }
+  clk.mark(1);
   // (2) step length from the Gershgorin interval (or the caller's alpha).
-  PFSM_TRY(gershgorin_alpha(At, n, n, pl->q, pl->alpha, (double*)(W + pl->o_glo), (double*)(W + pl->o_ghi), scal, s));
+  PFSM_TRY(gershgorin_alpha(At, n, n, pl->q, pl->alpha, (double*)(W + pl->o_glo), (double*)(W + pl->o_ghi), scal, info, s));
+  clk.mark(2);
 
   // (3) submatrix eigenproblems, (4) zero-padded start vectors and shifts.
   EighBatch e = {};
@@ -259,10 +286,12 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
   e.rflag = (int*)(W + pl->o_rflag); e.state = (int*)(W + pl->o_state); e.sel = (int*)(W + pl->o_sel);
   e.wstart = pl->d_wstart; e.wsize = pl->d_wsize; e.offset = pl->d_offset; e.part_start = pl->d_part_start;
   e.info = info;
+  e.scal = scal;
   PFSM_TRY(eigh_batched_run(e, At, n, pl->max_sweeps, s));
   double* X = buf1;
   double* Wt = buf0;
   PFSM_TRY(embed_start_vectors(e, X, n, eps, n, s));
+  clk.mark(3);
 
   // (5) folded-spectrum iterations.
   for (int it = 0; it < pl->iterations; ++it) {
@@ -280,19 +309,24 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
       g.M = n; g.N = n; g.K = n; g.A = At; g.lda = n; g.B = X; g.ldb = n; g.C = Wt; g.ldc = n;
       g.eps = eps; g.krange = kr;
       PFSM_TRY(gemm_f64(false, false, EPI_SHIFT, g, s));  // Y = (At - eps) X
+      if (it < 8) clk.mark(4 + 2 * it);
       GemmArgs h = {};
       h.M = n; h.N = n; h.K = n; h.A = At; h.lda = n; h.B = Wt; h.ldb = n; h.C = X; h.ldc = n;
       h.D = X; h.ldd = n; h.eps = eps; h.alpha_dev = scal;
       PFSM_TRY(gemm_f64(false, false, EPI_FSUPD, h, s));  // X <- X - a (At - eps) Y  (in place: reads only Y)
+      if (it < 8) clk.mark(5 + 2 * it);
     } else {
       GemmArgs g = {};
       g.M = n; g.N = n; g.K = n; g.A = At; g.lda = n; g.B = X; g.ldb = n; g.C = Wt; g.ldc = n;
       g.D = X; g.ldd = n; g.eps = eps; g.alpha_dev = scal; g.krange = kr;
+      if (it < 8) clk.mark(4 + 2 * it);
       PFSM_TRY(gemm_f64(false, false, EPI_FSUPD, g, s));  // X' = X - a (At - eps) X
+      if (it < 8) clk.mark(5 + 2 * it);
       std::swap(X, Wt);
     }
   }
 
+  clk.mark(19);
   // (6) Cholesky-QR: S = X^T X (lower tiles), S = L L^T, X <- X L^{-T}.
   double* S = Wt;
   {
@@ -300,8 +334,10 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
     g.M = n; g.N = n; g.K = n; g.A = X; g.lda = n; g.B = X; g.ldb = n; g.C = S; g.ldc = n;
     g.alpha = 1.0; g.lower_only = 1;
     PFSM_TRY(gemm_f64(true, false, EPI_STORE, g, s));
+    clk.mark(20);
     PFSM_TRY(cholesky_qr(S, n, X, n, n, n, (double*)(W + pl->o_T), info, s));
   }
+  clk.mark(21);
   // (7) Rayleigh quotients x_j^T At x_j.
   {
     GemmArgs r = {};
@@ -310,16 +346,57 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
     PFSM_TRY(gemm_f64(false, false, EPI_RQ, r, s));
     PFSM_TRY(rq_reduce(part, tiles_m, n, nullptr, lamu, s));
   }
+  clk.mark(22);
   // (8) sign convention, ascending order, back-rotation V_out = V X_perm.
   double* Xp = S;
   PFSM_TRY(finalize_order(lamu, X, n, n, Xp, n, dLam, (int*)(W + pl->o_rank), (double*)(W + pl->o_sgn), info, s));
+  clk.mark(23);
   {
     GemmArgs g = {};
     g.M = n; g.N = n; g.K = n; g.A = dV; g.lda = ldv; g.B = Xp; g.ldb = n; g.C = dVout; g.ldc = ldvo;
     g.alpha = 1.0;
     PFSM_TRY(gemm_f64(false, false, EPI_STORE, g, s));
   }
+  clk.mark(24);
+  clk.mark(25);
   return hip_status(hipGetLastError());
+}
+
+pfsm_status pfsm_timing_begin(pfsm_plan* pl, int32_t max_solves) {
+  if (!pl || max_solves < 1 || max_solves > 4096) return PFSM_INVALID_ARG;
+  pfsm_timing_end(pl);
+  pl->tev.resize((size_t)max_solves * PFSM_TIMING_BOUNDS);
+  for (auto& ev : pl->tev)
+    if (hipEventCreate(&ev) != hipSuccess) return PFSM_HIP_ERROR;
+  pl->t_max = max_solves;
+  pl->t_count = 0;
+  return PFSM_OK;
+}
+
+pfsm_status pfsm_timing_read(pfsm_plan* pl, float* ms, int32_t capacity, int32_t* solves) {
+  if (!pl || !ms || !solves) return PFSM_INVALID_ARG;
+  const int per = PFSM_TIMING_BOUNDS - 1;
+  if (capacity < pl->t_count * per) return PFSM_INVALID_ARG;
+  for (int sv = 0; sv < pl->t_count; ++sv) {
+    hipEvent_t* e = &pl->tev[(size_t)sv * PFSM_TIMING_BOUNDS];
+    if (hipEventSynchronize(e[PFSM_TIMING_BOUNDS - 1]) != hipSuccess) return PFSM_HIP_ERROR;
+    for (int k = 0; k < per; ++k) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, e[k], e[k + 1]) != hipSuccess) return PFSM_HIP_ERROR;
+      ms[sv * per + k] = t;
+    }
+  }
+  *solves = pl->t_count;
+  return PFSM_OK;
+}
+
+pfsm_status pfsm_timing_end(pfsm_plan* pl) {
+  if (!pl) return PFSM_INVALID_ARG;
+  for (auto& ev : pl->tev) (void)hipEventDestroy(ev);
+  pl->tev.clear();
+  pl->t_max = 0;
+  pl->t_count = 0;
+  return PFSM_OK;
 }
 
 pfsm_status pfsm_backward(pfsm_plan* pl, const double* dLam, const double* dV, int64_t ldv, const double* gLam,
