@@ -36,6 +36,9 @@
  *         vectors do not span: a randomly mixed, non-diagonally-dominant input
  *         as the Methodology section warns, or duplicated previous vectors)
  *     -1  a non-finite eigenvalue (non-finite input propagates to it)
+ *     -2  mixed precision: the overlap factor is too far from the identity for the
+ *         short series used for X L^{-T} (max |L - I| > 1e-3: the start vectors
+ *         are far from orthogonal, outside the diagonally dominant regime)
  *     -3  a submatrix eigensolver did not converge within its sweep limit
  * The first condition found wins.
  */
@@ -60,9 +63,10 @@ typedef enum pfsm_status {
 
 typedef enum pfsm_precision {
   PFSM_PREC_FP64 = 0,       /* every product in FP64 on matrix cores */
-  PFSM_PREC_MIXED_BF16 = 1  /* BF16-split products with FP32 accumulation for the bulk,
-                               FP64 submatrix eigensolver, Cholesky and final
-                               Rayleigh-Ritz refinement against A */
+  PFSM_PREC_MIXED_BF16 = 1  /* products on BF16 matrix cores with every operand split into
+                               hi + lo BF16 parts (three products, FP32 accumulation); FP64 for
+                               the submatrix eigensolver, the Cholesky of the overlap and the
+                               final Rayleigh quotients / cluster Rayleigh-Ritz against A */
 } pfsm_precision;
 
 typedef enum pfsm_shift_mode {
@@ -83,8 +87,13 @@ typedef struct pfsm_desc {
   int32_t shift_mode;          /* pfsm_shift_mode */
   int32_t precision;           /* pfsm_precision */
   int32_t max_sweeps;          /* submatrix Jacobi sweep limit; <= 0: 10 */
-  int32_t reserved;            /* must be 0 */
+  int32_t flags;               /* PFSM_FLAG_* bits; 0 = defaults */
 } pfsm_desc;
+
+/* Mixed precision only: skip the FP64 refinement against A and return the
+ * eigenvalue estimates of the reduced-precision step (Rayleigh quotients in the
+ * rotated basis) -- the "FP32 result" of the mixed path. */
+#define PFSM_FLAG_NO_REFINE 1
 
 typedef struct pfsm_plan pfsm_plan;
 

@@ -23,7 +23,10 @@ LIB_PATH = os.path.join(_HERE, "libpfsm.so")
 
 PFSM_PREC = {"fp64": 0, "mixed_bf16": 1}
 PFSM_SHIFT = {"fixed": 0, "rayleigh": 1}
-INFO_TEXT = {0: "ok", -1: "non-finite eigenvalue", -3: "submatrix eigensolver did not converge"}
+INFO_TEXT = {0: "ok", -1: "non-finite eigenvalue",
+             -2: "overlap factor too far from the identity for the mixed-precision orthonormalisation",
+             -3: "submatrix eigensolver did not converge"}
+FLAG_NO_REFINE = 1
 
 
 class PfsmDesc(ctypes.Structure):
@@ -38,7 +41,7 @@ class PfsmDesc(ctypes.Structure):
         ("shift_mode", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("max_sweeps", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
     ]
 
 
@@ -104,11 +107,12 @@ class Plan:
 
     def __init__(self, n: int, part_offsets: Sequence[int], halo: int = -1, iterations: int = 3,
                  fs_power: int = 2, alpha: float = 0.0, shift_mode: str = "fixed", precision: str = "fp64",
-                 max_sweeps: int = 0):
+                 max_sweeps: int = 0, refine: bool = True):
         lib = load_library()
         offs = (ctypes.c_int64 * len(part_offsets))(*[int(x) for x in part_offsets])
         d = PfsmDesc(int(n), len(part_offsets) - 1, offs, int(halo), int(iterations), int(fs_power), float(alpha),
-                     PFSM_SHIFT[shift_mode], PFSM_PREC[precision], int(max_sweeps), 0)
+                     PFSM_SHIFT[shift_mode], PFSM_PREC[precision], int(max_sweeps),
+                     0 if refine else FLAG_NO_REFINE)
         h = ctypes.c_void_p()
         _check(lib.pfsm_plan_create(ctypes.byref(h), ctypes.byref(d)))
         self._h = h

@@ -74,9 +74,8 @@ __global__ __launch_bounds__(256) void potrf_diag(double* S, int64_t lds, int64_
 
 }  // namespace
 
-hipError_t cholesky_qr(double* S, int64_t lds, double* X, int64_t ldx, int64_t n, int64_t m,
-                       double* Tbuf, int* info, hipStream_t s) {
-  // S: n x n overlap (lower triangle valid) -> L.  X: m x n, overwritten by X L^{-T}.
+hipError_t cholesky_factor(double* S, int64_t lds, int64_t n, double* Tbuf, int* info, hipStream_t s) {
+  // S: n x n (lower triangle valid) -> L in place; Tbuf receives the inverse-transposed diagonal blocks.
   const int64_t nblk = (n + NB - 1) / NB;
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t k0 = b * NB;
@@ -105,6 +104,15 @@ hipError_t cholesky_qr(double* S, int64_t lds, double* X, int64_t ldx, int64_t n
       if (e != hipSuccess) return e;
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t cholesky_qr(double* S, int64_t lds, double* X, int64_t ldx, int64_t n, int64_t m,
+                       double* Tbuf, int* info, hipStream_t s) {
+  // S: n x n overlap (lower triangle valid) -> L.  X: m x n, overwritten by X L^{-T}.
+  const int64_t nblk = (n + NB - 1) / NB;
+  hipError_t e0 = cholesky_factor(S, lds, n, Tbuf, info, s);
+  if (e0 != hipSuccess) return e0;
   // X <- X L^{-T}: right-looking over column blocks.
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t k0 = b * NB;

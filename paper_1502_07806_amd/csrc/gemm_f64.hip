@@ -29,22 +29,37 @@ __device__ inline int xcd_tile(int b, int total) {
   return (b % 8) * (total / 8) + b / 8;
 }
 
+__device__ inline void tri_index(int t, int& a, int& b) {
+  // t -> (a, b) with a >= b, row-major over the lower triangle
+  int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  a = r;
+  b = t - r * (r + 1) / 2;
+}
+
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   __shared__ double As[2][BK][LDA_S];
   __shared__ double Bs[2][BK][LDB_S];
   __shared__ double red[2][BN];
 
-  const int total = tiles_m * tiles_n;
-  const int t_lin = xcd_tile(blockIdx.x, total);
-  // group 8 row tiles together so consecutive tiles reuse B columns and A rows
-  const int GROUP = 8;
-  const int group_id = t_lin / (GROUP * tiles_n);
-  const int first_m = group_id * GROUP;
-  const int gsz = min(tiles_m - first_m, GROUP);
-  const int tm = first_m + (t_lin % (GROUP * tiles_n)) % gsz;
-  const int tn = (t_lin % (GROUP * tiles_n)) / gsz;
-  if (g.lower_only && tm < tn) return;
+  int tm, tn;
+  if (g.lower_only) {
+    // only tiles on or below the diagonal are launched (tiles_m == tiles_n)
+    const int total = tiles_m * (tiles_m + 1) / 2;
+    tri_index(xcd_tile(blockIdx.x, total), tm, tn);
+  } else {
+    const int total = tiles_m * tiles_n;
+    const int t_lin = xcd_tile(blockIdx.x, total);
+    // group 8 row tiles together so consecutive tiles reuse B columns and A rows
+    const int GROUP = 8;
+    const int group_id = t_lin / (GROUP * tiles_n);
+    const int first_m = group_id * GROUP;
+    const int gsz = min(tiles_m - first_m, GROUP);
+    tm = first_m + (t_lin % (GROUP * tiles_n)) % gsz;
+    tn = (t_lin % (GROUP * tiles_n)) / gsz;
+  }
 
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int tid = threadIdx.x;
@@ -196,7 +211,8 @@ template <bool TA, bool TB>
 hipError_t launch_epi(int epi, const GemmArgs& a, hipStream_t s) {
   int tm = (int)((a.M + BM - 1) / BM), tn = (int)((a.N + BN - 1) / BN);
   if (tm == 0 || tn == 0) return hipSuccess;
-  dim3 grid(tm * tn), block(NT);
+  if (a.lower_only && tm != tn) return hipErrorInvalidValue;
+  dim3 grid(a.lower_only ? tm * (tm + 1) / 2 : tm * tn), block(NT);
   switch (epi) {
     case EPI_STORE: hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, EPI_STORE>), grid, block, 0, s, a, tm, tn); break;
     case EPI_SHIFT: hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, EPI_SHIFT>), grid, block, 0, s, a, tm, tn); break;

@@ -1,0 +1,61 @@
+// BF16 hi/lo split ("x3") GEMM on CDNA4 matrix cores and its operand packing.
+//
+// A real matrix x is carried as two bfloat16 planes, hi = bf16(x) and
+// lo = bf16(x - hi); a product uses hi*hi + hi*lo + lo*hi with FP32
+// accumulation (v_mfma_f32_32x32x16_bf16), about 16 significant bits per
+// product term instead of BF16's 8.
+//
+// Packed operand layout: for an operand with rows r (output index) and
+// reduction index k, row r holds ceil(K/32) chunks of 64 bf16 values:
+// [32 hi values | 32 lo values] for k = 32c .. 32c+31 (zero-filled past K).
+// Row stride = 64 * ceil(K/32) bf16 (128 bytes per chunk).  Both GEMM operands
+// use this layout: op(A) by its rows i, op(B) by its columns j.
+#pragma once
+#include "common.h"
+
+namespace pfsm {
+
+typedef unsigned short bf16_t;
+
+constexpr int X3_BM = 256, X3_BN = 256, X3_BK = 32;
+
+inline int64_t x3_row_stride(int64_t K) { return 64 * ((K + 31) / 32); }
+
+enum X3Epi : int {
+  X3_STORE = 0,  // C = alpha*acc + beta*C
+  X3_SHIFT = 1,  // C = acc - B32(i,j) * eps[j]                (FP32 out)
+  X3_FSUPD = 2,  // C = D32(i,j) - a*(acc - B32(i,j)*eps[j])    (FP32 out)
+  X3_ADD = 3,    // C = acc + D(i,j)   (D float or double)
+  X3_RQ = 4,     // part[tile_m][j] = sum_i acc(i,j) * D32(i,j)
+};
+
+enum X3Tiles : int { X3_FULL = 0, X3_LOWER = 1, X3_UPPER_TRI = 2, X3_KPREFIX = 3 };
+
+struct X3Args {
+  int64_t M, N, K;
+  const bf16_t* Ap; int64_t ldap;   // packed rows of op(A)
+  const bf16_t* Bp; int64_t ldbp;   // packed columns of op(B)
+  void* C; int64_t ldc; int c_double;
+  double alpha, beta;
+  const float* B32; int64_t ldb32;  // unpacked op(B) for SHIFT / FSUPD (FP32, column-major)
+  const void* D; int64_t ldd; int d_double;  // FSUPD / ADD / RQ partner
+  const double* eps;
+  const double* alpha_dev;
+  double* part;
+  const int32_t* krange;            // optional [tiles_n][2] (multiples of 32)
+  int tiles;                        // X3Tiles
+  int kprefix_skip;                 // X3_KPREFIX: K range [0, (tn+1)*BN) (right operand upper triangular)
+};
+
+hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s);
+
+// Packing.  Without PACK_BY_ROWS, row r of the packed operand is column r of X
+// (k runs down the column); with it, row r is row r of X (a transpose).  X is
+// column-major with ld; src_double selects FP64 or FP32 storage.
+// PACK_SUB_I packs X - I; PACK_LOWER / PACK_UPPER keep only the lower / upper
+// triangle of X (row >= col / row <= col), zeros elsewhere.
+enum PackFlags : int { PACK_BY_ROWS = 1, PACK_SUB_I = 2, PACK_LOWER = 4, PACK_UPPER = 8 };
+hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P, int64_t ldp,
+                   hipStream_t s);
+
+}  // namespace pfsm

@@ -1,0 +1,313 @@
+// BF16 hi/lo split GEMM (see gemm_x3.h).  Block tile 256x256x32, 256 threads =
+// 4 waves in a 2x2 grid, each wave 128x128 = 4x4 blocks of
+// v_mfma_f32_32x32x16_bf16; per block and k16 step three products
+// (hi*hi, hi*lo, lo*hi).  Operand tiles go through registers into LDS
+// (double buffered, 144-byte rows so 16 consecutive rows read by a
+// ds_read_b128 hit distinct banks).  The MFMA is issued with the B fragment
+// first so that each lane's accumulators run down a column of C, which keeps
+// the column-major stores contiguous.
+#include "common.h"
+#include "gemm_x3.h"
+
+namespace pfsm {
+namespace {
+
+constexpr int BM = X3_BM, BN = X3_BN, BK = X3_BK;
+constexpr int NT = 256;
+constexpr int ROWB = 144;                 // LDS bytes per packed row (128 + 16 pad)
+constexpr int TILE_BYTES = BM * ROWB;     // 36864 per operand per stage
+
+__device__ inline int xcd_remap(int b, int total) {
+  if (total % 8 != 0) return b;
+  return (b % 8) * (total / 8) + b / 8;
+}
+
+__device__ inline void tri_index(int t, int& a, int& b) {
+  // t -> (a, b) with a >= b, row-major over the lower triangle
+  int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  a = r;
+  b = t - r * (r + 1) / 2;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline v8bf as_bf(u32x4 v) { return __builtin_bit_cast(v8bf, v); }
+
+template <int EPI>
+__global__ __launch_bounds__(NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, int tiles_n) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  unsigned char* As = lds;                       // [2][BM][ROWB]
+  unsigned char* Bs = lds + 2 * TILE_BYTES;      // [2][BN][ROWB]
+  __shared__ double red[2][BN];
+
+  int tm, tn;
+  {
+    int total;
+    if (g.tiles == X3_LOWER || g.tiles == X3_UPPER_TRI) total = tiles_m * (tiles_m + 1) / 2;
+    else total = tiles_m * tiles_n;
+    int t = xcd_remap(blockIdx.x, total);
+    if (g.tiles == X3_LOWER) {
+      tri_index(t, tm, tn);
+    } else if (g.tiles == X3_UPPER_TRI) {
+      tri_index(t, tn, tm);
+    } else {
+      const int GROUP = 4;
+      int group_id = t / (GROUP * tiles_n);
+      int first_m = group_id * GROUP;
+      int gsz = min(tiles_m - first_m, GROUP);
+      tm = first_m + (t % (GROUP * tiles_n)) % gsz;
+      tn = (t % (GROUP * tiles_n)) / gsz;
+    }
+  }
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi0 = (wave & 1) * 128, wj0 = (wave >> 1) * 128;
+  const int l32 = lane & 31, lh = lane >> 5;
+
+  int64_t kbeg = 0, kend = (g.K + 31) / 32 * 32;
+  if (g.krange) {
+    kbeg = g.krange[2 * tn];
+    kend = g.krange[2 * tn + 1];
+  }
+  if (g.tiles == X3_UPPER_TRI) {
+    kbeg = max<int64_t>(kbeg, m0);
+    kend = min<int64_t>(kend, n0 + BN);
+  } else if (g.tiles == X3_KPREFIX) {
+    kend = min<int64_t>(kend, n0 + BN);
+  }
+
+  v16f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  // global -> register staging: thread t loads chunk (t % 8) of rows t/8 + 32 q, q < 8
+  const int chunk = tid & 7, rbase = tid >> 3;
+  u32x4 ra[8], rb[8];
+  auto load_tile = [&](int64_t k0) {
+    const int64_t kc = k0 / 32;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = rbase + 32 * q;
+      const int64_t gi = m0 + r, gj = n0 + r;
+      u32x4 z = {0u, 0u, 0u, 0u};
+      ra[q] = (gi < g.M) ? *(const u32x4*)(g.Ap + gi * g.ldap + kc * 64 + chunk * 8) : z;
+      rb[q] = (gj < g.N) ? *(const u32x4*)(g.Bp + gj * g.ldbp + kc * 64 + chunk * 8) : z;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = rbase + 32 * q;
+      *(u32x4*)(As + buf * TILE_BYTES + r * ROWB + chunk * 16) = ra[q];
+      *(u32x4*)(Bs + buf * TILE_BYTES + r * ROWB + chunk * 16) = rb[q];
+    }
+  };
+
+  const int64_t ntk = kend > kbeg ? (kend - kbeg) / BK : 0;
+  if (ntk > 0) {
+    load_tile(kbeg);
+    store_tile(0);
+    __syncthreads();
+    for (int64_t t = 0; t < ntk; ++t) {
+      const int cur = (int)(t & 1);
+      if (t + 1 < ntk) load_tile(kbeg + (t + 1) * BK);
+      const unsigned char* Ab = As + cur * TILE_BYTES;
+      const unsigned char* Bb = Bs + cur * TILE_BYTES;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int koff = 32 * s + 16 * lh;  // byte offset of this lane's 8 k values in the hi plane
+        v8bf ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+          const unsigned char* p = Ab + (wi0 + ib * 32 + l32) * ROWB + koff;
+          ah[ib] = as_bf(*(const u32x4*)p);
+          al[ib] = as_bf(*(const u32x4*)(p + 64));
+        }
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+          const unsigned char* p = Bb + (wj0 + jb * 32 + l32) * ROWB + koff;
+          bh[jb] = as_bf(*(const u32x4*)p);
+          bl[jb] = as_bf(*(const u32x4*)(p + 64));
+        }
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+          for (int jb = 0; jb < 4; ++jb) {
+            acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh[jb], ah[ib], acc[ib][jb], 0, 0, 0);
+            acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl[jb], ah[ib], acc[ib][jb], 0, 0, 0);
+            acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh[jb], al[ib], acc[ib][jb], 0, 0, 0);
+          }
+      }
+      if (t + 1 < ntk) store_tile(cur ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // ------------------------------------------------------------------ epilogue
+  // acc[ib][jb][r] is C(i, j) with i = wi0 + 32 ib + lane%32,
+  // j = wj0 + 32 jb + 8 (r/4) + 4 (lane/32) + r%4.
+  if (EPI == X3_RQ) {
+    const float* D = (const float*)g.D;
+    double cs[4][16];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
+        double sum = 0.0;
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+          const int64_t gi = m0 + wi0 + ib * 32 + l32;
+          if (gi < g.M && gj < g.N) sum += (double)acc[ib][jb][r] * (double)D[gi + gj * g.ldd];
+        }
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) sum += __shfl_xor(sum, off, 64);
+        cs[jb][r] = sum;
+      }
+    if (l32 == 0) {
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[wave & 1][wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4)] = cs[jb][r];
+    }
+    __syncthreads();
+    if (tid < BN) {
+      const int64_t gj = n0 + tid;
+      if (gj < g.N) g.part[(int64_t)tm * g.N + gj] = red[0][tid] + red[1][tid];
+    }
+    return;
+  }
+  double a_eff = g.alpha;
+  if (EPI == X3_FSUPD && g.alpha_dev) a_eff = *g.alpha_dev;
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib) {
+    const int64_t gi = m0 + wi0 + ib * 32 + l32;
+    if (gi >= g.M) continue;
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
+        if (gj >= g.N) continue;
+        const double v = (double)acc[ib][jb][r];
+        double outv;
+        if (EPI == X3_STORE) {
+          outv = g.alpha * v;
+          if (g.beta != 0.0)
+            outv += g.beta * (g.c_double ? ((const double*)g.C)[gi + gj * g.ldc] : (double)((const float*)g.C)[gi + gj * g.ldc]);
+        } else if (EPI == X3_SHIFT) {
+          outv = v - (double)g.B32[gi + gj * g.ldb32] * g.eps[gj];
+        } else if (EPI == X3_FSUPD) {
+          const double dv = (double)((const float*)g.D)[gi + gj * g.ldd];
+          outv = dv - a_eff * (v - (double)g.B32[gi + gj * g.ldb32] * g.eps[gj]);
+        } else {  // X3_ADD
+          const double dv = g.d_double ? ((const double*)g.D)[gi + gj * g.ldd] : (double)((const float*)g.D)[gi + gj * g.ldd];
+          outv = v + dv;
+        }
+        if (g.c_double) ((double*)g.C)[gi + gj * g.ldc] = outv;
+        else ((float*)g.C)[gi + gj * g.ldc] = (float)outv;
+      }
+  }
+}
+
+// ---------------------------------------------------------------- packing
+__device__ inline bf16_t f2bf(float x) {
+  // round to nearest even (finite inputs; NaN stays NaN)
+  uint32_t b = __builtin_bit_cast(uint32_t, x);
+  if ((b & 0x7f800000u) == 0x7f800000u) return (bf16_t)((b >> 16) | ((b & 0xffffu) ? 0x40u : 0u));
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (bf16_t)(b >> 16);
+}
+__device__ inline float bf2f(bf16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+
+// One workgroup packs a 32 (k) x 64 (r) block: reads through LDS so that
+// both the column-major source and the packed destination are contiguous.
+__global__ __launch_bounds__(256) void k_pack(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx,
+                                              int flags, bf16_t* P, int64_t ldp) {
+  const int by_rows = flags & PACK_BY_ROWS;
+  __shared__ double tile[64][33];
+  // packed operand: rows r in [0, R), k in [0, K); R = by_rows ? m : n, K = by_rows ? n : m
+  const int64_t R = by_rows ? m : n;
+  const int64_t K = by_rows ? n : m;
+  const int64_t r0 = (int64_t)blockIdx.y * 64;
+  const int64_t kc = blockIdx.x;  // chunk of 32 k values
+  const int tid = threadIdx.x;
+  // load X values for (r, k) r in [r0, r0+64), k in [32 kc, 32 kc + 32)
+  for (int idx = tid; idx < 64 * 32; idx += 256) {
+    int rr, kk;
+    int64_t row, col;  // position in X (column-major)
+    if (by_rows) {  // X(r, k): contiguous in r for fixed k
+      rr = idx % 64; kk = idx / 64;
+      row = r0 + rr; col = 32 * kc + kk;
+    } else {        // X(k, r): contiguous in k for fixed r
+      kk = idx % 32; rr = idx / 32;
+      row = 32 * kc + kk; col = r0 + rr;
+    }
+    double v = 0.0;
+    const bool keep = !((flags & PACK_LOWER) && row < col) && !((flags & PACK_UPPER) && row > col);
+    if ((by_rows ? (row < R && col < K) : (row < K && col < R)) && keep) {
+      v = src_double ? ((const double*)X)[row + col * ldx] : (double)((const float*)X)[row + col * ldx];
+      if ((flags & PACK_SUB_I) && row == col) v -= 1.0;
+    }
+    tile[rr][kk] = v;
+  }
+  __syncthreads();
+  // write: 64 rows x 64 bf16 (hi 32 | lo 32)
+  for (int idx = tid; idx < 64 * 32; idx += 256) {
+    int kk = idx % 32, rr = idx / 32;
+    int64_t r = r0 + rr;
+    if (r >= R) continue;
+    double v = tile[rr][kk];
+    float vf = (float)v;
+    bf16_t h = f2bf(vf);
+    bf16_t l = f2bf((float)(v - (double)bf2f(h)));
+    bf16_t* dst = P + r * ldp + kc * 64;
+    dst[kk] = h;
+    dst[32 + kk] = l;
+  }
+}
+
+}  // namespace
+
+hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
+  const int tm = (int)((a.M + BM - 1) / BM), tn = (int)((a.N + BN - 1) / BN);
+  if (tm == 0 || tn == 0) return hipSuccess;
+  if ((a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) && tm != tn) return hipErrorInvalidValue;
+  int total = (a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) ? tm * (tm + 1) / 2 : tm * tn;
+  const size_t lds = 4 * (size_t)TILE_BYTES;
+  dim3 grid(total), block(NT);
+  switch (epi) {
+#define X3_CASE(E)                                                                                    \
+  case E:                                                                                             \
+    hipFuncSetAttribute((const void*)gemm_x3_kernel<E>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+                        (int)lds);                                                                    \
+    hipLaunchKernelGGL(gemm_x3_kernel<E>, grid, block, lds, s, a, tm, tn);                            \
+    break;
+    X3_CASE(X3_STORE)
+    X3_CASE(X3_SHIFT)
+    X3_CASE(X3_FSUPD)
+    X3_CASE(X3_ADD)
+    X3_CASE(X3_RQ)
+#undef X3_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P, int64_t ldp,
+                   hipStream_t s) {
+  const bool by_rows = flags & PACK_BY_ROWS;
+  const int64_t R = by_rows ? m : n;
+  const int64_t K = by_rows ? n : m;
+  dim3 grid((unsigned)((K + 31) / 32), (unsigned)((R + 63) / 64));
+  hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, s, X, src_double, m, n, ldx, flags, P, ldp);
+  return hipGetLastError();
+}
+
+}  // namespace pfsm

@@ -8,6 +8,8 @@ hipError_t rq_reduce(const double* part, int tiles_m, int64_t n, const double* d
 hipError_t col_norm2(const double* X, int64_t m, int64_t n, int64_t ldx, double* out, hipStream_t s);
 hipError_t finalize_order(const double* lam_u, const double* X, int64_t n, int64_t ldx, double* Xp, int64_t ldxp,
                           double* lam_out, int* rank, double* sgn, int* info, hipStream_t s);
+// Stable ascending ranks of lam_u (NaN last, info = -1 for non-finite) and lam_out[rank] = lam_u.
+hipError_t finalize_order_values(const double* lam_u, int64_t n, double* lam_out, int* rank, int* info, hipStream_t s);
 hipError_t adjoint_middle(double* T, int64_t ldt, int64_t n, const double* lam, const double* glam, double eta,
                           bool have_t, hipStream_t s);
 hipError_t symmetrize(double* C, int64_t n, int64_t ldc, hipStream_t s);

@@ -310,6 +310,11 @@ hipError_t finalize_order(const double* lam_u, const double* X, int64_t n, int64
   return hipGetLastError();
 }
 
+hipError_t finalize_order_values(const double* lam_u, int64_t n, double* lam_out, int* rank, int* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_rank, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, lam_u, n, rank, lam_out, info);
+  return hipGetLastError();
+}
+
 hipError_t adjoint_middle(double* T, int64_t ldt, int64_t n, const double* lam, const double* glam, double eta,
                           bool have_t, hipStream_t s) {
   dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 64), (unsigned)n);

@@ -5,6 +5,8 @@
 #include "eigh.h"
 #include "chol.h"
 #include "misc.h"
+#include "gemm_x3.h"
+#include "refine.h"
 
 #include <algorithm>
 #include <new>
@@ -16,11 +18,12 @@ struct pfsm_plan {
   int64_t n = 0;
   int P = 0;
   int64_t halo = 0;
-  int iterations = 0, q = 2, shift_mode = 0, precision = 0, max_sweeps = 10;
+  int iterations = 0, q = 2, shift_mode = 0, precision = 0, max_sweeps = 10, flags = 0;
   double alpha = 0.0;
   std::vector<int64_t> part_start, wstart;
   std::vector<int32_t> part_size, wsize, offset;
-  std::vector<int32_t> krange;  // [tiles_n][2] K range of the first folded-spectrum product
+  std::vector<int32_t> krange;  // [tiles_n][2] K range of the first folded-spectrum product (128-column tiles)
+  std::vector<int32_t> krange_x3;  // same for the 256-column tiles of the split-BF16 GEMM
   int Mp = 0, nb = 0;
   int device = 0;
   // device table
@@ -30,12 +33,15 @@ struct pfsm_plan {
   int32_t* d_offset = nullptr;
   int64_t* d_part_start = nullptr;
   int32_t* d_krange = nullptr;
+  int32_t* d_krange_x3 = nullptr;
   // workspace layout (byte offsets)
   // stage timing
   std::vector<hipEvent_t> tev;
   int t_max = 0, t_count = 0;
   size_t o_At, o_b0, o_b1, o_Bw, o_Uw, o_Rw, o_rflag, o_state, o_sel, o_T, o_part, o_eps, o_lamu, o_sgn, o_rank,
       o_scal, o_glo, o_ghi, o_den, total;
+  // mixed-precision workspace (byte offsets)
+  size_t m_At32, m_X32, m_Y32, m_S64, m_Apk, m_Vpk, m_Atpk, m_Xpk, m_Ypk, m_Rpk, m_rb;
 };
 
 namespace {
@@ -100,7 +106,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   if (d->fs_power != 1 && d->fs_power != 2) return PFSM_INVALID_ARG;
   if (d->shift_mode != PFSM_SHIFT_FIXED && d->shift_mode != PFSM_SHIFT_RAYLEIGH) return PFSM_INVALID_ARG;
   if (d->precision != PFSM_PREC_FP64 && d->precision != PFSM_PREC_MIXED_BF16) return PFSM_INVALID_ARG;
-  if (d->reserved != 0) return PFSM_INVALID_ARG;
+  if (d->flags & ~PFSM_FLAG_NO_REFINE) return PFSM_INVALID_ARG;
   if (!(d->alpha == d->alpha)) return PFSM_INVALID_ARG;  // NaN
   const int64_t n = d->n;
   const int P = d->num_parts;
@@ -111,7 +117,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     if (m < 1) return PFSM_INVALID_ARG;
     mmax = std::max(mmax, m);
   }
-  if (d->precision == PFSM_PREC_MIXED_BF16) return PFSM_NOT_SUPPORTED;  // enabled with the mixed kernels
+  if (d->precision == PFSM_PREC_MIXED_BF16 && d->shift_mode != PFSM_SHIFT_FIXED) return PFSM_NOT_SUPPORTED;
 
   pfsm_plan* pl = new (std::nothrow) pfsm_plan();
   if (!pl) return PFSM_OOM;
@@ -124,6 +130,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   pl->shift_mode = d->shift_mode;
   pl->precision = d->precision;
   pl->max_sweeps = d->max_sweeps > 0 ? d->max_sweeps : 10;
+  pl->flags = d->flags;
   int Mmax = 0;
   for (int p = 0; p < P; ++p) {
     int64_t s = d->part_offsets[p], m = d->part_offsets[p + 1] - s;
@@ -156,6 +163,21 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     pl->krange.push_back((int32_t)lo);
     pl->krange.push_back((int32_t)hi);
   }
+  const int64_t tiles_x3 = (n + X3_BN - 1) / X3_BN;
+  for (int64_t t = 0; t < tiles_x3; ++t) {
+    int64_t c0 = t * X3_BN, c1 = std::min<int64_t>(n, c0 + X3_BN);
+    int64_t lo = n, hi = 0;
+    for (int p = 0; p < P; ++p) {
+      int64_t s = pl->part_start[p], e = s + pl->part_size[p];
+      if (e <= c0 || s >= c1) continue;
+      lo = std::min(lo, pl->wstart[p]);
+      hi = std::max(hi, pl->wstart[p] + pl->wsize[p]);
+    }
+    lo = lo / 32 * 32;
+    hi = std::min<int64_t>((n + 31) / 32 * 32, (hi + 31) / 32 * 32);
+    pl->krange_x3.push_back((int32_t)lo);
+    pl->krange_x3.push_back((int32_t)hi);
+  }
   // device table
   size_t tb = 0;
   size_t o_ws = tb; tb = align256(tb + P * sizeof(int64_t));
@@ -163,6 +185,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   size_t o_of = tb; tb = align256(tb + P * sizeof(int32_t));
   size_t o_ps = tb; tb = align256(tb + P * sizeof(int64_t));
   size_t o_kr = tb; tb = align256(tb + pl->krange.size() * sizeof(int32_t));
+  size_t o_k3 = tb; tb = align256(tb + pl->krange_x3.size() * sizeof(int32_t));
   if (hipGetDevice(&pl->device) != hipSuccess || hipMalloc(&pl->dtab, tb) != hipSuccess) {
     delete pl;
     return PFSM_HIP_ERROR;
@@ -173,12 +196,15 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   pl->d_offset = (int32_t*)(base + o_of);
   pl->d_part_start = (int64_t*)(base + o_ps);
   pl->d_krange = (int32_t*)(base + o_kr);
+  pl->d_krange_x3 = (int32_t*)(base + o_k3);
   bool ok = hipMemcpy(pl->d_wstart, pl->wstart.data(), P * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(pl->d_wsize, pl->wsize.data(), P * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(pl->d_offset, pl->offset.data(), P * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(pl->d_part_start, pl->part_start.data(), P * sizeof(int64_t), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(pl->d_krange, pl->krange.data(), pl->krange.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(pl->d_krange_x3, pl->krange_x3.data(), pl->krange_x3.size() * sizeof(int32_t),
                       hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) {
     hipFree(pl->dtab);
@@ -209,6 +235,21 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   pl->o_glo = w; w = align256(w + n * sizeof(double));
   pl->o_ghi = w; w = align256(w + n * sizeof(double));
   pl->o_den = w; w = align256(w + n * sizeof(double));
+  if (pl->precision == PFSM_PREC_MIXED_BF16) {
+    const size_t N4 = (size_t)n * n * sizeof(float);
+    const size_t PK = (size_t)n * x3_row_stride(n) * sizeof(bf16_t);
+    pl->m_At32 = w; w = align256(w + N4);
+    pl->m_X32 = w; w = align256(w + N4);
+    pl->m_Y32 = w; w = align256(w + N4);
+    pl->m_S64 = w; w = align256(w + N2);
+    pl->m_Apk = w; w = align256(w + PK);
+    pl->m_Vpk = w; w = align256(w + PK);
+    pl->m_Atpk = w; w = align256(w + PK);
+    pl->m_Xpk = w; w = align256(w + PK);
+    pl->m_Ypk = w; w = align256(w + PK);
+    pl->m_Rpk = w; w = align256(w + PK);
+    pl->m_rb = w; w = align256(w + (size_t)(7 * n + 8) * sizeof(double));
+  }
   pl->total = w;
   *out = pl;
   return PFSM_OK;
@@ -229,6 +270,9 @@ void pfsm_plan_destroy(pfsm_plan* pl) {
   }
   delete pl;
 }
+
+static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv,
+                               double* dLam, double* dVout, int64_t ldvo, char* W, int* info, hipStream_t s);
 
 pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv, double* dLam,
                        double* dVout, int64_t ldvo, void* dWork, size_t work_bytes, int32_t* dInfo, void* stream) {
@@ -255,6 +299,7 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
   double* scal = (double*)(W + pl->o_scal);
   const int tiles_m = (int)((n + GEMM_BM - 1) / GEMM_BM);
   int* info = (int*)dInfo;
+  if (pl->precision == PFSM_PREC_MIXED_BF16) return solve_mixed(pl, dA, lda, dV, ldv, dLam, dVout, ldvo, W, info, s);
 
   StageClock clk(pl, s);
   PFSM_TRY(fill_i32(info, 1, 0, s));
@@ -358,6 +403,162 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
     PFSM_TRY(gemm_f64(false, false, EPI_STORE, g, s));
   }
   clk.mark(24);
+  clk.mark(25);
+  return hip_status(hipGetLastError());
+}
+
+
+// Mixed precision: every large product on BF16 matrix cores with hi/lo split
+// operands (FP32 accumulation); FP64 submatrix eigensolver, FP64 Cholesky of
+// the overlap, FP64 Rayleigh quotients and cluster Rayleigh-Ritz against A.
+static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv,
+                               double* dLam, double* dVout, int64_t ldvo, char* W, int* info, hipStream_t s) {
+  const int64_t n = pl->n;
+  const int64_t ldp = x3_row_stride(n);
+  double* At64 = (double*)(W + pl->o_At);
+  double* B64a = (double*)(W + pl->o_b0);   // X0 (FP64), later Z = A V_new
+  double* Vn64 = (double*)(W + pl->o_b1);   // V_new before ordering
+  float* At32 = (float*)(W + pl->m_At32);
+  float* X32 = (float*)(W + pl->m_X32);
+  float* Y32 = (float*)(W + pl->m_Y32);
+  double* S64 = (double*)(W + pl->m_S64);
+  bf16_t* Apk = (bf16_t*)(W + pl->m_Apk);
+  bf16_t* Vpk = (bf16_t*)(W + pl->m_Vpk);
+  bf16_t* Atpk = (bf16_t*)(W + pl->m_Atpk);
+  bf16_t* Xpk = (bf16_t*)(W + pl->m_Xpk);
+  bf16_t* Ypk = (bf16_t*)(W + pl->m_Ypk);
+  bf16_t* Rpk = (bf16_t*)(W + pl->m_Rpk);
+  double* eps = (double*)(W + pl->o_eps);
+  double* scal = (double*)(W + pl->o_scal);
+  double* part = (double*)(W + pl->o_part);
+  double* rb = (double*)(W + pl->m_rb);
+  StageClock clk(pl, s);
+  PFSM_TRY(fill_i32(info, 1, 0, s));
+  clk.mark(0);
+
+  auto x3 = [&](int epi, int64_t M, int64_t N, int64_t K, const bf16_t* Ap, const bf16_t* Bp, void* C, int64_t ldc,
+                int c_double) {
+    X3Args g = {};
+    g.M = M; g.N = N; g.K = K; g.Ap = Ap; g.ldap = ldp; g.Bp = Bp; g.ldbp = ldp; g.C = C; g.ldc = ldc;
+    g.c_double = c_double; g.alpha = 1.0;
+    return g;
+  };
+
+  // (1) basis change: W = A V, At = V^T W (lower tiles), FP64 copy for the eigensolver.
+  PFSM_TRY(pack_x3(dA, 1, n, n, lda, 0, Apk, ldp, s));        // rows of A (= columns, A symmetric)
+  PFSM_TRY(pack_x3(dV, 1, n, n, ldv, 0, Vpk, ldp, s));        // columns of V
+  {
+    X3Args g = x3(X3_STORE, n, n, n, Apk, Vpk, Y32, n, 0);
+    PFSM_TRY(gemm_x3(X3_STORE, g, s));
+    PFSM_TRY(pack_x3(Y32, 0, n, n, n, 0, Ypk, ldp, s));       // columns of W
+    X3Args h = x3(X3_STORE, n, n, n, Vpk, Ypk, At32, n, 0);
+    h.tiles = X3_LOWER;
+    PFSM_TRY(gemm_x3(X3_STORE, h, s));
+    PFSM_TRY(f32_mirror_to_f64(At32, At64, n, s));
+    PFSM_TRY(pack_x3(At32, 0, n, n, n, 0, Atpk, ldp, s));
+  }
+  clk.mark(1);
+  PFSM_TRY(gershgorin_alpha(At64, n, n, pl->q, pl->alpha, (double*)(W + pl->o_glo), (double*)(W + pl->o_ghi), scal,
+                            info, s));
+  clk.mark(2);
+  // (2) submatrix eigensolver (FP64) and start vectors.
+  EighBatch e = {};
+  e.P = pl->P; e.Mp = pl->Mp; e.nb = pl->nb; e.inner_max_sweeps = 30;
+  e.Bw = (double*)(W + pl->o_Bw); e.Uw = (double*)(W + pl->o_Uw); e.Rw = (double*)(W + pl->o_Rw);
+  e.rflag = (int*)(W + pl->o_rflag); e.state = (int*)(W + pl->o_state); e.sel = (int*)(W + pl->o_sel);
+  e.wstart = pl->d_wstart; e.wsize = pl->d_wsize; e.offset = pl->d_offset; e.part_start = pl->d_part_start;
+  e.info = info; e.scal = scal;
+  PFSM_TRY(eigh_batched_run(e, At64, n, pl->max_sweeps, s));
+  PFSM_TRY(embed_start_vectors(e, B64a, n, eps, n, s));
+  PFSM_TRY(f64_to_f32(B64a, n, X32, n, n, n, s));
+  PFSM_TRY(pack_x3(X32, 0, n, n, n, 0, Xpk, ldp, s));
+  clk.mark(3);
+  // (3) folded-spectrum iterations (X master copy in FP32).
+  for (int it = 0; it < pl->iterations; ++it) {
+    const int32_t* kr = (it == 0) ? pl->d_krange_x3 : nullptr;
+    if (pl->q == 2) {
+      X3Args g = x3(X3_SHIFT, n, n, n, Atpk, Xpk, Y32, n, 0);
+      g.B32 = X32; g.ldb32 = n; g.eps = eps; g.krange = kr;
+      PFSM_TRY(gemm_x3(X3_SHIFT, g, s));  // Y = (At - eps) X
+      PFSM_TRY(pack_x3(Y32, 0, n, n, n, 0, Ypk, ldp, s));
+      if (it < 8) clk.mark(4 + 2 * it);
+      X3Args h = x3(X3_FSUPD, n, n, n, Atpk, Ypk, X32, n, 0);
+      h.B32 = Y32; h.ldb32 = n; h.D = X32; h.ldd = n; h.eps = eps; h.alpha_dev = scal;
+      PFSM_TRY(gemm_x3(X3_FSUPD, h, s));  // X <- X - a (At - eps) Y
+    } else {
+      if (it < 8) clk.mark(4 + 2 * it);
+      X3Args h = x3(X3_FSUPD, n, n, n, Atpk, Xpk, X32, n, 0);
+      h.B32 = X32; h.ldb32 = n; h.D = X32; h.ldd = n; h.eps = eps; h.alpha_dev = scal; h.krange = kr;
+      PFSM_TRY(gemm_x3(X3_FSUPD, h, s));  // X <- X - a (At - eps) X (operand read from the packed copy)
+    }
+    PFSM_TRY(pack_x3(X32, 0, n, n, n, 0, Xpk, ldp, s));
+    if (it < 8) clk.mark(5 + 2 * it);
+  }
+  clk.mark(19);
+  // (4) overlap S = X^T X (FP64 output, lower tiles) and its FP64 Cholesky.
+  {
+    X3Args g = x3(X3_STORE, n, n, n, Xpk, Xpk, S64, n, 1);
+    g.tiles = X3_LOWER;
+    PFSM_TRY(gemm_x3(X3_STORE, g, s));
+  }
+  clk.mark(20);
+  PFSM_TRY(cholesky_factor(S64, n, n, (double*)(W + pl->o_T), info, s));
+  // X <- X L^{-T} = X + X D, D = -U + U^2 (U = (L - I)^T, max |U| <= 1e-3 checked).
+  PFSM_TRY(lower_minus_identity_check(S64, n, n, rb, info, s));
+  {
+    PFSM_TRY(pack_x3(S64, 1, n, n, n, PACK_SUB_I | PACK_LOWER, Ypk, ldp, s));                 // rows of U
+    PFSM_TRY(pack_x3(S64, 1, n, n, n, PACK_SUB_I | PACK_LOWER | PACK_BY_ROWS, Rpk, ldp, s));  // columns of U
+    X3Args g = x3(X3_STORE, n, n, n, Ypk, Rpk, Y32, n, 0);
+    g.tiles = X3_UPPER_TRI;
+    PFSM_TRY(gemm_x3(X3_STORE, g, s));  // U^2 (upper tiles)
+    PFSM_TRY(series_d(S64, n, Y32, n, Y32, n, n, s));  // D = -U + U^2, zero below the diagonal (in place)
+    PFSM_TRY(pack_x3(Y32, 0, n, n, n, 0, Ypk, ldp, s));            // columns of D
+    PFSM_TRY(pack_x3(X32, 0, n, n, n, PACK_BY_ROWS, Rpk, ldp, s));  // rows of X
+    X3Args h = x3(X3_ADD, n, n, n, Rpk, Ypk, X32, n, 0);
+    h.D = X32; h.ldd = n; h.d_double = 0; h.tiles = X3_KPREFIX;
+    PFSM_TRY(gemm_x3(X3_ADD, h, s));  // X <- X + X D (in place: the operand comes from the packed copy)
+  }
+  clk.mark(21);
+  // (5) sign convention; V_new = V + V (X - I) (FP64 output).
+  PFSM_TRY(col_sign_f32(X32, n, n, (double*)(W + pl->o_sgn), s));
+  PFSM_TRY(pack_x3(X32, 0, n, n, n, 0, Xpk, ldp, s));
+  const bool refine = !(pl->flags & PFSM_FLAG_NO_REFINE);
+  if (!refine) {
+    // eigenvalue estimates of the reduced-precision step: x_j^T At x_j
+    X3Args r = x3(X3_RQ, n, n, n, Atpk, Xpk, nullptr, n, 0);
+    r.D = X32; r.ldd = n; r.part = part;
+    PFSM_TRY(gemm_x3(X3_RQ, r, s));
+    PFSM_TRY(rq_reduce(part, (int)((n + X3_BM - 1) / X3_BM), n, nullptr, (double*)(W + pl->o_lamu), s));
+  }
+  clk.mark(22);
+  PFSM_TRY(pack_x3(X32, 0, n, n, n, PACK_SUB_I, Xpk, ldp, s));  // columns of X - I
+  PFSM_TRY(pack_x3(dV, 1, n, n, ldv, PACK_BY_ROWS, Rpk, ldp, s));  // rows of V
+  {
+    X3Args g = x3(X3_ADD, n, n, n, Rpk, Xpk, Vn64, n, 1);
+    g.D = dV; g.ldd = ldv; g.d_double = 1;
+    PFSM_TRY(gemm_x3(X3_ADD, g, s));
+  }
+  clk.mark(23);
+  if (!refine) {
+    int* rank = (int*)(W + pl->o_rank);
+    PFSM_TRY(finalize_order_values((double*)(W + pl->o_lamu), n, dLam, rank, info, s));
+    PFSM_TRY(permute_f64_cols(Vn64, n, rank, dVout, ldvo, n, n, s));
+    clk.mark(24);
+    clk.mark(25);
+    return hip_status(hipGetLastError());
+  }
+  clk.mark(24);
+  // (6) FP64 refinement: Z = A V_new, Rayleigh quotients, cluster Rayleigh-Ritz, order.
+  {
+    GemmArgs g = {};
+    g.M = n; g.N = n; g.K = n; g.A = dA; g.lda = lda; g.B = Vn64; g.ldb = n; g.C = B64a; g.ldc = n; g.alpha = 1.0;
+    PFSM_TRY(gemm_f64(false, false, EPI_STORE, g, s));
+    RefineBufs b;
+    b.d = rb; b.nn = rb + n; b.lam_s = rb + 2 * n;
+    b.rank = (int*)(rb + 3 * n); b.inv = (int*)(rb + 4 * n); b.cstart = (int*)(rb + 5 * n);
+    b.csize = (int*)(rb + 6 * n); b.clus = (int*)(rb + 7 * n);
+    PFSM_TRY(refine_rr(Vn64, n, B64a, n, n, REFINE_TAU, dLam, dVout, ldvo, b, info, s));
+  }
   clk.mark(25);
   return hip_status(hipGetLastError());
 }

@@ -1,0 +1,37 @@
+#pragma once
+#include "common.h"
+namespace pfsm {
+constexpr int REFINE_KMAX = 32;         // largest cluster handled by one Rayleigh-Ritz block
+constexpr double REFINE_TAU = 1e-4;     // relative gap below which neighbours are refined together
+constexpr int PFSM_INFO_SERIES = -2;    // orthonormalisation series outside its range (mixed path)
+
+struct RefineBufs {
+  double* d;       // [n] v_j^T z_j
+  double* nn;      // [n] v_j^T v_j
+  double* lam_s;   // [n] sorted estimates
+  int* rank;       // [n] column -> sorted position
+  int* inv;        // [n] sorted position -> column
+  int* clus;       // [n + 2] cluster list: clus[0] = count, then (start, size) pairs packed as start | size << 20... see kernel
+  int* cstart;     // [n] cluster starts
+  int* csize;      // [n] cluster sizes
+};
+
+// FP64 refinement of the eigenpair estimates (columns of V, Z = A V):
+// Rayleigh quotients, ascending order, Rayleigh-Ritz on each cluster of
+// estimates closer than tau * max|lambda|, normalisation; writes lambda and
+// Vout (column-major, ldvo).
+hipError_t refine_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz, int64_t n, double tau,
+                     double* lam, double* Vout, int64_t ldvo, RefineBufs b, int* info, hipStream_t s);
+
+// Mixed-path helpers.
+hipError_t f32_mirror_to_f64(float* At32, double* At64, int64_t n, hipStream_t s);   // lower -> both, FP64 copy
+hipError_t f64_to_f32(const double* X, int64_t ldx, float* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t s);
+// D = -U + U2 (upper triangle, zero below), U = (L - I)^T from the lower factor L.
+hipError_t series_d(const double* L, int64_t ldl, const float* U2, int64_t ldu, float* D, int64_t ldd, int64_t n,
+                    hipStream_t s);
+hipError_t lower_minus_identity_check(const double* L, int64_t ldl, int64_t n, double* scratch, int* info,
+                                      hipStream_t s);
+hipError_t col_sign_f32(float* X, int64_t n, int64_t ldx, double* sgn, hipStream_t s);  // flips in place
+hipError_t permute_f64_cols(const double* X, int64_t ldx, const int* rank, double* Y, int64_t ldy, int64_t m,
+                            int64_t n, hipStream_t s);
+}  // namespace pfsm

@@ -1,0 +1,467 @@
+// FP64 refinement of the mixed-precision eigenpair estimates against the
+// original matrix, plus small conversion helpers of the mixed path.
+//
+// With Z = A V (FP64 GEMM), each estimate gets its Rayleigh quotient
+// lambda_j = v_j^T z_j / v_j^T v_j.  Estimates are ordered; runs of neighbours
+// whose gaps are below tau * max|lambda| form clusters, and each cluster is
+// replaced by the Ritz pairs of the pencil (V_c^T Z_c, V_c^T V_c) (Cholesky of
+// the small Gram matrix + cyclic Jacobi), which removes the mixing that the
+// reduced-precision products cause between close eigenvalues.  Isolated
+// estimates are only normalised.
+#include "common.h"
+#include "refine.h"
+#include "order_key.h"
+
+namespace pfsm {
+namespace {
+
+constexpr int NT = 256;
+constexpr int KM = REFINE_KMAX;
+
+__device__ inline double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+  return t;
+}
+
+__global__ __launch_bounds__(NT) void k_dots(const double* V, int64_t ldv, const double* Z, int64_t ldz, int64_t n,
+                                             double* d, double* nn) {
+  __shared__ double sh[NT / 64];
+  const int64_t j = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    double v = V[i + j * ldv];
+    a += v * Z[i + j * ldz];
+    b += v * v;
+  }
+  a = block_sum(a, sh);
+  b = block_sum(b, sh);
+  if (threadIdx.x == 0) {
+    d[j] = a;
+    nn[j] = b;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_rank_rq(const double* d, const double* nn, int64_t n, int* rank, int* inv,
+                                                double* lam_s, int* info) {
+  __shared__ double tile[NT];
+  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const double lj = j < n ? d[j] / nn[j] : 0.0;
+  int64_t r = 0;
+  for (int64_t base = 0; base < n; base += NT) {
+    __syncthreads();
+    if (base + threadIdx.x < n) tile[threadIdx.x] = d[base + threadIdx.x] / nn[base + threadIdx.x];
+    __syncthreads();
+    const int cnt = (int)min<int64_t>(NT, n - base);
+    for (int t = 0; t < cnt; ++t) r += order_before(tile[t], base + t, lj, j);
+  }
+  if (j < n) {
+    if (!isfinite(lj)) atomicCAS(info, 0, -1);
+    rank[j] = (int)r;
+    inv[r] = (int)j;
+    lam_s[r] = lj;
+  }
+}
+
+// Single workgroup: cluster boundaries over the sorted estimates.
+__global__ __launch_bounds__(1024) void k_clusters(const double* lam_s, int64_t n, double tau, int* count, int* cstart,
+                                                   int* csize) {
+  __shared__ double smax[1024];
+  __shared__ int scan[1024];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    double a = fabs(lam_s[i]);
+    m = (a > m || a != a) ? a : m;
+  }
+  smax[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double thr = tau * smax[0];
+  // sequential scan in chunks: thread t owns a contiguous range
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b0 = (int64_t)threadIdx.x * per, b1 = min<int64_t>(n, b0 + per);
+  // count cluster starts in my range (a start: i == 0 or gap > thr); clusters longer than KM are cut
+  int cnt = 0;
+  for (int64_t i = b0; i < b1; ++i) {
+    bool start = (i == 0) || !(lam_s[i] - lam_s[i - 1] <= thr);
+    cnt += start;
+  }
+  scan[threadIdx.x] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int t = 0; t < 1024; ++t) {
+      int c = scan[t];
+      scan[t] = acc;
+      acc += c;
+    }
+    *count = acc;  // number of natural clusters (before cutting at KM)
+  }
+  __syncthreads();
+  int idx = scan[threadIdx.x];
+  for (int64_t i = b0; i < b1; ++i) {
+    bool start = (i == 0) || !(lam_s[i] - lam_s[i - 1] <= thr);
+    if (start) {
+      int64_t e = i + 1;
+      while (e < n && lam_s[e] - lam_s[e - 1] <= thr) ++e;
+      cstart[idx] = (int)i;
+      csize[idx] = (int)(e - i);
+      ++idx;
+    }
+  }
+}
+
+// One workgroup per (natural) cluster; clusters longer than KM are processed
+// as consecutive pieces of at most KM estimates.
+__global__ __launch_bounds__(NT) void k_cluster_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz, int64_t n,
+                                                   const int* count, const int* cstart, const int* csize, const int* inv,
+                                                   const double* lam_s, const double* nn, double* lam, double* Vout,
+                                                   int64_t ldvo) {
+  const int c = blockIdx.x;
+  if (c >= *count) return;
+  __shared__ double G[KM][KM + 1], Mm[KM][KM + 1], Y[KM][KM + 1];
+  __shared__ double rows[NT / 8][KM];  // staging for the rotation, 32 rows at a time
+  __shared__ int col[KM];
+  __shared__ double cs_c[KM / 2], cs_s[KM / 2];
+  __shared__ int pp[KM / 2], qq[KM / 2];
+  __shared__ int rot;
+  const int tid = threadIdx.x;
+  const int s_all = cstart[c], k_all = csize[c];
+  for (int piece = 0; piece < k_all; piece += KM) {
+    const int s = s_all + piece;
+    const int k = min(KM, k_all - piece);
+    if (k == 1) {
+      if (tid == 0) lam[s] = lam_s[s];
+      const int j = inv[s];
+      const double inv_norm = 1.0 / sqrt(nn[j]);
+      for (int64_t i = tid; i < n; i += NT) Vout[i + (int64_t)s * ldvo] = V[i + (int64_t)j * ldv] * inv_norm;
+      __syncthreads();
+      continue;
+    }
+    if (tid < k) col[tid] = inv[s + tid];
+    __syncthreads();
+    // G = V_c^T Z_c, Mm = V_c^T V_c: each wave takes (a, b) pairs
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int pidx = wave; pidx < k * k; pidx += NT / 64) {
+      const int a = pidx % k, b = pidx / k;
+      if (a > b) continue;
+      const double* va = V + (int64_t)col[a] * ldv;
+      const double* vb = V + (int64_t)col[b] * ldv;
+      const double* za = Z + (int64_t)col[a] * ldz;
+      const double* zb = Z + (int64_t)col[b] * ldz;
+      double g1 = 0.0, g2 = 0.0, m = 0.0;
+      for (int64_t i = lane; i < n; i += 64) {
+        double x = va[i], y = vb[i];
+        g1 += x * zb[i];
+        g2 += y * za[i];
+        m += x * y;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        g1 += __shfl_xor(g1, off, 64);
+        g2 += __shfl_xor(g2, off, 64);
+        m += __shfl_xor(m, off, 64);
+      }
+      if (lane == 0) {
+        double g = 0.5 * (g1 + g2);
+        G[a][b] = g; G[b][a] = g;
+        Mm[a][b] = m; Mm[b][a] = m;
+      }
+    }
+    __syncthreads();
+    // Cholesky Mm = R R^T (lower R, in Mm), then G <- R^{-1} G R^{-T}
+    if (tid == 0) {
+      for (int j = 0; j < k; ++j) {
+        double dj = Mm[j][j];
+        for (int t = 0; t < j; ++t) dj -= Mm[j][t] * Mm[j][t];
+        dj = sqrt(fmax(dj, 1e-300));
+        Mm[j][j] = dj;
+        for (int i = j + 1; i < k; ++i) {
+          double v = Mm[i][j];
+          for (int t = 0; t < j; ++t) v -= Mm[i][t] * Mm[j][t];
+          Mm[i][j] = v / dj;
+        }
+      }
+      // W = R^{-1} G (forward substitution per column), then C = W R^{-T}
+      for (int b = 0; b < k; ++b)
+        for (int i = 0; i < k; ++i) {
+          double v = G[i][b];
+          for (int t = 0; t < i; ++t) v -= Mm[i][t] * G[t][b];
+          G[i][b] = v / Mm[i][i];
+        }
+      for (int a = 0; a < k; ++a)
+        for (int i = 0; i < k; ++i) {
+          double v = G[a][i];
+          for (int t = 0; t < i; ++t) v -= G[a][t] * Mm[i][t];
+          G[a][i] = v / Mm[i][i];
+        }
+      for (int a = 0; a < k; ++a)
+        for (int b = a + 1; b < k; ++b) {
+          double v = 0.5 * (G[a][b] + G[b][a]);
+          G[a][b] = v; G[b][a] = v;
+        }
+    }
+    for (int idx = tid; idx < KM * KM; idx += NT) Y[idx % KM][idx / KM] = (idx % KM == idx / KM) ? 1.0 : 0.0;
+    __syncthreads();
+    // cyclic Jacobi on the k x k matrix G (k <= 32): parallel order over a padded even size
+    const int k2 = (k + 1) & ~1;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      if (tid == 0) rot = 0;
+      __syncthreads();
+      for (int r = 0; r < k2 - 1; ++r) {
+        if (tid < k2 / 2) {
+          int a = (tid == 0) ? 0 : ((tid - 1 + r) % (k2 - 1)) + 1;
+          int bpos = k2 - 1 - tid;
+          int b = (bpos == 0) ? 0 : ((bpos - 1 + r) % (k2 - 1)) + 1;
+          int p = min(a, b), q = max(a, b);
+          double cc = 1.0, ss = 0.0;
+          if (q < k) {
+            double apq = G[p][q], app = G[p][p], aqq = G[q][q];
+            if (fabs(apq) > 1e-300 && fabs(apq) > 1.1102230246251565e-16 * sqrt(fabs(app) * fabs(aqq))) {
+              double tau = (aqq - app) / (2.0 * apq);
+              double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+              cc = 1.0 / sqrt(1.0 + t * t);
+              ss = t * cc;
+              rot = 1;
+            }
+          }
+          cs_c[tid] = cc; cs_s[tid] = ss; pp[tid] = p; qq[tid] = q;
+        }
+        __syncthreads();
+        // rotate rows then columns: thread handles one index column for each pair
+        for (int idx = tid; idx < (k2 / 2) * KM; idx += NT) {
+          int kk = idx % (k2 / 2), i = idx / (k2 / 2);
+          int p = pp[kk], q = qq[kk];
+          if (q >= k || i >= k) continue;
+          double cc = cs_c[kk], ss = cs_s[kk];
+          double gp = G[p][i], gq = G[q][i];
+          G[p][i] = cc * gp - ss * gq;
+          G[q][i] = ss * gp + cc * gq;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < (k2 / 2) * KM; idx += NT) {
+          int kk = idx % (k2 / 2), i = idx / (k2 / 2);
+          int p = pp[kk], q = qq[kk];
+          if (q >= k || i >= k) continue;
+          double cc = cs_c[kk], ss = cs_s[kk];
+          double gp = G[i][p], gq = G[i][q];
+          G[i][p] = cc * gp - ss * gq;
+          G[i][q] = ss * gp + cc * gq;
+          double yp = Y[i][p], yq = Y[i][q];
+          Y[i][p] = cc * yp - ss * yq;
+          Y[i][q] = ss * yp + cc * yq;
+        }
+        __syncthreads();
+        if (tid < k2 / 2) {
+          int p = pp[tid], q = qq[tid];
+          if (q < k && cs_s[tid] != 0.0) { G[p][q] = 0.0; G[q][p] = 0.0; }
+        }
+        __syncthreads();
+      }
+      if (!rot) break;
+    }
+    // Y <- R^{-T} Y (back substitution), eigenvalues sorted ascending by selection
+    if (tid == 0) {
+      for (int b = 0; b < k; ++b)
+        for (int i = k - 1; i >= 0; --i) {
+          double v = Y[i][b];
+          for (int t = i + 1; t < k; ++t) v -= Mm[t][i] * Y[t][b];
+          Y[i][b] = v / Mm[i][i];
+        }
+      // order Ritz values ascending (selection sort on the diagonal of G, permuting Y's columns)
+      for (int a = 0; a < k; ++a) {
+        int best = a;
+        for (int b = a + 1; b < k; ++b)
+          if (order_before(G[b][b], b, G[best][best], best)) best = b;
+        if (best != a) {
+          double t = G[a][a]; G[a][a] = G[best][best]; G[best][best] = t;
+          for (int i = 0; i < k; ++i) { double u = Y[i][a]; Y[i][a] = Y[i][best]; Y[i][best] = u; }
+        }
+        lam[s + a] = G[a][a];
+      }
+    }
+    __syncthreads();
+    // Vout[:, s + t] = sum_a V[:, col[a]] Y[a][t], 32 rows per pass
+    const int rl = tid / 8, sub = tid % 8;
+    for (int64_t i0 = 0; i0 < n; i0 += NT / 8) {
+      const int64_t i = i0 + rl;
+      for (int a = sub; a < k; a += 8) rows[rl][a] = (i < n) ? V[i + (int64_t)col[a] * ldv] : 0.0;
+      __syncthreads();
+      if (i < n)
+        for (int t = sub; t < k; t += 8) {
+          double acc = 0.0;
+          for (int a = 0; a < k; ++a) acc += rows[rl][a] * Y[a][t];
+          Vout[i + (int64_t)(s + t) * ldvo] = acc;
+        }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_mirror_f32_to_f64(float* A32, double* A64, int64_t n) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float v = (i >= j) ? A32[i + j * n] : A32[j + i * n];
+    A64[i + j * n] = (double)v;
+  }
+}
+__global__ void k_fix_upper_f32(float* A32, int64_t n) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < j; i += (int64_t)gridDim.x * blockDim.x)
+    A32[i + j * n] = A32[j + i * n];
+}
+
+__global__ void k_f64_to_f32(const double* X, int64_t ldx, float* Y, int64_t ldy, int64_t m) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    Y[i + j * ldy] = (float)X[i + j * ldx];
+}
+
+// max |L - I| over the lower triangle (one workgroup per column, then a max).
+__global__ __launch_bounds__(NT) void k_lmi_col(const double* L, int64_t ldl, int64_t n, double* out) {
+  __shared__ double sh[NT];
+  const int64_t j = blockIdx.x;
+  double m = 0.0;
+  for (int64_t i = j + threadIdx.x; i < n; i += NT) {
+    double v = fabs(L[i + j * ldl] - (i == j ? 1.0 : 0.0));
+    m = (v > m || v != v) ? v : m;
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      double o = sh[threadIdx.x + w];
+      sh[threadIdx.x] = (o > sh[threadIdx.x] || o != o) ? o : sh[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = sh[0];
+}
+__global__ __launch_bounds__(NT) void k_lmi_final(const double* col, int64_t n, double limit, int* info) {
+  __shared__ double sh[NT];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    double v = col[i];
+    m = (v > m || v != v) ? v : m;
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      double o = sh[threadIdx.x + w];
+      sh[threadIdx.x] = (o > sh[threadIdx.x] || o != o) ? o : sh[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && !(sh[0] <= limit)) atomicCAS(info, 0, PFSM_INFO_SERIES);
+}
+
+__global__ __launch_bounds__(NT) void k_col_sign_f32(float* X, int64_t n, int64_t ldx, double* sgn) {
+  __shared__ float sv[NT];
+  __shared__ int64_t si[NT];
+  const int64_t j = blockIdx.x;
+  float* c = X + j * ldx;
+  float best = -1.f;
+  int64_t bi = 0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    float a = fabsf(c[i]);
+    if (a > best) { best = a; bi = i; }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      float a = sv[threadIdx.x + w];
+      int64_t ai = si[threadIdx.x + w];
+      if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && ai < si[threadIdx.x])) {
+        sv[threadIdx.x] = a;
+        si[threadIdx.x] = ai;
+      }
+    }
+    __syncthreads();
+  }
+  const float sg = (c[si[0]] < 0.f) ? -1.f : 1.f;
+  __syncthreads();
+  if (sg < 0.f)
+    for (int64_t i = threadIdx.x; i < n; i += NT) c[i] = -c[i];
+  if (threadIdx.x == 0 && sgn) sgn[j] = sg;
+}
+
+__global__ void k_series_d(const double* L, int64_t ldl, const float* U2, int64_t ldu, float* D, int64_t ldd,
+                           int64_t n) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float v = 0.f;
+    if (i <= j) v = (float)(-(L[j + i * ldl] - (i == j ? 1.0 : 0.0)) + (double)U2[i + j * ldu]);
+    D[i + j * ldd] = v;
+  }
+}
+
+__global__ void k_permute_f64(const double* X, int64_t ldx, const int* rank, double* Y, int64_t ldy, int64_t m) {
+  const int64_t j = blockIdx.y;
+  double* dst = Y + (int64_t)rank[j] * ldy;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = X[i + j * ldx];
+}
+
+}  // namespace
+
+hipError_t refine_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz, int64_t n, double tau, double* lam,
+                     double* Vout, int64_t ldvo, RefineBufs b, int* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots, dim3((unsigned)n), dim3(NT), 0, s, V, ldv, Z, ldz, n, b.d, b.nn);
+  hipLaunchKernelGGL(k_rank_rq, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, b.d, b.nn, n, b.rank, b.inv,
+                     b.lam_s, info);
+  hipLaunchKernelGGL(k_clusters, dim3(1), dim3(1024), 0, s, b.lam_s, n, tau, b.clus, b.cstart, b.csize);
+  hipLaunchKernelGGL(k_cluster_rr, dim3((unsigned)n), dim3(NT), 0, s, V, ldv, Z, ldz, n, b.clus, b.cstart, b.csize,
+                     b.inv, b.lam_s, b.nn, lam, Vout, ldvo);
+  return hipGetLastError();
+}
+
+hipError_t f32_mirror_to_f64(float* At32, double* At64, int64_t n, hipStream_t s) {
+  dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 32), (unsigned)n);
+  hipLaunchKernelGGL(k_mirror_f32_to_f64, grid, dim3(256), 0, s, At32, At64, n);
+  hipLaunchKernelGGL(k_fix_upper_f32, grid, dim3(256), 0, s, At32, n);
+  return hipGetLastError();
+}
+
+hipError_t f64_to_f32(const double* X, int64_t ldx, float* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t s) {
+  dim3 grid((unsigned)std::min<int64_t>((m + 255) / 256, 32), (unsigned)n);
+  hipLaunchKernelGGL(k_f64_to_f32, grid, dim3(256), 0, s, X, ldx, Y, ldy, m);
+  return hipGetLastError();
+}
+
+hipError_t lower_minus_identity_check(const double* L, int64_t ldl, int64_t n, double* scratch, int* info,
+                                      hipStream_t s) {
+  hipLaunchKernelGGL(k_lmi_col, dim3((unsigned)n), dim3(NT), 0, s, L, ldl, n, scratch);
+  hipLaunchKernelGGL(k_lmi_final, dim3(1), dim3(NT), 0, s, scratch, n, 1e-3, info);
+  return hipGetLastError();
+}
+
+hipError_t col_sign_f32(float* X, int64_t n, int64_t ldx, double* sgn, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_sign_f32, dim3((unsigned)n), dim3(NT), 0, s, X, n, ldx, sgn);
+  return hipGetLastError();
+}
+
+hipError_t series_d(const double* L, int64_t ldl, const float* U2, int64_t ldu, float* D, int64_t ldd, int64_t n,
+                    hipStream_t s) {
+  dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 32), (unsigned)n);
+  hipLaunchKernelGGL(k_series_d, grid, dim3(256), 0, s, L, ldl, U2, ldu, D, ldd, n);
+  return hipGetLastError();
+}
+
+hipError_t permute_f64_cols(const double* X, int64_t ldx, const int* rank, double* Y, int64_t ldy, int64_t m, int64_t n,
+                            hipStream_t s) {
+  dim3 grid((unsigned)std::min<int64_t>((m + 255) / 256, 32), (unsigned)n);
+  hipLaunchKernelGGL(k_permute_f64, grid, dim3(256), 0, s, X, ldx, rank, Y, ldy, m);
+  return hipGetLastError();
+}
+
+}  // namespace pfsm
