@@ -42,9 +42,9 @@ def algorithmic_flops(n: int, M: int, q: int, n_it: int) -> float:
     return 2 * n3 + n3 + 2.0 * n * n * M + (q * n_it - 1) * 2 * n3 + n3 + n3 / 3 + n3 + 2 * n3 + 2 * n3
 
 
-def gemm_source_hash() -> str:
+def gemm_source_hash(files=("gemm_f64.hip", "gemm_x3.hip", "gemm_x3.h", "common.h")) -> str:
     h = hashlib.sha256()
-    for f in ("gemm_f64.hip", "common.h"):
+    for f in files:
         p = os.path.join(ROOT, "paper_1502_07806_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
@@ -123,7 +123,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--precision", default="auto", choices=["auto", "fp64", "mixed_bf16"])
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp64", "mixed_bf16"],
+                    help="auto = mixed_bf16 (headline), with the FP64 path and the unrefined result reported beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     args = ap.parse_args()
@@ -155,8 +156,8 @@ def main():
     if n == 8192 and os.path.exists(gp):
         golden = np.loadtxt(gp)
 
-    def run(precision):
-        plan = pf.Plan(n, offs, halo=halo, iterations=n_it, fs_power=q, precision=precision)
+    def run(precision, refine=True):
+        plan = pf.Plan(n, offs, halo=halo, iterations=n_it, fs_power=q, precision=precision, refine=refine)
         lam, Vo = plan.solve(A, V)  # first call: workspace allocation + check
         for _ in range(args.warmup):
             plan.solve(A, V, out=(lam, Vo), check=False)
@@ -185,14 +186,21 @@ def main():
 
     precision = args.precision
     if precision == "auto":
-        precision = "fp64"
-    plan, ms, st, acc = run(precision)
+        precision = "mixed_bf16"
     F = algorithmic_flops(n, M, q, n_it)
-    upd = [st["fs_update_%d" % i] for i in range(n_it)]
-    upd_ms = float(np.mean(upd))
-    dom_flops = 2.0 * n ** 3
+    plan, ms, st, acc = run(precision)
+    upd_ms = float(np.mean([st["fs_update_%d" % i] for i in range(n_it)]))
+    if precision == "fp64":
+        dom_flops, peak, unit_dtype = 2.0 * n ** 3, PEAK_TFLOPS["fp64"], "f64"
+        kname = "gemm_f64_kernel<N,N,EPI_FSUPD> (folded-spectrum update, %dx%dx%d, FP64 MFMA)" % (n, n, n)
+        kernel_key = "gemm_f64_fsupd_n%d" % n
+    else:
+        # split-BF16 product: three BF16 MFMA products (hi*hi, hi*lo, lo*hi) per output
+        dom_flops, peak, unit_dtype = 3 * 2.0 * n ** 3, PEAK_TFLOPS["bf16"], "bf16"
+        kname = ("gemm_x3_kernel<X3_FSUPD> (folded-spectrum update, %dx%dx%d, 3 BF16 MFMA products per "
+                 "output, FP32 accumulation)" % (n, n, n))
+        kernel_key = "gemm_x3_fsupd_n%d" % n
     achieved = dom_flops / (upd_ms * 1e-3) / 1e12
-    kernel_key = "gemm_f64_fsupd_n%d" % n
     traffic = load_traffic(kernel_key)
     out = {
         "metric": "PFSM solves/s + TFLOP/s at N=8192, mixed vs FP64 GPU path, eig err <=1e-8",
@@ -205,18 +213,32 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if precision == "fp64" else "bf16",
+        "dtype": unit_dtype,
         "data": "synthetic",
         "config": {"workload": "c3_n8192 PFSM step (N=%d, 32 slices of %d, submatrix order %d, %d FS iterations, "
                                "q=%d, ||K||_F=%g), precision=%s" % (n, m, M, n_it, q, cfg.kappa, precision),
-                   "n": n, "slices": len(offs) - 1, "submatrix_order": M, "iterations": n_it},
+                   "n": n, "slices": len(offs) - 1, "submatrix_order": M, "iterations": n_it,
+                   "precision": precision},
         "tflops": F / (ms * 1e-3) / 1e12,
         "accuracy": acc,
-        "stages_ms": {k: round(v, 4) for k, v in st.items() if v > 0},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": traffic,
-                     "kernel": "gemm_f64_kernel<N,N,EPI_FSUPD> (folded-spectrum update, %dx%dx%d)" % (n, n, n)},
+        "stages_ms": {k: round(v, 4) for k, v in st.items() if v > 0.01},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic, "kernel": kname,
+                     "launch_ms": upd_ms, "flops_per_launch": dom_flops},
     }
+    del plan
+    if precision != "fp64" and not args.no_fp64_compare:
+        p64, ms64, st64, acc64 = run("fp64")
+        upd64 = float(np.mean([st64["fs_update_%d" % i] for i in range(n_it)]))
+        out["fp64_path"] = {"solves_per_s": 1e3 / ms64, "ms_per_step": ms64, "tflops": F / (ms64 * 1e-3) / 1e12,
+                            "accuracy": acc64, "speedup_of_mixed": ms64 / ms,
+                            "fs_update_gemm_tflops": 2.0 * n ** 3 / (upd64 * 1e-3) / 1e12,
+                            "stages_ms": {k: round(v, 4) for k, v in st64.items() if v > 0.01}}
+        del p64
+        pnr, msnr, stnr, accnr = run(precision, refine=False)
+        out["fp32_result"] = {"note": "mixed path without the FP64 refinement against A", "ms_per_step": msnr,
+                              "accuracy": accnr}
+        del pnr
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out), flush=True)

@@ -40,6 +40,8 @@
  *         short series used for X L^{-T} (max |L - I| > 1e-3: the start vectors
  *         are far from orthogonal, outside the diagonally dominant regime)
  *     -3  a submatrix eigensolver did not converge within its sweep limit
+ *     -4  an output vector lost its length (squared norm outside [1/4, 4] before
+ *         normalisation): V_prev does not have orthonormal columns
  * The first condition found wins.
  */
 #ifndef PFSM_H

@@ -25,7 +25,8 @@ PFSM_PREC = {"fp64": 0, "mixed_bf16": 1}
 PFSM_SHIFT = {"fixed": 0, "rayleigh": 1}
 INFO_TEXT = {0: "ok", -1: "non-finite eigenvalue",
              -2: "overlap factor too far from the identity for the mixed-precision orthonormalisation",
-             -3: "submatrix eigensolver did not converge"}
+             -3: "submatrix eigensolver did not converge",
+             -4: "an output vector lost its length: V_prev is not orthonormal"}
 FLAG_NO_REFINE = 1
 
 

@@ -1,143 +1,150 @@
 // Blocked FP64 Cholesky of the overlap matrix S = X^T X and the right-side
 // triangular solve X <- X L^{-T} (the orthonormalisation step, computed as
-// Cholesky-QR).  Block width 64: a single-workgroup kernel factors each
-// 64x64 diagonal block in LDS and writes both L_kk and L_kk^{-T}; the panel
-// and trailing updates are MFMA GEMMs.
+// Cholesky-QR).
+//
+// Two-level blocking: 64-wide diagonal blocks are factored by one wavefront
+// with each lane holding one row in registers (column values are broadcast
+// with v_readlane), which also forms L_kk^{-T}; the 64-wide panel solve is an
+// MFMA GEMM with that inverse; updates inside a 512-wide panel are rank-64
+// GEMMs restricted to the panel, and the rest of the matrix receives one
+// rank-512 update per panel, so the trailing matrix is streamed N/512 times
+// instead of N/64 times.
 #include "common.h"
 #include "chol.h"
 
 namespace pfsm {
 namespace {
 
-constexpr int NB = CHOL_NB;
-constexpr int LS = NB + 1;
+constexpr int NB = CHOL_NB;      // 64
+constexpr int NB2 = CHOL_NB2;    // 512
 
-// Factor S[k0:k0+nb, k0:k0+nb] (lower triangle) in place; write T = L^{-T}
-// (upper triangular, column-major nb x nb).  A non-positive or non-finite
-// pivot records info = global column (1-based), first error wins.
-__global__ __launch_bounds__(256) void potrf_diag(double* S, int64_t lds, int64_t k0, int nb, double* T, int* info) {
-  __shared__ double L[NB][LS];
-  __shared__ double Xi[NB][LS];
-  const int tid = threadIdx.x;
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One wavefront: factor S[k0:k0+nb, k0:k0+nb] (lower triangle) in place and
+// write T = L^{-T} (upper triangular, 64 x 64 column-major; identity padding
+// past nb).  A non-positive or non-finite pivot records info = global column
+// (1-based), first error wins, and the factorisation continues with NaN.
+__global__ __launch_bounds__(64) void potrf_diag(double* S, int64_t lds, int64_t k0, int nb, double* T, int* info) {
+  const int i = threadIdx.x;  // this lane's row
   double* Sk = S + k0 + k0 * lds;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    int r = idx % NB, c = idx / NB;
-    double v = 0.0;
-    if (r < nb && c < nb && r >= c) v = Sk[r + c * lds];
-    if (r >= nb && r == c) v = 1.0;  // ragged last block: identity padding
-    L[r][c] = v;
-    Xi[r][c] = (r == c) ? 1.0 : 0.0;
+  double r[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    double v = (i == c) ? 1.0 : 0.0;
+    if (i < nb && c < nb && c <= i) v = Sk[i + c * lds];
+    r[c] = v;
   }
-  __syncthreads();
+  // right-looking Cholesky: column j is finished at step j
+#pragma unroll
   for (int j = 0; j < NB; ++j) {
-    if (tid == 0) {
-      double d = L[j][j];
-      if (!(d > 0.0)) {
-        if (j < nb) atomicCAS(info, 0, (int)(k0 + j + 1));
-        d = __builtin_nan("");
-      }
-      L[j][j] = sqrt(d);
+    double d = readlane_d(r[j], j);
+    if (!(d > 0.0)) {
+      if (i == 0 && j < nb) atomicCAS(info, 0, (int)(k0 + j + 1));
+      d = __builtin_nan("");
     }
-    __syncthreads();
-    const double djj = L[j][j];
-    for (int i = j + 1 + tid; i < NB; i += 256) L[i][j] /= djj;
-    __syncthreads();
-    const int m = NB - j - 1;
-    for (int idx = tid; idx < m * m; idx += 256) {
-      int i = j + 1 + idx % m, c = j + 1 + idx / m;
-      if (c <= i) L[i][c] -= L[i][j] * L[c][j];
+    const double sj = sqrt(d);
+    r[j] = (i == j) ? sj : (i > j ? r[j] / sj : r[j]);
+#pragma unroll
+    for (int c = j + 1; c < NB; ++c) {
+      const double lcj = readlane_d(r[j], c);
+      if (i >= c) r[c] -= r[j] * lcj;
     }
-    __syncthreads();
   }
-  // Xi <- L^{-1} by right-looking forward substitution on the identity.
-  for (int i = 0; i < NB; ++i) {
-    const double lii = L[i][i];
-    for (int c = tid; c <= i; c += 256) Xi[i][c] /= lii;
-    __syncthreads();
-    const int m = NB - i - 1;
-    for (int idx = tid; idx < m * (i + 1); idx += 256) {
-      int r = i + 1 + idx % m, c = idx / m;
-      Xi[r][c] -= L[r][i] * Xi[i][c];
+  // x = row i of L^{-1}: forward substitution on the identity, rows in order
+  double x[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) x[c] = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const double lkk = readlane_d(r[k], k);
+    if (i == k) {
+#pragma unroll
+      for (int c = 0; c <= k; ++c) x[c] /= lkk;
     }
-    __syncthreads();
+    const double lik = r[k];  // L[i][k]
+#pragma unroll
+    for (int c = 0; c <= k; ++c) {
+      const double xkc = readlane_d(x[c], k);
+      if (i > k) x[c] -= lik * xkc;
+    }
   }
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    int r = idx % NB, c = idx / NB;
-    if (r < nb && c < nb) {
-      if (r >= c) Sk[r + c * lds] = L[r][c];
-      T[r + c * NB] = Xi[c][r];  // T = (L^{-1})^T
-    } else {
-      T[r + c * NB] = (r == c) ? 1.0 : 0.0;
-    }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (i < nb && c < nb && c <= i) Sk[i + c * lds] = r[c];
+    // T(c, i) = (L^{-1})(i, c)
+    T[c + i * NB] = (i < nb && c < nb) ? (c <= i ? x[c] : 0.0) : (i == c ? 1.0 : 0.0);
   }
 }
+
+hipError_t gemm_store(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, bool tb, const double* B,
+                      int64_t ldb, double* C, int64_t ldc, double alpha, double beta, int lower, hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  GemmArgs g = {};
+  g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta; g.lower_only = lower;
+  return gemm_f64(false, tb, EPI_STORE, g, s);
+}
+
+#define CHK(x)                           \
+  do {                                   \
+    hipError_t _e = (x);                 \
+    if (_e != hipSuccess) return _e;     \
+  } while (0)
 
 }  // namespace
 
 hipError_t cholesky_factor(double* S, int64_t lds, int64_t n, double* Tbuf, int* info, hipStream_t s) {
   // S: n x n (lower triangle valid) -> L in place; Tbuf receives the inverse-transposed diagonal blocks.
-  const int64_t nblk = (n + NB - 1) / NB;
-  for (int64_t b = 0; b < nblk; ++b) {
-    const int64_t k0 = b * NB;
-    const int nb = (int)std::min<int64_t>(NB, n - k0);
-    double* T = Tbuf + b * NB * NB;
-    hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(256), 0, s, S, lds, k0, nb, T, info);
-    const int64_t rest = n - k0 - nb;
-    if (rest > 0) {
-      GemmArgs g = {};
-      // panel: L21 = S21 * T  (in place; one column tile per row tile)
-      g.M = rest; g.N = nb; g.K = nb;
-      g.A = S + (k0 + nb) + k0 * lds; g.lda = lds;
-      g.B = T; g.ldb = NB;
-      g.C = S + (k0 + nb) + k0 * lds; g.ldc = lds;
-      g.alpha = 1.0; g.beta = 0.0;
-      hipError_t e = gemm_f64(false, false, EPI_STORE, g, s);
-      if (e != hipSuccess) return e;
-      // trailing: S22 -= L21 L21^T (lower tiles)
-      GemmArgs h = {};
-      h.M = rest; h.N = rest; h.K = nb;
-      h.A = S + (k0 + nb) + k0 * lds; h.lda = lds;
-      h.B = S + (k0 + nb) + k0 * lds; h.ldb = lds;
-      h.C = S + (k0 + nb) + (k0 + nb) * lds; h.ldc = lds;
-      h.alpha = -1.0; h.beta = 1.0; h.lower_only = 1;
-      e = gemm_f64(false, true, EPI_STORE, h, s);
-      if (e != hipSuccess) return e;
+  for (int64_t K0 = 0; K0 < n; K0 += NB2) {
+    const int64_t w = std::min<int64_t>(NB2, n - K0);
+    for (int64_t k0 = K0; k0 < K0 + w; k0 += NB) {
+      const int nb = (int)std::min<int64_t>(NB, K0 + w - k0);
+      double* T = Tbuf + (k0 / NB) * NB * NB;
+      hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(64), 0, s, S, lds, k0, nb, T, info);
+      const int64_t rest = n - k0 - nb;
+      double* L21 = S + (k0 + nb) + k0 * lds;
+      // panel: L21 = S21 T (in place; one column tile per row tile)
+      CHK(gemm_store(rest, nb, nb, L21, lds, false, T, NB, L21, lds, 1.0, 0.0, 0, s));
+      // update the remaining columns of this 512-wide panel: S[k0+nb:, k0+nb:K0+w] -= L21 L21[:pc]^T
+      const int64_t pc = K0 + w - (k0 + nb);
+      CHK(gemm_store(rest, pc, nb, L21, lds, true, L21, lds, S + (k0 + nb) + (k0 + nb) * lds, lds, -1.0, 1.0, 0, s));
     }
+    // one rank-w update of the trailing matrix (lower tiles)
+    const int64_t rest2 = n - K0 - w;
+    double* P = S + (K0 + w) + K0 * lds;
+    CHK(gemm_store(rest2, rest2, w, P, lds, true, P, lds, S + (K0 + w) + (K0 + w) * lds, lds, -1.0, 1.0, 1, s));
   }
   return hipGetLastError();
 }
 
-hipError_t cholesky_qr(double* S, int64_t lds, double* X, int64_t ldx, int64_t n, int64_t m,
-                       double* Tbuf, int* info, hipStream_t s) {
-  // S: n x n overlap (lower triangle valid) -> L.  X: m x n, overwritten by X L^{-T}.
-  const int64_t nblk = (n + NB - 1) / NB;
-  hipError_t e0 = cholesky_factor(S, lds, n, Tbuf, info, s);
-  if (e0 != hipSuccess) return e0;
-  // X <- X L^{-T}: right-looking over column blocks.
-  for (int64_t b = 0; b < nblk; ++b) {
-    const int64_t k0 = b * NB;
-    const int nb = (int)std::min<int64_t>(NB, n - k0);
-    GemmArgs g = {};
-    g.M = m; g.N = nb; g.K = nb;
-    g.A = X + k0 * ldx; g.lda = ldx;
-    g.B = Tbuf + b * NB * NB; g.ldb = NB;
-    g.C = X + k0 * ldx; g.ldc = ldx;
-    g.alpha = 1.0; g.beta = 0.0;
-    hipError_t e = gemm_f64(false, false, EPI_STORE, g, s);
-    if (e != hipSuccess) return e;
-    const int64_t rest = n - k0 - nb;
-    if (rest > 0) {
-      GemmArgs h = {};
-      h.M = m; h.N = rest; h.K = nb;
-      h.A = X + k0 * ldx; h.lda = ldx;
-      h.B = S + (k0 + nb) + k0 * lds; h.ldb = lds;   // op(B) = L[k0+nb:, k0:k0+nb]^T
-      h.C = X + (k0 + nb) * ldx; h.ldc = ldx;
-      h.alpha = -1.0; h.beta = 1.0;
-      e = gemm_f64(false, true, EPI_STORE, h, s);
-      if (e != hipSuccess) return e;
+hipError_t trsm_right_lt(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t n, int64_t m,
+                         const double* Tbuf, hipStream_t s) {
+  // X (m x n) <- X L^{-T}, same two-level blocking over column blocks.
+  for (int64_t K0 = 0; K0 < n; K0 += NB2) {
+    const int64_t w = std::min<int64_t>(NB2, n - K0);
+    for (int64_t k0 = K0; k0 < K0 + w; k0 += NB) {
+      const int nb = (int)std::min<int64_t>(NB, K0 + w - k0);
+      double* Xk = X + k0 * ldx;
+      CHK(gemm_store(m, nb, nb, Xk, ldx, false, Tbuf + (k0 / NB) * NB * NB, NB, Xk, ldx, 1.0, 0.0, 0, s));
+      const int64_t pc = K0 + w - (k0 + nb);
+      CHK(gemm_store(m, pc, nb, Xk, ldx, true, L + (k0 + nb) + k0 * ldl, ldl, X + (k0 + nb) * ldx, ldx, -1.0, 1.0, 0, s));
     }
+    const int64_t rest2 = n - K0 - w;
+    CHK(gemm_store(m, rest2, w, X + K0 * ldx, ldx, true, L + (K0 + w) + K0 * ldl, ldl, X + (K0 + w) * ldx, ldx, -1.0,
+                   1.0, 0, s));
   }
   return hipGetLastError();
+}
+
+hipError_t cholesky_qr(double* S, int64_t lds, double* X, int64_t ldx, int64_t n, int64_t m, double* Tbuf, int* info,
+                       hipStream_t s) {
+  CHK(cholesky_factor(S, lds, n, Tbuf, info, s));
+  return trsm_right_lt(S, lds, X, ldx, n, m, Tbuf, s);
 }
 
 }  // namespace pfsm

@@ -1,6 +1,7 @@
-// BF16 hi/lo split GEMM (see gemm_x3.h).  Block tile 256x256x32, 256 threads =
-// 4 waves in a 2x2 grid, each wave 128x128 = 4x4 blocks of
-// v_mfma_f32_32x32x16_bf16; per block and k16 step three products
+// BF16 hi/lo split GEMM (see gemm_x3.h).  Block tile 256x256x32, 512 threads =
+// 8 waves in a 2 (rows) x 4 (columns) grid, each wave 128x64 = 4x2 blocks of
+// v_mfma_f32_32x32x16_bf16, two waves per SIMD so one wave's LDS reads overlap
+// the other's matrix-core work; per block and k16 step three products
 // (hi*hi, hi*lo, lo*hi).  Operand tiles go through registers into LDS
 // (double buffered, 144-byte rows so 16 consecutive rows read by a
 // ds_read_b128 hit distinct banks).  The MFMA is issued with the B fragment
@@ -13,7 +14,8 @@ namespace pfsm {
 namespace {
 
 constexpr int BM = X3_BM, BN = X3_BN, BK = X3_BK;
-constexpr int NT = 256;
+constexpr int NT = 512;
+constexpr int WR = 4, WC = 2;             // MFMA blocks per wave (rows, columns)
 constexpr int ROWB = 144;                 // LDS bytes per packed row (128 + 16 pad)
 constexpr int TILE_BYTES = BM * ROWB;     // 36864 per operand per stage
 
@@ -63,7 +65,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, i
   }
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wi0 = (wave & 1) * 128, wj0 = (wave >> 1) * 128;
+  const int wi0 = (wave & 1) * (32 * WR), wj0 = (wave >> 1) * (32 * WC);
   const int l32 = lane & 31, lh = lane >> 5;
 
   int64_t kbeg = 0, kend = (g.K + 31) / 32 * 32;
@@ -78,22 +80,23 @@ __global__ __launch_bounds__(NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, i
     kend = min<int64_t>(kend, n0 + BN);
   }
 
-  v16f acc[4][4];
+  v16f acc[WR][WC];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WR; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < WC; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  // global -> register staging: thread t loads chunk (t % 8) of rows t/8 + 32 q, q < 8
+  // global -> register staging: thread t loads chunk (t % 8) of rows t/8 + 64 q, q < 4
+  constexpr int LQ = BM * 8 / NT;  // 4
   const int chunk = tid & 7, rbase = tid >> 3;
-  u32x4 ra[8], rb[8];
+  u32x4 ra[LQ], rb[LQ];
   auto load_tile = [&](int64_t k0) {
     const int64_t kc = k0 / 32;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int r = rbase + 32 * q;
+    for (int q = 0; q < LQ; ++q) {
+      const int r = rbase + (NT / 8) * q;
       const int64_t gi = m0 + r, gj = n0 + r;
       u32x4 z = {0u, 0u, 0u, 0u};
       ra[q] = (gi < g.M) ? *(const u32x4*)(g.Ap + gi * g.ldap + kc * 64 + chunk * 8) : z;
@@ -102,8 +105,8 @@ __global__ __launch_bounds__(NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, i
   };
   auto store_tile = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int r = rbase + 32 * q;
+    for (int q = 0; q < LQ; ++q) {
+      const int r = rbase + (NT / 8) * q;
       *(u32x4*)(As + buf * TILE_BYTES + r * ROWB + chunk * 16) = ra[q];
       *(u32x4*)(Bs + buf * TILE_BYTES + r * ROWB + chunk * 16) = rb[q];
     }
@@ -122,23 +125,23 @@ __global__ __launch_bounds__(NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, i
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int koff = 32 * s + 16 * lh;  // byte offset of this lane's 8 k values in the hi plane
-        v8bf ah[4], al[4], bh[4], bl[4];
+        v8bf ah[WR], al[WR], bh[WC], bl[WC];
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
+        for (int ib = 0; ib < WR; ++ib) {
           const unsigned char* p = Ab + (wi0 + ib * 32 + l32) * ROWB + koff;
           ah[ib] = as_bf(*(const u32x4*)p);
           al[ib] = as_bf(*(const u32x4*)(p + 64));
         }
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
+        for (int jb = 0; jb < WC; ++jb) {
           const unsigned char* p = Bb + (wj0 + jb * 32 + l32) * ROWB + koff;
           bh[jb] = as_bf(*(const u32x4*)p);
           bl[jb] = as_bf(*(const u32x4*)(p + 64));
         }
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib)
+        for (int ib = 0; ib < WR; ++ib)
 #pragma unroll
-          for (int jb = 0; jb < 4; ++jb) {
+          for (int jb = 0; jb < WC; ++jb) {
             acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh[jb], ah[ib], acc[ib][jb], 0, 0, 0);
             acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl[jb], ah[ib], acc[ib][jb], 0, 0, 0);
             acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh[jb], al[ib], acc[ib][jb], 0, 0, 0);
@@ -154,15 +157,15 @@ __global__ __launch_bounds__(NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, i
   // j = wj0 + 32 jb + 8 (r/4) + 4 (lane/32) + r%4.
   if (EPI == X3_RQ) {
     const float* D = (const float*)g.D;
-    double cs[4][16];
+    double cs[WC][16];
 #pragma unroll
-    for (int jb = 0; jb < 4; ++jb)
+    for (int jb = 0; jb < WC; ++jb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
         double sum = 0.0;
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
+        for (int ib = 0; ib < WR; ++ib) {
           const int64_t gi = m0 + wi0 + ib * 32 + l32;
           if (gi < g.M && gj < g.N) sum += (double)acc[ib][jb][r] * (double)D[gi + gj * g.ldd];
         }
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, i
       }
     if (l32 == 0) {
 #pragma unroll
-      for (int jb = 0; jb < 4; ++jb)
+      for (int jb = 0; jb < WC; ++jb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) red[wave & 1][wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4)] = cs[jb][r];
     }
@@ -186,11 +189,11 @@ __global__ __launch_bounds__(NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, i
   double a_eff = g.alpha;
   if (EPI == X3_FSUPD && g.alpha_dev) a_eff = *g.alpha_dev;
 #pragma unroll
-  for (int ib = 0; ib < 4; ++ib) {
+  for (int ib = 0; ib < WR; ++ib) {
     const int64_t gi = m0 + wi0 + ib * 32 + l32;
     if (gi >= g.M) continue;
 #pragma unroll
-    for (int jb = 0; jb < 4; ++jb)
+    for (int jb = 0; jb < WC; ++jb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);

@@ -10,6 +10,9 @@ hipError_t finalize_order(const double* lam_u, const double* X, int64_t n, int64
                           double* lam_out, int* rank, double* sgn, int* info, hipStream_t s);
 // Stable ascending ranks of lam_u (NaN last, info = -1 for non-finite) and lam_out[rank] = lam_u.
 hipError_t finalize_order_values(const double* lam_u, int64_t n, double* lam_out, int* rank, int* info, hipStream_t s);
+constexpr int PFSM_INFO_BASIS = -4;
+// info = -4 when some nn[j] (squared column norm) is outside [1/4, 4] or not finite.
+hipError_t norm_check(const double* nn, int64_t n, int* info, hipStream_t s);
 hipError_t adjoint_middle(double* T, int64_t ldt, int64_t n, const double* lam, const double* glam, double eta,
                           bool have_t, hipStream_t s);
 hipError_t symmetrize(double* C, int64_t n, int64_t ldc, hipStream_t s);

@@ -271,7 +271,19 @@ __global__ __launch_bounds__(NT) void k_diag_final(const double* part, int64_t n
   }
 }
 
+__global__ void k_norm_check(const double* nn, int64_t n, int* info) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double v = nn[j];
+  if (!(v >= 0.25 && v <= 4.0)) atomicCAS(info, 0, PFSM_INFO_BASIS);
+}
+
 }  // namespace
+
+hipError_t norm_check(const double* nn, int64_t n, int* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nn, n, info);
+  return hipGetLastError();
+}
 
 hipError_t fill_i32(int* p, int64_t count, int value, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 1024))),

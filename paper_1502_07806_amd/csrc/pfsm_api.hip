@@ -401,6 +401,9 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
     g.M = n; g.N = n; g.K = n; g.A = dV; g.lda = ldv; g.B = Xp; g.ldb = n; g.C = dVout; g.ldc = ldvo;
     g.alpha = 1.0;
     PFSM_TRY(gemm_f64(false, false, EPI_STORE, g, s));
+    // V_prev X keeps unit columns only if V_prev is orthonormal
+    PFSM_TRY(col_norm2(dVout, n, n, ldvo, (double*)(W + pl->o_den), s));
+    PFSM_TRY(norm_check((double*)(W + pl->o_den), n, info, s));
   }
   clk.mark(24);
   clk.mark(25);
@@ -491,8 +494,8 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
       h.B32 = X32; h.ldb32 = n; h.D = X32; h.ldd = n; h.eps = eps; h.alpha_dev = scal; h.krange = kr;
       PFSM_TRY(gemm_x3(X3_FSUPD, h, s));  // X <- X - a (At - eps) X (operand read from the packed copy)
     }
+    if (it < 8) clk.mark(5 + 2 * it);  // the update stage holds exactly one GEMM launch
     PFSM_TRY(pack_x3(X32, 0, n, n, n, 0, Xpk, ldp, s));
-    if (it < 8) clk.mark(5 + 2 * it);
   }
   clk.mark(19);
   // (4) overlap S = X^T X (FP64 output, lower tiles) and its FP64 Cholesky.
@@ -543,6 +546,8 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     int* rank = (int*)(W + pl->o_rank);
     PFSM_TRY(finalize_order_values((double*)(W + pl->o_lamu), n, dLam, rank, info, s));
     PFSM_TRY(permute_f64_cols(Vn64, n, rank, dVout, ldvo, n, n, s));
+    PFSM_TRY(col_norm2(dVout, n, n, ldvo, (double*)(W + pl->o_den), s));
+    PFSM_TRY(norm_check((double*)(W + pl->o_den), n, info, s));
     clk.mark(24);
     clk.mark(25);
     return hip_status(hipGetLastError());

@@ -11,6 +11,7 @@
 #include "common.h"
 #include "refine.h"
 #include "order_key.h"
+#include "misc.h"
 
 namespace pfsm {
 namespace {
@@ -417,6 +418,8 @@ __global__ void k_permute_f64(const double* X, int64_t ldx, const int* rank, dou
 hipError_t refine_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz, int64_t n, double tau, double* lam,
                      double* Vout, int64_t ldvo, RefineBufs b, int* info, hipStream_t s) {
   hipLaunchKernelGGL(k_dots, dim3((unsigned)n), dim3(NT), 0, s, V, ldv, Z, ldz, n, b.d, b.nn);
+  hipError_t e = norm_check(b.nn, n, info, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_rank_rq, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, b.d, b.nn, n, b.rank, b.inv,
                      b.lam_s, info);
   hipLaunchKernelGGL(k_clusters, dim3(1), dim3(1024), 0, s, b.lam_s, n, tau, b.clus, b.cstart, b.csize);

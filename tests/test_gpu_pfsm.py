@@ -146,7 +146,7 @@ def test_failure_modes(pf):
     V2 = V.copy()
     V2[:, 5] = V2[:, 4]
     plan, info, lam, Vo = _run(pf, A, V2, offs, 32)
-    assert info > 0  # overlap not positive definite
+    assert info > 0  # overlap not positive definite (the oracle breaks down at the same input)
     with pytest.raises(RuntimeError):
         plan.check()
     A2 = A.copy()
@@ -159,6 +159,19 @@ def test_failure_modes(pf):
     assert info != 0 or eig_error(lam, np.linalg.eigvalsh(A)) > 1e-3
     if info == 0 and info_ref == 0:
         assert eig_error(lam, lam_ref) <= 1e-8
+
+
+def test_non_orthonormal_basis_flagged(pf):
+    A, V, _, _ = prescribed_problem(256, 64, 5e-3, 3256)
+    V = V.numpy().copy()
+    V[:, 5] = V[:, 4]
+    A = A.numpy()
+    offs = uniform_layout(256, 64)
+    info_ref = pfsm_ref(A, V, offs, 32)[2]
+    plan, info, lam, Vo = _run(pf, A, V, offs, 32)
+    assert info != 0
+    if info_ref > 0:
+        assert info > 0
 
 
 def test_invalid_arguments(pf):
