@@ -165,6 +165,14 @@ pfsm_status pfsm_diagnostics(pfsm_plan* plan, const double* dA, int64_t lda, con
  * back-rotation, 24 refinement (mixed precision).  pfsm_timing_end releases the events.
  * Errors: INVALID_ARG, HIP_ERROR. */
 #define PFSM_TIMING_BOUNDS 26
+/* Internal counters of the last solve (instrumentation; synchronises the
+ * device).  out[2p] = sweep at which submatrix p was found converged (0: never),
+ * out[2p+1] = pair problems of submatrix p that needed rotations; then, for
+ * mixed precision, the number of refinement clusters, of clusters with more
+ * than one estimate, and the largest cluster.  *count = 2P + 3.
+ * Errors: INVALID_ARG (capacity < 2P + 3), HIP_ERROR. */
+pfsm_status pfsm_debug_stats(pfsm_plan* plan, const void* dWork, size_t work_bytes, int32_t* out, int32_t capacity,
+                             int32_t* count);
 pfsm_status pfsm_timing_begin(pfsm_plan* plan, int32_t max_solves);
 pfsm_status pfsm_timing_read(pfsm_plan* plan, float* ms, int32_t capacity, int32_t* solves_recorded);
 pfsm_status pfsm_timing_end(pfsm_plan* plan);

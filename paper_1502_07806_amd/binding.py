@@ -71,6 +71,8 @@ def load_library(path: str = LIB_PATH):
     lib.pfsm_diagnostics.restype = ctypes.c_int
     lib.pfsm_plan_destroy.argtypes = [vp]
     lib.pfsm_plan_destroy.restype = None
+    lib.pfsm_debug_stats.argtypes = [vp, vp, sz, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
+    lib.pfsm_debug_stats.restype = ctypes.c_int
     lib.pfsm_timing_begin.argtypes = [vp, i32]
     lib.pfsm_timing_begin.restype = ctypes.c_int
     lib.pfsm_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
@@ -194,6 +196,18 @@ class Plan:
                                                 self.workspace_bytes, _stream_handle()))
         o = out.cpu()
         return float(o[0]), float(o[1])
+
+    def debug_stats(self):
+        """Counters of the last solve: per-submatrix sweeps and rotating pair problems, refinement clusters."""
+        P = len(self.part_offsets) - 1
+        cap = 2 * P + 3
+        buf = (ctypes.c_int32 * cap)()
+        cnt = ctypes.c_int32()
+        _check(load_library().pfsm_debug_stats(self._h, self._work.data_ptr(), self.workspace_bytes, buf, cap,
+                                               ctypes.byref(cnt)))
+        v = list(buf)
+        return {"converged_sweep": v[0:2 * P:2], "rotating_pairs": v[1:2 * P:2],
+                "clusters": v[2 * P], "multi_clusters": v[2 * P + 1], "max_cluster": v[2 * P + 2]}
 
     # -- stage timing (instrumentation for benchmarks)
     TIMING_BOUNDS = 26

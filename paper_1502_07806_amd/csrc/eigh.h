@@ -18,6 +18,7 @@ struct EighBatch {
   double* Rw;              // [P][nb/2][2b][2b] pair rotations of the current round
   int* rflag;              // [P][nb/2] 1 if the pair's rotation is not the identity
   int* state;              // [P][2] {done, rotated-this-sweep}
+  int* stats;              // [P][2] {sweep found converged (0: not), rotating pair problems}
   int* sel;                // [P][Mp] ascending rank -> local index
   const int64_t* wstart;   // [P] first row/column of the submatrix in At
   const int32_t* wsize;    // [P] order M_p

@@ -74,6 +74,8 @@ __global__ void gather_windows(EighBatch e, const double* __restrict__ At, int64
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     e.state[2 * p] = 0;      // done flag
     e.state[2 * p + 1] = 0;  // rotations in current sweep
+    e.stats[2 * p] = 0;      // sweep at which the submatrix was found converged
+    e.stats[2 * p + 1] = 0;  // pair problems that needed rotations, all sweeps
   }
 }
 
@@ -81,7 +83,10 @@ __global__ void gather_windows(EighBatch e, const double* __restrict__ At, int64
 __global__ void sweep_begin(EighBatch e, int sweep) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= e.P) return;
-  if (sweep > 0 && e.state[2 * p + 1] == 0) e.state[2 * p] = 1;
+  if (sweep > 0 && e.state[2 * p + 1] == 0 && !e.state[2 * p]) {
+    e.state[2 * p] = 1;
+    e.stats[2 * p] = sweep;
+  }
   e.state[2 * p + 1] = 0;
 }
 
@@ -181,6 +186,7 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   if (tid == 0) {
     *flagR = 1;
     atomicOr(&e.state[2 * p + 1], 1);
+    atomicAdd(&e.stats[2 * p + 1], 1);
   }
 }
 

@@ -38,6 +38,7 @@ struct pfsm_plan {
   // stage timing
   std::vector<hipEvent_t> tev;
   int t_max = 0, t_count = 0;
+  size_t o_stats = 0;
   size_t o_At, o_b0, o_b1, o_Bw, o_Uw, o_Rw, o_rflag, o_state, o_sel, o_T, o_part, o_eps, o_lamu, o_sgn, o_rank,
       o_scal, o_glo, o_ghi, o_den, total;
   // mixed-precision workspace (byte offsets)
@@ -80,6 +81,19 @@ struct StageClock {
     hipError_t _e = (expr);                     \
     if (_e != hipSuccess) return PFSM_HIP_ERROR; \
   } while (0)
+
+// Submatrix eigensolver arguments: every pointer into the plan's workspace layout.
+EighBatch eigh_batch(const pfsm_plan* pl, char* W, int* info, const double* scal) {
+  EighBatch e = {};
+  e.P = pl->P; e.Mp = pl->Mp; e.nb = pl->nb; e.inner_max_sweeps = 30;
+  e.Bw = (double*)(W + pl->o_Bw); e.Uw = (double*)(W + pl->o_Uw); e.Rw = (double*)(W + pl->o_Rw);
+  e.rflag = (int*)(W + pl->o_rflag); e.state = (int*)(W + pl->o_state); e.sel = (int*)(W + pl->o_sel);
+  e.stats = (int*)(W + pl->o_stats);
+  e.wstart = pl->d_wstart; e.wsize = pl->d_wsize; e.offset = pl->d_offset; e.part_start = pl->d_part_start;
+  e.info = info;
+  e.scal = scal;
+  return e;
+}
 
 }  // namespace
 
@@ -224,6 +238,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   pl->o_Rw = w; w = align256(w + (size_t)P * (pl->nb / 2) * B2 * B2 * sizeof(double));
   pl->o_rflag = w; w = align256(w + (size_t)P * (pl->nb / 2) * sizeof(int));
   pl->o_state = w; w = align256(w + (size_t)P * 2 * sizeof(int));
+  pl->o_stats = w; w = align256(w + (size_t)P * 2 * sizeof(int));
   pl->o_sel = w; w = align256(w + (size_t)P * pl->Mp * sizeof(int));
   pl->o_T = w; w = align256(w + (size_t)((n + CHOL_NB - 1) / CHOL_NB) * CHOL_NB * CHOL_NB * sizeof(double));
   pl->o_part = w; w = align256(w + (size_t)std::max<int64_t>(tiles_m, 3) * n * sizeof(double));
@@ -325,13 +340,7 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
   clk.mark(2);
 
   // (3) submatrix eigenproblems, (4) zero-padded start vectors and shifts.
-  EighBatch e = {};
-  e.P = pl->P; e.Mp = pl->Mp; e.nb = pl->nb; e.inner_max_sweeps = 30;
-  e.Bw = (double*)(W + pl->o_Bw); e.Uw = (double*)(W + pl->o_Uw); e.Rw = (double*)(W + pl->o_Rw);
-  e.rflag = (int*)(W + pl->o_rflag); e.state = (int*)(W + pl->o_state); e.sel = (int*)(W + pl->o_sel);
-  e.wstart = pl->d_wstart; e.wsize = pl->d_wsize; e.offset = pl->d_offset; e.part_start = pl->d_part_start;
-  e.info = info;
-  e.scal = scal;
+  EighBatch e = eigh_batch(pl, W, info, scal);
   PFSM_TRY(eigh_batched_run(e, At, n, pl->max_sweeps, s));
   double* X = buf1;
   double* Wt = buf0;
@@ -465,12 +474,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
                             info, s));
   clk.mark(2);
   // (2) submatrix eigensolver (FP64) and start vectors.
-  EighBatch e = {};
-  e.P = pl->P; e.Mp = pl->Mp; e.nb = pl->nb; e.inner_max_sweeps = 30;
-  e.Bw = (double*)(W + pl->o_Bw); e.Uw = (double*)(W + pl->o_Uw); e.Rw = (double*)(W + pl->o_Rw);
-  e.rflag = (int*)(W + pl->o_rflag); e.state = (int*)(W + pl->o_state); e.sel = (int*)(W + pl->o_sel);
-  e.wstart = pl->d_wstart; e.wsize = pl->d_wsize; e.offset = pl->d_offset; e.part_start = pl->d_part_start;
-  e.info = info; e.scal = scal;
+  EighBatch e = eigh_batch(pl, W, info, scal);
   PFSM_TRY(eigh_batched_run(e, At64, n, pl->max_sweeps, s));
   PFSM_TRY(embed_start_vectors(e, B64a, n, eps, n, s));
   PFSM_TRY(f64_to_f32(B64a, n, X32, n, n, n, s));
@@ -566,6 +570,40 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   }
   clk.mark(25);
   return hip_status(hipGetLastError());
+}
+
+pfsm_status pfsm_debug_stats(pfsm_plan* pl, const void* dWork, size_t work_bytes, int32_t* out, int32_t capacity,
+                             int32_t* count) {
+  if (!pl || !dWork || !out || !count || work_bytes < pl->total) return PFSM_INVALID_ARG;
+  const int64_t n = pl->n;
+  const int32_t need = 2 * pl->P + 3;
+  if (capacity < need) return PFSM_INVALID_ARG;
+  if (hipDeviceSynchronize() != hipSuccess) return PFSM_HIP_ERROR;
+  if (hipMemcpy(out, (const char*)dWork + pl->o_stats, 2 * pl->P * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return PFSM_HIP_ERROR;
+  out[2 * pl->P] = out[2 * pl->P + 1] = out[2 * pl->P + 2] = 0;
+  if (pl->precision == PFSM_PREC_MIXED_BF16) {
+    // refinement clusters: count, then the largest cluster size
+    const double* rb = (const double*)((const char*)dWork + pl->m_rb);
+    int cnt = 0;
+    if (hipMemcpy(&cnt, (const int*)(rb + 7 * n), sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+      return PFSM_HIP_ERROR;
+    std::vector<int> sizes((size_t)std::max(cnt, 0));
+    if (cnt > 0 && hipMemcpy(sizes.data(), (const int*)(rb + 6 * n), cnt * sizeof(int), hipMemcpyDeviceToHost) !=
+                       hipSuccess)
+      return PFSM_HIP_ERROR;
+    int multi = 0, mx = 0;
+    for (int v : sizes) {
+      multi += v > 1;
+      mx = std::max(mx, v);
+    }
+    out[2 * pl->P] = cnt;
+    out[2 * pl->P + 1] = multi;
+    out[2 * pl->P + 2] = mx;
+  }
+  *count = need;
+  return PFSM_OK;
 }
 
 pfsm_status pfsm_timing_begin(pfsm_plan* pl, int32_t max_solves) {
