@@ -137,6 +137,41 @@ pfsm_status pfsm_backward(pfsm_plan* plan, const double* dLambda, const double* 
                           double* dGradA, int64_t ldga, void* dWork, size_t work_bytes, int32_t* dInfo,
                           void* stream);
 
+/* Batched plans: `count` independent instances (k-points / spins), each with
+ * its own descriptor (order, slices, options).  pfsm_workspace_size reports
+ * the sum of the instances' workspaces.  Errors as pfsm_plan_create, for the
+ * first instance that fails. */
+pfsm_status pfsm_plan_create_batched(pfsm_plan** plan, const pfsm_desc* descs, int32_t count);
+
+/* One PFSM step for every instance of a batched plan.  The pointer and
+ * leading-dimension arrays are HOST arrays of length count (device pointers
+ * inside, read during the call); dInfo points to count device int32 words.
+ * The instances are enqueued largest first over internal streams forked from
+ * and joined back into `stream` with events, so the call is capturable: a
+ * hipStreamBeginCapture / EndCapture around it yields one graph whose
+ * branches run the instances concurrently.  Errors: INVALID_ARG (non-batched
+ * plan, null pointer, bad leading dimension; nothing is enqueued),
+ * WORKSPACE_TOO_SMALL, HIP_ERROR. */
+pfsm_status pfsm_solve_batched(pfsm_plan* plan, const double* const* dA, const int64_t* lda,
+                               const double* const* dVprev, const int64_t* ldv, double* const* dLambda,
+                               double* const* dVout, const int64_t* ldvo, void* dWork, size_t work_bytes,
+                               int32_t* dInfo, void* stream);
+
+/* Number of instances of a batched plan (0 for a single plan or NULL). */
+int32_t pfsm_batch_count(const pfsm_plan* plan);
+
+/* Tile autotuning of the split-BF16 products (mixed precision): times each
+ * tile configuration on an N x N x N product in the plan's workspace (on
+ * `stream`, synchronising it) and keeps the fastest in the plan (for a batched
+ * plan, per instance).  *chosen (nullable) receives the configuration, -1 when
+ * nothing was tuned (FP64 plans, batched plans).  Call it outside any stream
+ * capture.  Errors: INVALID_ARG, HIP_ERROR. */
+pfsm_status pfsm_autotune(pfsm_plan* plan, void* dWork, size_t work_bytes, int32_t* chosen, void* stream);
+
+/* Fix the split-BF16 tile configuration (-1: library default, 0..2: see
+ * pfsm_autotune) for a plan and its instances.  Errors: INVALID_ARG. */
+pfsm_status pfsm_set_tile_config(pfsm_plan* plan, int32_t cfg);
+
 /* Release the plan and its device table (synchronises the device first). */
 void pfsm_plan_destroy(pfsm_plan* plan);
 

@@ -71,6 +71,18 @@ def load_library(path: str = LIB_PATH):
     lib.pfsm_diagnostics.restype = ctypes.c_int
     lib.pfsm_plan_destroy.argtypes = [vp]
     lib.pfsm_plan_destroy.restype = None
+    lib.pfsm_plan_create_batched.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PfsmDesc), i32]
+    lib.pfsm_plan_create_batched.restype = ctypes.c_int
+    lib.pfsm_solve_batched.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
+                                       ctypes.POINTER(i64), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                       ctypes.POINTER(i64), vp, sz, vp, vp]
+    lib.pfsm_solve_batched.restype = ctypes.c_int
+    lib.pfsm_batch_count.argtypes = [vp]
+    lib.pfsm_batch_count.restype = i32
+    lib.pfsm_autotune.argtypes = [vp, vp, sz, ctypes.POINTER(i32), vp]
+    lib.pfsm_autotune.restype = ctypes.c_int
+    lib.pfsm_set_tile_config.argtypes = [vp, i32]
+    lib.pfsm_set_tile_config.restype = ctypes.c_int
     lib.pfsm_debug_stats.argtypes = [vp, vp, sz, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
     lib.pfsm_debug_stats.restype = ctypes.c_int
     lib.pfsm_timing_begin.argtypes = [vp, i32]
@@ -105,6 +117,14 @@ def _stream_handle() -> int:
     return torch.cuda.current_stream().cuda_stream
 
 
+def _desc(n, part_offsets, halo=-1, iterations=3, fs_power=2, alpha=0.0, shift_mode="fixed", precision="fp64",
+          max_sweeps=0, refine=True):
+    offs = (ctypes.c_int64 * len(part_offsets))(*[int(x) for x in part_offsets])
+    d = PfsmDesc(int(n), len(part_offsets) - 1, offs, int(halo), int(iterations), int(fs_power), float(alpha),
+                 PFSM_SHIFT[shift_mode], PFSM_PREC[precision], int(max_sweeps), 0 if refine else FLAG_NO_REFINE)
+    return d, offs  # keep offs alive while d is used
+
+
 class Plan:
     """A PFSM plan: partition layout, submatrix policy and iteration options for order n."""
 
@@ -112,10 +132,8 @@ class Plan:
                  fs_power: int = 2, alpha: float = 0.0, shift_mode: str = "fixed", precision: str = "fp64",
                  max_sweeps: int = 0, refine: bool = True):
         lib = load_library()
-        offs = (ctypes.c_int64 * len(part_offsets))(*[int(x) for x in part_offsets])
-        d = PfsmDesc(int(n), len(part_offsets) - 1, offs, int(halo), int(iterations), int(fs_power), float(alpha),
-                     PFSM_SHIFT[shift_mode], PFSM_PREC[precision], int(max_sweeps),
-                     0 if refine else FLAG_NO_REFINE)
+        d, _keep = _desc(n, part_offsets, halo, iterations, fs_power, alpha, shift_mode, precision, max_sweeps,
+                         refine)
         h = ctypes.c_void_p()
         _check(lib.pfsm_plan_create(ctypes.byref(h), ctypes.byref(d)))
         self._h = h
@@ -197,6 +215,17 @@ class Plan:
         o = out.cpu()
         return float(o[0]), float(o[1])
 
+    def autotune(self) -> int:
+        """Pick the fastest split-BF16 tile configuration for this plan (mixed precision); returns it (-1: none)."""
+        work = self._workspace(torch.device("cuda", torch.cuda.current_device()))
+        c = ctypes.c_int32()
+        _check(load_library().pfsm_autotune(self._h, work.data_ptr(), self.workspace_bytes, ctypes.byref(c),
+                                            _stream_handle()))
+        return int(c.value)
+
+    def set_tile_config(self, cfg: int):
+        _check(load_library().pfsm_set_tile_config(self._h, int(cfg)))
+
     def debug_stats(self):
         """Counters of the last solve: per-submatrix sweeps and rotating pair problems, refinement clusters."""
         P = len(self.part_offsets) - 1
@@ -232,6 +261,85 @@ class Plan:
 
     def timing_end(self):
         _check(load_library().pfsm_timing_end(self._h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.pfsm_plan_destroy(h)
+            self._h = None
+
+
+class BatchedPlan:
+    """Many independent PFSM instances (e.g. k-points / spins) solved by one call.
+
+    specs: list of dicts with the Plan keyword arguments plus "n" and "part_offsets".
+    The call is capturable into one CUDA/HIP graph (torch.cuda.graph)."""
+
+    def __init__(self, specs):
+        lib = load_library()
+        self.count = len(specs)
+        descs = (PfsmDesc * self.count)()
+        keep = []
+        for i, sp in enumerate(specs):
+            sp = dict(sp)
+            d, k = _desc(sp.pop("n"), sp.pop("part_offsets"), **sp)
+            descs[i] = d
+            keep.append(k)
+        h = ctypes.c_void_p()
+        _check(lib.pfsm_plan_create_batched(ctypes.byref(h), descs, self.count))
+        self._h = h
+        self.n = [int(sp["n"]) for sp in specs]
+        sz = ctypes.c_size_t()
+        _check(lib.pfsm_workspace_size(h, ctypes.byref(sz)))
+        self.workspace_bytes = int(sz.value)
+        self._work = None
+        self.info = None
+
+    def _workspace(self, device):
+        if self._work is None or self._work.device != device:
+            self._work = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+            self.info = torch.zeros(self.count, dtype=torch.int32, device=device)
+        return self._work
+
+    def outputs(self, device):
+        """Allocate (lams, Vs) output tensors (column-major eigenvector matrices)."""
+        lams = [torch.empty(n, dtype=torch.float64, device=device) for n in self.n]
+        Vs = [torch.empty((n, n), dtype=torch.float64, device=device).t() for n in self.n]
+        return lams, Vs
+
+    def solve(self, As, Vprevs, out=None, check: bool = True):
+        dev = As[0].device
+        work = self._workspace(dev)
+        cols = [_colmajor(A) for A in As]
+        vcols = [_colmajor(V) for V in Vprevs]
+        lams, Vs = out if out is not None else self.outputs(dev)
+        for V in Vs:
+            if V.stride(0) != 1:
+                raise ValueError("output eigenvector matrices must be column-major")
+        c = self.count
+        P = ctypes.c_void_p * c
+        I = ctypes.c_int64 * c
+        _check(load_library().pfsm_solve_batched(
+            self._h, P(*[a.data_ptr() for a, _ in cols]), I(*[l for _, l in cols]),
+            P(*[v.data_ptr() for v, _ in vcols]), I(*[l for _, l in vcols]),
+            P(*[x.data_ptr() for x in lams]), P(*[x.data_ptr() for x in Vs]), I(*[x.stride(1) for x in Vs]),
+            work.data_ptr(), self.workspace_bytes, self.info.data_ptr(), _stream_handle()))
+        self._keep = (cols, vcols)  # inputs may be temporaries; keep them alive until the next call
+        if check:
+            self.check()
+        return lams, Vs
+
+    def check(self):
+        codes = self.info.cpu().tolist()
+        bad = [(i, c) for i, c in enumerate(codes) if c != 0]
+        if bad:
+            raise RuntimeError("pfsm batched device info (instance, code): %s" % bad[:8])
+
+    def autotune(self):
+        work = self._workspace(torch.device("cuda", torch.cuda.current_device()))
+        c = ctypes.c_int32()
+        _check(load_library().pfsm_autotune(self._h, work.data_ptr(), self.workspace_bytes, ctypes.byref(c),
+                                            _stream_handle()))
 
     def __del__(self):
         h = getattr(self, "_h", None)

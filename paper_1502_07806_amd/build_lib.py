@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpfsm.so")
+HOOKS_LIB = os.path.join(HERE, "libpfsm_testhooks.so")
 ARCH = "gfx950"
 
 CFLAGS = [
@@ -44,19 +45,27 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _link(objs, out):
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr[-4000:])
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = True) -> str:
+    """Build libpfsm.so (the product) and libpfsm_testhooks.so (same objects plus
+    C entry points to internal kernels, used only by kernel-level tests)."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    hooks = sorted(glob.glob(os.path.join(CSRC, "testhooks", "*.hip")))
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs) + len(hooks))) as ex:
+        objs = list(ex.map(_compile, srcs + hooks))
+    _link(objs[:len(srcs)], LIB)
+    _link(objs, HOOKS_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", HOOKS_LIB)
     return LIB
 
 

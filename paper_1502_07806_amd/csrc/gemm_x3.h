@@ -44,8 +44,13 @@ struct X3Args {
   double* part;
   const int32_t* krange;            // optional [tiles_n][2] (multiples of 32)
   int tiles;                        // X3Tiles
-  int kprefix_skip;                 // X3_KPREFIX: K range [0, (tn+1)*BN) (right operand upper triangular)
+  int kprefix_skip;                 // unused
+  int cfg;                          // tile configuration (see gemm_x3.hip); -1 = library default
 };
+
+constexpr int X3_NUM_CFG = 3;
+extern int x3_default_cfg;
+hipError_t x3_init();  // once per process and device, before the first split-BF16 launch
 
 hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s);
 

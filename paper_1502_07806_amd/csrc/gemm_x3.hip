@@ -14,10 +14,17 @@ namespace pfsm {
 namespace {
 
 constexpr int BM = X3_BM, BN = X3_BN, BK = X3_BK;
-constexpr int NT = 512;
-constexpr int WR = 4, WC = 2;             // MFMA blocks per wave (rows, columns)
 constexpr int ROWB = 144;                 // LDS bytes per packed row (128 + 16 pad)
 constexpr int TILE_BYTES = BM * ROWB;     // 36864 per operand per stage
+
+// Tile configurations: waves per workgroup and MFMA blocks (32x32) per wave.
+//   CFG 0: 8 waves in 2 x 4, wave tile 128 x 64  (two waves per SIMD)
+//   CFG 1: 4 waves in 2 x 2, wave tile 128 x 128 (one wave per SIMD, least LDS traffic)
+//   CFG 2: 8 waves in 4 x 2, wave tile 64 x 128
+template <int CFG> struct X3Cfg;
+template <> struct X3Cfg<0> { static constexpr int NT = 512, WGR = 2, WR = 4, WC = 2; };
+template <> struct X3Cfg<1> { static constexpr int NT = 256, WGR = 2, WR = 4, WC = 4; };
+template <> struct X3Cfg<2> { static constexpr int NT = 512, WGR = 4, WR = 2, WC = 4; };
 
 __device__ inline int xcd_remap(int b, int total) {
   if (total % 8 != 0) return b;
@@ -37,12 +44,13 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline v8bf as_bf(u32x4 v) { return __builtin_bit_cast(v8bf, v); }
 
-template <int EPI>
-__global__ __launch_bounds__(NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, int tiles_n) {
+template <int EPI, int CFG>
+__global__ __launch_bounds__(X3Cfg<CFG>::NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, int tiles_n) {
+  constexpr int NT = X3Cfg<CFG>::NT, WGR = X3Cfg<CFG>::WGR, WR = X3Cfg<CFG>::WR, WC = X3Cfg<CFG>::WC;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   unsigned char* As = lds;                       // [2][BM][ROWB]
   unsigned char* Bs = lds + 2 * TILE_BYTES;      // [2][BN][ROWB]
-  __shared__ double red[2][BN];
+  __shared__ double red[WGR][BN];
 
   int tm, tn;
   {
@@ -65,7 +73,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, i
   }
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wi0 = (wave & 1) * (32 * WR), wj0 = (wave >> 1) * (32 * WC);
+  const int wi0 = (wave % WGR) * (32 * WR), wj0 = (wave / WGR) * (32 * WC);
   const int l32 = lane & 31, lh = lane >> 5;
 
   int64_t kbeg = 0, kend = (g.K + 31) / 32 * 32;
@@ -177,12 +185,15 @@ __global__ __launch_bounds__(NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, i
 #pragma unroll
       for (int jb = 0; jb < WC; ++jb)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) red[wave & 1][wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4)] = cs[jb][r];
+        for (int r = 0; r < 16; ++r) red[wave % WGR][wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4)] = cs[jb][r];
     }
     __syncthreads();
     if (tid < BN) {
       const int64_t gj = n0 + tid;
-      if (gj < g.N) g.part[(int64_t)tm * g.N + gj] = red[0][tid] + red[1][tid];
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < WGR; ++w) sum += red[w][tid];
+      if (gj < g.N) g.part[(int64_t)tm * g.N + gj] = sum;
     }
     return;
   }
@@ -276,21 +287,15 @@ __global__ __launch_bounds__(256) void k_pack(const void* X, int src_double, int
   }
 }
 
-}  // namespace
-
-hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
-  const int tm = (int)((a.M + BM - 1) / BM), tn = (int)((a.N + BN - 1) / BN);
-  if (tm == 0 || tn == 0) return hipSuccess;
-  if ((a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) && tm != tn) return hipErrorInvalidValue;
+template <int CFG>
+hipError_t launch_cfg(int epi, const X3Args& a, int tm, int tn, hipStream_t s) {
   int total = (a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) ? tm * (tm + 1) / 2 : tm * tn;
   const size_t lds = 4 * (size_t)TILE_BYTES;
-  dim3 grid(total), block(NT);
+  dim3 grid(total), block(X3Cfg<CFG>::NT);
   switch (epi) {
-#define X3_CASE(E)                                                                                    \
-  case E:                                                                                             \
-    hipFuncSetAttribute((const void*)gemm_x3_kernel<E>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
-                        (int)lds);                                                                    \
-    hipLaunchKernelGGL(gemm_x3_kernel<E>, grid, block, lds, s, a, tm, tn);                            \
+#define X3_CASE(E)                                                                \
+  case E:                                                                         \
+    hipLaunchKernelGGL((gemm_x3_kernel<E, CFG>), grid, block, lds, s, a, tm, tn); \
     break;
     X3_CASE(X3_STORE)
     X3_CASE(X3_SHIFT)
@@ -301,6 +306,49 @@ hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int CFG>
+hipError_t set_attrs() {
+  const int lds = 4 * TILE_BYTES;
+  hipError_t e = hipSuccess;
+#define X3_ATTR(E)                                                                                        \
+  if (e == hipSuccess)                                                                                    \
+    e = hipFuncSetAttribute((const void*)gemm_x3_kernel<E, CFG>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            lds);
+  X3_ATTR(X3_STORE)
+  X3_ATTR(X3_SHIFT)
+  X3_ATTR(X3_FSUPD)
+  X3_ATTR(X3_ADD)
+  X3_ATTR(X3_RQ)
+#undef X3_ATTR
+  return e;
+}
+
+}  // namespace
+
+int x3_default_cfg = 0;
+
+hipError_t x3_init() {
+  // Dynamic LDS above 64 KiB must be enabled per kernel before the first
+  // launch; done once at plan creation so that solves stay capturable.
+  hipError_t e = set_attrs<0>();
+  if (e == hipSuccess) e = set_attrs<1>();
+  if (e == hipSuccess) e = set_attrs<2>();
+  return e;
+}
+
+hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
+  const int tm = (int)((a.M + BM - 1) / BM), tn = (int)((a.N + BN - 1) / BN);
+  if (tm == 0 || tn == 0) return hipSuccess;
+  if ((a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) && tm != tn) return hipErrorInvalidValue;
+  const int cfg = a.cfg >= 0 ? a.cfg : x3_default_cfg;
+  switch (cfg) {
+    case 0: return launch_cfg<0>(epi, a, tm, tn, s);
+    case 1: return launch_cfg<1>(epi, a, tm, tn, s);
+    case 2: return launch_cfg<2>(epi, a, tm, tn, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P, int64_t ldp,

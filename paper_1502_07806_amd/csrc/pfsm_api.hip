@@ -35,6 +35,12 @@ struct pfsm_plan {
   int32_t* d_krange = nullptr;
   int32_t* d_krange_x3 = nullptr;
   // workspace layout (byte offsets)
+  int x3_cfg = -1;  // split-BF16 GEMM tile configuration (-1: library default), set by pfsm_autotune
+  // batched plans: independent sub-plans solved concurrently on internal streams
+  std::vector<pfsm_plan*> sub;
+  std::vector<size_t> sub_off;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> fork_ev, join_ev;
   // stage timing
   std::vector<hipEvent_t> tev;
   int t_max = 0, t_count = 0;
@@ -200,7 +206,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   size_t o_ps = tb; tb = align256(tb + P * sizeof(int64_t));
   size_t o_kr = tb; tb = align256(tb + pl->krange.size() * sizeof(int32_t));
   size_t o_k3 = tb; tb = align256(tb + pl->krange_x3.size() * sizeof(int32_t));
-  if (hipGetDevice(&pl->device) != hipSuccess || hipMalloc(&pl->dtab, tb) != hipSuccess) {
+  if (hipGetDevice(&pl->device) != hipSuccess || x3_init() != hipSuccess || hipMalloc(&pl->dtab, tb) != hipSuccess) {
     delete pl;
     return PFSM_HIP_ERROR;
   }
@@ -279,6 +285,11 @@ pfsm_status pfsm_workspace_size(const pfsm_plan* pl, size_t* bytes) {
 void pfsm_plan_destroy(pfsm_plan* pl) {
   if (!pl) return;
   pfsm_timing_end(pl);
+  if (!pl->sub.empty() || !pl->streams.empty()) (void)hipDeviceSynchronize();
+  for (pfsm_plan* q : pl->sub) pfsm_plan_destroy(q);
+  for (hipStream_t st : pl->streams) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : pl->fork_ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : pl->join_ev) (void)hipEventDestroy(ev);
   if (pl->dtab) {
     (void)hipDeviceSynchronize();
     (void)hipFree(pl->dtab);
@@ -292,6 +303,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
 pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv, double* dLam,
                        double* dVout, int64_t ldvo, void* dWork, size_t work_bytes, int32_t* dInfo, void* stream) {
   if (!pl || !dA || !dV || !dLam || !dVout || !dWork || !dInfo) return PFSM_INVALID_ARG;
+  if (!pl->sub.empty()) return PFSM_INVALID_ARG;  // batched plans go through pfsm_solve_batched
   const int64_t n = pl->n;
   if (lda < n || ldv < n || ldvo < n) return PFSM_INVALID_ARG;
   if (((uintptr_t)dWork) % 256 != 0) return PFSM_INVALID_ARG;
@@ -452,7 +464,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
                 int c_double) {
     X3Args g = {};
     g.M = M; g.N = N; g.K = K; g.Ap = Ap; g.ldap = ldp; g.Bp = Bp; g.ldbp = ldp; g.C = C; g.ldc = ldc;
-    g.c_double = c_double; g.alpha = 1.0;
+    g.c_double = c_double; g.alpha = 1.0; g.cfg = pl->x3_cfg;
     return g;
   };
 
@@ -603,6 +615,146 @@ pfsm_status pfsm_debug_stats(pfsm_plan* pl, const void* dWork, size_t work_bytes
     out[2 * pl->P + 2] = mx;
   }
   *count = need;
+  return PFSM_OK;
+}
+
+
+pfsm_status pfsm_plan_create_batched(pfsm_plan** out, const pfsm_desc* descs, int32_t count) {
+  if (!out || !descs || count < 1 || count > 4096) return PFSM_INVALID_ARG;
+  *out = nullptr;
+  pfsm_plan* pl = new (std::nothrow) pfsm_plan();
+  if (!pl) return PFSM_OOM;
+  size_t w = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    pfsm_plan* q = nullptr;
+    pfsm_status st = pfsm_plan_create(&q, &descs[i]);
+    if (st != PFSM_OK) {
+      pfsm_plan_destroy(pl);
+      return st;
+    }
+    pl->sub.push_back(q);
+    pl->sub_off.push_back(w);
+    w = align256(w + q->total);
+  }
+  pl->total = w;
+  pl->n = 0;
+  if (hipGetDevice(&pl->device) != hipSuccess) {
+    pfsm_plan_destroy(pl);
+    return PFSM_HIP_ERROR;
+  }
+  // Instances run concurrently on a few internal streams (default priority),
+  // joined back into the caller's stream with events, so that a stream
+  // capture of pfsm_solve_batched yields one graph with parallel branches.
+  const int ns = std::min<int32_t>(count, 4);
+  for (int k = 0; k < ns; ++k) {
+    hipStream_t st;
+    hipEvent_t a, b;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+      pfsm_plan_destroy(pl);
+      return PFSM_HIP_ERROR;
+    }
+    pl->streams.push_back(st);
+    pl->fork_ev.push_back(a);
+    pl->join_ev.push_back(b);
+  }
+  *out = pl;
+  return PFSM_OK;
+}
+
+pfsm_status pfsm_solve_batched(pfsm_plan* pl, const double* const* dA, const int64_t* lda, const double* const* dV,
+                               const int64_t* ldv, double* const* dLam, double* const* dVout, const int64_t* ldvo,
+                               void* dWork, size_t work_bytes, int32_t* dInfo, void* stream) {
+  if (!pl || pl->sub.empty() || !dA || !lda || !dV || !ldv || !dLam || !dVout || !ldvo || !dWork || !dInfo)
+    return PFSM_INVALID_ARG;
+  if (((uintptr_t)dWork) % 256 != 0) return PFSM_INVALID_ARG;
+  if (work_bytes < pl->total) return PFSM_WORKSPACE_TOO_SMALL;
+  const int count = (int)pl->sub.size();
+  // validate every instance before enqueuing anything
+  for (int i = 0; i < count; ++i) {
+    const int64_t n = pl->sub[i]->n;
+    if (!dA[i] || !dV[i] || !dLam[i] || !dVout[i] || lda[i] < n || ldv[i] < n || ldvo[i] < n) return PFSM_INVALID_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int ns = (int)pl->streams.size();
+  for (int k = 0; k < ns; ++k) {
+    PFSM_TRY(hipEventRecord(pl->fork_ev[k], s));
+    PFSM_TRY(hipStreamWaitEvent(pl->streams[k], pl->fork_ev[k], 0));
+  }
+  // largest instances first, round-robin over the streams
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pl->sub[a]->n > pl->sub[b]->n; });
+  for (int t = 0; t < count; ++t) {
+    const int i = order[t];
+    pfsm_status st = pfsm_solve(pl->sub[i], dA[i], lda[i], dV[i], ldv[i], dLam[i], dVout[i], ldvo[i],
+                                (char*)dWork + pl->sub_off[i], pl->sub[i]->total, dInfo + i, pl->streams[t % ns]);
+    if (st != PFSM_OK) return st;
+  }
+  for (int k = 0; k < ns; ++k) {
+    PFSM_TRY(hipEventRecord(pl->join_ev[k], pl->streams[k]));
+    PFSM_TRY(hipStreamWaitEvent(s, pl->join_ev[k], 0));
+  }
+  return PFSM_OK;
+}
+
+int32_t pfsm_batch_count(const pfsm_plan* pl) { return pl ? (int32_t)pl->sub.size() : 0; }
+
+// Tile autotuning for the split-BF16 products: time each configuration of
+// the N x N x N product on the plan's workspace and keep the fastest.
+pfsm_status pfsm_autotune(pfsm_plan* pl, void* dWork, size_t work_bytes, int32_t* chosen, void* stream) {
+  if (!pl || !dWork || work_bytes < pl->total) return PFSM_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (!pl->sub.empty()) {
+    for (size_t i = 0; i < pl->sub.size(); ++i) {
+      pfsm_status st = pfsm_autotune(pl->sub[i], (char*)dWork + pl->sub_off[i], pl->sub[i]->total, nullptr, stream);
+      if (st != PFSM_OK) return st;
+    }
+    if (chosen) *chosen = -1;
+    return PFSM_OK;
+  }
+  if (pl->precision != PFSM_PREC_MIXED_BF16) {
+    if (chosen) *chosen = -1;
+    return PFSM_OK;
+  }
+  const int64_t n = pl->n;
+  const int64_t ldp = x3_row_stride(n);
+  char* W = (char*)dWork;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PFSM_HIP_ERROR;
+  // operands: zero-filled packed buffers (timing does not depend on the values)
+  PFSM_TRY(hipMemsetAsync(W + pl->m_Apk, 0, (size_t)n * ldp * sizeof(bf16_t), s));
+  PFSM_TRY(hipMemsetAsync(W + pl->m_Vpk, 0, (size_t)n * ldp * sizeof(bf16_t), s));
+  float best = 1e30f;
+  int best_cfg = 0;
+  for (int cfg = 0; cfg < X3_NUM_CFG; ++cfg) {
+    X3Args g = {};
+    g.M = n; g.N = n; g.K = n; g.Ap = (bf16_t*)(W + pl->m_Apk); g.ldap = ldp; g.Bp = (bf16_t*)(W + pl->m_Vpk);
+    g.ldbp = ldp; g.C = W + pl->m_Y32; g.ldc = n; g.alpha = 1.0; g.cfg = cfg;
+    PFSM_TRY(gemm_x3(X3_STORE, g, s));  // warm-up
+    PFSM_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < 3; ++r) PFSM_TRY(gemm_x3(X3_STORE, g, s));
+    PFSM_TRY(hipEventRecord(e1, s));
+    PFSM_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    PFSM_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_cfg = cfg;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  pl->x3_cfg = best_cfg;
+  if (chosen) *chosen = best_cfg;
+  return PFSM_OK;
+}
+
+pfsm_status pfsm_set_tile_config(pfsm_plan* pl, int32_t cfg) {
+  if (!pl || cfg < -1 || cfg >= X3_NUM_CFG) return PFSM_INVALID_ARG;
+  pl->x3_cfg = cfg;
+  for (pfsm_plan* q : pl->sub) q->x3_cfg = cfg;
   return PFSM_OK;
 }
 

@@ -1,0 +1,44 @@
+// Test hooks: C entry points to internal kernels for kernel-level parity tests
+// and microbenchmarks.  Linked only into libpfsm_testhooks.so, never into the
+// product library libpfsm.so.
+#include "../common.h"
+#include "../gemm_x3.h"
+
+using namespace pfsm;
+
+extern "C" {
+
+int pfsm_test_gemm_f64(int ta, int tb, int epi, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                       const double* B, int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
+                       const double* eps, const double* D, int64_t ldd, double* part, int lower_only, void* stream) {
+  GemmArgs g = {};
+  g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta; g.eps = eps; g.D = D; g.ldd = ldd; g.part = part; g.lower_only = lower_only;
+  return (int)gemm_f64(ta != 0, tb != 0, epi, g, (hipStream_t)stream);
+}
+
+int pfsm_test_pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, void* P,
+                      int64_t ldp, void* stream) {
+  return (int)pack_x3(X, src_double, m, n, ldx, flags, (bf16_t*)P, ldp, (hipStream_t)stream);
+}
+
+int pfsm_test_gemm_x3(int epi, int cfg, int tiles, int64_t M, int64_t N, int64_t K, const void* Ap, int64_t ldap,
+                      const void* Bp, int64_t ldbp, void* C, int64_t ldc, int c_double, double alpha, double beta,
+                      const float* B32, int64_t ldb32, const void* D, int64_t ldd, int d_double, const double* eps,
+                      double* part, void* stream) {
+  X3Args g = {};
+  g.M = M; g.N = N; g.K = K; g.Ap = (const bf16_t*)Ap; g.ldap = ldap; g.Bp = (const bf16_t*)Bp; g.ldbp = ldbp;
+  g.C = C; g.ldc = ldc; g.c_double = c_double; g.alpha = alpha; g.beta = beta; g.B32 = B32; g.ldb32 = ldb32;
+  g.D = D; g.ldd = ldd; g.d_double = d_double; g.eps = eps; g.part = part; g.tiles = tiles; g.cfg = cfg;
+  static bool init = false;
+  if (!init) {
+    hipError_t e = x3_init();
+    if (e != hipSuccess) return (int)e;
+    init = true;
+  }
+  return (int)gemm_x3(epi, g, (hipStream_t)stream);
+}
+
+int64_t pfsm_test_x3_row_stride(int64_t K) { return x3_row_stride(K); }
+
+}  // extern "C"

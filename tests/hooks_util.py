@@ -1,0 +1,45 @@
+"""ctypes access to libpfsm_testhooks.so (internal kernels, tests only)."""
+import ctypes
+import os
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HOOKS = os.path.join(ROOT, "paper_1502_07806_amd", "libpfsm_testhooks.so")
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(HOOKS):
+            raise RuntimeError("libpfsm_testhooks.so missing: run python -m paper_1502_07806_amd.build_lib")
+        L = ctypes.CDLL(HOOKS)
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        L.pfsm_test_gemm_f64.argtypes = [i32, i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, dbl, dbl, vp, vp,
+                                         i64, vp, i32, vp]
+        L.pfsm_test_gemm_f64.restype = i32
+        L.pfsm_test_pack_x3.argtypes = [vp, i32, i64, i64, i64, i32, vp, i64, vp]
+        L.pfsm_test_pack_x3.restype = i32
+        L.pfsm_test_gemm_x3.argtypes = [i32, i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, dbl, dbl, vp,
+                                        i64, vp, i64, i32, vp, vp, vp]
+        L.pfsm_test_gemm_x3.restype = i32
+        L.pfsm_test_x3_row_stride.argtypes = [i64]
+        L.pfsm_test_x3_row_stride.restype = i64
+        _lib = L
+    return _lib
+
+
+def bf16_round(x):
+    """Round-to-nearest-even to bfloat16 (as float32 values)."""
+    x = np.asarray(x, np.float32)
+    b = x.view(np.uint32).astype(np.uint64)
+    r = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def split_hi_lo(x):
+    x = np.asarray(x, np.float64)
+    hi = bf16_round(x.astype(np.float32)).astype(np.float64)
+    lo = bf16_round((x - hi).astype(np.float32)).astype(np.float64)
+    return hi, lo

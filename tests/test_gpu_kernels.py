@@ -1,0 +1,136 @@
+"""Kernel-level parity (through libpfsm_testhooks.so): the FP64 MFMA GEMM in
+all transpose combinations and epilogues against NumPy FP64 products, and
+the split-BF16 GEMM against an FP64 product of the same split operands, on
+ragged shapes that are not tile multiples."""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from hooks_util import lib, split_hi_lo  # noqa: E402
+
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    lib()
+    return torch.device("cuda:0")
+
+
+def _cm(x, dev):
+    """column-major device copy of a 2-D numpy array"""
+    return torch.from_numpy(np.asarray(x)).to(dev).t().contiguous().t()
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("M,N,K", [(129, 257, 70), (300, 1, 33), (1, 5, 400), (256, 256, 256)])
+def test_gemm_f64_store(dev, ta, tb, M, N, K):
+    g = np.random.default_rng(M * 7 + N + K)
+    A = g.standard_normal((K, M) if ta else (M, K))
+    B = g.standard_normal((N, K) if tb else (K, N))
+    C0 = g.standard_normal((M, N))
+    dA, dB, dC = _cm(A, dev), _cm(B, dev), _cm(C0, dev)
+    rc = lib().pfsm_test_gemm_f64(ta, tb, 0, M, N, K, _p(dA), dA.stride(1), _p(dB), dB.stride(1), _p(dC), dC.stride(1),
+                                  -0.5, 2.0, None, None, 0, None, 0, _stream())
+    assert rc == 0
+    ref = -0.5 * ((A.T if ta else A) @ (B.T if tb else B)) + 2.0 * C0
+    bound = 2 * K * U64 * (np.abs(A).max() * np.abs(B).max() * K + np.abs(C0).max())
+    assert np.max(np.abs(_np(dC) - ref)) <= bound
+
+
+def test_gemm_f64_epilogues(dev):
+    n = 300
+    g = np.random.default_rng(5)
+    At = g.standard_normal((n, n))
+    At = 0.5 * (At + At.T)
+    X = g.standard_normal((n, n))
+    D = g.standard_normal((n, n))
+    eps = g.standard_normal(n)
+    dA, dX, dD, de = _cm(At, dev), _cm(X, dev), _cm(D, dev), torch.from_numpy(eps).to(dev)
+    C = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+    L = lib()
+    assert L.pfsm_test_gemm_f64(0, 0, 1, n, n, n, _p(dA), n, _p(dX), n, _p(C), n, 1.0, 0.0, _p(de), None, 0, None, 0,
+                                _stream()) == 0
+    tol = 4 * n * U64 * np.abs(At).max() * np.abs(X).max() * n
+    assert np.max(np.abs(_np(C) - (At @ X - X * eps))) <= tol
+    assert L.pfsm_test_gemm_f64(0, 0, 2, n, n, n, _p(dA), n, _p(dX), n, _p(C), n, 0.3, 0.0, _p(de), _p(dD), n, None,
+                                0, _stream()) == 0
+    assert np.max(np.abs(_np(C) - (D - 0.3 * (At @ X - X * eps)))) <= tol
+    tiles_m = (n + 127) // 128
+    part = torch.empty(tiles_m * n, dtype=torch.float64, device=dev)
+    assert L.pfsm_test_gemm_f64(0, 0, 3, n, n, n, _p(dA), n, _p(dX), n, None, n, 1.0, 0.0, None, _p(dX), n,
+                                _p(part), 0, _stream()) == 0
+    rq = _np(part).reshape(tiles_m, n).sum(0)
+    assert np.max(np.abs(rq - np.sum(X * (At @ X), 0))) <= tol * 10
+    # lower tiles only: entries on and below the diagonal are right, the rest untouched
+    C2 = torch.zeros((n, n), dtype=torch.float64, device=dev).t()
+    assert L.pfsm_test_gemm_f64(1, 0, 0, n, n, n, _p(dX), n, _p(dX), n, _p(C2), n, 1.0, 0.0, None, None, 0, None, 1,
+                                _stream()) == 0
+    S = X.T @ X
+    low = np.tril_indices(n)
+    assert np.max(np.abs(_np(C2)[low] - S[low])) <= tol
+
+
+def _pack(x, by_rows, dev, flags_extra=0):
+    L = lib()
+    m, n = x.shape
+    R, K = (m, n) if by_rows else (n, m)
+    ldp = L.pfsm_test_x3_row_stride(K)
+    P = torch.empty(R * ldp, dtype=torch.int16, device=dev)
+    dx = _cm(x, dev)
+    assert L.pfsm_test_pack_x3(_p(dx), 1, m, n, dx.stride(1), (1 if by_rows else 0) | flags_extra, _p(P), ldp,
+                               _stream()) == 0
+    return P, ldp
+
+
+def test_pack_roundtrip(dev):
+    g = np.random.default_rng(9)
+    x = g.standard_normal((70, 45)) * np.exp(g.standard_normal((70, 45)))
+    P, ldp = _pack(x, False, dev)
+    raw = P.cpu().numpy().view(np.uint16).reshape(45, ldp).astype(np.uint32) << 16
+    vals = raw.view(np.float32).astype(np.float64)
+    K = 70
+    hi = np.concatenate([vals[:, 64 * c:64 * c + 32] for c in range((K + 31) // 32)], axis=1)[:, :K]
+    lo = np.concatenate([vals[:, 64 * c + 32:64 * c + 64] for c in range((K + 31) // 32)], axis=1)[:, :K]
+    rec = (hi + lo).T
+    assert np.max(np.abs(rec - x) / np.abs(x)) <= 2.0 ** -16
+    h_ref, l_ref = split_hi_lo(x)
+    assert np.array_equal(hi.T, h_ref) and np.array_equal(lo.T, l_ref)
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("M,N,K", [(300, 270, 100), (256, 512, 64), (33, 600, 257)])
+def test_gemm_x3(dev, cfg, M, N, K):
+    g = np.random.default_rng(M + N + K + cfg)
+    A = g.standard_normal((M, K))
+    B = g.standard_normal((K, N))
+    Ap, lda = _pack(A, True, dev)     # rows of A
+    Bp, ldb = _pack(B, False, dev)    # columns of B
+    C = torch.empty((M, N), dtype=torch.float64, device=dev).t()
+    assert lib().pfsm_test_gemm_x3(0, cfg, 0, M, N, K, _p(Ap), lda, _p(Bp), ldb, _p(C), M, 1, 1.0, 0.0, None, 0, None,
+                                   0, 0, None, None, _stream()) == 0
+    ah, al = split_hi_lo(A)
+    bh, bl = split_hi_lo(B)
+    ref3 = ah @ bh + ah @ bl + al @ bh
+    # FP32 accumulation of K products of magnitude |a||b|
+    tol = 4 * K * 2.0 ** -24 * np.abs(A).max() * np.abs(B).max()
+    assert np.max(np.abs(_np(C) - ref3)) <= tol
+    assert np.max(np.abs(_np(C) - A @ B)) <= 2.0 ** -14 * np.sqrt(K) * np.abs(A).max() * np.abs(B).max() + tol
