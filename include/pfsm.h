@@ -131,6 +131,8 @@ pfsm_status pfsm_solve(pfsm_plan* plan, const double* dA, int64_t lda, const dou
  *   dGradLambda   dL/dlambda (n) or NULL (zero)
  *   dGradV        dL/dV (n x n, ldg) or NULL (zero)
  *   dGradA        output n x n symmetric, ldga >= n; must not overlap the inputs
+ * The three n x n products run in FP64 for an FP64 plan and as split-BF16
+ * matrix-core products (FP32-class accuracy) for a mixed-precision plan.
  * Errors: INVALID_ARG, WORKSPACE_TOO_SMALL, HIP_ERROR. */
 pfsm_status pfsm_backward(pfsm_plan* plan, const double* dLambda, const double* dV, int64_t ldv,
                           const double* dGradLambda, const double* dGradV, int64_t ldg, double eta,

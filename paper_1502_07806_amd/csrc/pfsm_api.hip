@@ -816,6 +816,32 @@ pfsm_status pfsm_backward(pfsm_plan* pl, const double* dLam, const double* dV, i
   double* T = (double*)(W + pl->o_b0);
   double* G = (double*)(W + pl->o_b1);
   PFSM_TRY(fill_i32((int*)dInfo, 1, 0, s));
+  if (pl->precision == PFSM_PREC_MIXED_BF16) {
+    // split-BF16 products (FP32-class accuracy); the middle factor in FP64
+    const int64_t ldp = x3_row_stride(n);
+    bf16_t* Pa = (bf16_t*)(W + pl->m_Apk);
+    bf16_t* Pb = (bf16_t*)(W + pl->m_Vpk);
+    bf16_t* Pr = (bf16_t*)(W + pl->m_Rpk);
+    auto x3 = [&](const bf16_t* Ap, const bf16_t* Bp, void* C, int64_t ldc, int c_double) {
+      X3Args g = {};
+      g.M = n; g.N = n; g.K = n; g.Ap = Ap; g.ldap = ldp; g.Bp = Bp; g.ldbp = ldp; g.C = C; g.ldc = ldc;
+      g.c_double = c_double; g.alpha = 1.0; g.cfg = pl->x3_cfg;
+      return gemm_x3(X3_STORE, g, s);
+    };
+    if (gV) {
+      PFSM_TRY(pack_x3(dV, 1, n, n, ldv, 0, Pa, ldp, s));   // columns of V (rows of V^T)
+      PFSM_TRY(pack_x3(gV, 1, n, n, ldg, 0, Pb, ldp, s));   // columns of gV
+      PFSM_TRY(x3(Pa, Pb, T, n, 1));                        // T = V^T gV
+    }
+    PFSM_TRY(adjoint_middle(T, n, n, dLam, gLam, eta, gV != nullptr, s));
+    PFSM_TRY(pack_x3(dV, 1, n, n, ldv, PACK_BY_ROWS, Pr, ldp, s));  // rows of V
+    PFSM_TRY(pack_x3(T, 1, n, n, n, 0, Pb, ldp, s));                // columns of M
+    PFSM_TRY(x3(Pr, Pb, G, n, 1));                                  // G = V M
+    PFSM_TRY(pack_x3(G, 1, n, n, n, PACK_BY_ROWS, Pa, ldp, s));     // rows of G
+    PFSM_TRY(x3(Pa, Pr, dGradA, ldga, 1));                          // dA = G V^T (columns of V^T = rows of V)
+    PFSM_TRY(symmetrize(dGradA, n, ldga, s));
+    return hip_status(hipGetLastError());
+  }
   if (gV) {
     GemmArgs g = {};
     g.M = n; g.N = n; g.K = n; g.A = dV; g.lda = ldv; g.B = gV; g.ldb = ldg; g.C = T; g.ldc = n; g.alpha = 1.0;

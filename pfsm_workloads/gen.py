@@ -99,9 +99,19 @@ def antisym_k(n: int, kappa: float, seed: int, device="cpu") -> torch.Tensor:
     return K * (kappa / torch.linalg.matrix_norm(K))
 
 
-def expm_small(K: torch.Tensor, terms: int = 12) -> torch.Tensor:
-    """exp(K) by a Taylor series in Horner form; valid for ||K|| <= 0.1 (here 1e-2)."""
+def expm_small(K: torch.Tensor, terms: Optional[int] = None) -> torch.Tensor:
+    """exp(K) by a Taylor series in Horner form, for ||K||_F <= 0.1.
+
+    With terms=None the series is cut after the first t whose remainder bound
+    ||K||_F^(t+1) / (t+1)! falls below 1e-18."""
     n = K.shape[0]
+    if terms is None:
+        r = float(torch.linalg.matrix_norm(K))
+        assert r <= 0.1, "expm_small is meant for small perturbations"
+        terms, bound = 1, r * r / 2.0
+        while bound > 1e-18:
+            terms += 1
+            bound *= r / (terms + 1)
     I = torch.eye(n, dtype=K.dtype, device=K.device)
     E = I.clone()
     for j in range(terms, 0, -1):

@@ -262,3 +262,22 @@ def test_timing_stages(pf):
         assert all(v >= 0 for v in s.values())
         # stages that do not run (iteration 3 of 3) only see back-to-back event records
         assert s["basis_change"] > 0 and s["fs_update_2"] > 0 and s["fs_update_3"] < 0.05
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed_bf16", 1e-4)])
+def test_backward_c5_full_size(pf, precision, tol):
+    """Differentiation workload at N = 4096 (16 slices of 256): the library's
+    adjoint against the FP64 CPU formula on the same (lambda, V); loss =
+    weighted occupied eigenvalues + <v_j, D v_j> over the occupied set."""
+    cfg = CONFIGS["c5_grad_n4096"]
+    dev = torch.device("cuda:0")
+    A, V, _, _ = prescribed_problem(cfg.n, cfg.n_occ, cfg.kappa, cfg.seed_base, cfg.clusters, device=dev)
+    plan = pf.Plan(cfg.n, uniform_layout(cfg.n, cfg.slice_size), halo=cfg.halo, precision=precision)
+    lam, Vo = plan.solve(A, V)
+    w, d = loss_weights(cfg.n_occ, cfg.n, cfg.seed_base)
+    lam_np, V_np = lam.cpu().numpy(), Vo.cpu().numpy()
+    dlam, dV = occupied_loss_grads(lam_np, V_np, w, d)
+    gA = plan.backward(lam, Vo, torch.from_numpy(dlam).to(dev), torch.from_numpy(dV).to(dev), eta=1e-8).cpu().numpy()
+    ref = eigh_adjoint(lam_np, V_np, dlam, dV, 1e-8)
+    assert np.max(np.abs(gA - ref)) <= tol * np.max(np.abs(ref))
+    assert np.array_equal(gA, gA.T)
