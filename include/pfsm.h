@@ -170,7 +170,7 @@ int32_t pfsm_batch_count(const pfsm_plan* plan);
  * capture.  Errors: INVALID_ARG, HIP_ERROR. */
 pfsm_status pfsm_autotune(pfsm_plan* plan, void* dWork, size_t work_bytes, int32_t* chosen, void* stream);
 
-/* Fix the split-BF16 tile configuration (-1: library default, 0..2: see
+/* Fix the split-BF16 tile configuration (-1: library default, 0..3: see
  * pfsm_autotune) for a plan and its instances.  Errors: INVALID_ARG. */
 pfsm_status pfsm_set_tile_config(pfsm_plan* plan, int32_t cfg);
 
