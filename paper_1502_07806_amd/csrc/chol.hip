@@ -4,7 +4,7 @@
 //
 // Two-level blocking: 64-wide diagonal blocks are factored by one wavefront
 // with each lane holding one row in registers (column values are broadcast
-// with v_readlane), which also forms L_kk^{-T}; the 64-wide panel solve is an
+// through LDS), which also forms L_kk^{-T}; the 64-wide panel solve is an
 // MFMA GEMM with that inverse; updates inside a 512-wide panel are rank-64
 // GEMMs restricted to the panel, and the rest of the matrix receives one
 // rank-512 update per panel, so the trailing matrix is streamed N/512 times
@@ -18,66 +18,66 @@ namespace {
 constexpr int NB = CHOL_NB;      // 64
 constexpr int NB2 = CHOL_NB2;    // 512
 
-__device__ inline double readlane_d(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // One wavefront: factor S[k0:k0+nb, k0:k0+nb] (lower triangle) in place and
 // write T = L^{-T} (upper triangular, 64 x 64 column-major; identity padding
-// past nb).  A non-positive or non-finite pivot records info = global column
-// (1-based), first error wins, and the factorisation continues with NaN.
+// past nb).  The block lives in LDS (row-major, padded); lane i updates row i,
+// and the column being eliminated is read as a broadcast (all lanes read the
+// same address).  With a single-wave workgroup each barrier is cheap.  A
+// non-positive or non-finite pivot records info = global column (1-based),
+// first error wins, and the factorisation continues with NaN.
 __global__ __launch_bounds__(64) void potrf_diag(double* S, int64_t lds, int64_t k0, int nb, double* T, int* info) {
+  __shared__ double L[NB][NB + 1];
+  __shared__ double X[NB][NB + 1];
   const int i = threadIdx.x;  // this lane's row
   double* Sk = S + k0 + k0 * lds;
-  double r[NB];
-#pragma unroll
   for (int c = 0; c < NB; ++c) {
     double v = (i == c) ? 1.0 : 0.0;
     if (i < nb && c < nb && c <= i) v = Sk[i + c * lds];
-    r[c] = v;
+    L[i][c] = v;
+    X[i][c] = (i == c) ? 1.0 : 0.0;
   }
+  __syncthreads();
   // right-looking Cholesky: column j is finished at step j
-#pragma unroll
   for (int j = 0; j < NB; ++j) {
-    double d = readlane_d(r[j], j);
+    double d = L[j][j];
     if (!(d > 0.0)) {
       if (i == 0 && j < nb) atomicCAS(info, 0, (int)(k0 + j + 1));
       d = __builtin_nan("");
     }
     const double sj = sqrt(d);
-    r[j] = (i == j) ? sj : (i > j ? r[j] / sj : r[j]);
-#pragma unroll
+    const double lij = (i == j) ? sj : L[i][j] / sj;
+    __syncthreads();
+    if (i >= j) L[i][j] = lij;
+    __syncthreads();
+#pragma unroll 4
     for (int c = j + 1; c < NB; ++c) {
-      const double lcj = readlane_d(r[j], c);
-      if (i >= c) r[c] -= r[j] * lcj;
+      const double lcj = L[c][j];
+      if (i >= c) L[i][c] -= lij * lcj;
     }
+    __syncthreads();
   }
-  // x = row i of L^{-1}: forward substitution on the identity, rows in order
-  double x[NB];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) x[c] = (i == c) ? 1.0 : 0.0;
-#pragma unroll
+  // X = L^{-1}: right-looking forward substitution on the identity (row k final at step k)
   for (int k = 0; k < NB; ++k) {
-    const double lkk = readlane_d(r[k], k);
-    if (i == k) {
-#pragma unroll
-      for (int c = 0; c <= k; ++c) x[c] /= lkk;
-    }
-    const double lik = r[k];  // L[i][k]
-#pragma unroll
+    const double lkk = L[k][k];
+    if (i <= k) X[k][i] /= lkk;  // lane c scales X[k][c]
+    __syncthreads();
+    const double lik = L[i][k];
+#pragma unroll 4
     for (int c = 0; c <= k; ++c) {
-      const double xkc = readlane_d(x[c], k);
-      if (i > k) x[c] -= lik * xkc;
+      const double xkc = X[k][c];
+      if (i > k) X[i][c] -= lik * xkc;
     }
+    __syncthreads();
   }
-#pragma unroll
   for (int c = 0; c < NB; ++c) {
-    if (i < nb && c < nb && c <= i) Sk[i + c * lds] = r[c];
-    // T(c, i) = (L^{-1})(i, c)
-    T[c + i * NB] = (i < nb && c < nb) ? (c <= i ? x[c] : 0.0) : (i == c ? 1.0 : 0.0);
+    if (i < nb && c < nb && c <= i) Sk[i + c * lds] = L[i][c];
+  }
+  // T(r, c) = (L^{-1})(c, r): lane i writes column i of T = row i of L^{-1}
+  for (int r = 0; r < NB; ++r) {
+    double v;
+    if (i < nb && r < nb) v = (r <= i) ? X[i][r] : 0.0;
+    else v = (r == i) ? 1.0 : 0.0;
+    T[r + i * NB] = v;
   }
 }
 

@@ -12,6 +12,7 @@
 //     apply   (one workgroup per 2b x 2b tile): B <- J^T B J and U <- U J
 //             with J = diag of the R's, as small MFMA products in LDS.
 //
+// (The pair problem is solved by a one-sided Jacobi, see pair_solve.)
 // A sweep in which no pair needed a rotation marks the submatrix converged;
 // later kernels of that submatrix return immediately.  A pair (p, q) is
 // rotated when |b_pq| > 2^-53 sqrt(|b_pp b_qq|) (relative accuracy) and
@@ -91,88 +92,91 @@ __global__ void sweep_begin(EighBatch e, int sweep) {
 }
 
 // ------------------------------------------------------------------ pair solve
+// The 2b x 2b pair problem S = [B_II B_IJ; B_JI B_JJ] is diagonalised by a
+// one-sided (Hestenes) Jacobi on W = S + sigma I, sigma = 2 max|Gershgorin
+// bound| so that W is positive definite: column pairs of W are rotated until
+// all columns are orthogonal; the accumulated rotation R (W = W0 R) holds the
+// eigenvectors of S.  Eight lanes own a column pair (8 rows each) and reduce
+// the 2x2 Gram entries with shuffles, so a round needs one barrier.  Padding
+// indices (beyond the submatrix order) never rotate.
 __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   const int npairs = e.nb / 2;
   const int p = blockIdx.x / npairs, k = blockIdx.x % npairs;
   int* flagR = e.rflag + (int64_t)p * npairs + k;
   if (e.state[2 * p]) { if (threadIdx.x == 0) *flagR = 0; return; }
-  __shared__ double S[B2][LS];
-  __shared__ double R[B2][LS];
-  __shared__ double cs_c[B2 / 2], cs_s[B2 / 2];
-  __shared__ int pp[B2 / 2], qq[B2 / 2];
-  __shared__ int any_rot, sweep_rot;
+  __shared__ double W[B2][LS];   // column-major: W[col][row]
+  __shared__ double R[B2][LS];   // column-major: R[col][row]
+  __shared__ int any_rot;
+  __shared__ int sweep_rot;
   const int Mp = e.Mp;
+  const int msize = e.wsize[p];
   int I, J;
   pair_blocks(k, round, e.nb, I, J);
   const double* B = e.Bw + (int64_t)p * Mp * Mp;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < B2 * B2; idx += NT) {
-    int r = idx % B2, c = idx / B2;
-    S[r][c] = B[pair_idx(r, I, J) + (int64_t)pair_idx(c, I, J) * Mp];
-    R[r][c] = (r == c) ? 1.0 : 0.0;
-  }
+  const double fl = noise_floor(e);
+  // pass 1: copy S (as columns) and decide whether any rotation is needed
   if (tid == 0) any_rot = 0;
   __syncthreads();
-  // Is any rotation needed at all?
-  const double fl = noise_floor(e);
   int need = 0;
   for (int idx = tid; idx < B2 * B2; idx += NT) {
     int r = idx % B2, c = idx / B2;
-    if (r < c && must_rotate(S[r][c], S[r][r], S[c][c], fl)) need = 1;
+    W[c][r] = B[pair_idx(r, I, J) + (int64_t)pair_idx(c, I, J) * Mp];
+    R[c][r] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < B2 * B2; idx += NT) {
+    int r = idx % B2, c = idx / B2;
+    if (r < c && must_rotate(W[c][r], W[r][r], W[c][c], fl)) need = 1;
   }
   if (need) any_rot = 1;
   __syncthreads();
   if (!any_rot) { if (tid == 0) *flagR = 0; return; }
-
+  const double sigma = 2.0 * fmax(fabs(e.scal[1]), fabs(e.scal[2])) + TINY;
+  for (int t = tid; t < B2; t += NT) {
+    const bool pad = pair_idx(t, I, J) >= msize;
+    W[t][t] = pad ? 1.0 : W[t][t] + sigma;  // a padding column becomes a unit vector (no overflow)
+  }
+  __syncthreads();
+  const int slot = tid >> 3, sub = tid & 7;  // 32 column pairs x 8 lanes
   for (int sweep = 0; sweep < e.inner_max_sweeps; ++sweep) {
     if (tid == 0) sweep_rot = 0;
     __syncthreads();
     for (int r = 0; r < B2 - 1; ++r) {
-      if (tid < B2 / 2) {
-        int a = rr_index(tid, r, B2), b = rr_index(B2 - 1 - tid, r, B2);
-        int pi = min(a, b), qi = max(a, b);
-        double apq = S[pi][qi], app = S[pi][pi], aqq = S[qi][qi];
-        double c = 1.0, s = 0.0;
-        if (must_rotate(apq, app, aqq, fl)) {
-          double tau = (aqq - app) / (2.0 * apq);
-          double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-          sweep_rot = 1;
-        }
-        cs_c[tid] = c; cs_s[tid] = s; pp[tid] = pi; qq[tid] = qi;
+      const int a = rr_index(slot, r, B2), b = rr_index(B2 - 1 - slot, r, B2);
+      const int pc = min(a, b), qc = max(a, b);
+      double aa = 0.0, bb = 0.0, ab = 0.0;
+#pragma unroll
+      for (int m = 0; m < B2 / 8; ++m) {
+        const int row = sub + 8 * m;
+        const double x = W[pc][row], y = W[qc][row];
+        aa += x * x;
+        bb += y * y;
+        ab += x * y;
       }
-      __syncthreads();
-      // S <- J^T S J on every 2x2 block (pair k1 rows, pair k2 cols), k1 <= k2;
-      // the transposed block is written from the same values so S stays exactly symmetric.
-      for (int idx = tid; idx < (B2 / 2) * (B2 / 2); idx += NT) {
-        int k1 = idx % (B2 / 2), k2 = idx / (B2 / 2);
-        if (k1 > k2) continue;
-        int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
-        double c1 = cs_c[k1], s1 = cs_s[k1], c2 = cs_c[k2], s2 = cs_s[k2];
-        double x_pp = S[p1][p2], x_pq = S[p1][q2], x_qp = S[q1][p2], x_qq = S[q1][q2];
-        // rows: p' = c p - s q ; q' = s p + c q
-        double y_pp = c1 * x_pp - s1 * x_qp, y_pq = c1 * x_pq - s1 * x_qq;
-        double y_qp = s1 * x_pp + c1 * x_qp, y_qq = s1 * x_pq + c1 * x_qq;
-        // cols: p' = c p - s q ; q' = s p + c q
-        double z_pp = c2 * y_pp - s2 * y_pq, z_pq = s2 * y_pp + c2 * y_pq;
-        double z_qp = c2 * y_qp - s2 * y_qq, z_qq = s2 * y_qp + c2 * y_qq;
-        if (k1 == k2) {
-          if (s1 != 0.0) { z_pq = 0.0; z_qp = 0.0; }
-          S[p1][p1] = z_pp; S[q1][q1] = z_qq; S[p1][q1] = z_pq; S[q1][p1] = z_qp;
-        } else {
-          S[p1][p2] = z_pp; S[p1][q2] = z_pq; S[q1][p2] = z_qp; S[q1][q2] = z_qq;
-          S[p2][p1] = z_pp; S[q2][p1] = z_pq; S[p2][q1] = z_qp; S[q2][q1] = z_qq;
-        }
+#pragma unroll
+      for (int off = 1; off < 8; off <<= 1) {
+        aa += __shfl_xor(aa, off, 64);
+        bb += __shfl_xor(bb, off, 64);
+        ab += __shfl_xor(ab, off, 64);
       }
-      // R <- R J
-      for (int idx = tid; idx < B2 * (B2 / 2); idx += NT) {
-        int i = idx % B2, kk = idx / B2;
-        int pc = pp[kk], qc = qq[kk];
-        double c = cs_c[kk], s = cs_s[kk];
-        double rp = R[i][pc], rq = R[i][qc];
-        R[i][pc] = c * rp - s * rq;
-        R[i][qc] = s * rp + c * rq;
+      const bool padpair = pair_idx(pc, I, J) >= msize || pair_idx(qc, I, J) >= msize;
+      if (!padpair && fabs(ab) > TINY && fabs(ab) > TOL * sqrt(aa * bb)) {
+        const double zeta = (bb - aa) / (2.0 * ab);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double sn = t * c;
+#pragma unroll
+        for (int m = 0; m < B2 / 8; ++m) {
+          const int row = sub + 8 * m;
+          const double x = W[pc][row], y = W[qc][row];
+          W[pc][row] = c * x - sn * y;
+          W[qc][row] = sn * x + c * y;
+          const double u = R[pc][row], v = R[qc][row];
+          R[pc][row] = c * u - sn * v;
+          R[qc][row] = sn * u + c * v;
+        }
+        if (sub == 0) sweep_rot = 1;
       }
       __syncthreads();
     }
@@ -181,7 +185,7 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   double* Rg = e.Rw + ((int64_t)p * npairs + k) * B2 * B2;
   for (int idx = tid; idx < B2 * B2; idx += NT) {
     int r = idx % B2, c = idx / B2;
-    Rg[idx] = R[r][c];
+    Rg[idx] = R[c][r];
   }
   if (tid == 0) {
     *flagR = 1;

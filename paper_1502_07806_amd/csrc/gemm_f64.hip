@@ -18,6 +18,12 @@ namespace {
 constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = GEMM_BK;
 constexpr int PAD = 16;                 // row stride 144 doubles: k and k+1 rows hit opposite bank halves
 constexpr int LDA_S = BM + PAD, LDB_S = BN + PAD;
+// An operand whose tile is contiguous along k in memory (op(A) = A^T, op(B) = B)
+// is kept in LDS as [row][k] with an odd stride (17 doubles), so both the
+// coalesced global->LDS stores (consecutive k) and the MFMA fragment reads
+// (consecutive rows) avoid bank conflicts; the other operands stay [k][row].
+constexpr int KS = BK + 1;
+constexpr int BUF = (BK * LDA_S > BM * KS ? BK * LDA_S : BM * KS);  // doubles per operand buffer
 constexpr int NT = 256;
 constexpr int A_PER_T = BM * BK / NT;   // 8
 constexpr int B_PER_T = BN * BK / NT;   // 8
@@ -40,9 +46,12 @@ __device__ inline void tri_index(int t, int& a, int& b) {
 
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m, int tiles_n) {
-  __shared__ double As[2][BK][LDA_S];
-  __shared__ double Bs[2][BK][LDB_S];
+  __shared__ double As[2][BUF];
+  __shared__ double Bs[2][BUF];
   __shared__ double red[2][BN];
+  // element (row, k) of the A tile / (k, col) of the B tile in buffer b
+  auto a_at = [&](int b, int row, int k) -> double& { return TA ? As[b][row * KS + k] : As[b][k * LDA_S + row]; };
+  auto b_at = [&](int b, int k, int col) -> double& { return TB ? Bs[b][k * LDB_S + col] : Bs[b][col * KS + k]; };
 
   int tm, tn;
   if (g.lower_only) {
@@ -109,14 +118,14 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m
       int idx = tid + NT * r;
       int i, k;
       if (!TA) { i = idx % BM; k = idx / BM; } else { k = idx % BK; i = idx / BK; }
-      As[buf][k][i] = ra[r];
+      a_at(buf, i, k) = ra[r];
     }
 #pragma unroll
     for (int r = 0; r < B_PER_T; ++r) {
       int idx = tid + NT * r;
       int j, k;
       if (!TB) { k = idx % BK; j = idx / BK; } else { j = idx % BN; k = idx / BN; }
-      Bs[buf][k][j] = rb[r];
+      b_at(buf, k, j) = rb[r];
     }
   };
 
@@ -132,9 +141,9 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m
       for (int kk = 0; kk < BK; kk += 4) {
         double af[4], bf[4];
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) af[ib] = As[cur][kk + lq][wi0 + ib * 16 + l16];
+        for (int ib = 0; ib < 4; ++ib) af[ib] = a_at(cur, wi0 + ib * 16 + l16, kk + lq);
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) bf[jb] = Bs[cur][kk + lq][wj0 + jb * 16 + l16];
+        for (int jb = 0; jb < 4; ++jb) bf[jb] = b_at(cur, kk + lq, wj0 + jb * 16 + l16);
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib)
 #pragma unroll

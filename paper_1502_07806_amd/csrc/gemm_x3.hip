@@ -350,7 +350,7 @@ hipError_t set_attrs() {
 
 }  // namespace
 
-int x3_default_cfg = 0;
+int x3_default_cfg = 2;  // fastest measured at N = 8192 (64 x 128 wave tiles)
 
 hipError_t x3_init() {
   // Dynamic LDS above 64 KiB must be enabled per kernel before the first

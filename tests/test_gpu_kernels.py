@@ -124,7 +124,7 @@ def test_gemm_x3(dev, cfg, M, N, K):
     B = g.standard_normal((K, N))
     Ap, lda = _pack(A, True, dev)     # rows of A
     Bp, ldb = _pack(B, False, dev)    # columns of B
-    C = torch.empty((M, N), dtype=torch.float64, device=dev).t()
+    C = torch.empty((N, M), dtype=torch.float64, device=dev).t()  # column-major M x N
     assert lib().pfsm_test_gemm_x3(0, cfg, 0, M, N, K, _p(Ap), lda, _p(Bp), ldb, _p(C), M, 1, 1.0, 0.0, None, 0, None,
                                    0, 0, None, None, _stream()) == 0
     ah, al = split_hi_lo(A)
