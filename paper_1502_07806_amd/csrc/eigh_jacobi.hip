@@ -161,7 +161,9 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
         ab += __shfl_xor(ab, off, 64);
       }
       const bool padpair = pair_idx(pc, I, J) >= msize || pair_idx(qc, I, J) >= msize;
-      if (!padpair && fabs(ab) > TINY && fabs(ab) > TOL * sqrt(aa * bb)) {
+      // columns count as orthogonal below 8 u relative: the rounding noise of
+      // the dot products stays under it, so converged pairs stop rotating
+      if (!padpair && fabs(ab) > TINY && fabs(ab) > 8.0 * TOL * sqrt(aa * bb)) {
         const double zeta = (bb - aa) / (2.0 * ab);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t);
