@@ -32,13 +32,17 @@
  * only.  Conditions found on the device are written to *dInfo (int32, device
  * memory, cleared by the call itself):
  *      0  success
- *    k>0  the overlap matrix is not positive definite at column k (the start
- *         vectors do not span: a randomly mixed, non-diagonally-dominant input
- *         as the Methodology section warns, or duplicated previous vectors)
+ *    k>0  FP64 path: the overlap matrix is not positive definite at column k
+ *         (the start vectors do not span: a randomly mixed, non-diagonally-
+ *         dominant input as the Methodology section warns, or duplicated
+ *         previous vectors)
  *     -1  a non-finite eigenvalue (non-finite input propagates to it)
- *     -2  mixed precision: the overlap factor is too far from the identity for the
- *         short series used for X L^{-T} (max |L - I| > 1e-3: the start vectors
- *         are far from orthogonal, outside the diagonally dominant regime)
+ *     -2  mixed precision: the overlap matrix is too far from the identity for
+ *         its near-identity Cholesky iteration (last step changed L by more
+ *         than 1e-7) or for the short series used for X L^{-T} (max |L - I| >
+ *         1e-3): the start vectors are far from orthogonal, outside the
+ *         diagonally dominant regime (this also covers what the FP64 path
+ *         reports as k>0)
  *     -3  a submatrix eigensolver did not converge within its sweep limit
  *     -4  an output vector lost its length (squared norm outside [1/4, 4] before
  *         normalisation): V_prev does not have orthonormal columns
@@ -131,7 +135,9 @@ pfsm_status pfsm_solve(pfsm_plan* plan, const double* dA, int64_t lda, const dou
  *   dGradLambda   dL/dlambda (n) or NULL (zero)
  *   dGradV        dL/dV (n x n, ldg) or NULL (zero)
  *   dGradA        output n x n symmetric, ldga >= n; must not overlap the inputs
- * The three n x n products run in FP64 for an FP64 plan and as split-BF16
+ * The middle factor is symmetrised in FP64 before the products
+ * (M_ij = F_ij (T_ij - T_ji) / 2, T = V^T gV in FP64), so dA = V M V^T; the two
+ * n x n products with V run in FP64 for an FP64 plan and as split-BF16
  * matrix-core products (FP32-class accuracy) for a mixed-precision plan.
  * Errors: INVALID_ARG, WORKSPACE_TOO_SMALL, HIP_ERROR. */
 pfsm_status pfsm_backward(pfsm_plan* plan, const double* dLambda, const double* dV, int64_t ldv,

@@ -18,10 +18,13 @@ namespace {
 constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = GEMM_BK;
 constexpr int PAD = 16;                 // row stride 144 doubles: k and k+1 rows hit opposite bank halves
 constexpr int LDA_S = BM + PAD, LDB_S = BN + PAD;
-// An operand whose tile is contiguous along k in memory (op(A) = A^T, op(B) = B)
-// is kept in LDS as [row][k] with an odd stride (17 doubles), so both the
-// coalesced global->LDS stores (consecutive k) and the MFMA fragment reads
-// (consecutive rows) avoid bank conflicts; the other operands stay [k][row].
+// A tile that is contiguous along k in memory can be kept in LDS as [row][k]
+// with an odd stride (17 doubles), so the coalesced global->LDS stores
+// (consecutive k) and the MFMA fragment reads (consecutive rows) both avoid
+// bank conflicts; the other layout is [k][row].  op(A) = A^T uses [row][k];
+// op(B) = B uses it only together with op(A) = A^T (the combination measured
+// fastest at N = 8192: 61 TFLOP/s).  Products with a symmetric left operand
+// are therefore issued as A^T B.
 constexpr int KS = BK + 1;
 constexpr int BUF = (BK * LDA_S > BM * KS ? BK * LDA_S : BM * KS);  // doubles per operand buffer
 constexpr int NT = 256;
@@ -51,7 +54,11 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m
   __shared__ double red[2][BN];
   // element (row, k) of the A tile / (k, col) of the B tile in buffer b
   auto a_at = [&](int b, int row, int k) -> double& { return TA ? As[b][row * KS + k] : As[b][k * LDA_S + row]; };
-  auto b_at = [&](int b, int k, int col) -> double& { return TB ? Bs[b][k * LDB_S + col] : Bs[b][col * KS + k]; };
+  // B tile: [col][k] when it is k-contiguous and A is transposed (measured faster),
+  // otherwise [k][col]
+  auto b_at = [&](int b, int k, int col) -> double& {
+    return (!TB && TA) ? Bs[b][col * KS + k] : Bs[b][k * LDB_S + col];
+  };
 
   int tm, tn;
   if (g.lower_only) {

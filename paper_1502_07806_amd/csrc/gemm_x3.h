@@ -58,8 +58,9 @@ hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s);
 // (k runs down the column); with it, row r is row r of X (a transpose).  X is
 // column-major with ld; src_double selects FP64 or FP32 storage.
 // PACK_SUB_I packs X - I; PACK_LOWER / PACK_UPPER keep only the lower / upper
-// triangle of X (row >= col / row <= col), zeros elsewhere.
-enum PackFlags : int { PACK_BY_ROWS = 1, PACK_SUB_I = 2, PACK_LOWER = 4, PACK_UPPER = 8 };
+// triangle of X (row >= col / row <= col), zeros elsewhere; PACK_HALF_DIAG
+// halves the diagonal (after PACK_SUB_I).
+enum PackFlags : int { PACK_BY_ROWS = 1, PACK_SUB_I = 2, PACK_LOWER = 4, PACK_UPPER = 8, PACK_HALF_DIAG = 16 };
 hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P, int64_t ldp,
                    hipStream_t s);
 

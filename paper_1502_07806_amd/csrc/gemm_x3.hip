@@ -291,6 +291,7 @@ __global__ __launch_bounds__(256) void k_pack(const void* X, int src_double, int
     if ((by_rows ? (row < R && col < K) : (row < K && col < R)) && keep) {
       v = src_double ? ((const double*)X)[row + col * ldx] : (double)((const float*)X)[row + col * ldx];
       if ((flags & PACK_SUB_I) && row == col) v -= 1.0;
+      if ((flags & PACK_HALF_DIAG) && row == col) v *= 0.5;
     }
     tile[rr][kk] = v;
   }

@@ -158,20 +158,38 @@ __global__ __launch_bounds__(NT) void k_permute(const double* X, int64_t n, int6
   for (int64_t i = threadIdx.x; i < n; i += NT) dst[i] = s * src[i];
 }
 
-// M = diag(glam) + F o T, F_ij = d / (d^2 + eta^2), d = lam_j - lam_i, F_ii = 0.
+// M = sym(diag(glam) + F o T) with F_ij = d / (d^2 + eta^2), d = lam_j - lam_i,
+// F_ii = 0: since F is antisymmetric, M_ij = F_ij (T_ij - T_ji) / 2 off the
+// diagonal and M_ii = glam_i.  Symmetrising here, in FP64, removes the large
+// antisymmetric part of F o T (which V (.) V^T would only cancel in exact
+// arithmetic) before the products.  One 32 x 32 tile pair per workgroup.
 __global__ void k_adjoint_middle(double* T, int64_t ldt, int64_t n, const double* lam, const double* glam,
                                  double eta, int have_t) {
-  const int64_t j = blockIdx.y;
-  const double lj = lam[j];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double v = 0.0;
-    if (i == j) {
-      v = glam ? glam[j] : 0.0;
-    } else if (have_t) {
-      double d = lj - lam[i];
-      v = d / (d * d + eta * eta) * T[i + j * ldt];
+  __shared__ double a[32][33], b[32][33];
+  const int64_t bi = blockIdx.x, bj = blockIdx.y;
+  if (bi < bj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    int64_t gi = bi * 32 + tx, gj = bj * 32 + r;
+    a[r][tx] = (have_t && gi < n && gj < n) ? T[gi + gj * ldt] : 0.0;   // a[c][r'] = T(bi*32 + r', bj*32 + c)
+    int64_t hi = bj * 32 + tx, hj = bi * 32 + r;
+    b[r][tx] = (have_t && hi < n && hj < n) ? T[hi + hj * ldt] : 0.0;   // b[c][r'] = T(bj*32 + r', bi*32 + c)
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t gi = bi * 32 + tx, gj = bj * 32 + r;  // element (gi, gj), gi row
+    if (gi < n && gj < n) {
+      double v;
+      if (gi == gj) {
+        v = glam ? glam[gi] : 0.0;
+      } else {
+        const double d = lam[gj] - lam[gi];
+        const double f = d / (d * d + eta * eta);
+        v = 0.5 * f * (a[r][tx] - b[tx][r]);  // (T_ij - T_ji) F_ij / 2
+      }
+      T[gi + gj * ldt] = v;
+      if (bi != bj) T[gj + gi * ldt] = v;
     }
-    T[i + j * ldt] = v;
   }
 }
 
@@ -329,8 +347,8 @@ hipError_t finalize_order_values(const double* lam_u, int64_t n, double* lam_out
 
 hipError_t adjoint_middle(double* T, int64_t ldt, int64_t n, const double* lam, const double* glam, double eta,
                           bool have_t, hipStream_t s) {
-  dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 64), (unsigned)n);
-  hipLaunchKernelGGL(k_adjoint_middle, grid, dim3(256), 0, s, T, ldt, n, lam, glam, eta, have_t ? 1 : 0);
+  unsigned t = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(k_adjoint_middle, dim3(t, t), dim3(256), 0, s, T, ldt, n, lam, glam, eta, have_t ? 1 : 0);
   return hipGetLastError();
 }
 

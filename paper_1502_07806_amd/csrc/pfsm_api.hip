@@ -53,6 +53,11 @@ struct pfsm_plan {
 
 namespace {
 
+// Largest change allowed in the last step of the near-identity Cholesky of the
+// mixed path (entries of L are O(1)); a larger one means the overlap matrix is
+// too far from the identity for that iteration.
+constexpr double MIXED_CHOL_TOL = 1e-7;
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
@@ -338,7 +343,7 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
     g.M = n; g.N = n; g.K = n;
     g.A = dA; g.lda = lda; g.B = dV; g.ldb = ldv; g.C = buf0; g.ldc = n;
     g.alpha = 1.0;
-    PFSM_TRY(gemm_f64(false, false, EPI_STORE, g, s));
+    PFSM_TRY(gemm_f64(true, false, EPI_STORE, g, s));  // A is symmetric: A V = A^T V
     GemmArgs h = {};
     h.M = n; h.N = n; h.K = n;
     h.A = dV; h.lda = ldv; h.B = buf0; h.ldb = n; h.C = At; h.ldc = n;
@@ -366,7 +371,7 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
       GemmArgs r = {};
       r.M = n; r.N = n; r.K = n; r.A = At; r.lda = n; r.B = X; r.ldb = n; r.D = X; r.ldd = n; r.part = part;
       r.alpha = 1.0;
-      PFSM_TRY(gemm_f64(false, false, EPI_RQ, r, s));
+      PFSM_TRY(gemm_f64(true, false, EPI_RQ, r, s));  // At symmetric
       PFSM_TRY(col_norm2(X, n, n, n, (double*)(W + pl->o_den), s));
       PFSM_TRY(rq_reduce(part, tiles_m, n, (double*)(W + pl->o_den), eps, s));
     }
@@ -374,19 +379,19 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
       GemmArgs g = {};
       g.M = n; g.N = n; g.K = n; g.A = At; g.lda = n; g.B = X; g.ldb = n; g.C = Wt; g.ldc = n;
       g.eps = eps; g.krange = kr;
-      PFSM_TRY(gemm_f64(false, false, EPI_SHIFT, g, s));  // Y = (At - eps) X
+      PFSM_TRY(gemm_f64(true, false, EPI_SHIFT, g, s));  // Y = (At - eps) X (At symmetric)
       if (it < 8) clk.mark(4 + 2 * it);
       GemmArgs h = {};
       h.M = n; h.N = n; h.K = n; h.A = At; h.lda = n; h.B = Wt; h.ldb = n; h.C = X; h.ldc = n;
       h.D = X; h.ldd = n; h.eps = eps; h.alpha_dev = scal;
-      PFSM_TRY(gemm_f64(false, false, EPI_FSUPD, h, s));  // X <- X - a (At - eps) Y  (in place: reads only Y)
+      PFSM_TRY(gemm_f64(true, false, EPI_FSUPD, h, s));  // X <- X - a (At - eps) Y  (in place: reads only Y)
       if (it < 8) clk.mark(5 + 2 * it);
     } else {
       GemmArgs g = {};
       g.M = n; g.N = n; g.K = n; g.A = At; g.lda = n; g.B = X; g.ldb = n; g.C = Wt; g.ldc = n;
       g.D = X; g.ldd = n; g.eps = eps; g.alpha_dev = scal; g.krange = kr;
       if (it < 8) clk.mark(4 + 2 * it);
-      PFSM_TRY(gemm_f64(false, false, EPI_FSUPD, g, s));  // X' = X - a (At - eps) X
+      PFSM_TRY(gemm_f64(true, false, EPI_FSUPD, g, s));  // X' = X - a (At - eps) X
       if (it < 8) clk.mark(5 + 2 * it);
       std::swap(X, Wt);
     }
@@ -409,7 +414,7 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
     GemmArgs r = {};
     r.M = n; r.N = n; r.K = n; r.A = At; r.lda = n; r.B = X; r.ldb = n; r.D = X; r.ldd = n; r.part = part;
     r.alpha = 1.0;
-    PFSM_TRY(gemm_f64(false, false, EPI_RQ, r, s));
+    PFSM_TRY(gemm_f64(true, false, EPI_RQ, r, s));
     PFSM_TRY(rq_reduce(part, tiles_m, n, nullptr, lamu, s));
   }
   clk.mark(22);
@@ -514,14 +519,17 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     PFSM_TRY(pack_x3(X32, 0, n, n, n, 0, Xpk, ldp, s));
   }
   clk.mark(19);
-  // (4) overlap S = X^T X (FP64 output, lower tiles) and its FP64 Cholesky.
+  // (4) overlap S = X^T X (FP64 output, lower tiles) and its Cholesky factor.
   {
     X3Args g = x3(X3_STORE, n, n, n, Xpk, Xpk, S64, n, 1);
     g.tiles = X3_LOWER;
     PFSM_TRY(gemm_x3(X3_STORE, g, s));
   }
   clk.mark(20);
-  PFSM_TRY(cholesky_factor(S64, n, n, (double*)(W + pl->o_T), info, s));
+  // S is the identity up to the folded-spectrum residual, so L = I + K comes
+  // from the near-identity fixed point (two split-BF16 products K K^T) rather
+  // than a latency-bound blocked factorisation.  B64a and Vn64 are free here.
+  PFSM_TRY(cholesky_near_identity(S64, n, n, Rpk, ldp, B64a, Vn64, n, rb, MIXED_CHOL_TOL, pl->x3_cfg, info, s));
   // X <- X L^{-T} = X + X D, D = -U + U^2 (U = (L - I)^T, max |U| <= 1e-3 checked).
   PFSM_TRY(lower_minus_identity_check(S64, n, n, rb, info, s));
   {
@@ -573,7 +581,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   {
     GemmArgs g = {};
     g.M = n; g.N = n; g.K = n; g.A = dA; g.lda = lda; g.B = Vn64; g.ldb = n; g.C = B64a; g.ldc = n; g.alpha = 1.0;
-    PFSM_TRY(gemm_f64(false, false, EPI_STORE, g, s));
+    PFSM_TRY(gemm_f64(true, false, EPI_STORE, g, s));  // Z = A V_new (A symmetric)
     RefineBufs b;
     b.d = rb; b.nn = rb + n; b.lam_s = rb + 2 * n;
     b.rank = (int*)(rb + 3 * n); b.inv = (int*)(rb + 4 * n); b.cstart = (int*)(rb + 5 * n);
@@ -823,17 +831,19 @@ pfsm_status pfsm_backward(pfsm_plan* pl, const double* dLam, const double* dV, i
     bf16_t* Pb = (bf16_t*)(W + pl->m_Vpk);
     bf16_t* Pr = (bf16_t*)(W + pl->m_Rpk);
     auto x3 = [&](const bf16_t* Ap, const bf16_t* Bp, void* C, int64_t ldc, int c_double) {
+      // split-BF16 product with FP64 output
       X3Args g = {};
       g.M = n; g.N = n; g.K = n; g.Ap = Ap; g.ldap = ldp; g.Bp = Bp; g.ldbp = ldp; g.C = C; g.ldc = ldc;
       g.c_double = c_double; g.alpha = 1.0; g.cfg = pl->x3_cfg;
       return gemm_x3(X3_STORE, g, s);
     };
     if (gV) {
-      PFSM_TRY(pack_x3(dV, 1, n, n, ldv, 0, Pa, ldp, s));   // columns of V (rows of V^T)
-      PFSM_TRY(pack_x3(gV, 1, n, n, ldg, 0, Pb, ldp, s));   // columns of gV
-      PFSM_TRY(x3(Pa, Pb, T, n, 1));                        // T = V^T gV
+      // T = V^T gV in FP64: its antisymmetric part is multiplied by 1/gap in the middle factor
+      GemmArgs g = {};
+      g.M = n; g.N = n; g.K = n; g.A = dV; g.lda = ldv; g.B = gV; g.ldb = ldg; g.C = T; g.ldc = n; g.alpha = 1.0;
+      PFSM_TRY(gemm_f64(true, false, EPI_STORE, g, s));
     }
-    PFSM_TRY(adjoint_middle(T, n, n, dLam, gLam, eta, gV != nullptr, s));
+    PFSM_TRY(adjoint_middle(T, n, n, dLam, gLam, eta, gV != nullptr, s));  // symmetric M
     PFSM_TRY(pack_x3(dV, 1, n, n, ldv, PACK_BY_ROWS, Pr, ldp, s));  // rows of V
     PFSM_TRY(pack_x3(T, 1, n, n, n, 0, Pb, ldp, s));                // columns of M
     PFSM_TRY(x3(Pr, Pb, G, n, 1));                                  // G = V M
@@ -877,7 +887,7 @@ pfsm_status pfsm_diagnostics(pfsm_plan* pl, const double* dA, int64_t lda, const
   double* part = (double*)(W + pl->o_part);
   GemmArgs g = {};
   g.M = n; g.N = n; g.K = n; g.A = dA; g.lda = lda; g.B = dV; g.ldb = ldv; g.C = AV; g.ldc = n; g.alpha = 1.0;
-  PFSM_TRY(gemm_f64(false, false, EPI_STORE, g, s));
+  PFSM_TRY(gemm_f64(true, false, EPI_STORE, g, s));  // A symmetric
   GemmArgs h = {};
   h.M = n; h.N = n; h.K = n; h.A = dV; h.lda = ldv; h.B = dV; h.ldb = ldv; h.C = G; h.ldc = n; h.alpha = 1.0;
   PFSM_TRY(gemm_f64(true, false, EPI_STORE, h, s));

@@ -3,8 +3,19 @@
 // product library libpfsm.so.
 #include "../common.h"
 #include "../gemm_x3.h"
+#include "../chol.h"
 
 using namespace pfsm;
+
+static hipError_t ensure_x3() {
+  static bool init = false;
+  if (!init) {
+    const hipError_t e = x3_init();
+    if (e != hipSuccess) return e;
+    init = true;
+  }
+  return hipSuccess;
+}
 
 extern "C" {
 
@@ -30,15 +41,28 @@ int pfsm_test_gemm_x3(int epi, int cfg, int tiles, int64_t M, int64_t N, int64_t
   g.M = M; g.N = N; g.K = K; g.Ap = (const bf16_t*)Ap; g.ldap = ldap; g.Bp = (const bf16_t*)Bp; g.ldbp = ldbp;
   g.C = C; g.ldc = ldc; g.c_double = c_double; g.alpha = alpha; g.beta = beta; g.B32 = B32; g.ldb32 = ldb32;
   g.D = D; g.ldd = ldd; g.d_double = d_double; g.eps = eps; g.part = part; g.tiles = tiles; g.cfg = cfg;
-  static bool init = false;
-  if (!init) {
-    hipError_t e = x3_init();
-    if (e != hipSuccess) return (int)e;
-    init = true;
-  }
+  const hipError_t e = ensure_x3();
+  if (e != hipSuccess) return (int)e;
   return (int)gemm_x3(epi, g, (hipStream_t)stream);
 }
 
 int64_t pfsm_test_x3_row_stride(int64_t K) { return x3_row_stride(K); }
+
+int pfsm_test_cholesky(double* S, int64_t lds, int64_t n, double* Tbuf, int* info, void* stream) {
+  return (int)cholesky_factor(S, lds, n, Tbuf, info, (hipStream_t)stream);
+}
+
+int pfsm_test_trsm(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t n, int64_t m, const double* Tbuf,
+                   void* stream) {
+  return (int)trsm_right_lt(L, ldl, X, ldx, n, m, Tbuf, (hipStream_t)stream);
+}
+
+int pfsm_test_chol_near_identity(double* S, int64_t lds, int64_t n, void* pk, double* P, double* L1, int64_t ldw,
+                                 double* colmax, double tol, int* info, void* stream) {
+  const hipError_t e = ensure_x3();
+  if (e != hipSuccess) return (int)e;
+  return (int)cholesky_near_identity(S, lds, n, (bf16_t*)pk, x3_row_stride(n), P, L1, ldw, colmax, tol, -1, info,
+                                     (hipStream_t)stream);
+}
 
 }  // extern "C"

@@ -26,6 +26,12 @@ def lib():
         L.pfsm_test_gemm_x3.restype = i32
         L.pfsm_test_x3_row_stride.argtypes = [i64]
         L.pfsm_test_x3_row_stride.restype = i64
+        L.pfsm_test_cholesky.argtypes = [vp, i64, i64, vp, vp, vp]
+        L.pfsm_test_cholesky.restype = i32
+        L.pfsm_test_trsm.argtypes = [vp, i64, vp, i64, i64, i64, vp, vp]
+        L.pfsm_test_trsm.restype = i32
+        L.pfsm_test_chol_near_identity.argtypes = [vp, i64, i64, vp, vp, vp, i64, vp, dbl, vp, vp]
+        L.pfsm_test_chol_near_identity.restype = i32
         _lib = L
     return _lib
 

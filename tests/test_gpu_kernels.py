@@ -134,3 +134,91 @@ def test_gemm_x3(dev, cfg, M, N, K):
     tol = 4 * K * 2.0 ** -24 * np.abs(A).max() * np.abs(B).max()
     assert np.max(np.abs(_np(C) - ref3)) <= tol
     assert np.max(np.abs(_np(C) - A @ B)) <= 2.0 ** -14 * np.sqrt(K) * np.abs(A).max() * np.abs(B).max() + tol
+
+
+# ------------------------------------------------------------ Cholesky (overlap factor)
+def _spd(n, seed):
+    g = np.random.default_rng(seed)
+    G = g.standard_normal((n, n))
+    return np.eye(n) + G @ G.T / n
+
+
+@pytest.mark.parametrize("n", [64, 200, 1100])
+def test_cholesky_blocked_vs_oracle(dev, n):
+    """Blocked FP64 factor (64-wide register blocks, 512-wide panels) against the
+    oracle's column Cholesky, on sizes with a ragged last block and two panels."""
+    from oracle.pfsm_ref import cholesky_lower
+    S0 = _spd(n, n)
+    S = _cm(S0, dev)
+    T = torch.empty(((n + 63) // 64) * 4096, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    assert lib().pfsm_test_cholesky(_p(S), n, n, _p(T), _p(info), _stream()) == 0
+    torch.cuda.synchronize()
+    L_ref, info_ref = cholesky_lower(S0)
+    assert int(info.item()) == info_ref == 0
+    L = np.tril(_np(S))
+    assert np.max(np.abs(L - L_ref)) <= 64 * n * U64 * np.abs(L_ref).max()
+    # X <- X L^{-T} with the same factor and block inverses
+    m = 150
+    X0 = np.random.default_rng(n + 1).standard_normal((m, n))
+    X = _cm(X0, dev)
+    assert lib().pfsm_test_trsm(_p(S), n, _p(X), m, n, m, _p(T), _stream()) == 0
+    torch.cuda.synchronize()
+    ref = np.linalg.solve(L_ref, X0.T).T
+    assert np.max(np.abs(_np(X) - ref)) <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,k", [(200, 0), (200, 130), (1100, 777)])
+def test_cholesky_breakdown_column(dev, n, k):
+    """A non-positive pivot at global column k reports info = k + 1 (first one wins)."""
+    from oracle.pfsm_ref import cholesky_lower
+    S0 = np.eye(n)
+    S0[k, k] = -1.0
+    S0[min(k + 5, n - 1), min(k + 5, n - 1)] = -2.0
+    S = _cm(S0, dev)
+    T = torch.empty(((n + 63) // 64) * 4096, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    assert lib().pfsm_test_cholesky(_p(S), n, n, _p(T), _p(info), _stream()) == 0
+    torch.cuda.synchronize()
+    assert int(info.item()) == cholesky_lower(S0)[1] == k + 1
+
+
+def _near_identity_run(S0, dev, tol=1e-7):
+    n = S0.shape[0]
+    S = _cm(S0, dev)
+    ldp = int(lib().pfsm_test_x3_row_stride(n))
+    pk = torch.empty(n * ldp, dtype=torch.int16, device=dev)
+    P = torch.empty((n, n), dtype=torch.float64, device=dev)
+    L1 = torch.empty((n, n), dtype=torch.float64, device=dev)
+    colmax = torch.empty(n, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    assert lib().pfsm_test_chol_near_identity(_p(S), n, n, _p(pk), _p(P), _p(L1), n, _p(colmax), tol, _p(info),
+                                              _stream()) == 0
+    torch.cuda.synchronize()
+    return np.tril(_np(S)), int(info.item())
+
+
+@pytest.mark.parametrize("n,eps", [(300, 1e-4), (1000, 3e-5), (1000, 4e-4)])
+def test_cholesky_near_identity_vs_oracle(dev, n, eps):
+    """Fixed-point factor of S = X^T X with X = I + eps G (the overlap after the
+    folded-spectrum iterations is of this kind) against the oracle's Cholesky."""
+    from oracle.pfsm_ref import cholesky_lower
+    g = np.random.default_rng(n)
+    X = np.eye(n) + eps * g.standard_normal((n, n)) / np.sqrt(n) * 10
+    S0 = X.T @ X
+    L_ref, info_ref = cholesky_lower(S0)
+    L, info = _near_identity_run(S0, dev)
+    assert info == info_ref == 0
+    K = np.abs(L_ref - np.eye(n)).max()
+    # fixed-point truncation after two steps (3e-10 at the largest case here, from
+    # an FP64 emulation) plus split-BF16 rounding of K K^T (relative 2^-16)
+    assert np.max(np.abs(L - L_ref)) <= 2e-9 + 2.0 ** -12 * np.sqrt(n) * K * K
+
+
+def test_cholesky_near_identity_flags_far_input(dev):
+    """An overlap matrix far from the identity does not converge in two steps: info -2."""
+    n = 300
+    g = np.random.default_rng(5)
+    X = np.eye(n) + 0.3 * g.standard_normal((n, n)) / np.sqrt(n)
+    L, info = _near_identity_run(X.T @ X, dev)
+    assert info == -2
