@@ -7,6 +7,7 @@
 #include "misc.h"
 #include "gemm_x3.h"
 #include "refine.h"
+#include "gemm_oz.h"
 
 #include <algorithm>
 #include <new>
@@ -49,6 +50,7 @@ struct pfsm_plan {
       o_scal, o_glo, o_ghi, o_den, total;
   // mixed-precision workspace (byte offsets)
   size_t m_At32, m_X32, m_Y32, m_S64, m_Apk, m_Vpk, m_Atpk, m_Xpk, m_Ypk, m_Rpk, m_rb;
+  size_t m_oz;  // digit planes of A and V_new for the refinement product, then 2n exponents
 };
 
 namespace {
@@ -211,7 +213,8 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   size_t o_ps = tb; tb = align256(tb + P * sizeof(int64_t));
   size_t o_kr = tb; tb = align256(tb + pl->krange.size() * sizeof(int32_t));
   size_t o_k3 = tb; tb = align256(tb + pl->krange_x3.size() * sizeof(int32_t));
-  if (hipGetDevice(&pl->device) != hipSuccess || x3_init() != hipSuccess || hipMalloc(&pl->dtab, tb) != hipSuccess) {
+  if (hipGetDevice(&pl->device) != hipSuccess || x3_init() != hipSuccess || oz_init() != hipSuccess ||
+      hipMalloc(&pl->dtab, tb) != hipSuccess) {
     delete pl;
     return PFSM_HIP_ERROR;
   }
@@ -275,6 +278,15 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     pl->m_Ypk = w; w = align256(w + PK);
     pl->m_Rpk = w; w = align256(w + PK);
     pl->m_rb = w; w = align256(w + (size_t)(7 * n + 8) * sizeof(double));
+    // The refinement runs after the packed copies of A, V and At are dead:
+    // its digit planes reuse that span when they fit (they do when n is a
+    // multiple of 128), else they get their own region.
+    const size_t oz = align256(2 * oz_plane_bytes(n, n, REFINE_OZ_SLICES)) + 2 * n * sizeof(int);
+    if (oz <= pl->m_Xpk - pl->m_Apk) {
+      pl->m_oz = pl->m_Apk;
+    } else {
+      pl->m_oz = w; w = align256(w + oz);
+    }
   }
   pl->total = w;
   *out = pl;
@@ -579,9 +591,14 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   clk.mark(24);
   // (6) FP64 refinement: Z = A V_new, Rayleigh quotients, cluster Rayleigh-Ritz, order.
   {
-    GemmArgs g = {};
-    g.M = n; g.N = n; g.K = n; g.A = dA; g.lda = lda; g.B = Vn64; g.ldb = n; g.C = B64a; g.ldc = n; g.alpha = 1.0;
-    PFSM_TRY(gemm_f64(true, false, EPI_STORE, g, s));  // Z = A V_new (A symmetric)
+    // Z = A V_new to FP64 accuracy on the int8 matrix cores: digits of the
+    // rows of A (its columns, A symmetric) and of the columns of V_new.
+    int8_t* ozA = (int8_t*)(W + pl->m_oz);
+    int8_t* ozV = ozA + oz_plane_bytes(n, n, REFINE_OZ_SLICES);
+    int* ozE = (int*)(W + pl->m_oz + align256(2 * oz_plane_bytes(n, n, REFINE_OZ_SLICES)));
+    PFSM_TRY(oz_split(dA, lda, n, n, REFINE_OZ_SLICES, ozA, ozE, info, s));
+    PFSM_TRY(oz_split(Vn64, n, n, n, REFINE_OZ_SLICES, ozV, ozE + n, info, s));
+    PFSM_TRY(gemm_oz(n, n, n, REFINE_OZ_SLICES, ozA, ozE, ozV, ozE + n, B64a, n, s));
     RefineBufs b;
     b.d = rb; b.nn = rb + n; b.lam_s = rb + 2 * n;
     b.rank = (int*)(rb + 3 * n); b.inv = (int*)(rb + 4 * n); b.cstart = (int*)(rb + 5 * n);

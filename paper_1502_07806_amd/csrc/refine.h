@@ -4,6 +4,9 @@ namespace pfsm {
 constexpr int REFINE_KMAX = 32;         // largest cluster handled by one Rayleigh-Ritz block
 constexpr double REFINE_TAU = 1e-4;     // relative gap below which neighbours are refined together
 constexpr int PFSM_INFO_SERIES = -2;    // orthonormalisation series outside its range (mixed path)
+// Digits per operand of the refinement product Z = A V_new on the int8 matrix
+// cores (error about 2^-42 sqrt(n) of the row and column maxima).
+constexpr int REFINE_OZ_SLICES = 6;
 
 struct RefineBufs {
   double* d;       // [n] v_j^T z_j

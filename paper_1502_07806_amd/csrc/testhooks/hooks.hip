@@ -4,6 +4,7 @@
 #include "../common.h"
 #include "../gemm_x3.h"
 #include "../chol.h"
+#include "../gemm_oz.h"
 
 using namespace pfsm;
 
@@ -64,5 +65,23 @@ int pfsm_test_chol_near_identity(double* S, int64_t lds, int64_t n, void* pk, do
   return (int)cholesky_near_identity(S, lds, n, (bf16_t*)pk, x3_row_stride(n), P, L1, ldw, colmax, tol, -1, info,
                                      (hipStream_t)stream);
 }
+
+int pfsm_test_oz_split(const double* X, int64_t ldx, int64_t K, int64_t ncols, int s, void* P, int* expo, int* info,
+                       void* stream) {
+  return (int)oz_split(X, ldx, K, ncols, s, (int8_t*)P, expo, info, (hipStream_t)stream);
+}
+
+int pfsm_test_gemm_oz(int64_t M, int64_t N, int64_t K, int s, const void* Ap, const int* ea, const void* Bp,
+                      const int* eb, double* C, int64_t ldc, void* stream) {
+  static bool init = false;
+  if (!init) {
+    const hipError_t e = oz_init();
+    if (e != hipSuccess) return (int)e;
+    init = true;
+  }
+  return (int)gemm_oz(M, N, K, s, (const int8_t*)Ap, ea, (const int8_t*)Bp, eb, C, ldc, (hipStream_t)stream);
+}
+
+int64_t pfsm_test_oz_row_stride(int64_t K) { return oz_row_stride(K); }
 
 }  // extern "C"

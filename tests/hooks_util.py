@@ -32,6 +32,12 @@ def lib():
         L.pfsm_test_trsm.restype = i32
         L.pfsm_test_chol_near_identity.argtypes = [vp, i64, i64, vp, vp, vp, i64, vp, dbl, vp, vp]
         L.pfsm_test_chol_near_identity.restype = i32
+        L.pfsm_test_oz_split.argtypes = [vp, i64, i64, i64, i32, vp, vp, vp, vp]
+        L.pfsm_test_oz_split.restype = i32
+        L.pfsm_test_gemm_oz.argtypes = [i64, i64, i64, i32, vp, vp, vp, vp, vp, i64, vp]
+        L.pfsm_test_gemm_oz.restype = i32
+        L.pfsm_test_oz_row_stride.argtypes = [i64]
+        L.pfsm_test_oz_row_stride.restype = i64
         _lib = L
     return _lib
 
@@ -49,3 +55,20 @@ def split_hi_lo(x):
     hi = bf16_round(x.astype(np.float32)).astype(np.float64)
     lo = bf16_round((x - hi).astype(np.float32)).astype(np.float64)
     return hi, lo
+
+
+def oz_digits(X, s):
+    """Digits of the columns of X as the int8 digit GEMM defines them: each column
+    scaled by 2^-e (e the frexp exponent of its largest magnitude), then s
+    round-to-nearest-even digits of the remainder, the first at weight 2^-6 and
+    each next one 2^-7 smaller.  Returns (list of s float arrays, e)."""
+    X = np.asarray(X, np.float64)
+    mx = np.max(np.abs(X), axis=0)
+    e = np.where(mx > 0, np.frexp(mx)[1], 0).astype(np.int64)
+    t = np.ldexp(X, (6 - e)[None, :])
+    D = []
+    for _ in range(s):
+        d = np.rint(t)
+        D.append(d)
+        t = (t - d) * 128.0
+    return D, e

@@ -222,3 +222,73 @@ def test_cholesky_near_identity_flags_far_input(dev):
     X = np.eye(n) + 0.3 * g.standard_normal((n, n)) / np.sqrt(n)
     L, info = _near_identity_run(X.T @ X, dev)
     assert info == -2
+
+
+# ------------------------------------------------------------ int8 digit GEMM (FP64-accurate products)
+def _oz_split_dev(X, s, dev):
+    """GPU digits of the columns of X: (planes as numpy [s, ncols, ldp] int8, exponents, info)."""
+    K, nc = X.shape
+    ldp = int(lib().pfsm_test_oz_row_stride(K))
+    P = torch.full((s * nc * ldp,), 7, dtype=torch.int8, device=dev)
+    ex = torch.empty(nc, dtype=torch.int32, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    Xd = _cm(X, dev)
+    assert lib().pfsm_test_oz_split(_p(Xd), K, K, nc, s, _p(P), _p(ex), _p(info), _stream()) == 0
+    torch.cuda.synchronize()
+    return P, P.cpu().numpy().reshape(s, nc, ldp), ex.cpu().numpy(), int(info.item()), ldp, ex
+
+
+def test_oz_split_digits(dev):
+    from hooks_util import oz_digits
+    g = np.random.default_rng(21)
+    K, nc, s = 300, 70, 6
+    X = g.standard_normal((K, nc)) * np.exp(3 * g.standard_normal((1, nc))) * np.exp(g.standard_normal((K, nc)))
+    X[:, 5] = 0.0
+    X[:, 6] = 0.5  # exact power of two at the maximum
+    _, planes, ex, info, ldp, _ = _oz_split_dev(X, s, dev)
+    D, e = oz_digits(X, s)
+    assert info == 0
+    assert np.array_equal(ex, e)
+    for p in range(s):
+        assert np.array_equal(planes[p, :, :K].astype(np.float64), D[p].T)
+        assert np.all(planes[p, :, K:] == 0)
+        assert np.abs(planes[p]).max() <= 64
+    rec = sum(np.ldexp(D[p], (e - 6 - 7 * p)[None, :]) for p in range(s))
+    assert np.all(np.abs(rec - X) <= np.ldexp(1.0, e - 7 * s)[None, :])
+
+
+def test_oz_split_nonfinite(dev):
+    X = np.ones((130, 3))
+    X[7, 1] = np.nan
+    _, planes, ex, info, _, _ = _oz_split_dev(X, 3, dev)
+    assert info == -1
+    assert np.all(planes[:, 1, :] == 0)
+    assert np.all(planes[0, 0, :130] == 32) and np.all(planes[1:, 0, :] == 0)  # 1 = 32 * 2^(1 - 6)
+
+
+@pytest.mark.parametrize("M,N,K,s", [(300, 270, 1000, 6), (256, 512, 128, 4), (33, 600, 257, 5)])
+def test_gemm_oz(dev, M, N, K, s):
+    """C = A B from digits: equal (to FP64 rounding of the group sums) to the same
+    truncated digit expansion evaluated in FP64 from digits made on the host, and
+    within the truncation bound of the FP64 product."""
+    from hooks_util import oz_digits
+    g = np.random.default_rng(M + N + K + s)
+    A = g.standard_normal((M, K)) * np.exp(g.standard_normal((M, 1)))
+    B = g.standard_normal((K, N)) * np.exp(g.standard_normal((1, N)))
+    Ap, _, ea_h, info_a, _, ea = _oz_split_dev(A.T, s, dev)   # rows of A
+    Bp, _, eb_h, info_b, _, eb = _oz_split_dev(B, s, dev)     # columns of B
+    assert info_a == info_b == 0
+    C = torch.empty((N, M), dtype=torch.float64, device=dev).t()
+    assert lib().pfsm_test_gemm_oz(M, N, K, s, _p(Ap), _p(ea), _p(Bp), _p(eb), _p(C), M, _stream()) == 0
+    torch.cuda.synchronize()
+    Da, e_a = oz_digits(A.T, s)
+    Db, e_b = oz_digits(B, s)
+    ref = np.zeros((M, N))
+    for grp in range(s + 1, 1, -1):
+        G = sum(Da[p - 1].T @ Db[grp - p - 1] for p in range(max(1, grp - s), min(s, grp - 1) + 1))
+        ref += np.ldexp(G, -12 - 7 * (grp - 2))  # integer-valued G: exact in FP64
+    ref = ref * np.ldexp(1.0, e_a)[:, None] * np.ldexp(1.0, e_b)[None, :]
+    out = _np(C)
+    scale = np.ldexp(1.0, e_a)[:, None] * np.ldexp(1.0, e_b)[None, :]
+    assert np.max(np.abs(out - ref) / scale) <= 8 * U64 * K
+    assert np.max(np.abs(out - A @ B) / scale) <= 2 * s * K * 2.0 ** (-7 * s)

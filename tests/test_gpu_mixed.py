@@ -89,8 +89,11 @@ def test_mixed_full_size(pf):
     Vs = Vo[:, cols]
     nrm = torch.linalg.vector_norm(Vs, dim=0).cpu().numpy()
     assert np.max(np.abs(nrm - 1.0)) <= 1e-12
+    # returned eigenvalues are the Rayleigh quotients of the returned vectors, up
+    # to the error of the refinement product A V_new (int8 digit product with 6
+    # digits: about 2^-42 sqrt(n) max|A| max|V| per entry, 1e-11 here)
     rq = torch.sum(Vs * (A @ Vs), dim=0).cpu().numpy()
-    assert np.max(np.abs(rq - lam_np[cols.cpu().numpy()])) <= 1e-12
+    assert np.max(np.abs(rq - lam_np[cols.cpu().numpy()])) <= 1e-10
 
 
 def test_mixed_failure_modes(pf):
