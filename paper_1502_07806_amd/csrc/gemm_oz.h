@@ -38,7 +38,8 @@ hipError_t oz_split(const double* X, int64_t ldx, int64_t K, int64_t ncols, int 
 // both split with the same s and K.  One launch per weight group, smallest
 // weights first, the first one storing and the others adding.
 hipError_t gemm_oz(int64_t M, int64_t N, int64_t K, int s, const int8_t* Ap, const int* ea, const int8_t* Bp,
-                   const int* eb, double* C, int64_t ldc, hipStream_t st);
+                   const int* eb, double* C, int64_t ldc, hipStream_t st, int cfg = -1);
+extern int oz_default_cfg;  // tile configuration used when cfg < 0
 
 hipError_t oz_init();  // once per process and device, before the first launch (large dynamic LDS)
 

@@ -1,14 +1,10 @@
-// Int8 digit GEMM (see gemm_oz.h).  Block tile 256 x 256 x 128 (k bytes),
-// 256 threads = 4 waves in 2 x 2, wave tile 128 x 128 = 4 x 4 blocks of
-// v_mfma_i32_32x32x32_i8: one wave per SIMD with 256 int32 accumulators per
-// lane, 8 fragment reads per 16 MFMAs (half the LDS rate).  Operand tiles go
-// global -> registers -> LDS, double buffered, 144-byte rows so that the
-// 16-byte fragment reads of consecutive rows fall in distinct banks.  The
-// MFMA takes the B fragment first, so a lane's accumulators run along a row
-// of C and one register across lanes runs down a column (contiguous
-// column-major stores).  The k loop of one launch walks every digit pair
-// (p, q) of one weight group back to back: the int32 sum of the group is
-// exact, and the epilogue scales it by its power of two into FP64.
+// Int8 digit GEMM (see gemm_oz.h).  Block tile 256 x 256, 512 threads = 8
+// waves (two per SIMD), blocks of v_mfma_i32_32x32x32_i8.  The MFMA takes the
+// B fragment first, so a lane's accumulators run along a row of C and one
+// register across lanes runs down a column (contiguous column-major
+// stores).  The k loop walks every digit pair (p, q) of a weight group back
+// to back: the int32 sum of the group is exact, and the epilogue scales it
+// by its power of two into FP64.
 #include "common.h"
 #include "gemm_oz.h"
 
@@ -19,11 +15,20 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int BM = OZ_BM, BN = OZ_BN, BK = OZ_BK;
-constexpr int NT = 256;
 constexpr int ROWB = BK + 16;        // LDS bytes per operand row
 constexpr int TILE = BM * ROWB;      // 36864 bytes per operand per stage
-constexpr int WR = 4, WC = 4;        // 32 x 32 blocks per wave
-constexpr int LQ = BM * (BK / 16) / NT;  // 16-byte chunks per thread and operand (8)
+
+// Tile configurations (all 256 x 256 block tiles, 8 waves, two per SIMD):
+//   CFG 0: one launch for all weight groups, direct-to-LDS 4-stage ring,
+//          waves in 2 x 4 of 128 x 64 (gemm_oz_fused; the default)
+//   CFG 1: CFG 0 with waves in 4 x 2 of 64 x 128
+//   CFG 2: one launch per weight group, direct-to-LDS ring (gemm_oz_dl), 4 x 2
+//   CFG 3: one launch per weight group, tiles staged through registers into
+//          double-buffered LDS (gemm_oz_kernel), 4 x 2
+// The per-group kernels keep the running sum in C (read-modify-write per
+// launch); the fused kernel pays that launch and epilogue cost once per tile.
+template <int CFG> struct OzCfg;
+template <> struct OzCfg<3> { static constexpr int NT = 512, WGR = 4, WR = 2, WC = 4; };
 
 struct OzArgs {
   int64_t M, N, ldp, pa, pb;  // ldp: digit-row stride; pa / pb: plane strides (bytes)
@@ -42,7 +47,10 @@ __device__ inline int xcd_remap(int b, int total) {
   return (b % 8) * (total / 8) + b / 8;
 }
 
-__global__ __launch_bounds__(NT, 1) void gemm_oz_kernel(OzArgs a, int tiles_m, int tiles_n) {
+template <int CFG>
+__global__ __launch_bounds__(OzCfg<CFG>::NT, 1) void gemm_oz_kernel(OzArgs a, int tiles_m, int tiles_n) {
+  constexpr int NT = OzCfg<CFG>::NT, WGR = OzCfg<CFG>::WGR, WR = OzCfg<CFG>::WR, WC = OzCfg<CFG>::WC;
+  constexpr int LQ = BM * (BK / 16) / NT;  // 16-byte chunks per thread and operand
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   unsigned char* As = lds;              // [2][BM][ROWB]
   unsigned char* Bs = lds + 2 * TILE;   // [2][BN][ROWB]
@@ -57,7 +65,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_oz_kernel(OzArgs a, int tiles_m, i
   }
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wi0 = (wave & 1) * (32 * WR), wj0 = (wave >> 1) * (32 * WC);
+  const int wi0 = (wave % WGR) * (32 * WR), wj0 = (wave / WGR) * (32 * WC);
   const int l32 = lane & 31, lh = lane >> 5;
   // digit pairs of the group: p + q = g with 1 <= p, q <= s
   const int p_lo = max(1, a.g - a.s);
@@ -72,7 +80,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_oz_kernel(OzArgs a, int tiles_m, i
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
 
-  const int chunk = tid & 7, rbase = tid >> 3;  // rows rbase + 32 q
+  const int chunk = tid & 7, rbase = tid >> 3;  // rows rbase + (NT / 8) u
   v4i ra[LQ], rb[LQ];
   auto load_tile = [&](int t) {
     const int pair = t / a.ntk, kt = t - pair * a.ntk;
@@ -146,6 +154,283 @@ __global__ __launch_bounds__(NT, 1) void gemm_oz_kernel(OzArgs a, int tiles_m, i
   }
 }
 
+// Direct global -> LDS loads (16 bytes per lane, no register
+// staging) into a 4-stage ring of 64-byte k tiles, so loads run three tiles
+// ahead of the matrix cores.  A wave-wide load fills 1 KB of LDS in lane
+// order, i.e. 16 rows of 64 bytes; the lane -> global mapping applies the XOR
+// swizzle chunk ^ ((row >> 1) ^ (row >> 2)) & 3, which keeps the fragment
+// reads of 8 and of 16 consecutive rows in distinct banks.  Rows past the
+// matrix edge read the last row (their outputs are not stored).
+constexpr int DBK = 64, DST = 4, DTILE = BM * DBK;  // 16 KB per operand and stage
+
+__device__ inline int dswz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
+template <int WAITS> __device__ inline void wait_vm() {
+  // vmcnt = WAITS (0..63); expcnt and lgkmcnt left at their maxima
+  __builtin_amdgcn_s_waitcnt((WAITS & 15) | (7 << 4) | (15 << 8) | (((WAITS >> 4) & 3) << 14));
+}
+
+template <int NT, int WGR, int WR, int WC>
+__global__ __launch_bounds__(NT, 1) void gemm_oz_dl(OzArgs a, int tiles_m, int tiles_n) {
+  constexpr int NW = NT / 64;
+  constexpr int CPW = 16 / NW;  // 1 KB row groups per wave, operand and stage
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  int tm, tn;
+  {
+    const int t = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+    const int GROUP = 4;
+    const int first_m = (t / (GROUP * tiles_n)) * GROUP;
+    const int gsz = min(tiles_m - first_m, GROUP);
+    tm = first_m + (t % (GROUP * tiles_n)) % gsz;
+    tn = (t % (GROUP * tiles_n)) / gsz;
+  }
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wi0 = (wave % WGR) * (32 * WR), wj0 = (wave / WGR) * (32 * WC);
+  const int l32 = lane & 31, lh = lane >> 5;
+  const int p_lo = max(1, a.g - a.s);
+  const int p_hi = min(a.s, a.g - 1);
+  const int ntk = (int)(a.ldp / DBK);
+  const int total = (p_hi - p_lo + 1) * ntk;
+
+  int64_t offA[CPW], offB[CPW];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int row = 16 * (wave * CPW + j) + (lane >> 2);
+    const int c = (lane & 3) ^ dswz(row);
+    offA[j] = min<int64_t>(m0 + row, a.M - 1) * a.ldp + 16 * c;
+    offB[j] = min<int64_t>(n0 + row, a.N - 1) * a.ldp + 16 * c;
+  }
+  auto issue = [&](int t) {
+    const int pair = t / ntk, kt = t - pair * ntk;
+    const int p = p_lo + pair, q = a.g - p;
+    const int8_t* A = a.Ap + (int64_t)(p - 1) * a.pa + (int64_t)kt * DBK;
+    const int8_t* B = a.Bp + (int64_t)(q - 1) * a.pb + (int64_t)kt * DBK;
+    unsigned char* sA = lds + (t % DST) * 2 * DTILE;
+    unsigned char* sB = sA + DTILE;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(A + offA[j]),
+                                       (void __attribute__((address_space(3)))*)(sA + (wave * CPW + j) * 1024), 16, 0,
+                                       0);
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(B + offB[j]),
+                                       (void __attribute__((address_space(3)))*)(sB + (wave * CPW + j) * 1024), 16, 0,
+                                       0);
+    }
+  };
+
+  v16i acc[WR][WC];
+#pragma unroll
+  for (int i = 0; i < WR; ++i)
+#pragma unroll
+    for (int j = 0; j < WC; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+
+  for (int t = 0; t < DST - 1 && t < total; ++t) issue(t);
+  for (int t = 0; t < total; ++t) {
+    // tile t has landed once at most min(DST - 2, total - 1 - t) later tiles are outstanding
+    const int later = min(DST - 2, total - 1 - t);
+    if (later >= 2) wait_vm<2 * 2 * CPW>();
+    else if (later == 1) wait_vm<2 * CPW>();
+    else wait_vm<0>();
+    // Bare barrier: a fenced one would wait for every outstanding load.  After
+    // it, every wave's part of tile t is in LDS (each waited for its own
+    // loads above) and stage (t - 1) % DST is free (its fragments were
+    // consumed by MFMAs before the barrier).
+    __builtin_amdgcn_s_barrier();
+    if (t + DST - 1 < total) issue(t + DST - 1);
+    const unsigned char* Ab = lds + (t % DST) * 2 * DTILE;
+    const unsigned char* Bb = Ab + DTILE;
+#pragma unroll
+    for (int sub = 0; sub < DBK / 32; ++sub) {
+      const int c = 2 * sub + lh;  // logical 16-byte chunk of this lane's k values
+      v4i af[WR], bf[WC];
+#pragma unroll
+      for (int ib = 0; ib < WR; ++ib) {
+        const int row = wi0 + ib * 32 + l32;
+        af[ib] = *(const v4i*)(Ab + row * DBK + 16 * (c ^ dswz(row)));
+      }
+#pragma unroll
+      for (int jb = 0; jb < WC; ++jb) {
+        const int row = wj0 + jb * 32 + l32;
+        bf[jb] = *(const v4i*)(Bb + row * DBK + 16 * (c ^ dswz(row)));
+      }
+#pragma unroll
+      for (int ib = 0; ib < WR; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < WC; ++jb)
+          acc[ib][jb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[jb], af[ib], acc[ib][jb], 0, 0, 0);
+    }
+  }
+
+  const int shift = -12 - 7 * (a.g - 2);
+#pragma unroll
+  for (int ib = 0; ib < WR; ++ib) {
+    const int64_t gi = m0 + wi0 + ib * 32 + l32;
+    if (gi >= a.M) continue;
+    const int ei = a.ea[gi] + shift;
+#pragma unroll
+    for (int jb = 0; jb < WC; ++jb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
+        if (gj >= a.N) continue;
+        const double v = ldexp((double)acc[ib][jb][r], ei + a.eb[gj]);
+        double* cp = a.C + gi + gj * a.ldc;
+        *cp = a.first ? v : *cp + v;
+      }
+  }
+}
+
+// One launch for all weight groups.  Each workgroup walks the
+// k tiles of every digit pair of every group of its own output tile as one
+// sequence through the direct-to-LDS ring (so loads keep running ahead across
+// pair and group boundaries), and at the end of each group adds the scaled
+// int32 group sum into C (read-modify-write of its own tile only: no other
+// workgroup touches it).  Groups run from the smallest weights up.
+struct OzCursor {
+  int g, p, kt;  // weight group, first digit index of the pair, k tile
+};
+
+template <int NT, int WGR, int WR, int WC>
+__global__ __launch_bounds__(NT, 1) void gemm_oz_fused(OzArgs a, int tiles_m, int tiles_n) {
+  constexpr int NW = NT / 64;
+  constexpr int CPW = 16 / NW;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  int tm, tn;
+  {
+    const int t = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+    const int GROUP = 4;
+    const int first_m = (t / (GROUP * tiles_n)) * GROUP;
+    const int gsz = min(tiles_m - first_m, GROUP);
+    tm = first_m + (t % (GROUP * tiles_n)) % gsz;
+    tn = (t % (GROUP * tiles_n)) / gsz;
+  }
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wi0 = (wave % WGR) * (32 * WR), wj0 = (wave / WGR) * (32 * WC);
+  const int l32 = lane & 31, lh = lane >> 5;
+  const int ntk = (int)(a.ldp / DBK);
+  const int S = a.s;
+  // total k tiles over all groups: s (s + 1) / 2 pairs
+  const int total = S * (S + 1) / 2 * ntk;
+  auto plo = [&](int g) { return max(1, g - S); };
+  auto phi = [&](int g) { return min(S, g - 1); };
+  auto advance = [&](OzCursor& c) {
+    if (++c.kt == ntk) {
+      c.kt = 0;
+      if (++c.p > phi(c.g)) {
+        --c.g;
+        c.p = plo(c.g);
+      }
+    }
+  };
+
+  int64_t offA[CPW], offB[CPW];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int row = 16 * (wave * CPW + j) + (lane >> 2);
+    const int c = (lane & 3) ^ dswz(row);
+    offA[j] = min<int64_t>(m0 + row, a.M - 1) * a.ldp + 16 * c;
+    offB[j] = min<int64_t>(n0 + row, a.N - 1) * a.ldp + 16 * c;
+  }
+  auto issue = [&](const OzCursor& c, int t) {
+    const int q = c.g - c.p;
+    const int8_t* A = a.Ap + (int64_t)(c.p - 1) * a.pa + (int64_t)c.kt * DBK;
+    const int8_t* B = a.Bp + (int64_t)(q - 1) * a.pb + (int64_t)c.kt * DBK;
+    unsigned char* sA = lds + (t % DST) * 2 * DTILE;
+    unsigned char* sB = sA + DTILE;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(A + offA[j]),
+                                       (void __attribute__((address_space(3)))*)(sA + (wave * CPW + j) * 1024), 16, 0,
+                                       0);
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(B + offB[j]),
+                                       (void __attribute__((address_space(3)))*)(sB + (wave * CPW + j) * 1024), 16, 0,
+                                       0);
+    }
+  };
+
+  v16i acc[WR][WC];
+  auto zero = [&]() {
+#pragma unroll
+    for (int i = 0; i < WR; ++i)
+#pragma unroll
+      for (int j = 0; j < WC; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+  };
+  auto flush = [&](int g, bool first) {
+    const int shift = -12 - 7 * (g - 2);
+#pragma unroll
+    for (int ib = 0; ib < WR; ++ib) {
+      const int64_t gi = m0 + wi0 + ib * 32 + l32;
+      if (gi >= a.M) continue;
+      const int ei = a.ea[gi] + shift;
+#pragma unroll
+      for (int jb = 0; jb < WC; ++jb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
+          if (gj >= a.N) continue;
+          const double v = ldexp((double)acc[ib][jb][r], ei + a.eb[gj]);
+          double* cp = a.C + gi + gj * a.ldc;
+          *cp = first ? v : *cp + v;
+        }
+    }
+  };
+  zero();
+
+  OzCursor cc = {S + 1, plo(S + 1), 0};  // compute cursor
+  OzCursor ic = cc;                       // issue cursor
+  for (int t = 0; t < DST - 1 && t < total; ++t) {
+    issue(ic, t);
+    advance(ic);
+  }
+  for (int t = 0; t < total; ++t) {
+    const int later = min(DST - 2, total - 1 - t);
+    if (later >= 2) wait_vm<2 * 2 * CPW>();
+    else if (later == 1) wait_vm<2 * CPW>();
+    else wait_vm<0>();
+    __builtin_amdgcn_s_barrier();  // as in gemm_oz_dl
+    if (t + DST - 1 < total) {
+      issue(ic, t + DST - 1);
+      advance(ic);
+    }
+    const unsigned char* Ab = lds + (t % DST) * 2 * DTILE;
+    const unsigned char* Bb = Ab + DTILE;
+#pragma unroll
+    for (int sub = 0; sub < DBK / 32; ++sub) {
+      const int c = 2 * sub + lh;
+      v4i af[WR], bf[WC];
+#pragma unroll
+      for (int ib = 0; ib < WR; ++ib) {
+        const int row = wi0 + ib * 32 + l32;
+        af[ib] = *(const v4i*)(Ab + row * DBK + 16 * (c ^ dswz(row)));
+      }
+#pragma unroll
+      for (int jb = 0; jb < WC; ++jb) {
+        const int row = wj0 + jb * 32 + l32;
+        bf[jb] = *(const v4i*)(Bb + row * DBK + 16 * (c ^ dswz(row)));
+      }
+#pragma unroll
+      for (int ib = 0; ib < WR; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < WC; ++jb)
+          acc[ib][jb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[jb], af[ib], acc[ib][jb], 0, 0, 0);
+    }
+    const int g = cc.g;
+    advance(cc);
+    if (cc.g != g || t + 1 == total) {  // group g complete
+      flush(g, g == S + 1);
+      zero();
+    }
+  }
+}
+
 // One block per column: exponent of the column maximum, then the digits of
 // four consecutive k per thread (one 32-bit word per plane).
 __global__ __launch_bounds__(256) void k_oz_split(const double* X, int64_t ldx, int64_t K, int64_t ldp,
@@ -194,10 +479,23 @@ __global__ __launch_bounds__(256) void k_oz_split(const double* X, int64_t ldx, 
   }
 }
 
+
 }  // namespace
 
+int oz_default_cfg = 0;  // fastest measured at N = 8192
+
 hipError_t oz_init() {
-  return hipFuncSetAttribute((const void*)gemm_oz_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 4 * TILE);
+  hipError_t e = hipFuncSetAttribute((const void*)gemm_oz_kernel<3>, hipFuncAttributeMaxDynamicSharedMemorySize, 4 * TILE);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)gemm_oz_dl<512, 4, 2, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            DST * 2 * DTILE);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)gemm_oz_fused<512, 2, 4, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            DST * 2 * DTILE);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)gemm_oz_fused<512, 4, 2, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            DST * 2 * DTILE);
+  return e;
 }
 
 hipError_t oz_split(const double* X, int64_t ldx, int64_t K, int64_t ncols, int s, int8_t* P, int* expo, int* info,
@@ -211,7 +509,9 @@ hipError_t oz_split(const double* X, int64_t ldx, int64_t K, int64_t ncols, int 
 }
 
 hipError_t gemm_oz(int64_t M, int64_t N, int64_t K, int s, const int8_t* Ap, const int* ea, const int8_t* Bp,
-                   const int* eb, double* C, int64_t ldc, hipStream_t st) {
+                   const int* eb, double* C, int64_t ldc, hipStream_t st, int cfg) {
+  if (cfg < 0) cfg = oz_default_cfg;
+  if (cfg > 3) return hipErrorInvalidValue;
   if (s < 1 || s > OZ_MAX_SLICES || K < 0 || (int64_t)s * K >= (1 << 19)) return hipErrorInvalidValue;
   if (M <= 0 || N <= 0) return hipSuccess;
   OzArgs a = {};
@@ -219,10 +519,22 @@ hipError_t gemm_oz(int64_t M, int64_t N, int64_t K, int s, const int8_t* Ap, con
   a.Ap = Ap; a.Bp = Bp; a.ea = ea; a.eb = eb; a.C = C; a.ldc = ldc; a.s = s;
   a.ntk = (int)(a.ldp / BK);
   const int tm = (int)((M + BM - 1) / BM), tn = (int)((N + BN - 1) / BN);
+  const dim3 grid((unsigned)(tm * tn));
+  if (cfg == 0) {
+    hipLaunchKernelGGL((gemm_oz_fused<512, 2, 4, 2>), grid, dim3(512), DST * 2 * DTILE, st, a, tm, tn);
+    return hipGetLastError();
+  }
+  if (cfg == 1) {
+    hipLaunchKernelGGL((gemm_oz_fused<512, 4, 2, 4>), grid, dim3(512), DST * 2 * DTILE, st, a, tm, tn);
+    return hipGetLastError();
+  }
   for (int g = s + 1; g >= 2; --g) {  // smallest weights first
     a.g = g;
     a.first = (g == s + 1);
-    hipLaunchKernelGGL(gemm_oz_kernel, dim3((unsigned)(tm * tn)), dim3(NT), 4 * TILE, st, a, tm, tn);
+    if (cfg == 2)
+      hipLaunchKernelGGL((gemm_oz_dl<512, 4, 2, 4>), grid, dim3(512), DST * 2 * DTILE, st, a, tm, tn);
+    else
+      hipLaunchKernelGGL(gemm_oz_kernel<3>, grid, dim3(512), 4 * TILE, st, a, tm, tn);
   }
   return hipGetLastError();
 }

@@ -72,14 +72,14 @@ int pfsm_test_oz_split(const double* X, int64_t ldx, int64_t K, int64_t ncols, i
 }
 
 int pfsm_test_gemm_oz(int64_t M, int64_t N, int64_t K, int s, const void* Ap, const int* ea, const void* Bp,
-                      const int* eb, double* C, int64_t ldc, void* stream) {
+                      const int* eb, double* C, int64_t ldc, int cfg, void* stream) {
   static bool init = false;
   if (!init) {
     const hipError_t e = oz_init();
     if (e != hipSuccess) return (int)e;
     init = true;
   }
-  return (int)gemm_oz(M, N, K, s, (const int8_t*)Ap, ea, (const int8_t*)Bp, eb, C, ldc, (hipStream_t)stream);
+  return (int)gemm_oz(M, N, K, s, (const int8_t*)Ap, ea, (const int8_t*)Bp, eb, C, ldc, (hipStream_t)stream, cfg);
 }
 
 int64_t pfsm_test_oz_row_stride(int64_t K) { return oz_row_stride(K); }

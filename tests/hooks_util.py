@@ -34,7 +34,7 @@ def lib():
         L.pfsm_test_chol_near_identity.restype = i32
         L.pfsm_test_oz_split.argtypes = [vp, i64, i64, i64, i32, vp, vp, vp, vp]
         L.pfsm_test_oz_split.restype = i32
-        L.pfsm_test_gemm_oz.argtypes = [i64, i64, i64, i32, vp, vp, vp, vp, vp, i64, vp]
+        L.pfsm_test_gemm_oz.argtypes = [i64, i64, i64, i32, vp, vp, vp, vp, vp, i64, i32, vp]
         L.pfsm_test_gemm_oz.restype = i32
         L.pfsm_test_oz_row_stride.argtypes = [i64]
         L.pfsm_test_oz_row_stride.restype = i64

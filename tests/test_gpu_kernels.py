@@ -266,8 +266,9 @@ def test_oz_split_nonfinite(dev):
     assert np.all(planes[0, 0, :130] == 32) and np.all(planes[1:, 0, :] == 0)  # 1 = 32 * 2^(1 - 6)
 
 
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
 @pytest.mark.parametrize("M,N,K,s", [(300, 270, 1000, 6), (256, 512, 128, 4), (33, 600, 257, 5)])
-def test_gemm_oz(dev, M, N, K, s):
+def test_gemm_oz(dev, cfg, M, N, K, s):
     """C = A B from digits: equal (to FP64 rounding of the group sums) to the same
     truncated digit expansion evaluated in FP64 from digits made on the host, and
     within the truncation bound of the FP64 product."""
@@ -279,7 +280,7 @@ def test_gemm_oz(dev, M, N, K, s):
     Bp, _, eb_h, info_b, _, eb = _oz_split_dev(B, s, dev)     # columns of B
     assert info_a == info_b == 0
     C = torch.empty((N, M), dtype=torch.float64, device=dev).t()
-    assert lib().pfsm_test_gemm_oz(M, N, K, s, _p(Ap), _p(ea), _p(Bp), _p(eb), _p(C), M, _stream()) == 0
+    assert lib().pfsm_test_gemm_oz(M, N, K, s, _p(Ap), _p(ea), _p(Bp), _p(eb), _p(C), M, cfg, _stream()) == 0
     torch.cuda.synchronize()
     Da, e_a = oz_digits(A.T, s)
     Db, e_b = oz_digits(B, s)
