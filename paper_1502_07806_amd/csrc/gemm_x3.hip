@@ -24,6 +24,8 @@ constexpr int TILE_BYTES = BM * ROWB;     // 36864 per operand per stage
 //   CFG 3: CFG 0 plus an L2 warm-up load (one dword per 128-byte row chunk) of
 //          the K tile two steps ahead, consumed one step later, so first-touch
 //          HBM latency overlaps two tiles of matrix-core work
+//   CFG 4: 8 waves in 4 x 2 fed by direct global -> LDS loads into a 4-stage
+//          ring (gemm_x3_dl)
 template <int CFG> struct X3Cfg;
 template <> struct X3Cfg<0> { static constexpr int NT = 512, WGR = 2, WR = 4, WC = 2, PF = 0; };
 template <> struct X3Cfg<1> { static constexpr int NT = 256, WGR = 2, WR = 4, WC = 4, PF = 0; };
@@ -48,40 +50,32 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline v8bf as_bf(u32x4 v) { return __builtin_bit_cast(v8bf, v); }
 
-template <int EPI, int CFG>
-__global__ __launch_bounds__(X3Cfg<CFG>::NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, int tiles_n) {
-  constexpr int NT = X3Cfg<CFG>::NT, WGR = X3Cfg<CFG>::WGR, WR = X3Cfg<CFG>::WR, WC = X3Cfg<CFG>::WC;
-  constexpr int PF = X3Cfg<CFG>::PF;
-  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  unsigned char* As = lds;                       // [2][BM][ROWB]
-  unsigned char* Bs = lds + 2 * TILE_BYTES;      // [2][BN][ROWB]
-  __shared__ double red[WGR][BN];
-
-  int tm, tn;
-  {
-    int total;
-    if (g.tiles == X3_LOWER || g.tiles == X3_UPPER_TRI) total = tiles_m * (tiles_m + 1) / 2;
-    else total = tiles_m * tiles_n;
-    int t = xcd_remap(blockIdx.x, total);
-    if (g.tiles == X3_LOWER) {
-      tri_index(t, tm, tn);
-    } else if (g.tiles == X3_UPPER_TRI) {
-      tri_index(t, tn, tm);
-    } else {
-      const int GROUP = 4;
-      int group_id = t / (GROUP * tiles_n);
-      int first_m = group_id * GROUP;
-      int gsz = min(tiles_m - first_m, GROUP);
-      tm = first_m + (t % (GROUP * tiles_n)) % gsz;
-      tn = (t % (GROUP * tiles_n)) / gsz;
-    }
+// Output tile of this block: XCD-grouped, lower / upper triangle enumeration
+// for the triangular modes, otherwise groups of 4 row tiles sharing column tiles.
+__device__ inline void x3_tile_coords(const X3Args& g, int tiles_m, int tiles_n, int& tm, int& tn) {
+  int total;
+  if (g.tiles == X3_LOWER || g.tiles == X3_UPPER_TRI) total = tiles_m * (tiles_m + 1) / 2;
+  else total = tiles_m * tiles_n;
+  const int t = xcd_remap(blockIdx.x, total);
+  if (g.tiles == X3_LOWER) {
+    tri_index(t, tm, tn);
+  } else if (g.tiles == X3_UPPER_TRI) {
+    tri_index(t, tn, tm);
+  } else {
+    const int GROUP = 4;
+    const int first_m = (t / (GROUP * tiles_n)) * GROUP;
+    const int gsz = min(tiles_m - first_m, GROUP);
+    tm = first_m + (t % (GROUP * tiles_n)) % gsz;
+    tn = (t % (GROUP * tiles_n)) / gsz;
   }
-  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wi0 = (wave % WGR) * (32 * WR), wj0 = (wave / WGR) * (32 * WC);
-  const int l32 = lane & 31, lh = lane >> 5;
+}
 
-  int64_t kbeg = 0, kend = (g.K + 31) / 32 * 32;
+// k range of a tile (multiples of 32): the optional per-column-tile range,
+// clipped by the triangular structure of the operands in the UPPER_TRI and
+// KPREFIX modes.
+__device__ inline void x3_k_range(const X3Args& g, int tn, int64_t m0, int64_t n0, int64_t& kbeg, int64_t& kend) {
+  kbeg = 0;
+  kend = (g.K + 31) / 32 * 32;
   if (g.krange) {
     kbeg = g.krange[2 * tn];
     kend = g.krange[2 * tn + 1];
@@ -92,6 +86,99 @@ __global__ __launch_bounds__(X3Cfg<CFG>::NT, 1) void gemm_x3_kernel(X3Args g, in
   } else if (g.tiles == X3_KPREFIX) {
     kend = min<int64_t>(kend, n0 + BN);
   }
+}
+
+// Epilogue shared by the split-BF16 kernels: acc[ib][jb][r] is C(i, j) with
+// i = wi0 + 32 ib + lane % 32, j = wj0 + 32 jb + 8 (r / 4) + 4 (lane / 32) + r % 4.
+template <int EPI, int WGR, int WR, int WC>
+__device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t m0, int64_t n0, int wi0, int wj0,
+                                   int tid, int tm, double (*red)[BN]) {
+  const int lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, lh = lane >> 5;
+  if (EPI == X3_RQ) {
+    const float* D = (const float*)g.D;
+    double cs[WC][16];
+#pragma unroll
+    for (int jb = 0; jb < WC; ++jb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
+        double sum = 0.0;
+#pragma unroll
+        for (int ib = 0; ib < WR; ++ib) {
+          const int64_t gi = m0 + wi0 + ib * 32 + l32;
+          if (gi < g.M && gj < g.N) sum += (double)acc[ib][jb][r] * (double)D[gi + gj * g.ldd];
+        }
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) sum += __shfl_xor(sum, off, 64);
+        cs[jb][r] = sum;
+      }
+    if (l32 == 0) {
+#pragma unroll
+      for (int jb = 0; jb < WC; ++jb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[wave % WGR][wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4)] = cs[jb][r];
+    }
+    __syncthreads();
+    if (tid < BN) {
+      const int64_t gj = n0 + tid;
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < WGR; ++w) sum += red[w][tid];
+      if (gj < g.N) g.part[(int64_t)tm * g.N + gj] = sum;
+    }
+    return;
+  }
+  double a_eff = g.alpha;
+  if (EPI == X3_FSUPD && g.alpha_dev) a_eff = *g.alpha_dev;
+#pragma unroll
+  for (int ib = 0; ib < WR; ++ib) {
+    const int64_t gi = m0 + wi0 + ib * 32 + l32;
+    if (gi >= g.M) continue;
+#pragma unroll
+    for (int jb = 0; jb < WC; ++jb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
+        if (gj >= g.N) continue;
+        const double v = (double)acc[ib][jb][r];
+        double outv;
+        if (EPI == X3_STORE) {
+          outv = g.alpha * v;
+          if (g.beta != 0.0)
+            outv += g.beta * (g.c_double ? ((const double*)g.C)[gi + gj * g.ldc] : (double)((const float*)g.C)[gi + gj * g.ldc]);
+        } else if (EPI == X3_SHIFT) {
+          outv = v - (double)g.B32[gi + gj * g.ldb32] * g.eps[gj];
+        } else if (EPI == X3_FSUPD) {
+          const double dv = (double)((const float*)g.D)[gi + gj * g.ldd];
+          outv = dv - a_eff * (v - (double)g.B32[gi + gj * g.ldb32] * g.eps[gj]);
+        } else {  // X3_ADD
+          const double dv = g.d_double ? ((const double*)g.D)[gi + gj * g.ldd] : (double)((const float*)g.D)[gi + gj * g.ldd];
+          outv = v + dv;
+        }
+        if (g.c_double) ((double*)g.C)[gi + gj * g.ldc] = outv;
+        else ((float*)g.C)[gi + gj * g.ldc] = (float)outv;
+      }
+  }
+}
+
+template <int EPI, int CFG>
+__global__ __launch_bounds__(X3Cfg<CFG>::NT, 1) void gemm_x3_kernel(X3Args g, int tiles_m, int tiles_n) {
+  constexpr int NT = X3Cfg<CFG>::NT, WGR = X3Cfg<CFG>::WGR, WR = X3Cfg<CFG>::WR, WC = X3Cfg<CFG>::WC;
+  constexpr int PF = X3Cfg<CFG>::PF;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  unsigned char* As = lds;                       // [2][BM][ROWB]
+  unsigned char* Bs = lds + 2 * TILE_BYTES;      // [2][BN][ROWB]
+  __shared__ double red[WGR][BN];
+
+  int tm, tn;
+  x3_tile_coords(g, tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi0 = (wave % WGR) * (32 * WR), wj0 = (wave / WGR) * (32 * WC);
+  const int l32 = lane & 31, lh = lane >> 5;
+  int64_t kbeg, kend;
+  x3_k_range(g, tn, m0, n0, kbeg, kend);
 
   v16f acc[WR][WC];
 #pragma unroll
@@ -183,74 +270,113 @@ __global__ __launch_bounds__(X3Cfg<CFG>::NT, 1) void gemm_x3_kernel(X3Args g, in
   }
 
   if (PF && pf_sink == 0x7fc0ffeeu && g.part) g.part[0] = 0.0;  // keeps the warm-up loads alive
-  // ------------------------------------------------------------------ epilogue
-  // acc[ib][jb][r] is C(i, j) with i = wi0 + 32 ib + lane%32,
-  // j = wj0 + 32 jb + 8 (r/4) + 4 (lane/32) + r%4.
-  if (EPI == X3_RQ) {
-    const float* D = (const float*)g.D;
-    double cs[WC][16];
+  x3_epilogue<EPI, WGR, WR, WC>(g, acc, m0, n0, wi0, wj0, tid, tm, red);
+}
+
+// Direct global -> LDS variant (CFG 4): a 4-stage ring of k16 stages filled
+// by 16-byte-per-lane direct loads, so loads run three stages ahead of the
+// matrix cores with no register staging.  A stage row is 64 bytes: the hi
+// and lo halves of 16 k values, two 16-byte chunks each, XOR-swizzled by
+// chunk ^ ((row >> 1) ^ (row >> 2)) & 3 (fragment reads of 8 and of 16
+// consecutive rows hit distinct banks).  8 waves in 4 x 2, wave tile 64 x 128.
+// Rows past the matrix edge read the last row (their outputs are not stored).
+constexpr int DST = 4, DROW = 64, DTILE = BM * DROW;  // 16 KB per operand and stage
+
+__device__ inline int dswz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
+template <int W> __device__ inline void wait_vm() {
+  // vmcnt = W (0..63); expcnt and lgkmcnt left at their maxima
+  __builtin_amdgcn_s_waitcnt((W & 15) | (7 << 4) | (15 << 8) | (((W >> 4) & 3) << 14));
+}
+
+template <int EPI>
+__global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int tiles_n) {
+  constexpr int NW = 8, WGR = 4, WR = 2, WC = 4, CPW = 16 / NW;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  __shared__ double red[WGR][BN];
+  int tm, tn;
+  x3_tile_coords(g, tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wi0 = (wave % WGR) * (32 * WR), wj0 = (wave / WGR) * (32 * WC);
+  const int l32 = lane & 31, lh = lane >> 5;
+  int64_t kbeg, kend;
+  x3_k_range(g, tn, m0, n0, kbeg, kend);
+  const int total = kend > kbeg ? (int)((kend - kbeg) / 16) : 0;
+
+  // byte offsets of this lane's 16-byte chunk in each 1 KB row group it loads
+  int64_t offA[CPW], offB[CPW];
 #pragma unroll
-    for (int jb = 0; jb < WC; ++jb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
-        double sum = 0.0;
-#pragma unroll
-        for (int ib = 0; ib < WR; ++ib) {
-          const int64_t gi = m0 + wi0 + ib * 32 + l32;
-          if (gi < g.M && gj < g.N) sum += (double)acc[ib][jb][r] * (double)D[gi + gj * g.ldd];
-        }
-#pragma unroll
-        for (int off = 1; off < 32; off <<= 1) sum += __shfl_xor(sum, off, 64);
-        cs[jb][r] = sum;
-      }
-    if (l32 == 0) {
-#pragma unroll
-      for (int jb = 0; jb < WC; ++jb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) red[wave % WGR][wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4)] = cs[jb][r];
-    }
-    __syncthreads();
-    if (tid < BN) {
-      const int64_t gj = n0 + tid;
-      double sum = 0.0;
-#pragma unroll
-      for (int w = 0; w < WGR; ++w) sum += red[w][tid];
-      if (gj < g.N) g.part[(int64_t)tm * g.N + gj] = sum;
-    }
-    return;
+  for (int j = 0; j < CPW; ++j) {
+    const int row = 16 * (wave * CPW + j) + (lane >> 2);
+    const int c = (lane & 3) ^ dswz(row);          // logical chunk: hi k0-7, hi k8-15, lo k0-7, lo k8-15
+    const int coff = (c >> 1) * 64 + (c & 1) * 16;
+    offA[j] = min<int64_t>(m0 + row, g.M - 1) * g.ldap * 2 + coff;
+    offB[j] = min<int64_t>(n0 + row, g.N - 1) * g.ldbp * 2 + coff;
   }
-  double a_eff = g.alpha;
-  if (EPI == X3_FSUPD && g.alpha_dev) a_eff = *g.alpha_dev;
+  auto issue = [&](int t) {
+    const int64_t k0 = kbeg + 16 * (int64_t)t;
+    const int64_t koff = (k0 >> 5) * 128 + ((k0 >> 4) & 1) * 32;
+    const unsigned char* A = (const unsigned char*)g.Ap + koff;
+    const unsigned char* B = (const unsigned char*)g.Bp + koff;
+    unsigned char* sA = lds + (t % DST) * 2 * DTILE;
+    unsigned char* sB = sA + DTILE;
 #pragma unroll
-  for (int ib = 0; ib < WR; ++ib) {
-    const int64_t gi = m0 + wi0 + ib * 32 + l32;
-    if (gi >= g.M) continue;
+    for (int j = 0; j < CPW; ++j) {
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(A + offA[j]),
+                                       (void __attribute__((address_space(3)))*)(sA + (wave * CPW + j) * 1024), 16, 0,
+                                       0);
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(B + offB[j]),
+                                       (void __attribute__((address_space(3)))*)(sB + (wave * CPW + j) * 1024), 16, 0,
+                                       0);
+    }
+  };
+
+  v16f acc[WR][WC];
 #pragma unroll
-    for (int jb = 0; jb < WC; ++jb)
+  for (int i = 0; i < WR; ++i)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
-        if (gj >= g.N) continue;
-        const double v = (double)acc[ib][jb][r];
-        double outv;
-        if (EPI == X3_STORE) {
-          outv = g.alpha * v;
-          if (g.beta != 0.0)
-            outv += g.beta * (g.c_double ? ((const double*)g.C)[gi + gj * g.ldc] : (double)((const float*)g.C)[gi + gj * g.ldc]);
-        } else if (EPI == X3_SHIFT) {
-          outv = v - (double)g.B32[gi + gj * g.ldb32] * g.eps[gj];
-        } else if (EPI == X3_FSUPD) {
-          const double dv = (double)((const float*)g.D)[gi + gj * g.ldd];
-          outv = dv - a_eff * (v - (double)g.B32[gi + gj * g.ldb32] * g.eps[gj]);
-        } else {  // X3_ADD
-          const double dv = g.d_double ? ((const double*)g.D)[gi + gj * g.ldd] : (double)((const float*)g.D)[gi + gj * g.ldd];
-          outv = v + dv;
-        }
-        if (g.c_double) ((double*)g.C)[gi + gj * g.ldc] = outv;
-        else ((float*)g.C)[gi + gj * g.ldc] = (float)outv;
+    for (int j = 0; j < WC; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  for (int t = 0; t < DST - 1 && t < total; ++t) issue(t);
+  for (int t = 0; t < total; ++t) {
+    const int later = min(DST - 2, total - 1 - t);  // stages issued after t that may still be in flight
+    if (later >= 2) wait_vm<2 * 2 * CPW>();
+    else if (later == 1) wait_vm<2 * CPW>();
+    else wait_vm<0>();
+    // Bare barrier (a fenced one would wait for every outstanding load):
+    // every wave's part of stage t has landed, and stage t - 1 was consumed.
+    __builtin_amdgcn_s_barrier();
+    if (t + DST - 1 < total) issue(t + DST - 1);
+    const unsigned char* Ab = lds + (t % DST) * 2 * DTILE;
+    const unsigned char* Bb = Ab + DTILE;
+    v8bf ah[WR], al[WR], bh[WC], bl[WC];
+#pragma unroll
+    for (int ib = 0; ib < WR; ++ib) {
+      const int row = wi0 + ib * 32 + l32, sw = dswz(row);
+      ah[ib] = as_bf(*(const u32x4*)(Ab + row * DROW + 16 * (lh ^ sw)));
+      al[ib] = as_bf(*(const u32x4*)(Ab + row * DROW + 16 * ((2 + lh) ^ sw)));
+    }
+#pragma unroll
+    for (int jb = 0; jb < WC; ++jb) {
+      const int row = wj0 + jb * 32 + l32, sw = dswz(row);
+      bh[jb] = as_bf(*(const u32x4*)(Bb + row * DROW + 16 * (lh ^ sw)));
+      bl[jb] = as_bf(*(const u32x4*)(Bb + row * DROW + 16 * ((2 + lh) ^ sw)));
+    }
+#pragma unroll
+    for (int ib = 0; ib < WR; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < WC; ++jb) {
+        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh[jb], ah[ib], acc[ib][jb], 0, 0, 0);
+        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl[jb], ah[ib], acc[ib][jb], 0, 0, 0);
+        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh[jb], al[ib], acc[ib][jb], 0, 0, 0);
       }
   }
+  __syncthreads();  // the RQ epilogue reuses shared memory; no wave may still be reading stages
+  x3_epilogue<EPI, WGR, WR, WC>(g, acc, m0, n0, wi0, wj0, tid, tm, red);
 }
 
 // ---------------------------------------------------------------- packing
@@ -351,7 +477,7 @@ hipError_t set_attrs() {
 
 }  // namespace
 
-int x3_default_cfg = 2;  // fastest measured at N = 8192 (64 x 128 wave tiles)
+int x3_default_cfg = 4;  // fastest measured at N = 8192 (direct-to-LDS ring)
 
 hipError_t x3_init() {
   // Dynamic LDS above 64 KiB must be enabled per kernel before the first
@@ -360,6 +486,15 @@ hipError_t x3_init() {
   if (e == hipSuccess) e = set_attrs<1>();
   if (e == hipSuccess) e = set_attrs<2>();
   if (e == hipSuccess) e = set_attrs<3>();
+  const int dl = DST * 2 * DTILE;
+#define X3_DL_ATTR(E) \
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)gemm_x3_dl<E>, hipFuncAttributeMaxDynamicSharedMemorySize, dl);
+  X3_DL_ATTR(X3_STORE)
+  X3_DL_ATTR(X3_SHIFT)
+  X3_DL_ATTR(X3_FSUPD)
+  X3_DL_ATTR(X3_ADD)
+  X3_DL_ATTR(X3_RQ)
+#undef X3_DL_ATTR
   return e;
 }
 
@@ -373,6 +508,24 @@ hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
     case 1: return launch_cfg<1>(epi, a, tm, tn, s);
     case 2: return launch_cfg<2>(epi, a, tm, tn, s);
     case 3: return launch_cfg<3>(epi, a, tm, tn, s);
+    case 4: {
+      const int total = (a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) ? tm * (tm + 1) / 2 : tm * tn;
+      const size_t dl = DST * 2 * DTILE;
+      switch (epi) {
+#define X3_DL_CASE(E)                                                                           \
+  case E:                                                                                       \
+    hipLaunchKernelGGL((gemm_x3_dl<E>), dim3(total), dim3(512), dl, s, a, tm, tn); \
+    break;
+        X3_DL_CASE(X3_STORE)
+        X3_DL_CASE(X3_SHIFT)
+        X3_DL_CASE(X3_FSUPD)
+        X3_DL_CASE(X3_ADD)
+        X3_DL_CASE(X3_RQ)
+#undef X3_DL_CASE
+        default: return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    }
     default: return hipErrorInvalidValue;
   }
 }
