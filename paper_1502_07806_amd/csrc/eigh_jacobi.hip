@@ -92,20 +92,53 @@ __global__ void sweep_begin(EighBatch e, int sweep) {
 }
 
 // ------------------------------------------------------------------ pair solve
+// Sum over the 8 lanes of an aligned lane group with DPP moves (no LDS
+// round trip): quad_perm [1,0,3,2], quad_perm [2,3,0,1], then the half-row
+// mirror (lane i <-> 7 - i) pairs the two quads.  Every lane of the group
+// ends with the bitwise same sum (IEEE addition is commutative), so lanes
+// that decide on a rotation independently always agree.
+template <int CTRL> __device__ inline double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double sum8(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  return v;
+}
+// Reciprocal and reciprocal square root: hardware estimates refined by
+// Newton steps (three each, quadratic convergence) to about one ulp.
+__device__ inline double rcp_d(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r = r * (2.0 - x * r);
+  return r;
+}
+__device__ inline double rsq_d(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r = r * (1.5 - 0.5 * x * r * r);
+  return r;
+}
+
 // The 2b x 2b pair problem S = [B_II B_IJ; B_JI B_JJ] is diagonalised by a
 // one-sided (Hestenes) Jacobi on W = S + sigma I, sigma = 2 max|Gershgorin
 // bound| so that W is positive definite: column pairs of W are rotated until
-// all columns are orthogonal; the accumulated rotation R (W = W0 R) holds the
-// eigenvectors of S.  Eight lanes own a column pair (8 rows each) and reduce
-// the 2x2 Gram entries with shuffles, so a round needs one barrier.  Padding
-// indices (beyond the submatrix order) never rotate.
+// all columns are orthogonal.  Then W = W0 R = R diag(lambda + sigma) for
+// the accumulated rotation R, so the eigenvectors are the normalised final
+// columns of W and R is never accumulated.  Eight lanes own a column pair
+// (8 rows each) and reduce the 2x2 Gram entries with DPP, so a round needs
+// one barrier.  Padding indices (beyond the submatrix order) never rotate.
 __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   const int npairs = e.nb / 2;
   const int p = blockIdx.x / npairs, k = blockIdx.x % npairs;
   int* flagR = e.rflag + (int64_t)p * npairs + k;
   if (e.state[2 * p]) { if (threadIdx.x == 0) *flagR = 0; return; }
   __shared__ double W[B2][LS];   // column-major: W[col][row]
-  __shared__ double R[B2][LS];   // column-major: R[col][row]
+  __shared__ double nrm[B2];
   __shared__ int any_rot;
   __shared__ int sweep_rot;
   const int Mp = e.Mp;
@@ -122,7 +155,6 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   for (int idx = tid; idx < B2 * B2; idx += NT) {
     int r = idx % B2, c = idx / B2;
     W[c][r] = B[pair_idx(r, I, J) + (int64_t)pair_idx(c, I, J) * Mp];
-    R[c][r] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
   for (int idx = tid; idx < B2 * B2; idx += NT) {
@@ -135,7 +167,11 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   const double sigma = 2.0 * fmax(fabs(e.scal[1]), fabs(e.scal[2])) + TINY;
   for (int t = tid; t < B2; t += NT) {
     const bool pad = pair_idx(t, I, J) >= msize;
-    W[t][t] = pad ? 1.0 : W[t][t] + sigma;  // a padding column becomes a unit vector (no overflow)
+    if (pad) {  // a padding column becomes a unit vector (no overflow, never rotated)
+      for (int r = 0; r < B2; ++r) W[t][r] = (r == t) ? 1.0 : 0.0;
+    } else {
+      W[t][t] += sigma;
+    }
   }
   __syncthreads();
   const int slot = tid >> 3, sub = tid & 7;  // 32 column pairs x 8 lanes
@@ -145,49 +181,61 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
     for (int r = 0; r < B2 - 1; ++r) {
       const int a = rr_index(slot, r, B2), b = rr_index(B2 - 1 - slot, r, B2);
       const int pc = min(a, b), qc = max(a, b);
+      double x[B2 / 8], y[B2 / 8];
       double aa = 0.0, bb = 0.0, ab = 0.0;
 #pragma unroll
       for (int m = 0; m < B2 / 8; ++m) {
         const int row = sub + 8 * m;
-        const double x = W[pc][row], y = W[qc][row];
-        aa += x * x;
-        bb += y * y;
-        ab += x * y;
+        x[m] = W[pc][row];
+        y[m] = W[qc][row];
+        aa += x[m] * x[m];
+        bb += y[m] * y[m];
+        ab += x[m] * y[m];
       }
-#pragma unroll
-      for (int off = 1; off < 8; off <<= 1) {
-        aa += __shfl_xor(aa, off, 64);
-        bb += __shfl_xor(bb, off, 64);
-        ab += __shfl_xor(ab, off, 64);
-      }
+      aa = sum8(aa);
+      bb = sum8(bb);
+      ab = sum8(ab);
       const bool padpair = pair_idx(pc, I, J) >= msize || pair_idx(qc, I, J) >= msize;
       // columns count as orthogonal below 8 u relative: the rounding noise of
       // the dot products stays under it, so converged pairs stop rotating
       if (!padpair && fabs(ab) > TINY && fabs(ab) > 8.0 * TOL * sqrt(aa * bb)) {
-        const double zeta = (bb - aa) / (2.0 * ab);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double zeta = 0.5 * (bb - aa) * rcp_d(ab);
+        const double az = fabs(zeta);
+        double t;
+        if (az > 6.7e7) {
+          t = 0.5 * rcp_d(zeta);  // sqrt(1 + zeta^2) = |zeta| to working precision
+        } else {
+          const double q = 1.0 + zeta * zeta;
+          t = copysign(rcp_d(az + q * rsq_d(q)), zeta);
+        }
+        const double c = rsq_d(1.0 + t * t);
         const double sn = t * c;
 #pragma unroll
         for (int m = 0; m < B2 / 8; ++m) {
           const int row = sub + 8 * m;
-          const double x = W[pc][row], y = W[qc][row];
-          W[pc][row] = c * x - sn * y;
-          W[qc][row] = sn * x + c * y;
-          const double u = R[pc][row], v = R[qc][row];
-          R[pc][row] = c * u - sn * v;
-          R[qc][row] = sn * u + c * v;
+          W[pc][row] = c * x[m] - sn * y[m];
+          W[qc][row] = sn * x[m] + c * y[m];
         }
         if (sub == 0) sweep_rot = 1;
       }
       __syncthreads();
     }
-    if (!sweep_rot) break;
+    // every thread reads the flag before thread 0 may clear it for the next sweep
+    const bool again = sweep_rot != 0;
+    __syncthreads();
+    if (!again) break;
   }
+  // eigenvectors: normalised columns of W
+  if (tid < B2) {
+    double s2 = 0.0;
+    for (int r = 0; r < B2; ++r) s2 += W[tid][r] * W[tid][r];
+    nrm[tid] = rsq_d(s2);
+  }
+  __syncthreads();
   double* Rg = e.Rw + ((int64_t)p * npairs + k) * B2 * B2;
   for (int idx = tid; idx < B2 * B2; idx += NT) {
     int r = idx % B2, c = idx / B2;
-    Rg[idx] = R[c][r];
+    Rg[idx] = W[c][r] * nrm[c];
   }
   if (tid == 0) {
     *flagR = 1;

@@ -165,6 +165,15 @@ constexpr int DBK = 64, DST = 4, DTILE = BM * DBK;  // 16 KB per operand and sta
 
 __device__ inline int dswz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
 
+// Workgroup barrier without the memory fence of __syncthreads (which would
+// wait for every outstanding direct-to-LDS load); the empty asm statements
+// keep the compiler from moving LDS accesses across it.
+__device__ inline void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 template <int WAITS> __device__ inline void wait_vm() {
   // vmcnt = WAITS (0..63); expcnt and lgkmcnt left at their maxima
   __builtin_amdgcn_s_waitcnt((WAITS & 15) | (7 << 4) | (15 << 8) | (((WAITS >> 4) & 3) << 14));
@@ -239,7 +248,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_oz_dl(OzArgs a, int tiles_m, int t
     // it, every wave's part of tile t is in LDS (each waited for its own
     // loads above) and stage (t - 1) % DST is free (its fragments were
     // consumed by MFMAs before the barrier).
-    __builtin_amdgcn_s_barrier();
+    lds_barrier();
     if (t + DST - 1 < total) issue(t + DST - 1);
     const unsigned char* Ab = lds + (t % DST) * 2 * DTILE;
     const unsigned char* Bb = Ab + DTILE;
@@ -395,7 +404,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_oz_fused(OzArgs a, int tiles_m, in
     if (later >= 2) wait_vm<2 * 2 * CPW>();
     else if (later == 1) wait_vm<2 * CPW>();
     else wait_vm<0>();
-    __builtin_amdgcn_s_barrier();  // as in gemm_oz_dl
+    lds_barrier();  // as in gemm_oz_dl
     if (t + DST - 1 < total) {
       issue(ic, t + DST - 1);
       advance(ic);

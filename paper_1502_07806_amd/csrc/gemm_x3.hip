@@ -284,6 +284,15 @@ constexpr int DST = 4, DROW = 64, DTILE = BM * DROW;  // 16 KB per operand and s
 
 __device__ inline int dswz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
 
+// Workgroup barrier without the memory fence of __syncthreads (which would
+// wait for every outstanding direct-to-LDS load); the empty asm statements
+// keep the compiler from moving LDS accesses across it.
+__device__ inline void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 template <int W> __device__ inline void wait_vm() {
   // vmcnt = W (0..63); expcnt and lgkmcnt left at their maxima
   __builtin_amdgcn_s_waitcnt((W & 15) | (7 << 4) | (15 << 8) | (((W >> 4) & 3) << 14));
@@ -349,7 +358,7 @@ __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int 
     else wait_vm<0>();
     // Bare barrier (a fenced one would wait for every outstanding load):
     // every wave's part of stage t has landed, and stage t - 1 was consumed.
-    __builtin_amdgcn_s_barrier();
+    lds_barrier();
     if (t + DST - 1 < total) issue(t + DST - 1);
     const unsigned char* Ab = lds + (t % DST) * 2 * DTILE;
     const unsigned char* Bb = Ab + DTILE;

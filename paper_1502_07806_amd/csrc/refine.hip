@@ -266,7 +266,10 @@ __global__ __launch_bounds__(NT) void k_cluster_rr(const double* V, int64_t ldv,
         }
         __syncthreads();
       }
-      if (!rot) break;
+      // every thread reads the flag before thread 0 may clear it for the next sweep
+      const bool again = rot != 0;
+      __syncthreads();
+      if (!again) break;
     }
     // Y <- R^{-T} Y (back substitution), eigenvalues sorted ascending by selection
     if (tid == 0) {
