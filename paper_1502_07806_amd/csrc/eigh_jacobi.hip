@@ -287,7 +287,9 @@ __device__ inline void store_acc(double (*Z)[LS], v4d acc[2][2]) {
 // ------------------------------------------------------------------ apply
 // Work items per submatrix: npairs(npairs+1)/2 tiles (k1 <= k2) of B, each also
 // written transposed into (k2, k1) so B stays exactly symmetric, then
-// (Mp/2b)*npairs tiles of U.
+// (Mp/2b)*npairs tiles of U.  Two 64 x 64 LDS tiles per workgroup (two
+// workgroups fit a CU); a product with an unrotated pair (identity R) is
+// skipped.
 __global__ __launch_bounds__(NT) void pair_apply(EighBatch e, int round) {
   const int npairs = e.nb / 2;
   const int nrc = e.Mp / B2;
@@ -300,7 +302,6 @@ __global__ __launch_bounds__(NT) void pair_apply(EighBatch e, int round) {
   const double* Rbase = e.Rw + (int64_t)p * npairs * B2 * B2;
   __shared__ double T[B2][LS];
   __shared__ double X[B2][LS];
-  __shared__ double Y[B2][LS];
   const int tid = threadIdx.x;
   v4d acc[2][2];
   if (w < ntri) {
@@ -318,24 +319,36 @@ __global__ __launch_bounds__(NT) void pair_apply(EighBatch e, int round) {
     for (int idx = tid; idx < B2 * B2; idx += NT) {
       int r = idx % B2, c = idx / B2;
       T[r][c] = B[pair_idx(r, I1, J1) + (int64_t)pair_idx(c, I2, J2) * Mp];
-      X[r][c] = f1 ? R1[idx] : (r == c ? 1.0 : 0.0);
-      Y[r][c] = f2 ? R2[idx] : (r == c ? 1.0 : 0.0);
+      if (f1) X[r][c] = R1[idx];
     }
     __syncthreads();
-    mm64<true>(X, T, acc);  // R1^T T
-    __syncthreads();
-    store_acc(T, acc);
-    __syncthreads();
-    mm64<false>(T, Y, acc);  // (R1^T T) R2
-    __syncthreads();
-    store_acc(T, acc);
-    __syncthreads();
+    if (f1) {
+      mm64<true>(X, T, acc);  // R1^T T
+      __syncthreads();
+      store_acc(T, acc);
+      if (f2) {
+        for (int idx = tid; idx < B2 * B2; idx += NT) X[idx % B2][idx / B2] = R2[idx];
+      }
+      __syncthreads();
+    } else {
+      for (int idx = tid; idx < B2 * B2; idx += NT) X[idx % B2][idx / B2] = R2[idx];
+      __syncthreads();
+    }
+    if (f2) {
+      mm64<false>(T, X, acc);  // (R1^T T) R2
+      __syncthreads();
+      store_acc(T, acc);
+      __syncthreads();
+    }
     for (int idx = tid; idx < B2 * B2; idx += NT) {
-      int r = idx % B2, c = idx / B2;
-      int gr = pair_idx(r, I1, J1), gc = pair_idx(c, I2, J2);
-      double v = T[r][c];
-      B[gr + (int64_t)gc * Mp] = v;
-      if (k1 != k2) B[gc + (int64_t)gr * Mp] = v;
+      const int r = idx % B2, c = idx / B2;
+      B[pair_idx(r, I1, J1) + (int64_t)pair_idx(c, I2, J2) * Mp] = T[r][c];
+    }
+    if (k1 != k2) {  // mirror tile, written with consecutive threads along its columns
+      for (int idx = tid; idx < B2 * B2; idx += NT) {
+        const int c = idx % B2, r = idx / B2;
+        B[pair_idx(c, I2, J2) + (int64_t)pair_idx(r, I1, J1) * Mp] = T[r][c];
+      }
     }
   } else {
     const int ww = w - ntri;
@@ -348,10 +361,10 @@ __global__ __launch_bounds__(NT) void pair_apply(EighBatch e, int round) {
     for (int idx = tid; idx < B2 * B2; idx += NT) {
       int r = idx % B2, c = idx / B2;
       T[r][c] = U[(rc * B2 + r) + (int64_t)pair_idx(c, I2, J2) * Mp];
-      Y[r][c] = R2[idx];
+      X[r][c] = R2[idx];
     }
     __syncthreads();
-    mm64<false>(T, Y, acc);
+    mm64<false>(T, X, acc);
     __syncthreads();
     store_acc(T, acc);
     __syncthreads();
