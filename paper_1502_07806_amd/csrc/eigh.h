@@ -7,6 +7,7 @@ namespace pfsm {
 constexpr int EIGH_B = 32;                 // column-block width; pair problems are 2b x 2b
 constexpr double EIGH_PAD_DIAG = 1e200;    // decoupled padding eigenvalue (sorts last)
 constexpr int PFSM_INFO_EIGH_NOCONV = -3;  // a submatrix needed rotations in its last sweep
+constexpr int EIGH_INNER_SWEEPS = 30;      // sweep limit of the in-LDS pair solver (4-6 are typical)
 
 struct EighBatch {
   int P;                   // number of submatrices

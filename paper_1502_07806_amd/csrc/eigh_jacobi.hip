@@ -175,6 +175,7 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   }
   __syncthreads();
   const int slot = tid >> 3, sub = tid & 7;  // 32 column pairs x 8 lanes
+  bool converged = false;
   for (int sweep = 0; sweep < e.inner_max_sweeps; ++sweep) {
     if (tid == 0) sweep_rot = 0;
     __syncthreads();
@@ -223,8 +224,15 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
     // every thread reads the flag before thread 0 may clear it for the next sweep
     const bool again = sweep_rot != 0;
     __syncthreads();
-    if (!again) break;
+    if (!again) {
+      converged = true;
+      break;
+    }
   }
+  // The normalised columns are orthonormal eigenvectors only once every
+  // column pair is orthogonal; a pair problem that did not get there is a
+  // convergence failure of the eigensolver.
+  if (!converged && tid == 0 && e.info) atomicCAS(e.info, 0, PFSM_INFO_EIGH_NOCONV);
   // eigenvectors: normalised columns of W
   if (tid < B2) {
     double s2 = 0.0;

@@ -8,6 +8,9 @@ hipError_t rq_reduce(const double* part, int tiles_m, int64_t n, const double* d
 hipError_t col_norm2(const double* X, int64_t m, int64_t n, int64_t ldx, double* out, hipStream_t s);
 hipError_t finalize_order(const double* lam_u, const double* X, int64_t n, int64_t ldx, double* Xp, int64_t ldxp,
                           double* lam_out, int* rank, double* sgn, int* info, hipStream_t s);
+// rank[j] = stable ascending rank of num[j] (of num[j] / den[j] when den is
+// given) in the NaN-last total order; a permutation of 0..n-1 for any input.
+hipError_t rank_ascending(const double* num, const double* den, int64_t n, int* rank, hipStream_t s);
 // Stable ascending ranks of lam_u (NaN last, info = -1 for non-finite) and lam_out[rank] = lam_u.
 hipError_t finalize_order_values(const double* lam_u, int64_t n, double* lam_out, int* rank, int* info, hipStream_t s);
 constexpr int PFSM_INFO_BASIS = -4;

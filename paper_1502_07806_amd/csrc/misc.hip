@@ -129,24 +129,36 @@ __global__ __launch_bounds__(NT) void k_col_sign(const double* X, int64_t n, int
   if (threadIdx.x == 0) sgn[j] = (c[si[0]] < 0.0) ? -1.0 : 1.0;
 }
 
-// Stable ascending rank: #{k : l_k < l_j} + #{k < j : l_k == l_j}.
-__global__ __launch_bounds__(NT) void k_rank(const double* lam, int64_t n, int* rank, double* lam_out, int* info) {
+// Stable ascending rank of v_j = num_j (or num_j / den_j): the number of
+// values ordered before it in the NaN-safe total order (ties by index), a
+// permutation of 0..n-1 for any input.  The comparison range is split over
+// gridDim.y slices whose partial counts are added atomically into rank
+// (cleared beforehand), so the O(n^2) comparisons spread over the chip.
+__global__ __launch_bounds__(NT) void k_rank_count(const double* num, const double* den, int64_t n, int* rank) {
   __shared__ double tile[NT];
   const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
-  const double lj = j < n ? lam[j] : 0.0;
-  int64_t r = 0;
-  for (int64_t base = 0; base < n; base += NT) {
+  const double lj = j < n ? (den ? num[j] / den[j] : num[j]) : 0.0;
+  const int64_t chunk = (n + gridDim.y - 1) / gridDim.y;
+  const int64_t lo = (int64_t)blockIdx.y * chunk, hi = min<int64_t>(n, lo + chunk);
+  int r = 0;
+  for (int64_t base = lo; base < hi; base += NT) {
     __syncthreads();
-    if (base + threadIdx.x < n) tile[threadIdx.x] = lam[base + threadIdx.x];
+    const int64_t k = base + threadIdx.x;
+    if (k < hi) tile[threadIdx.x] = den ? num[k] / den[k] : num[k];
     __syncthreads();
-    const int cnt = (int)min<int64_t>(NT, n - base);
+    const int cnt = (int)min<int64_t>(NT, hi - base);
     for (int t = 0; t < cnt; ++t) r += order_before(tile[t], base + t, lj, j);
   }
-  if (j < n) {
-    if (!isfinite(lj)) atomicCAS(info, 0, -1);
-    rank[j] = (int)r;  // a permutation of 0..n-1 for any input (NaN sorts last)
-    lam_out[r] = lj;
-  }
+  if (j < n && r) atomicAdd(&rank[j], r);
+}
+
+__global__ __launch_bounds__(NT) void k_rank_place(const double* lam, int64_t n, const int* rank, double* lam_out,
+                                                   int* info) {
+  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (j >= n) return;
+  const double lj = lam[j];
+  if (!isfinite(lj)) atomicCAS(info, 0, -1);
+  lam_out[rank[j]] = lj;
 }
 
 __global__ __launch_bounds__(NT) void k_permute(const double* X, int64_t n, int64_t ldx, const int* rank,
@@ -335,13 +347,24 @@ hipError_t col_norm2(const double* X, int64_t m, int64_t n, int64_t ldx, double*
 hipError_t finalize_order(const double* lam_u, const double* X, int64_t n, int64_t ldx, double* Xp, int64_t ldxp,
                           double* lam_out, int* rank, double* sgn, int* info, hipStream_t s) {
   hipLaunchKernelGGL(k_col_sign, dim3((unsigned)n), dim3(NT), 0, s, X, n, ldx, sgn);
-  hipLaunchKernelGGL(k_rank, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, lam_u, n, rank, lam_out, info);
+  hipError_t e = finalize_order_values(lam_u, n, lam_out, rank, info, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_permute, dim3((unsigned)n), dim3(NT), 0, s, X, n, ldx, rank, sgn, Xp, ldxp);
   return hipGetLastError();
 }
 
+hipError_t rank_ascending(const double* num, const double* den, int64_t n, int* rank, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipError_t e = fill_i32(rank, n, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rank_count, dim3((unsigned)((n + NT - 1) / NT), 16), dim3(NT), 0, s, num, den, n, rank);
+  return hipGetLastError();
+}
+
 hipError_t finalize_order_values(const double* lam_u, int64_t n, double* lam_out, int* rank, int* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_rank, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, lam_u, n, rank, lam_out, info);
+  hipError_t e = rank_ascending(lam_u, nullptr, n, rank, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rank_place, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, lam_u, n, rank, lam_out, info);
   return hipGetLastError();
 }
 

@@ -98,7 +98,7 @@ struct StageClock {
 // Submatrix eigensolver arguments: every pointer into the plan's workspace layout.
 EighBatch eigh_batch(const pfsm_plan* pl, char* W, int* info, const double* scal) {
   EighBatch e = {};
-  e.P = pl->P; e.Mp = pl->Mp; e.nb = pl->nb; e.inner_max_sweeps = 30;
+  e.P = pl->P; e.Mp = pl->Mp; e.nb = pl->nb; e.inner_max_sweeps = EIGH_INNER_SWEEPS;
   e.Bw = (double*)(W + pl->o_Bw); e.Uw = (double*)(W + pl->o_Uw); e.Rw = (double*)(W + pl->o_Rw);
   e.rflag = (int*)(W + pl->o_rflag); e.state = (int*)(W + pl->o_state); e.sel = (int*)(W + pl->o_sel);
   e.stats = (int*)(W + pl->o_stats);

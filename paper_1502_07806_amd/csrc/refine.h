@@ -14,7 +14,7 @@ struct RefineBufs {
   double* lam_s;   // [n] sorted estimates
   int* rank;       // [n] column -> sorted position
   int* inv;        // [n] sorted position -> column
-  int* clus;       // [n + 2] cluster list: clus[0] = count, then (start, size) pairs packed as start | size << 20... see kernel
+  int* clus;       // [1] number of clusters
   int* cstart;     // [n] cluster starts
   int* csize;      // [n] cluster sizes
 };

@@ -48,25 +48,16 @@ __global__ __launch_bounds__(NT) void k_dots(const double* V, int64_t ldv, const
   }
 }
 
-__global__ __launch_bounds__(NT) void k_rank_rq(const double* d, const double* nn, int64_t n, int* rank, int* inv,
-                                                double* lam_s, int* info) {
-  __shared__ double tile[NT];
+// Sorted estimates: inv[rank] = column, lam_s[rank] = d_j / nn_j (ranks from rank_ascending).
+__global__ __launch_bounds__(NT) void k_rank_finish(const double* d, const double* nn, int64_t n, const int* rank,
+                                                    int* inv, double* lam_s, int* info) {
   const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
-  const double lj = j < n ? d[j] / nn[j] : 0.0;
-  int64_t r = 0;
-  for (int64_t base = 0; base < n; base += NT) {
-    __syncthreads();
-    if (base + threadIdx.x < n) tile[threadIdx.x] = d[base + threadIdx.x] / nn[base + threadIdx.x];
-    __syncthreads();
-    const int cnt = (int)min<int64_t>(NT, n - base);
-    for (int t = 0; t < cnt; ++t) r += order_before(tile[t], base + t, lj, j);
-  }
-  if (j < n) {
-    if (!isfinite(lj)) atomicCAS(info, 0, -1);
-    rank[j] = (int)r;
-    inv[r] = (int)j;
-    lam_s[r] = lj;
-  }
+  if (j >= n) return;
+  const double lj = d[j] / nn[j];
+  if (!isfinite(lj)) atomicCAS(info, 0, -1);
+  const int r = rank[j];  // a permutation of 0..n-1 (total order)
+  inv[r] = (int)j;
+  lam_s[r] = lj;
 }
 
 // Single workgroup: cluster boundaries over the sorted estimates.
@@ -423,7 +414,9 @@ hipError_t refine_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz,
   hipLaunchKernelGGL(k_dots, dim3((unsigned)n), dim3(NT), 0, s, V, ldv, Z, ldz, n, b.d, b.nn);
   hipError_t e = norm_check(b.nn, n, info, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rank_rq, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, b.d, b.nn, n, b.rank, b.inv,
+  e = rank_ascending(b.d, b.nn, n, b.rank, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rank_finish, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, b.d, b.nn, n, b.rank, b.inv,
                      b.lam_s, info);
   hipLaunchKernelGGL(k_clusters, dim3(1), dim3(1024), 0, s, b.lam_s, n, tau, b.clus, b.cstart, b.csize);
   hipLaunchKernelGGL(k_cluster_rr, dim3((unsigned)n), dim3(NT), 0, s, V, ldv, Z, ldz, n, b.clus, b.cstart, b.csize,
