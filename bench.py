@@ -17,7 +17,6 @@ kernel measured with HIP events inside the timed region, CPU oracle baseline).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import platform
@@ -30,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+PEAK_TOPS_INT8 = 5000.0
 HBM_PEAK_GBS = 8000.0
 
 
@@ -42,15 +42,6 @@ def algorithmic_flops(n: int, M: int, q: int, n_it: int) -> float:
     return 2 * n3 + n3 + 2.0 * n * n * M + (q * n_it - 1) * 2 * n3 + n3 + n3 / 3 + n3 + 2 * n3 + 2 * n3
 
 
-def gemm_source_hash(files=("gemm_f64.hip", "gemm_x3.hip", "gemm_x3.h", "common.h")) -> str:
-    h = hashlib.sha256()
-    for f in files:
-        p = os.path.join(ROOT, "paper_1502_07806_amd", "csrc", f)
-        if os.path.exists(p):
-            h.update(open(p, "rb").read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(kernel_key: str):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3 counter runs,
     or None when absent or taken on a different kernel source."""
@@ -60,6 +51,7 @@ def load_traffic(kernel_key: str):
     try:
         d = json.load(open(p))
         e = d.get(kernel_key)
+        from paper_1502_07806_amd.traffic_probe import gemm_source_hash
         if not e or e.get("source_hash") != gemm_source_hash():
             return None
         return float(e["bytes_per_launch"])
@@ -197,7 +189,7 @@ def main():
     else:
         # split-BF16 product: three BF16 MFMA products (hi*hi, hi*lo, lo*hi) per output
         dom_flops, peak, unit_dtype = 3 * 2.0 * n ** 3, PEAK_TFLOPS["bf16"], "bf16"
-        kname = ("gemm_x3_kernel<X3_FSUPD> (folded-spectrum update, %dx%dx%d, 3 BF16 MFMA products per "
+        kname = ("gemm_x3_dl<X3_FSUPD> (folded-spectrum update, %dx%dx%d, 3 BF16 MFMA products per "
                  "output, FP32 accumulation)" % (n, n, n))
         kernel_key = "gemm_x3_fsupd_n%d" % n
     achieved = dom_flops / (upd_ms * 1e-3) / 1e12
@@ -226,6 +218,17 @@ def main():
                      "frac": achieved / peak, "traffic": traffic, "kernel": kname,
                      "launch_ms": upd_ms, "flops_per_launch": dom_flops},
     }
+    if precision != "fp64":
+        # the FP64-accurate refinement product Z = A V_new: 21 int8 digit products of 2N^3 ops
+        oz_ms = st["refine_product"]
+        oz_ops = 21 * 2.0 * n ** 3
+        out["roofline_refine"] = {
+            "bound": "mfma", "achieved": oz_ops / (oz_ms * 1e-3) / 1e12, "peak": PEAK_TOPS_INT8, "unit": "TOP/s",
+            "frac": oz_ops / (oz_ms * 1e-3) / 1e12 / PEAK_TOPS_INT8,
+            "kernel": "gemm_oz_fused (Z = A V_new from six 7-bit digits per operand, 21 int8 products, "
+                      "exact int32 accumulation, FP64 sum)",
+            "launch_ms": oz_ms, "ops_per_launch": oz_ops, "traffic": load_traffic("gemm_oz_n%d" % n),
+            "fp64_equivalent_tflops": 2.0 * n ** 3 / (oz_ms * 1e-3) / 1e12}
     del plan
     if precision != "fp64" and not args.no_fp64_compare:
         p64, ms64, st64, acc64 = run("fp64")

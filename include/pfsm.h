@@ -205,9 +205,13 @@ pfsm_status pfsm_diagnostics(pfsm_plan* plan, const double* dA, int64_t lda, con
  * submatrix eigensolver + start vectors, 3 + 2i shifted product of iteration i,
  * 4 + 2i folded-spectrum update of iteration i (i < iterations, at most 8),
  * 19 overlap, 20 Cholesky-QR, 21 Rayleigh quotients, 22 ordering, 23
- * back-rotation, 24 refinement (mixed precision).  pfsm_timing_end releases the events.
+ * back-rotation (mixed precision: with the digit split of A and V_new), 24
+ * refinement product Z = A V_new (mixed precision, one launch), 25
+ * refinement Rayleigh quotients, cluster Rayleigh-Ritz and ordering (mixed
+ * precision; the ordering of the unrefined mixed result also falls here).
+ * pfsm_timing_end releases the events.
  * Errors: INVALID_ARG, HIP_ERROR. */
-#define PFSM_TIMING_BOUNDS 26
+#define PFSM_TIMING_BOUNDS 27
 /* Internal counters of the last solve (instrumentation; synchronises the
  * device).  out[2p] = sweep at which submatrix p was found converged (0: never),
  * out[2p+1] = pair problems of submatrix p that needed rotations; then, for

@@ -239,10 +239,10 @@ class Plan:
                 "clusters": v[2 * P], "multi_clusters": v[2 * P + 1], "max_cluster": v[2 * P + 2]}
 
     # -- stage timing (instrumentation for benchmarks)
-    TIMING_BOUNDS = 26
+    TIMING_BOUNDS = 27
     STAGES = (["basis_change", "step_length", "submatrix_eigh"]
               + [x for i in range(8) for x in ("fs_shift_%d" % i, "fs_update_%d" % i)]
-              + ["overlap", "cholesky_qr", "rayleigh", "ordering", "back_rotation", "refinement"])
+              + ["overlap", "cholesky_qr", "rayleigh", "ordering", "back_rotation", "refine_product", "refine_rr"])
 
     def timing_begin(self, max_solves: int):
         _check(load_library().pfsm_timing_begin(self._h, int(max_solves)))

@@ -443,8 +443,7 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
     PFSM_TRY(col_norm2(dVout, n, n, ldvo, (double*)(W + pl->o_den), s));
     PFSM_TRY(norm_check((double*)(W + pl->o_den), n, info, s));
   }
-  clk.mark(24);
-  clk.mark(25);
+  clk.mark(PFSM_TIMING_BOUNDS - 1);
   return hip_status(hipGetLastError());
 }
 
@@ -560,16 +559,17 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   clk.mark(21);
   // (5) sign convention; V_new = V + V (X - I) (FP64 output).
   PFSM_TRY(col_sign_f32(X32, n, n, (double*)(W + pl->o_sgn), s));
-  PFSM_TRY(pack_x3(X32, 0, n, n, n, 0, Xpk, ldp, s));
   const bool refine = !(pl->flags & PFSM_FLAG_NO_REFINE);
   if (!refine) {
     // eigenvalue estimates of the reduced-precision step: x_j^T At x_j
+    PFSM_TRY(pack_x3(X32, 0, n, n, n, 0, Xpk, ldp, s));
     X3Args r = x3(X3_RQ, n, n, n, Atpk, Xpk, nullptr, n, 0);
     r.D = X32; r.ldd = n; r.part = part;
     PFSM_TRY(gemm_x3(X3_RQ, r, s));
     PFSM_TRY(rq_reduce(part, (int)((n + X3_BM - 1) / X3_BM), n, nullptr, (double*)(W + pl->o_lamu), s));
   }
   clk.mark(22);
+  clk.mark(23);  // the ordering comes with the refinement, after the back-rotation
   PFSM_TRY(pack_x3(X32, 0, n, n, n, PACK_SUB_I, Xpk, ldp, s));  // columns of X - I
   PFSM_TRY(pack_x3(dV, 1, n, n, ldv, PACK_BY_ROWS, Rpk, ldp, s));  // rows of V
   {
@@ -577,18 +577,17 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     g.D = dV; g.ldd = ldv; g.d_double = 1;
     PFSM_TRY(gemm_x3(X3_ADD, g, s));
   }
-  clk.mark(23);
   if (!refine) {
+    clk.mark(24);
+    clk.mark(25);
     int* rank = (int*)(W + pl->o_rank);
     PFSM_TRY(finalize_order_values((double*)(W + pl->o_lamu), n, dLam, rank, info, s));
     PFSM_TRY(permute_f64_cols(Vn64, n, rank, dVout, ldvo, n, n, s));
     PFSM_TRY(col_norm2(dVout, n, n, ldvo, (double*)(W + pl->o_den), s));
     PFSM_TRY(norm_check((double*)(W + pl->o_den), n, info, s));
-    clk.mark(24);
-    clk.mark(25);
+    clk.mark(26);
     return hip_status(hipGetLastError());
   }
-  clk.mark(24);
   // (6) FP64 refinement: Z = A V_new, Rayleigh quotients, cluster Rayleigh-Ritz, order.
   {
     // Z = A V_new to FP64 accuracy on the int8 matrix cores: digits of the
@@ -598,14 +597,16 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     int* ozE = (int*)(W + pl->m_oz + align256(2 * oz_plane_bytes(n, n, REFINE_OZ_SLICES)));
     PFSM_TRY(oz_split(dA, lda, n, n, REFINE_OZ_SLICES, ozA, ozE, info, s));
     PFSM_TRY(oz_split(Vn64, n, n, n, REFINE_OZ_SLICES, ozV, ozE + n, info, s));
+    clk.mark(24);  // the product stage holds exactly one launch
     PFSM_TRY(gemm_oz(n, n, n, REFINE_OZ_SLICES, ozA, ozE, ozV, ozE + n, B64a, n, s));
+    clk.mark(25);
     RefineBufs b;
     b.d = rb; b.nn = rb + n; b.lam_s = rb + 2 * n;
     b.rank = (int*)(rb + 3 * n); b.inv = (int*)(rb + 4 * n); b.cstart = (int*)(rb + 5 * n);
     b.csize = (int*)(rb + 6 * n); b.clus = (int*)(rb + 7 * n);
     PFSM_TRY(refine_rr(Vn64, n, B64a, n, n, REFINE_TAU, dLam, dVout, ldvo, b, info, s));
   }
-  clk.mark(25);
+  clk.mark(26);
   return hip_status(hipGetLastError());
 }
 

@@ -1,29 +1,82 @@
-"""Counter probe for the HBM traffic of the dominant kernels (run under
-`rocprofv3 --pmc FETCH_SIZE` and, separately, `--pmc WRITE_SIZE`).
+"""Counter probe for the HBM traffic of the dominant kernels.
 
     python -m paper_1502_07806_amd.traffic_probe [--n 8192]
+        dispatches the kernels; run it under `rocprofv3 --pmc FETCH_SIZE` and,
+        separately, `rocprofv3 --pmc WRITE_SIZE` (CSV output)
+    python -m paper_1502_07806_amd.traffic_probe --summarize FETCH.csv WRITE.csv --out profiles/traffic.json
+        turns the two counter files into HBM bytes per launch
 
 Dispatches, in order: a plain device copy of 1 GiB (calibration: 1 GiB read +
-1 GiB written), then one folded-spectrum update product of each path at order
-n on synthetic operands: the split-BF16 kernel (gemm_x3_kernel, FSUPD
-epilogue) and the FP64 kernel (gemm_f64_kernel, FSUPD epilogue).  The counter
-values per dispatch divided by the copy's give bytes per launch.  Needs
+1 GiB written), then at order n on synthetic operands: the split-BF16
+folded-spectrum update (FSUPD epilogue, default tile configuration), the
+FP64 folded-spectrum update, and the int8 digit product of the refinement
+(two digit splits, then one launch).  Each counter value of a dispatch is
+scaled by the copy's bytes over the copy's counter value.  Needs
 libpfsm_testhooks.so (the internal kernels' test entry points).
 """
 import argparse
+import csv
 import ctypes
+import hashlib
+import json
 import os
 
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+GEMM_SOURCES = ("gemm_f64.hip", "gemm_x3.hip", "gemm_x3.h", "gemm_oz.hip", "gemm_oz.h", "common.h")
+
+
+def gemm_source_hash() -> str:
+    """Hash of the GEMM kernel sources: stored traffic figures apply only to the
+    kernels they were measured on."""
+    h = hashlib.sha256()
+    for f in GEMM_SOURCES:
+        p = os.path.join(HERE, "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def summarize(fetch_csv: str, write_csv: str, n: int, out: str):
+    def per_dispatch(path):
+        d = {}
+        for r in csv.DictReader(open(path)):
+            k = int(r["Dispatch_Id"])
+            e = d.setdefault(k, {"name": r["Kernel_Name"], "kib": 0.0})
+            e["kib"] += float(r["Counter_Value"])
+        return [d[k] for k in sorted(d)]
+    fe, wr = per_dispatch(fetch_csv), per_dispatch(write_csv)
+    copy_f = [e for e in fe if "copyBuffer" in e["name"]][0]["kib"]
+    copy_w = [e for e in wr if "copyBuffer" in e["name"]][0]["kib"]
+    gib_kib = float(1 << 20)
+    sf, sw = gib_kib / copy_f, gib_kib / copy_w  # true bytes per counted byte (copy of 1 GiB)
+
+    def pick(lst, key):
+        return [e for e in lst if key in e["name"]][0]["kib"]
+    res = {"_calibration": {"copy_bytes": 1 << 30, "fetch_scale": sf, "write_scale": sw,
+                            "note": "FETCH_SIZE and WRITE_SIZE (KiB, summed over agents) per dispatch, each scaled "
+                                    "by what the same counter reads for a 1 GiB device copy"}}
+    for key, name in (("gemm_x3_fsupd_n%d" % n, "gemm_x3_dl<2>"), ("gemm_f64_fsupd_n%d" % n, "gemm_f64_kernel"),
+                      ("gemm_oz_n%d" % n, "gemm_oz_fused")):
+        f, w = pick(fe, name) * 1024 * sf, pick(wr, name) * 1024 * sw
+        res[key] = {"kernel": name, "fetch_bytes": f, "write_bytes": w, "bytes_per_launch": f + w,
+                    "source_hash": gemm_source_hash()}
+    with open(out, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res, indent=1))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(HERE), "profiles", "traffic.json"))
     a = ap.parse_args()
     n = a.n
+    if a.summarize:
+        summarize(a.summarize[0], a.summarize[1], n, a.out)
+        return
     L = ctypes.CDLL(os.path.join(HERE, "libpfsm_testhooks.so"))
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     L.pfsm_test_gemm_x3.argtypes = [i32, i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, dbl, dbl, vp, i64,
@@ -33,6 +86,10 @@ def main():
     L.pfsm_test_pack_x3.argtypes = [vp, i32, i64, i64, i64, i32, vp, i64, vp]
     L.pfsm_test_x3_row_stride.argtypes = [i64]
     L.pfsm_test_x3_row_stride.restype = i64
+    L.pfsm_test_oz_split.argtypes = [vp, i64, i64, i64, i32, vp, vp, vp, vp]
+    L.pfsm_test_gemm_oz.argtypes = [i64, i64, i64, i32, vp, vp, vp, vp, vp, i64, i32, vp]
+    L.pfsm_test_oz_row_stride.argtypes = [i64]
+    L.pfsm_test_oz_row_stride.restype = i64
     dev = torch.device("cuda:0")
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     P = lambda t: ctypes.c_void_p(t.data_ptr())
@@ -65,6 +122,18 @@ def main():
     torch.cuda.synchronize()
     assert L.pfsm_test_gemm_f64(0, 0, 2, n, n, n, P(M), n, P(B), n, P(C), n, 0.1, 0.0, P(eps), P(C), n, None, 0,
                                 s) == 0
+    torch.cuda.synchronize()
+    # int8 digit product (six digits), C = M B
+    s6 = 6
+    ldo = L.pfsm_test_oz_row_stride(n)
+    Ad = torch.empty(s6 * n * ldo, dtype=torch.int8, device=dev)
+    Bd = torch.empty(s6 * n * ldo, dtype=torch.int8, device=dev)
+    ea = torch.empty(n, dtype=torch.int32, device=dev)
+    eb = torch.empty(n, dtype=torch.int32, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    assert L.pfsm_test_oz_split(P(M), n, n, n, s6, P(Ad), P(ea), P(info), s) == 0
+    assert L.pfsm_test_oz_split(P(B), n, n, n, s6, P(Bd), P(eb), P(info), s) == 0
+    assert L.pfsm_test_gemm_oz(n, n, n, s6, P(Ad), P(ea), P(Bd), P(eb), P(C), n, -1, s) == 0
     torch.cuda.synchronize()
     print("traffic probe done (n=%d)" % n, flush=True)
 

@@ -262,6 +262,14 @@ def test_timing_stages(pf):
         assert all(v >= 0 for v in s.values())
         # stages that do not run (iteration 3 of 3) only see back-to-back event records
         assert s["basis_change"] > 0 and s["fs_update_2"] > 0 and s["fs_update_3"] < 0.05
+        assert s["refine_product"] < 0.05 and s["refine_rr"] < 0.05  # FP64 path: no refinement
+    pm = pf.Plan(256, uniform_layout(256, 64), halo=32, precision="mixed_bf16")
+    pm.solve(A, V)
+    pm.timing_begin(1)
+    pm.solve(A, V)
+    sm = pm.timing_read()[0]
+    pm.timing_end()
+    assert sm["back_rotation"] > 0 and sm["refine_product"] > 0 and sm["refine_rr"] > 0
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed_bf16", 1e-4)])
