@@ -131,6 +131,9 @@ __device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t
   }
   double a_eff = g.alpha;
   if (EPI == X3_FSUPD && g.alpha_dev) a_eff = *g.alpha_dev;
+  // C may alias D (in-place update): the inputs of 8 outputs are gathered
+  // before any of them is stored, so 8 loads are in flight instead of one.
+  constexpr int GR = 8;
 #pragma unroll
   for (int ib = 0; ib < WR; ++ib) {
     const int64_t gi = m0 + wi0 + ib * 32 + l32;
@@ -138,26 +141,45 @@ __device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t
 #pragma unroll
     for (int jb = 0; jb < WC; ++jb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
-        if (gj >= g.N) continue;
-        const double v = (double)acc[ib][jb][r];
-        double outv;
-        if (EPI == X3_STORE) {
-          outv = g.alpha * v;
-          if (g.beta != 0.0)
-            outv += g.beta * (g.c_double ? ((const double*)g.C)[gi + gj * g.ldc] : (double)((const float*)g.C)[gi + gj * g.ldc]);
-        } else if (EPI == X3_SHIFT) {
-          outv = v - (double)g.B32[gi + gj * g.ldb32] * g.eps[gj];
-        } else if (EPI == X3_FSUPD) {
-          const double dv = (double)((const float*)g.D)[gi + gj * g.ldd];
-          outv = dv - a_eff * (v - (double)g.B32[gi + gj * g.ldb32] * g.eps[gj]);
-        } else {  // X3_ADD
-          const double dv = g.d_double ? ((const double*)g.D)[gi + gj * g.ldd] : (double)((const float*)g.D)[gi + gj * g.ldd];
-          outv = v + dv;
+      for (int r0 = 0; r0 < 16; r0 += GR) {
+        // unconditional loads (columns past N read column N - 1), so that no
+        // branch separates them and all of them issue before the first use
+        double in1[GR], in2[GR], ev[GR];
+#pragma unroll
+        for (int u = 0; u < GR; ++u) {
+          const int r = r0 + u;
+          const int64_t gj = min<int64_t>(n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4), g.N - 1);
+          in1[u] = 0.0;
+          in2[u] = 0.0;
+          ev[u] = 0.0;
+          if (EPI == X3_STORE) {
+            if (g.beta != 0.0)
+              in1[u] = g.c_double ? ((const double*)g.C)[gi + gj * g.ldc] : (double)((const float*)g.C)[gi + gj * g.ldc];
+          } else if (EPI == X3_SHIFT) {
+            in1[u] = (double)g.B32[gi + gj * g.ldb32];
+            ev[u] = g.eps[gj];
+          } else if (EPI == X3_FSUPD) {
+            in1[u] = (double)g.B32[gi + gj * g.ldb32];
+            ev[u] = g.eps[gj];
+            in2[u] = (double)((const float*)g.D)[gi + gj * g.ldd];
+          } else {  // X3_ADD
+            in1[u] = g.d_double ? ((const double*)g.D)[gi + gj * g.ldd] : (double)((const float*)g.D)[gi + gj * g.ldd];
+          }
         }
-        if (g.c_double) ((double*)g.C)[gi + gj * g.ldc] = outv;
-        else ((float*)g.C)[gi + gj * g.ldc] = (float)outv;
+#pragma unroll
+        for (int u = 0; u < GR; ++u) {
+          const int r = r0 + u;
+          const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
+          if (gj >= g.N) continue;
+          const double v = (double)acc[ib][jb][r];
+          double outv;
+          if (EPI == X3_STORE) outv = g.alpha * v + g.beta * in1[u];
+          else if (EPI == X3_SHIFT) outv = v - in1[u] * ev[u];
+          else if (EPI == X3_FSUPD) outv = in2[u] - a_eff * (v - in1[u] * ev[u]);
+          else outv = v + in1[u];
+          if (g.c_double) ((double*)g.C)[gi + gj * g.ldc] = outv;
+          else ((float*)g.C)[gi + gj * g.ldc] = (float)outv;
+        }
       }
   }
 }
@@ -431,18 +453,23 @@ __global__ __launch_bounds__(256) void k_pack(const void* X, int src_double, int
     tile[rr][kk] = v;
   }
   __syncthreads();
-  // write: 64 rows x 64 bf16 (hi 32 | lo 32)
-  for (int idx = tid; idx < 64 * 32; idx += 256) {
-    int kk = idx % 32, rr = idx / 32;
-    int64_t r = r0 + rr;
-    if (r >= R) continue;
-    double v = tile[rr][kk];
-    float vf = (float)v;
-    bf16_t h = f2bf(vf);
-    bf16_t l = f2bf((float)(v - (double)bf2f(h)));
-    bf16_t* dst = P + r * ldp + kc * 64;
-    dst[kk] = h;
-    dst[32 + kk] = l;
+  // write: 64 rows x 64 bf16 (hi 32 | lo 32); thread (row, c) makes k = 8c .. 8c+7
+  // and stores one 16-byte chunk of each plane
+  const int rr = tid >> 2, c = tid & 3;
+  const int64_t r = r0 + rr;
+  if (r < R) {
+    u32x4 hw, lw;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double v0 = tile[rr][8 * c + 2 * u], v1 = tile[rr][8 * c + 2 * u + 1];
+      const bf16_t h0 = f2bf((float)v0), h1 = f2bf((float)v1);
+      const bf16_t l0 = f2bf((float)(v0 - (double)bf2f(h0))), l1 = f2bf((float)(v1 - (double)bf2f(h1)));
+      hw[u] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      lw[u] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    }
+    bf16_t* dst = P + r * ldp + kc * 64;  // 128-byte aligned: ldp is a multiple of 64
+    *(u32x4*)(dst + 8 * c) = hw;
+    *(u32x4*)(dst + 32 + 8 * c) = lw;
   }
 }
 
