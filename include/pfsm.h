@@ -46,6 +46,8 @@
  *     -3  a submatrix eigensolver did not converge within its sweep limit
  *     -4  an output vector lost its length (squared norm outside [1/4, 4] before
  *         normalisation): V_prev does not have orthonormal columns
+ *     -5  generalized -> standard conversion: a diagonal entry of B is not a
+ *         positive finite number
  * The first condition found wins.
  */
 #ifndef PFSM_H
@@ -223,6 +225,28 @@ pfsm_status pfsm_debug_stats(pfsm_plan* plan, const void* dWork, size_t work_byt
 pfsm_status pfsm_timing_begin(pfsm_plan* plan, int32_t max_solves);
 pfsm_status pfsm_timing_read(pfsm_plan* plan, float* ms, int32_t capacity, int32_t* solves_recorded);
 pfsm_status pfsm_timing_end(pfsm_plan* plan);
+
+/* Generalized -> standard conversion (Implementation section, Eqs. 13-15).
+ * For A x = lambda B x with B symmetric positive definite and diagonally
+ * dominant (the overlap matrix of ultrasoft pseudopotentials), writes
+ * Z = B^{-1} A, reached without forming B^{-1} by `iterations` steps of
+ * Z_{k+1} = (I - D^{-1} B) Z_k + D^{-1} A, D = diag(B), from Z_0 = A (the
+ * identity as the initial approximation of B^{-1}).  The steps converge when
+ * the spectral radius of I - D^{-1} B is below one; each costs one FP64
+ * matrix-core product (2 n^3 flop) and the columns of Z are independent.
+ *   dA, dB: n x n column-major (lda, ldb >= n), read only.
+ *   dZ: n x n output (ldz >= n); must not overlap A, B or the workspace.
+ *   dWork: >= pfsm_g2s_workspace_size(n) bytes, 256-byte aligned, caller-owned.
+ *   dResidual (nullable, device, `iterations` doubles): entry k receives
+ *     ||A - B Z_k||_F / ||A||_F, the residual of the iterate step k starts from.
+ *   dInfo (device int32, cleared by the call): -5 when a diagonal entry of B is
+ *     not a positive finite number, -1 when a residual is not finite.
+ * Enqueued on `stream` with no allocation and no synchronisation.
+ * Errors: INVALID_ARG, WORKSPACE_TOO_SMALL, HIP_ERROR. */
+pfsm_status pfsm_g2s_workspace_size(int64_t n, size_t* bytes);
+pfsm_status pfsm_generalized_to_standard(int64_t n, const double* dA, int64_t lda, const double* dB, int64_t ldb,
+                                         int32_t iterations, double* dZ, int64_t ldz, void* dWork,
+                                         size_t work_bytes, double* dResidual, int32_t* dInfo, void* stream);
 
 #ifdef __cplusplus
 }

@@ -3,4 +3,5 @@
 The compute path is libpfsm.so (hand-written HIP kernels for gfx950) behind
 the C ABI declared in include/pfsm.h; this package is its Python binding.
 """
-from .binding import BatchedPlan, Plan, PFSMFunction, load_library, solve, LIB_PATH  # noqa: F401
+from .binding import (BatchedPlan, Plan, PFSMFunction, load_library, solve, generalized_to_standard,  # noqa: F401
+                      LIB_PATH)

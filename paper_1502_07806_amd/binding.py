@@ -26,7 +26,8 @@ PFSM_SHIFT = {"fixed": 0, "rayleigh": 1}
 INFO_TEXT = {0: "ok", -1: "non-finite eigenvalue",
              -2: "overlap factor too far from the identity for the mixed-precision orthonormalisation",
              -3: "submatrix eigensolver did not converge",
-             -4: "an output vector lost its length: V_prev is not orthonormal"}
+             -4: "an output vector lost its length: V_prev is not orthonormal",
+             -5: "a diagonal entry of B is not a positive finite number"}
 FLAG_NO_REFINE = 1
 
 
@@ -91,6 +92,10 @@ def load_library(path: str = LIB_PATH):
     lib.pfsm_timing_read.restype = ctypes.c_int
     lib.pfsm_timing_end.argtypes = [vp]
     lib.pfsm_timing_end.restype = ctypes.c_int
+    lib.pfsm_g2s_workspace_size.argtypes = [i64, ctypes.POINTER(sz)]
+    lib.pfsm_g2s_workspace_size.restype = ctypes.c_int
+    lib.pfsm_generalized_to_standard.argtypes = [i64, vp, i64, vp, i64, i32, vp, i64, vp, sz, vp, vp, vp]
+    lib.pfsm_generalized_to_standard.restype = ctypes.c_int
     lib.pfsm_status_string.argtypes = [ctypes.c_int]
     lib.pfsm_status_string.restype = ctypes.c_char_p
     _lib = lib
@@ -372,3 +377,39 @@ class PFSMFunction(torch.autograd.Function):
         lam, V = ctx.saved_tensors
         gA = ctx.plan.backward(lam, V, grad_lam, grad_V, ctx.eta)
         return gA, None, None, None
+
+
+def generalized_to_standard(A: torch.Tensor, B: torch.Tensor, iterations: int, out: Optional[torch.Tensor] = None,
+                            residuals: bool = False, check: bool = True):
+    """Z = B^{-1} A for A x = lambda B x (Implementation section, Eqs. 13-15):
+    `iterations` steps of Z_{k+1} = (I - D^{-1} B) Z_k + D^{-1} A from Z_0 = A,
+    D = diag(B), each one FP64 product on the GPU (pfsm_generalized_to_standard).
+
+    A and B are n x n float64 GPU tensors (B symmetric).  Z is returned as a
+    column-major tensor (stride(0) == 1) holding Z itself; with `residuals`,
+    also the n_it values ||A - B Z_k||_F / ||A||_F (k = 0 .. iterations-1)."""
+    n = A.shape[0]
+    if A.shape != (n, n) or B.shape != (n, n):
+        raise ValueError("A and B must be square and of the same order")
+    Ac, lda = _colmajor(A)
+    Bc, ldb = _colmajor(B)
+    L = load_library()
+    need = ctypes.c_size_t(0)
+    _check(L.pfsm_g2s_workspace_size(n, ctypes.byref(need)))
+    work = torch.empty(need.value + 256, dtype=torch.uint8, device=A.device)
+    wp = (work.data_ptr() + 255) // 256 * 256
+    Z = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=A.device).t()
+    if Z.stride(0) != 1:
+        raise ValueError("out must be column-major (stride(0) == 1)")
+    res = torch.empty(max(iterations, 1), dtype=torch.float64, device=A.device) if residuals else None
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    _check(L.pfsm_generalized_to_standard(n, Ac.data_ptr(), lda, Bc.data_ptr(), ldb, int(iterations), Z.data_ptr(),
+                                          Z.stride(1), wp, need.value, res.data_ptr() if res is not None else None,
+                                          info.data_ptr(), _stream_handle()))
+    if check:
+        code = int(info.item())
+        if code != 0:
+            raise RuntimeError("pfsm device info %d: %s" % (code, INFO_TEXT.get(code, "error")))
+    if residuals:
+        return Z, res[:iterations], info
+    return Z, info

@@ -18,6 +18,8 @@ enum GemmEpi : int {
   EPI_SHIFT = 1,   // C = acc - B(i,j) * eps[j]            (B square operand, not transposed)
   EPI_FSUPD = 2,   // C = D(i,j) - a * (acc - B(i,j)*eps[j]), a = *alpha_dev or alpha
   EPI_RQ = 3,      // part[tile_m][j] = sum_{i in tile} acc(i,j) * D(i,j)   (C untouched)
+  EPI_G2S = 4,     // C = B(i,j) + eps[i] * (D(i,j) - acc); part[tile_m][j] = sum_i (D(i,j) - acc)^2
+                   // when part is set (B square operand, not transposed; C must not alias B)
 };
 
 struct GemmArgs {
@@ -27,7 +29,7 @@ struct GemmArgs {
   double* C; int64_t ldc;
   double alpha, beta;
   const double* alpha_dev;   // optional device scalar for EPI_FSUPD
-  const double* eps;         // column shifts for EPI_SHIFT / EPI_FSUPD
+  const double* eps;         // column shifts for EPI_SHIFT / EPI_FSUPD, row scales for EPI_G2S
   const double* D; int64_t ldd;  // FSUPD base matrix / RQ partner matrix
   double* part;              // RQ partial sums [tiles_m x N]
   const int32_t* krange;     // optional [tiles_n][2] K range per column tile

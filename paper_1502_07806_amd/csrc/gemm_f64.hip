@@ -196,6 +196,64 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m
     return;
   }
 
+  if (EPI == EPI_G2S) {
+    // C = Z + D^{-1}(A - B Z) for the generalized -> standard iteration, with
+    // per-column partial sums of the squared residual.  The loads of one row
+    // block are gathered before its stores.
+    double cs[4][4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cs[jb][r] = 0.0;
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib) {
+      const int64_t gi = m0 + wi0 + ib * 16 + l16;
+      if (gi >= g.M) continue;
+      const double di = g.eps[gi];
+      double zv[4][4], av[4][4];
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gj = min<int64_t>(n0 + wj0 + jb * 16 + lq + 4 * r, g.N - 1);
+          zv[jb][r] = g.B[gi + gj * g.ldb];
+          av[jb][r] = g.D[gi + gj * g.ldd];
+        }
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gj = n0 + wj0 + jb * 16 + lq + 4 * r;
+          if (gj >= g.N) continue;
+          const double res = av[jb][r] - acc[ib][jb][r];
+          g.C[gi + gj * g.ldc] = zv[jb][r] + di * res;
+          cs[jb][r] += res * res;
+        }
+    }
+    if (!g.part) return;
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double s = cs[jb][r];
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off, 64);
+        cs[jb][r] = s;
+      }
+    if (l16 == 0) {
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[wave & 1][wj0 + jb * 16 + lq + 4 * r] = cs[jb][r];
+    }
+    __syncthreads();
+    if (tid < BN) {
+      const int64_t gj = n0 + tid;
+      if (gj < g.N) g.part[(int64_t)tm * g.N + gj] = red[0][tid] + red[1][tid];
+    }
+    return;
+  }
+
   double a_eff = g.alpha;
   if (EPI == EPI_FSUPD && g.alpha_dev) a_eff = *g.alpha_dev;
 #pragma unroll
@@ -234,6 +292,7 @@ hipError_t launch_epi(int epi, const GemmArgs& a, hipStream_t s) {
     case EPI_SHIFT: hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, EPI_SHIFT>), grid, block, 0, s, a, tm, tn); break;
     case EPI_FSUPD: hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, EPI_FSUPD>), grid, block, 0, s, a, tm, tn); break;
     case EPI_RQ: hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, EPI_RQ>), grid, block, 0, s, a, tm, tn); break;
+    case EPI_G2S: hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, EPI_G2S>), grid, block, 0, s, a, tm, tn); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -243,7 +302,7 @@ hipError_t launch_epi(int epi, const GemmArgs& a, hipStream_t s) {
 
 hipError_t gemm_f64(bool ta, bool tb, int epi, const GemmArgs& a, hipStream_t s) {
   // SHIFT / FSUPD read B at output positions: only the non-transposed square case is valid.
-  if ((epi == EPI_SHIFT || epi == EPI_FSUPD) && (tb || a.K < a.M)) return hipErrorInvalidValue;
+  if ((epi == EPI_SHIFT || epi == EPI_FSUPD || epi == EPI_G2S) && (tb || a.K < a.M)) return hipErrorInvalidValue;
   if (!ta && !tb) return launch_epi<false, false>(epi, a, s);
   if (ta && !tb) return launch_epi<true, false>(epi, a, s);
   if (!ta && tb) return launch_epi<false, true>(epi, a, s);

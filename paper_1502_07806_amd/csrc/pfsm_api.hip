@@ -8,6 +8,7 @@
 #include "gemm_x3.h"
 #include "refine.h"
 #include "gemm_oz.h"
+#include "g2s.h"
 
 #include <algorithm>
 #include <new>
@@ -608,6 +609,31 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   }
   clk.mark(26);
   return hip_status(hipGetLastError());
+}
+
+pfsm_status pfsm_g2s_workspace_size(int64_t n, size_t* bytes) {
+  if (!bytes || n < 1) return PFSM_INVALID_ARG;
+  *bytes = g2s_workspace_bytes(n);
+  return PFSM_OK;
+}
+
+pfsm_status pfsm_generalized_to_standard(int64_t n, const double* dA, int64_t lda, const double* dB, int64_t ldb,
+                                         int32_t iterations, double* dZ, int64_t ldz, void* dWork,
+                                         size_t work_bytes, double* dResidual, int32_t* dInfo, void* stream) {
+  if (n < 1 || !dA || !dB || !dZ || !dWork || !dInfo || iterations < 0) return PFSM_INVALID_ARG;
+  if (lda < n || ldb < n || ldz < n) return PFSM_INVALID_ARG;
+  if (((uintptr_t)dWork) % 256 != 0) return PFSM_INVALID_ARG;
+  const size_t need = g2s_workspace_bytes(n);
+  if (work_bytes < need) return PFSM_WORKSPACE_TOO_SMALL;
+  const size_t bA = (size_t)(lda * (n - 1) + n) * sizeof(double);
+  const size_t bB = (size_t)(ldb * (n - 1) + n) * sizeof(double);
+  const size_t bZ = (size_t)(ldz * (n - 1) + n) * sizeof(double);
+  if (overlaps(dZ, bZ, dA, bA) || overlaps(dZ, bZ, dB, bB) || overlaps(dZ, bZ, dWork, need)) return PFSM_INVALID_ARG;
+  if (dResidual && (overlaps(dResidual, (size_t)iterations * sizeof(double), dZ, bZ) ||
+                    overlaps(dResidual, (size_t)iterations * sizeof(double), dWork, need)))
+    return PFSM_INVALID_ARG;
+  return hip_status(g2s_run(n, dA, lda, dB, ldb, iterations, dZ, ldz, g2s_carve(dWork, n), dResidual, dInfo,
+                            (hipStream_t)stream));
 }
 
 pfsm_status pfsm_debug_stats(pfsm_plan* pl, const void* dWork, size_t work_bytes, int32_t* out, int32_t capacity,

@@ -2,7 +2,7 @@
 
 This package only draws random numbers and assembles inputs (prescribed
 spectra, random orthogonal bases, perturbed previous eigenvectors, SCF-like
-sequences, batch layouts, loss weights).  It holds none of the method's
+sequences, batch layouts, loss weights, overlap matrices).  It holds none of the method's
 arithmetic, so both the CPU oracle and the GPU path can consume it.
 """
 from .gen import (  # noqa: F401
@@ -19,4 +19,5 @@ from .gen import (  # noqa: F401
     loss_weights,
     random_symmetric_unit,
     uniform_layout,
+    overlap_matrix,
 )

@@ -182,3 +182,17 @@ def uniform_layout(n: int, slice_size: int) -> List[int]:
     """Partition offsets 0, m, 2m, ..., n (last slice may be shorter)."""
     offs = list(range(0, n, slice_size)) + [n]
     return offs
+
+
+def overlap_matrix(n: int, delta: float, seed: int, device="cpu") -> torch.Tensor:
+    """Synthetic overlap matrix B = I + delta G G^T / n (G Gaussian, PCG64 seed):
+    symmetric positive definite with eigenvalues in about [1, 1 + 4 delta] and
+    diagonal near 1 + delta, so I - D^{-1} B has spectral radius about
+    3 delta / (1 + delta).  Stands in for the ultrasoft-pseudopotential overlap
+    of the paper's Implementation section (B close to, but not, the identity)."""
+    g = torch.Generator(device="cpu").manual_seed(int(seed))
+    G = torch.randn(n, n, dtype=torch.float64, generator=g).to(device)
+    B = (G @ G.T) * (delta / n)
+    B = 0.5 * (B + B.T)
+    B.diagonal().add_(1.0)
+    return B

@@ -70,3 +70,28 @@ def test_null_arguments(lib):
     assert lib.pfsm_solve(None, None, 0, None, 0, None, None, 0, None, 0, None, None) == 1
     assert lib.pfsm_backward(None, None, None, 0, None, None, 0, 0.0, None, 0, None, 0, None, None) == 1
     lib.pfsm_plan_destroy(None)
+
+
+def test_g2s_argument_validation(lib):
+    """Generalized -> standard conversion: workspace size and argument checks
+    (all rejected on the host, before any device work)."""
+    sz = ctypes.c_size_t(0)
+    assert lib.pfsm_g2s_workspace_size(0, ctypes.byref(sz)) == 1
+    assert lib.pfsm_g2s_workspace_size(1000, None) == 1
+    assert lib.pfsm_g2s_workspace_size(1000, ctypes.byref(sz)) == 0
+    assert sz.value >= 1000 * 1000 * 8 + 2 * 1000 * 8
+    f = lib.pfsm_generalized_to_standard
+    fake = 1 << 40  # never dereferenced: every call below fails validation first
+    assert f(0, fake, 1, fake, 1, 3, fake + (1 << 32), 1, fake + (1 << 33), sz.value, None, fake, None) == 1
+    assert f(1000, None, 1000, fake, 1000, 3, fake + (1 << 32), 1000, fake + (1 << 33), sz.value, None, fake, None) == 1
+    assert f(1000, fake, 999, fake, 1000, 3, fake + (1 << 32), 1000, fake + (1 << 33), sz.value, None, fake, None) == 1
+    assert f(1000, fake, 1000, fake, 1000, -1, fake + (1 << 32), 1000, fake + (1 << 33), sz.value, None, fake,
+             None) == 1
+    # Z overlapping A
+    assert f(1000, fake, 1000, fake + (1 << 34), 1000, 3, fake + 8, 1000, fake + (1 << 33), sz.value, None, fake,
+             None) == 1
+    # workspace too small, misaligned workspace
+    assert f(1000, fake, 1000, fake + (1 << 34), 1000, 3, fake + (1 << 32), 1000, fake + (1 << 33), sz.value - 1,
+             None, fake, None) == 5
+    assert f(1000, fake, 1000, fake + (1 << 34), 1000, 3, fake + (1 << 32), 1000, fake + (1 << 33) + 8, sz.value,
+             None, fake, None) == 1
