@@ -109,6 +109,43 @@ def cpu_baseline(n_full: int, sample_n: int = 4096):
     }
 
 
+def bench_g2s(n: int, args, iterations: int = 8):
+    """The conversion step in front of the path (Eqs. 13-15): Z = B^{-1} A by
+    `iterations` FP64 steps at order n on a synthetic overlap B = I + 0.05 G G^T / n;
+    timed with events on the stream it runs on; per-step FP64 product 2 n^3."""
+    import torch
+    import paper_1502_07806_amd as pf
+    from pfsm_workloads import overlap_matrix, prescribed_problem
+    dev = torch.device("cuda:0")
+    A = prescribed_problem(n, n // 4, 5e-3, 3000, clusters=True, device=dev)[0]
+    A = A.t().contiguous().t()
+    B = overlap_matrix(n, 0.05, 6007, device=dev).t().contiguous().t()
+    Z = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+    Z, res, _ = pf.generalized_to_standard(A, B, iterations, out=Z, residuals=True)
+    for _ in range(max(1, args.warmup // 2)):
+        pf.generalized_to_standard(A, B, iterations, out=Z, check=False)
+    ts = []
+    for _ in range(max(2, args.steps // 3)):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pf.generalized_to_standard(A, B, iterations, out=Z, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    step_ms = ms / iterations
+    fl = 2.0 * n ** 3
+    r = res.cpu().numpy()
+    return {"workload": "Z = B^-1 A at N=%d, %d steps, B = I + 0.05 G G^T / N" % (n, iterations),
+            "ms": ms, "ms_per_step": step_ms, "tflops": fl * iterations / (ms * 1e-3) / 1e12,
+            "residual_first_last": [float(r[0]), float(r[-1])],
+            "roofline": {"bound": "mfma", "achieved": fl / (step_ms * 1e-3) / 1e12, "peak": PEAK_TFLOPS["fp64"],
+                         "unit": "TFLOP/s", "frac": fl / (step_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
+                         "kernel": "gemm_f64_kernel<T,N,EPI_G2S> (one per step; step time includes a residual "
+                                   "reduction launch)"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +156,7 @@ def main():
                     help="auto = mixed_bf16 (headline), with the FP64 path and the unrefined result reported beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-g2s", action="store_true", help="skip the generalized-to-standard conversion measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: multi-GPU sharding of the slices is not part of this "
@@ -242,6 +280,8 @@ def main():
         out["fp32_result"] = {"note": "mixed path without the FP64 refinement against A", "ms_per_step": msnr,
                               "accuracy": accnr}
         del pnr
+    if not args.no_g2s:
+        out["generalized_to_standard"] = bench_g2s(n, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out), flush=True)

@@ -234,7 +234,8 @@ pfsm_status pfsm_timing_end(pfsm_plan* plan);
  * identity as the initial approximation of B^{-1}).  The steps converge when
  * the spectral radius of I - D^{-1} B is below one; each costs one FP64
  * matrix-core product (2 n^3 flop) and the columns of Z are independent.
- *   dA, dB: n x n column-major (lda, ldb >= n), read only.
+ *   dA, dB: n x n column-major (lda, ldb >= n), read only; B must be symmetric
+ *     (the product is formed as B^T Z).
  *   dZ: n x n output (ldz >= n); must not overlap A, B or the workspace.
  *   dWork: >= pfsm_g2s_workspace_size(n) bytes, 256-byte aligned, caller-owned.
  *   dResidual (nullable, device, `iterations` doubles): entry k receives

@@ -6,6 +6,7 @@
 // Z_{k+1} = Z_k + D^{-1}(A - B Z_k): one FP64 MFMA GEMM per step whose
 // epilogue applies the row scaling and the update and accumulates the
 // squared residual of Z_k per column.  Columns of Z evolve independently.
+// B is an overlap matrix, symmetric: the product is taken as B^T Z.
 #include "g2s.h"
 #include "misc.h"
 
@@ -101,7 +102,7 @@ hipError_t g2s_run(int64_t n, const double* A, int64_t lda, const double* B, int
     GemmArgs g = {};
     g.M = n; g.N = n; g.K = n; g.A = B; g.lda = ldb; g.B = cur; g.ldb = ldc; g.C = nxt; g.ldc = ldn;
     g.D = A; g.ldd = lda; g.eps = w.dinv; g.part = w.part;
-    e = gemm_f64(false, false, EPI_G2S, g, s);
+    e = gemm_f64(true, false, EPI_G2S, g, s);  // B symmetric: B^T Z = B Z in the faster TN layout
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_g2s_res, dim3(1), dim3(NT), 0, s, w.part, tiles_m * n, w.anorm2, n, res ? res + k : nullptr,
                        info);

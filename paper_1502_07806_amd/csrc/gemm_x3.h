@@ -48,7 +48,7 @@ struct X3Args {
   int cfg;                          // tile configuration (see gemm_x3.hip); -1 = library default
 };
 
-constexpr int X3_NUM_CFG = 5;
+constexpr int X3_NUM_CFG = 6;
 extern int x3_default_cfg;
 hipError_t x3_init();  // once per process and device, before the first split-BF16 launch
 

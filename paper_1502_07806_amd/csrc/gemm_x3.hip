@@ -26,6 +26,8 @@ constexpr int TILE_BYTES = BM * ROWB;     // 36864 per operand per stage
 //          HBM latency overlaps two tiles of matrix-core work
 //   CFG 4: 8 waves in 4 x 2 fed by direct global -> LDS loads into a 4-stage
 //          ring (gemm_x3_dl)
+//   CFG 5: CFG 4 with the LDS fragments of the next stage read while the
+//          MFMAs of the current one run
 template <int CFG> struct X3Cfg;
 template <> struct X3Cfg<0> { static constexpr int NT = 512, WGR = 2, WR = 4, WC = 2, PF = 0; };
 template <> struct X3Cfg<1> { static constexpr int NT = 256, WGR = 2, WR = 4, WC = 4, PF = 0; };
@@ -320,7 +322,7 @@ template <int W> __device__ inline void wait_vm() {
   __builtin_amdgcn_s_waitcnt((W & 15) | (7 << 4) | (15 << 8) | (((W >> 4) & 3) << 14));
 }
 
-template <int EPI>
+template <int EPI, bool PIPE>
 __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int tiles_n) {
   constexpr int NW = 8, WGR = 4, WR = 2, WC = 4, CPW = 16 / NW;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -372,39 +374,80 @@ __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int 
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  for (int t = 0; t < DST - 1 && t < total; ++t) issue(t);
-  for (int t = 0; t < total; ++t) {
-    const int later = min(DST - 2, total - 1 - t);  // stages issued after t that may still be in flight
-    if (later >= 2) wait_vm<2 * 2 * CPW>();
-    else if (later == 1) wait_vm<2 * CPW>();
-    else wait_vm<0>();
-    // Bare barrier (a fenced one would wait for every outstanding load):
-    // every wave's part of stage t has landed, and stage t - 1 was consumed.
-    lds_barrier();
-    if (t + DST - 1 < total) issue(t + DST - 1);
+  struct Frags {
+    v8bf ah[WR], al[WR], bh[WC], bl[WC];
+  };
+  auto read_frags = [&](int t, Frags& f) {
     const unsigned char* Ab = lds + (t % DST) * 2 * DTILE;
     const unsigned char* Bb = Ab + DTILE;
-    v8bf ah[WR], al[WR], bh[WC], bl[WC];
 #pragma unroll
     for (int ib = 0; ib < WR; ++ib) {
       const int row = wi0 + ib * 32 + l32, sw = dswz(row);
-      ah[ib] = as_bf(*(const u32x4*)(Ab + row * DROW + 16 * (lh ^ sw)));
-      al[ib] = as_bf(*(const u32x4*)(Ab + row * DROW + 16 * ((2 + lh) ^ sw)));
+      f.ah[ib] = as_bf(*(const u32x4*)(Ab + row * DROW + 16 * (lh ^ sw)));
+      f.al[ib] = as_bf(*(const u32x4*)(Ab + row * DROW + 16 * ((2 + lh) ^ sw)));
     }
 #pragma unroll
     for (int jb = 0; jb < WC; ++jb) {
       const int row = wj0 + jb * 32 + l32, sw = dswz(row);
-      bh[jb] = as_bf(*(const u32x4*)(Bb + row * DROW + 16 * (lh ^ sw)));
-      bl[jb] = as_bf(*(const u32x4*)(Bb + row * DROW + 16 * ((2 + lh) ^ sw)));
+      f.bh[jb] = as_bf(*(const u32x4*)(Bb + row * DROW + 16 * (lh ^ sw)));
+      f.bl[jb] = as_bf(*(const u32x4*)(Bb + row * DROW + 16 * ((2 + lh) ^ sw)));
     }
+  };
+  auto mma = [&](const Frags& f) {
 #pragma unroll
     for (int ib = 0; ib < WR; ++ib)
 #pragma unroll
       for (int jb = 0; jb < WC; ++jb) {
-        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh[jb], ah[ib], acc[ib][jb], 0, 0, 0);
-        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl[jb], ah[ib], acc[ib][jb], 0, 0, 0);
-        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh[jb], al[ib], acc[ib][jb], 0, 0, 0);
+        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bh[jb], f.ah[ib], acc[ib][jb], 0, 0, 0);
+        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bl[jb], f.ah[ib], acc[ib][jb], 0, 0, 0);
+        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bh[jb], f.al[ib], acc[ib][jb], 0, 0, 0);
       }
+  };
+
+  for (int t = 0; t < DST - 1 && t < total; ++t) issue(t);
+  if (!PIPE) {
+    for (int t = 0; t < total; ++t) {
+      const int later = min(DST - 2, total - 1 - t);  // stages issued after t that may still be in flight
+      if (later >= 2) wait_vm<2 * 2 * CPW>();
+      else if (later == 1) wait_vm<2 * CPW>();
+      else wait_vm<0>();
+      // Bare barrier (a fenced one would wait for every outstanding load):
+      // every wave's part of stage t has landed, and stage t - 1 was consumed.
+      lds_barrier();
+      if (t + DST - 1 < total) issue(t + DST - 1);
+      Frags f;
+      read_frags(t, f);
+      mma(f);
+    }
+  } else if (total > 0) {
+    // Fragments one stage ahead: stage t + 1 is read from LDS while the
+    // MFMAs of stage t run.  Stage t + 1 must have landed before that read
+    // (barrier at the top of iteration t); the slot refilled in iteration t,
+    // (t + 3) % 4, held stage t - 1, whose fragments were read in iteration
+    // t - 2 and consumed in iteration t - 1, before this barrier.
+    {
+      const int later0 = min(DST - 2, total - 1);
+      if (later0 >= 2) wait_vm<2 * 2 * CPW>();
+      else if (later0 == 1) wait_vm<2 * CPW>();
+      else wait_vm<0>();
+      lds_barrier();
+    }
+    Frags F0, F1;
+    read_frags(0, F0);
+    auto step = [&](int t, Frags& cur, Frags& nxt) {
+      if (t + 1 < total) {
+        if (t + 2 <= total - 1) wait_vm<2 * CPW>();  // stage t + 2 may still be in flight
+        else wait_vm<0>();
+        lds_barrier();
+        if (t + DST - 1 < total) issue(t + DST - 1);
+        read_frags(t + 1, nxt);
+      }
+      mma(cur);
+    };
+    for (int t = 0; t < total; t += 2) {
+      step(t, F0, F1);
+      if (t + 1 < total) step(t + 1, F1, F0);
+    }
   }
   __syncthreads();  // the RQ epilogue reuses shared memory; no wave may still be reading stages
   x3_epilogue<EPI, WGR, WR, WC>(g, acc, m0, n0, wi0, wj0, tid, tm, red);
@@ -523,8 +566,11 @@ hipError_t x3_init() {
   if (e == hipSuccess) e = set_attrs<2>();
   if (e == hipSuccess) e = set_attrs<3>();
   const int dl = DST * 2 * DTILE;
-#define X3_DL_ATTR(E) \
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)gemm_x3_dl<E>, hipFuncAttributeMaxDynamicSharedMemorySize, dl);
+#define X3_DL_ATTR(E)                                                                                         \
+  if (e == hipSuccess)                                                                                        \
+    e = hipFuncSetAttribute((const void*)gemm_x3_dl<E, false>, hipFuncAttributeMaxDynamicSharedMemorySize, dl); \
+  if (e == hipSuccess)                                                                                        \
+    e = hipFuncSetAttribute((const void*)gemm_x3_dl<E, true>, hipFuncAttributeMaxDynamicSharedMemorySize, dl);
   X3_DL_ATTR(X3_STORE)
   X3_DL_ATTR(X3_SHIFT)
   X3_DL_ATTR(X3_FSUPD)
@@ -544,13 +590,16 @@ hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
     case 1: return launch_cfg<1>(epi, a, tm, tn, s);
     case 2: return launch_cfg<2>(epi, a, tm, tn, s);
     case 3: return launch_cfg<3>(epi, a, tm, tn, s);
-    case 4: {
+    case 4:
+    case 5: {
       const int total = (a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) ? tm * (tm + 1) / 2 : tm * tn;
       const size_t dl = DST * 2 * DTILE;
+      const bool pipe = cfg == 5;
       switch (epi) {
 #define X3_DL_CASE(E)                                                                           \
   case E:                                                                                       \
-    hipLaunchKernelGGL((gemm_x3_dl<E>), dim3(total), dim3(512), dl, s, a, tm, tn); \
+    if (pipe) hipLaunchKernelGGL((gemm_x3_dl<E, true>), dim3(total), dim3(512), dl, s, a, tm, tn); \
+    else hipLaunchKernelGGL((gemm_x3_dl<E, false>), dim3(total), dim3(512), dl, s, a, tm, tn);     \
     break;
         X3_DL_CASE(X3_STORE)
         X3_DL_CASE(X3_SHIFT)

@@ -116,7 +116,7 @@ def test_pack_roundtrip(dev):
     assert np.array_equal(hi.T, h_ref) and np.array_equal(lo.T, l_ref)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("M,N,K", [(300, 270, 100), (256, 512, 64), (33, 600, 257)])
 def test_gemm_x3(dev, cfg, M, N, K):
     g = np.random.default_rng(M + N + K + cfg)
