@@ -556,7 +556,7 @@ hipError_t set_attrs() {
 
 }  // namespace
 
-int x3_default_cfg = 4;  // fastest measured at N = 8192 (direct-to-LDS ring)
+int x3_default_cfg = 5;  // fastest measured at N = 8192 (direct-to-LDS ring, fragments one stage ahead)
 
 hipError_t x3_init() {
   // Dynamic LDS above 64 KiB must be enabled per kernel before the first
