@@ -21,7 +21,9 @@ hipError_t cholesky_qr(double* S, int64_t lds, double* X, int64_t ldx, int64_t n
 // product K K^T is a split-BF16 GEMM on lower tiles.  S (lower valid) is
 // overwritten by L.  A last-step change larger than `tol` (no convergence)
 // records info = -2.  Scratch: pk (packed operand, n rows of stride ldp),
-// P and L1 (n x n FP64, leading dimension ldw), colmax (n doubles).
+// P and L1 (n x n FP64, leading dimension ldw), colmax (n doubles); split_ws
+// (nullable, split_bytes) is the K-split scratch of the products.
 hipError_t cholesky_near_identity(double* S, int64_t lds, int64_t n, bf16_t* pk, int64_t ldp, double* P, double* L1,
-                                  int64_t ldw, double* colmax, double tol, int x3_cfg, int* info, hipStream_t s);
+                                  int64_t ldw, double* colmax, double tol, int x3_cfg, float* split_ws,
+                                  size_t split_bytes, int* info, hipStream_t s);
 }  // namespace pfsm

@@ -265,11 +265,13 @@ hipError_t cholesky_qr(double* S, int64_t lds, double* X, int64_t ldx, int64_t n
 }
 
 hipError_t cholesky_near_identity(double* S, int64_t lds, int64_t n, bf16_t* pk, int64_t ldp, double* P, double* L1,
-                                  int64_t ldw, double* colmax, double tol, int x3_cfg, int* info, hipStream_t s) {
+                                  int64_t ldw, double* colmax, double tol, int x3_cfg, float* split_ws,
+                                  size_t split_bytes, int* info, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   X3Args g = {};
   g.M = n; g.N = n; g.K = n; g.Ap = pk; g.ldap = ldp; g.Bp = pk; g.ldbp = ldp; g.C = P; g.ldc = ldw;
   g.c_double = 1; g.alpha = 1.0; g.tiles = X3_LOWER; g.cfg = x3_cfg;
+  g.split_ws = split_ws; g.split_bytes = split_bytes;
   // step 1: K0 = Phi(S - I) packed by rows; L1 = I + Phi(S - I - K0 K0^T)
   CHK(pack_x3(S, 1, n, n, lds, PACK_BY_ROWS | PACK_LOWER | PACK_SUB_I | PACK_HALF_DIAG, pk, ldp, s));
   CHK(gemm_x3(X3_STORE, g, s));

@@ -9,6 +9,7 @@ struct G2SWork {
   double* dinv;    // [n] 1 / B_ii
   double* part;    // [ceil(n/128)][n] squared-residual partial sums
   double* anorm2;  // [n] squared column norms of A
+  double* blk;     // [256] block sums of part
 };
 size_t g2s_workspace_bytes(int64_t n);
 G2SWork g2s_carve(void* base, int64_t n);

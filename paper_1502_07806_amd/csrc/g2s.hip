@@ -37,25 +37,39 @@ __global__ __launch_bounds__(NT) void k_copy_cols(const double* X, int64_t ldx, 
     Y[i + j * ldy] = X[i + j * ldx];
 }
 
-// res[k] = sqrt(sum part / sum anorm2); a non-finite result records info = -1.
-__global__ __launch_bounds__(NT) void k_g2s_res(const double* part, int64_t count, const double* anorm2, int64_t n,
-                                                double* res, int* info) {
-  __shared__ double sa[NT], sb[NT];
-  double a = 0.0, b = 0.0;
-  for (int64_t i = threadIdx.x; i < count; i += NT) a += part[i];
-  for (int64_t i = threadIdx.x; i < n; i += NT) b += anorm2[i];
-  sa[threadIdx.x] = a;
-  sb[threadIdx.x] = b;
+constexpr int RB = 256;  // blocks of the first reduction stage
+
+__device__ inline double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
   __syncthreads();
   for (int w = NT / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      sa[threadIdx.x] += sa[threadIdx.x + w];
-      sb[threadIdx.x] += sb[threadIdx.x + w];
-    }
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
+  return sh[0];
+}
+
+// blk[b] = sum of part[i] over the i that block b strides over (fixed order).
+__global__ __launch_bounds__(NT) void k_g2s_res_part(const double* part, int64_t count, double* blk) {
+  __shared__ double sh[NT];
+  double a = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < count; i += (int64_t)RB * NT) a += part[i];
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) blk[blockIdx.x] = a;
+}
+
+// res[k] = sqrt(sum blk / sum anorm2); a non-finite result records info = -1.
+__global__ __launch_bounds__(NT) void k_g2s_res(const double* blk, const double* anorm2, int64_t n, double* res,
+                                                int* info) {
+  __shared__ double sh[NT];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < RB; i += NT) a += blk[i];
+  for (int64_t i = threadIdx.x; i < n; i += NT) b += anorm2[i];
+  a = block_sum(a, sh);
+  __syncthreads();
+  b = block_sum(b, sh);
   if (threadIdx.x == 0) {
-    const double r = sb[0] > 0.0 ? sqrt(sa[0] / sb[0]) : sqrt(sa[0]);
+    const double r = b > 0.0 ? sqrt(a / b) : sqrt(a);
     if (res) *res = r;
     if (!(r <= 1.7976931348623157e308)) atomicCAS(info, 0, -1);
   }
@@ -66,7 +80,8 @@ __global__ __launch_bounds__(NT) void k_g2s_res(const double* part, int64_t coun
 size_t g2s_workspace_bytes(int64_t n) {
   const int64_t tiles_m = (n + GEMM_BM - 1) / GEMM_BM;
   return al256((size_t)n * n * sizeof(double)) + al256((size_t)n * sizeof(double)) +
-         al256((size_t)tiles_m * n * sizeof(double)) + al256((size_t)n * sizeof(double));
+         al256((size_t)tiles_m * n * sizeof(double)) + al256((size_t)n * sizeof(double)) +
+         al256((size_t)RB * sizeof(double));
 }
 
 G2SWork g2s_carve(void* base, int64_t n) {
@@ -80,6 +95,8 @@ G2SWork g2s_carve(void* base, int64_t n) {
   w.part = (double*)p;
   p += al256((size_t)tiles_m * n * sizeof(double));
   w.anorm2 = (double*)p;
+  p += al256((size_t)n * sizeof(double));
+  w.blk = (double*)p;
   return w;
 }
 
@@ -104,8 +121,8 @@ hipError_t g2s_run(int64_t n, const double* A, int64_t lda, const double* B, int
     g.D = A; g.ldd = lda; g.eps = w.dinv; g.part = w.part;
     e = gemm_f64(true, false, EPI_G2S, g, s);  // B symmetric: B^T Z = B Z in the faster TN layout
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_g2s_res, dim3(1), dim3(NT), 0, s, w.part, tiles_m * n, w.anorm2, n, res ? res + k : nullptr,
-                       info);
+    hipLaunchKernelGGL(k_g2s_res_part, dim3(RB), dim3(NT), 0, s, w.part, tiles_m * n, w.blk);
+    hipLaunchKernelGGL(k_g2s_res, dim3(1), dim3(NT), 0, s, w.blk, w.anorm2, n, res ? res + k : nullptr, info);
     std::swap(cur, nxt);
     std::swap(ldc, ldn);
   }

@@ -46,6 +46,11 @@ struct X3Args {
   int tiles;                        // X3Tiles
   int kprefix_skip;                 // unused
   int cfg;                          // tile configuration (see gemm_x3.hip); -1 = library default
+  // Optional scratch (x3_split_bytes(M) bytes, device) for X3_LOWER STORE
+  // products: the tiles of a last, mostly empty wave of workgroups are split
+  // along K over the whole chip and summed by a second kernel.
+  float* split_ws; size_t split_bytes;
+  int split_full, split_s;          // set inside gemm_x3
 };
 
 constexpr int X3_NUM_CFG = 6;
@@ -53,6 +58,9 @@ extern int x3_default_cfg;
 hipError_t x3_init();  // once per process and device, before the first split-BF16 launch
 
 hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s);
+// Scratch bytes that let an order-n X3_LOWER product split its last wave (0:
+// no split at this order).  Valid after x3_init.
+size_t x3_split_bytes(int64_t n);
 
 // Packing.  Without PACK_BY_ROWS, row r of the packed operand is column r of X
 // (k runs down the column); with it, row r is row r of X (a transpose).  X is

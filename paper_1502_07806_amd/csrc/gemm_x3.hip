@@ -10,6 +10,8 @@
 #include "common.h"
 #include "gemm_x3.h"
 
+#include <algorithm>
+
 namespace pfsm {
 namespace {
 
@@ -54,15 +56,35 @@ __device__ inline v8bf as_bf(u32x4 v) { return __builtin_bit_cast(v8bf, v); }
 
 // Output tile of this block: XCD-grouped, lower / upper triangle enumeration
 // for the triangular modes, otherwise groups of 4 row tiles sharing column tiles.
+// KPREFIX and UPPER_TRI tiles differ in length (their K ranges follow the
+// triangle), so they are dealt longest first with consecutive blocks on
+// different XCDs, which balances the XCDs and fills the last wave with
+// short tiles.
 __device__ inline void x3_tile_coords(const X3Args& g, int tiles_m, int tiles_n, int& tm, int& tn) {
   int total;
   if (g.tiles == X3_LOWER || g.tiles == X3_UPPER_TRI) total = tiles_m * (tiles_m + 1) / 2;
   else total = tiles_m * tiles_n;
-  const int t = xcd_remap(blockIdx.x, total);
+  if (g.split_s > 0) total = g.split_full;  // whole tiles only (the split ones follow)
+  const int b = blockIdx.x;
+  if (g.tiles == X3_KPREFIX) {  // K range [0, n0 + BN): longest column tiles first
+    tn = tiles_n - 1 - b / tiles_m;
+    tm = b % tiles_m;
+    return;
+  }
+  if (g.tiles == X3_UPPER_TRI) {  // K range [m0, n0 + BN): by diagonal, longest first
+    // diagonal d = tn - tm holds tiles_m - d tiles; d = tiles_m - 1 comes first
+    int d = tiles_m - 1, r = b;
+    while (r >= tiles_m - d) {
+      r -= tiles_m - d;
+      --d;
+    }
+    tm = r;
+    tn = r + d;
+    return;
+  }
+  const int t = xcd_remap(b, total);
   if (g.tiles == X3_LOWER) {
     tri_index(t, tm, tn);
-  } else if (g.tiles == X3_UPPER_TRI) {
-    tri_index(t, tn, tm);
   } else {
     const int GROUP = 4;
     const int first_m = (t / (GROUP * tiles_n)) * GROUP;
@@ -327,8 +349,13 @@ __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int 
   constexpr int NW = 8, WGR = 4, WR = 2, WC = 4, CPW = 16 / NW;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   __shared__ double red[WGR][BN];
-  int tm, tn;
-  x3_tile_coords(g, tiles_m, tiles_n, tm, tn);
+  int tm, tn, unit = -1;  // unit: K-split piece of a tail tile, -1 for a whole tile
+  if (g.split_s > 0 && (int)blockIdx.x >= g.split_full) {
+    unit = (int)blockIdx.x - g.split_full;
+    tri_index(g.split_full + unit / g.split_s, tm, tn);
+  } else {
+    x3_tile_coords(g, tiles_m, tiles_n, tm, tn);
+  }
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -336,6 +363,12 @@ __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int 
   const int l32 = lane & 31, lh = lane >> 5;
   int64_t kbeg, kend;
   x3_k_range(g, tn, m0, n0, kbeg, kend);
+  if (unit >= 0) {  // piece unit % S of S equal runs of k16 stages
+    const int64_t st = kend > kbeg ? (kend - kbeg) / 16 : 0, sl = unit % g.split_s;
+    const int64_t b0 = kbeg + 16 * (st * sl / g.split_s), b1 = kbeg + 16 * (st * (sl + 1) / g.split_s);
+    kbeg = b0;
+    kend = b1;
+  }
   const int total = kend > kbeg ? (int)((kend - kbeg) / 16) : 0;
 
   // byte offsets of this lane's 16-byte chunk in each 1 KB row group it loads
@@ -450,7 +483,43 @@ __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int 
     }
   }
   __syncthreads();  // the RQ epilogue reuses shared memory; no wave may still be reading stages
+  if (unit >= 0) {
+    // partial sums of a K piece, tile-local column-major: ws[unit][j][i]
+    float* P = g.split_ws + (size_t)unit * BM * BN;
+#pragma unroll
+    for (int ib = 0; ib < WR; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < WC; ++jb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          P[(wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4)) * BM + wi0 + ib * 32 + l32] = acc[ib][jb][r];
+    return;
+  }
   x3_epilogue<EPI, WGR, WR, WC>(g, acc, m0, n0, wi0, wj0, tid, tm, red);
+}
+
+// Sum of the S K pieces of each split tail tile (fixed order) and the STORE
+// epilogue C = alpha * sum + beta * C.  Block (tile, column), thread = row.
+__global__ __launch_bounds__(256) void k_x3_split_sum(X3Args g) {
+  const int tile = blockIdx.x;
+  int tm, tn;
+  tri_index(g.split_full + tile, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int i = threadIdx.x;
+  const int64_t gi = m0 + i;
+  const int j = blockIdx.y;
+  const int64_t gj = n0 + j;
+  if (gi >= g.M || gj >= g.N) return;
+  {
+    const float* P = g.split_ws + ((size_t)tile * g.split_s * BN + j) * BM + i;
+    float sum = 0.f;
+    for (int u = 0; u < g.split_s; ++u) sum += P[(size_t)u * BM * BN];
+    double outv = g.alpha * (double)sum;
+    if (g.beta != 0.0)
+      outv += g.beta * (g.c_double ? ((const double*)g.C)[gi + gj * g.ldc] : (double)((const float*)g.C)[gi + gj * g.ldc]);
+    if (g.c_double) ((double*)g.C)[gi + gj * g.ldc] = outv;
+    else ((float*)g.C)[gi + gj * g.ldc] = (float)outv;
+  }
 }
 
 // ---------------------------------------------------------------- packing
@@ -516,6 +585,70 @@ __global__ __launch_bounds__(256) void k_pack(const void* X, int src_double, int
   }
 }
 
+// Packing without transpose (row r of the packed operand is column r of X, k
+// contiguous in memory): no staging is needed.  A thread turns 8 consecutive k
+// of one column into a 16-byte chunk of each plane; 16 threads cover 128 k of
+// a column (contiguous loads, 128-byte packed chunks).  VEC: X and ldx allow
+// 16-byte loads.
+template <bool DBL, bool VEC>
+__global__ __launch_bounds__(256) void k_pack_cols(const void* X, int64_t K, int64_t R, int64_t ldx, int flags,
+                                                   bf16_t* P, int64_t ldp) {
+  const int q = threadIdx.x & 15;
+  const int64_t r = (int64_t)blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int64_t k0 = (int64_t)blockIdx.x * 128 + 8 * q;
+  if (r >= R || k0 >= (K + 31) / 32 * 32) return;  // chunks past K are zero-filled
+  double v[8];
+  if (VEC && k0 + 8 <= K) {
+    if (DBL) {
+      const double2* src = (const double2*)((const double*)X + k0 + r * ldx);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 w = src[u];
+        v[2 * u] = w.x;
+        v[2 * u + 1] = w.y;
+      }
+    } else {
+      const float4* src = (const float4*)((const float*)X + k0 + r * ldx);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const float4 w = src[u];
+        v[4 * u] = w.x;
+        v[4 * u + 1] = w.y;
+        v[4 * u + 2] = w.z;
+        v[4 * u + 3] = w.w;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t k = k0 + u;
+      v[u] = k < K ? (DBL ? ((const double*)X)[k + r * ldx] : (double)((const float*)X)[k + r * ldx]) : 0.0;
+    }
+  }
+  if (flags & (PACK_LOWER | PACK_UPPER | PACK_SUB_I | PACK_HALF_DIAG)) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t k = k0 + u;  // X(row = k, col = r)
+      if (((flags & PACK_LOWER) && k < r) || ((flags & PACK_UPPER) && k > r)) v[u] = 0.0;
+      if (k == r && k < K) {
+        if (flags & PACK_SUB_I) v[u] -= 1.0;
+        if (flags & PACK_HALF_DIAG) v[u] *= 0.5;
+      }
+    }
+  }
+  u32x4 hw, lw;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const bf16_t h0 = f2bf((float)v[2 * u]), h1 = f2bf((float)v[2 * u + 1]);
+    const bf16_t l0 = f2bf((float)(v[2 * u] - (double)bf2f(h0))), l1 = f2bf((float)(v[2 * u + 1] - (double)bf2f(h1)));
+    hw[u] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+    lw[u] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+  }
+  bf16_t* dst = P + r * ldp + (k0 >> 5) * 64 + (k0 & 31);
+  *(u32x4*)dst = hw;
+  *(u32x4*)(dst + 32) = lw;
+}
+
 template <int CFG>
 hipError_t launch_cfg(int epi, const X3Args& a, int tm, int tn, hipStream_t s) {
   int total = (a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) ? tm * (tm + 1) / 2 : tm * tn;
@@ -557,8 +690,22 @@ hipError_t set_attrs() {
 }  // namespace
 
 int x3_default_cfg = 5;  // fastest measured at N = 8192 (direct-to-LDS ring, fragments one stage ahead)
+static int x3_num_cu = 0;  // compute units of the device (workgroups of one wave)
+
+size_t x3_split_bytes(int64_t n) {
+  const int64_t t = (n + BM - 1) / BM, tiles = t * (t + 1) / 2;
+  if (x3_num_cu <= 0 || tiles <= x3_num_cu) return 0;
+  return (size_t)x3_num_cu * BM * BN * sizeof(float);
+}
 
 hipError_t x3_init() {
+  {
+    int dev = 0, cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    x3_num_cu = cu;
+  }
   // Dynamic LDS above 64 KiB must be enabled per kernel before the first
   // launch; done once at plan creation so that solves stay capturable.
   hipError_t e = set_attrs<0>();
@@ -592,14 +739,32 @@ hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
     case 3: return launch_cfg<3>(epi, a, tm, tn, s);
     case 4:
     case 5: {
-      const int total = (a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) ? tm * (tm + 1) / 2 : tm * tn;
+      int total = (a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) ? tm * (tm + 1) / 2 : tm * tn;
       const size_t dl = DST * 2 * DTILE;
       const bool pipe = cfg == 5;
+      X3Args b = a;
+      b.split_full = 0;
+      b.split_s = 0;
+      if (epi == X3_STORE && a.tiles == X3_LOWER && a.split_ws && !a.krange && x3_num_cu > 0) {
+        // The tiles past the last whole wave of workgroups (rem of them, at
+        // most half a wave) are each cut into S pieces along K, so that the
+        // tail wave holds rem * S <= CUs short pieces instead of rem tiles.
+        const int cu = x3_num_cu, rem = total % cu;
+        const int64_t stages = (a.K + 31) / 32 * 2;
+        if (total > cu && rem > 0 && 2 * rem <= cu) {
+          const int S = (int)std::min<int64_t>(cu / rem, stages / 8);
+          if (S >= 2 && (size_t)rem * S * BM * BN * sizeof(float) <= a.split_bytes) {
+            b.split_full = total - rem;
+            b.split_s = S;
+            total = b.split_full + rem * S;
+          }
+        }
+      }
       switch (epi) {
 #define X3_DL_CASE(E)                                                                           \
   case E:                                                                                       \
-    if (pipe) hipLaunchKernelGGL((gemm_x3_dl<E, true>), dim3(total), dim3(512), dl, s, a, tm, tn); \
-    else hipLaunchKernelGGL((gemm_x3_dl<E, false>), dim3(total), dim3(512), dl, s, a, tm, tn);     \
+    if (pipe) hipLaunchKernelGGL((gemm_x3_dl<E, true>), dim3(total), dim3(512), dl, s, b, tm, tn); \
+    else hipLaunchKernelGGL((gemm_x3_dl<E, false>), dim3(total), dim3(512), dl, s, b, tm, tn);     \
     break;
         X3_DL_CASE(X3_STORE)
         X3_DL_CASE(X3_SHIFT)
@@ -608,6 +773,12 @@ hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
         X3_DL_CASE(X3_RQ)
 #undef X3_DL_CASE
         default: return hipErrorInvalidValue;
+      }
+      if (b.split_s > 0) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int rem = (total - b.split_full) / b.split_s;
+        hipLaunchKernelGGL(k_x3_split_sum, dim3(rem, BN), dim3(256), 0, s, b);
       }
       return hipGetLastError();
     }
@@ -620,6 +791,20 @@ hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t 
   const bool by_rows = flags & PACK_BY_ROWS;
   const int64_t R = by_rows ? m : n;
   const int64_t K = by_rows ? n : m;
+  if (R <= 0 || K <= 0) return hipSuccess;
+  if (!by_rows) {
+    const size_t es = src_double ? 8 : 4;
+    const bool vec = ((uintptr_t)X % 16 == 0) && ((size_t)ldx * es) % 16 == 0;
+    dim3 grid((unsigned)((K + 127) / 128), (unsigned)((R + 15) / 16));
+    if (src_double) {
+      if (vec) hipLaunchKernelGGL((k_pack_cols<true, true>), grid, dim3(256), 0, s, X, K, R, ldx, flags, P, ldp);
+      else hipLaunchKernelGGL((k_pack_cols<true, false>), grid, dim3(256), 0, s, X, K, R, ldx, flags, P, ldp);
+    } else {
+      if (vec) hipLaunchKernelGGL((k_pack_cols<false, true>), grid, dim3(256), 0, s, X, K, R, ldx, flags, P, ldp);
+      else hipLaunchKernelGGL((k_pack_cols<false, false>), grid, dim3(256), 0, s, X, K, R, ldx, flags, P, ldp);
+    }
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((K + 31) / 32), (unsigned)((R + 63) / 64));
   hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, s, X, src_double, m, n, ldx, flags, P, ldp);
   return hipGetLastError();

@@ -52,6 +52,7 @@ struct pfsm_plan {
   // mixed-precision workspace (byte offsets)
   size_t m_At32, m_X32, m_Y32, m_S64, m_Apk, m_Vpk, m_Atpk, m_Xpk, m_Ypk, m_Rpk, m_rb;
   size_t m_oz;  // digit planes of A and V_new for the refinement product, then 2n exponents
+  size_t m_split = 0, split_bytes = 0;  // K-split scratch of the lower-triangle split-BF16 products
 };
 
 namespace {
@@ -279,6 +280,8 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     pl->m_Ypk = w; w = align256(w + PK);
     pl->m_Rpk = w; w = align256(w + PK);
     pl->m_rb = w; w = align256(w + (size_t)(7 * n + 8) * sizeof(double));
+    pl->split_bytes = x3_split_bytes(n);
+    pl->m_split = w; w = align256(w + pl->split_bytes);
     // The refinement runs after the packed copies of A, V and At are dead:
     // its digit planes reuse that span when they fit (they do when n is a
     // multiple of 128), else they get their own region.
@@ -473,6 +476,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   double* scal = (double*)(W + pl->o_scal);
   double* part = (double*)(W + pl->o_part);
   double* rb = (double*)(W + pl->m_rb);
+  float* split_ws = pl->split_bytes ? (float*)(W + pl->m_split) : nullptr;
   StageClock clk(pl, s);
   PFSM_TRY(fill_i32(info, 1, 0, s));
   clk.mark(0);
@@ -494,6 +498,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     PFSM_TRY(pack_x3(Y32, 0, n, n, n, 0, Ypk, ldp, s));       // columns of W
     X3Args h = x3(X3_STORE, n, n, n, Vpk, Ypk, At32, n, 0);
     h.tiles = X3_LOWER;
+    h.split_ws = split_ws; h.split_bytes = pl->split_bytes;
     PFSM_TRY(gemm_x3(X3_STORE, h, s));
     PFSM_TRY(f32_mirror_to_f64(At32, At64, n, s));
     PFSM_TRY(pack_x3(At32, 0, n, n, n, 0, Atpk, ldp, s));
@@ -535,13 +540,15 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   {
     X3Args g = x3(X3_STORE, n, n, n, Xpk, Xpk, S64, n, 1);
     g.tiles = X3_LOWER;
+    g.split_ws = split_ws; g.split_bytes = pl->split_bytes;
     PFSM_TRY(gemm_x3(X3_STORE, g, s));
   }
   clk.mark(20);
   // S is the identity up to the folded-spectrum residual, so L = I + K comes
   // from the near-identity fixed point (two split-BF16 products K K^T) rather
   // than a latency-bound blocked factorisation.  B64a and Vn64 are free here.
-  PFSM_TRY(cholesky_near_identity(S64, n, n, Rpk, ldp, B64a, Vn64, n, rb, MIXED_CHOL_TOL, pl->x3_cfg, info, s));
+  PFSM_TRY(cholesky_near_identity(S64, n, n, Rpk, ldp, B64a, Vn64, n, rb, MIXED_CHOL_TOL, pl->x3_cfg, split_ws,
+                                  pl->split_bytes, info, s));
   // X <- X L^{-T} = X + X D, D = -U + U^2 (U = (L - I)^T, max |U| <= 1e-3 checked).
   PFSM_TRY(lower_minus_identity_check(S64, n, n, rb, info, s));
   {

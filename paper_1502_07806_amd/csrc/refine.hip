@@ -120,10 +120,10 @@ __global__ __launch_bounds__(NT) void k_cluster_rr(const double* V, int64_t ldv,
   const int c = blockIdx.x;
   if (c >= *count) return;
   __shared__ double G[KM][KM + 1], Mm[KM][KM + 1], Y[KM][KM + 1];
-  __shared__ double rows[NT / 8][KM];  // staging for the rotation, 32 rows at a time
   __shared__ int col[KM];
   __shared__ double cs_c[KM / 2], cs_s[KM / 2];
   __shared__ int pp[KM / 2], qq[KM / 2];
+  __shared__ int rk[KM];
   __shared__ int rot;
   const int tid = threadIdx.x;
   const int s_all = cstart[c], k_all = csize[c];
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(NT) void k_cluster_rr(const double* V, int64_t ldv,
       __syncthreads();
       continue;
     }
-    if (tid < k) col[tid] = inv[s + tid];
+    if (tid < KM) col[tid] = inv[s + min(tid, k - 1)];  // entries past k repeat a valid column
     __syncthreads();
     // G = V_c^T Z_c, Mm = V_c^T V_c: each wave takes (a, b) pairs
     const int lane = tid & 63, wave = tid >> 6;
@@ -150,11 +150,25 @@ __global__ __launch_bounds__(NT) void k_cluster_rr(const double* V, int64_t ldv,
       const double* za = Z + (int64_t)col[a] * ldz;
       const double* zb = Z + (int64_t)col[b] * ldz;
       double g1 = 0.0, g2 = 0.0, m = 0.0;
-      for (int64_t i = lane; i < n; i += 64) {
-        double x = va[i], y = vb[i];
-        g1 += x * zb[i];
-        g2 += y * za[i];
-        m += x * y;
+      constexpr int U = 8;  // rows per lane and pass: 4 U independent loads in flight
+      for (int64_t i0 = lane; i0 < n; i0 += 64 * U) {
+        double x[U], y[U], zx[U], zy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t i = min<int64_t>(i0 + 64 * u, n - 1);
+          x[u] = va[i];
+          y[u] = vb[i];
+          zx[u] = za[i];
+          zy[u] = zb[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (i0 + 64 * u < n) {
+            g1 += x[u] * zy[u];
+            g2 += y[u] * zx[u];
+            m += x[u] * y[u];
+          }
+        }
       }
       for (int off = 32; off > 0; off >>= 1) {
         g1 += __shfl_xor(g1, off, 64);
@@ -168,38 +182,47 @@ __global__ __launch_bounds__(NT) void k_cluster_rr(const double* V, int64_t ldv,
       }
     }
     __syncthreads();
-    // Cholesky Mm = R R^T (lower R, in Mm), then G <- R^{-1} G R^{-T}
-    if (tid == 0) {
-      for (int j = 0; j < k; ++j) {
-        double dj = Mm[j][j];
-        for (int t = 0; t < j; ++t) dj -= Mm[j][t] * Mm[j][t];
-        dj = sqrt(fmax(dj, 1e-300));
-        Mm[j][j] = dj;
-        for (int i = j + 1; i < k; ++i) {
-          double v = Mm[i][j];
-          for (int t = 0; t < j; ++t) v -= Mm[i][t] * Mm[j][t];
-          Mm[i][j] = v / dj;
-        }
+    // Cholesky Mm = R R^T (lower R, in Mm; right-looking, rows in parallel),
+    // then G <- R^{-1} G R^{-T} (independent triangular solves per column /
+    // row of G, one thread each).
+    for (int j = 0; j < k; ++j) {
+      if (tid == 0) Mm[j][j] = sqrt(fmax(Mm[j][j], 1e-300));
+      __syncthreads();
+      if (tid > j && tid < k) Mm[tid][j] /= Mm[j][j];
+      __syncthreads();
+      for (int idx = tid; idx < k * k; idx += NT) {
+        const int i = idx % k, l = idx / k;
+        if (l > j && i >= l) Mm[i][l] -= Mm[i][j] * Mm[l][j];
       }
-      // W = R^{-1} G (forward substitution per column), then C = W R^{-T}
-      for (int b = 0; b < k; ++b)
-        for (int i = 0; i < k; ++i) {
-          double v = G[i][b];
-          for (int t = 0; t < i; ++t) v -= Mm[i][t] * G[t][b];
-          G[i][b] = v / Mm[i][i];
-        }
-      for (int a = 0; a < k; ++a)
-        for (int i = 0; i < k; ++i) {
-          double v = G[a][i];
-          for (int t = 0; t < i; ++t) v -= G[a][t] * Mm[i][t];
-          G[a][i] = v / Mm[i][i];
-        }
-      for (int a = 0; a < k; ++a)
-        for (int b = a + 1; b < k; ++b) {
-          double v = 0.5 * (G[a][b] + G[b][a]);
-          G[a][b] = v; G[b][a] = v;
-        }
+      __syncthreads();
     }
+    if (tid < k) {  // W = R^{-1} G, column b = tid
+      const int b = tid;
+      for (int i = 0; i < k; ++i) {
+        double v = G[i][b];
+        for (int t = 0; t < i; ++t) v -= Mm[i][t] * G[t][b];
+        G[i][b] = v / Mm[i][i];
+      }
+    }
+    __syncthreads();
+    if (tid < k) {  // C = W R^{-T}, row a = tid
+      const int a = tid;
+      for (int i = 0; i < k; ++i) {
+        double v = G[a][i];
+        for (int t = 0; t < i; ++t) v -= G[a][t] * Mm[i][t];
+        G[a][i] = v / Mm[i][i];
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < k * k; idx += NT) {
+      const int a = idx % k, b = idx / k;
+      if (a < b) {
+        const double v = 0.5 * (G[a][b] + G[b][a]);
+        G[a][b] = v;
+        G[b][a] = v;
+      }
+    }
+    __syncthreads();
     for (int idx = tid; idx < KM * KM; idx += NT) Y[idx % KM][idx / KM] = (idx % KM == idx / KM) ? 1.0 : 0.0;
     __syncthreads();
     // cyclic Jacobi on the k x k matrix G (k <= 32): parallel order over a padded even size
@@ -262,55 +285,94 @@ __global__ __launch_bounds__(NT) void k_cluster_rr(const double* V, int64_t ldv,
       __syncthreads();
       if (!again) break;
     }
-    // Y <- R^{-T} Y (back substitution), eigenvalues sorted ascending by selection
-    if (tid == 0) {
-      for (int b = 0; b < k; ++b)
-        for (int i = k - 1; i >= 0; --i) {
-          double v = Y[i][b];
-          for (int t = i + 1; t < k; ++t) v -= Mm[t][i] * Y[t][b];
-          Y[i][b] = v / Mm[i][i];
-        }
-      // order Ritz values ascending (selection sort on the diagonal of G, permuting Y's columns)
-      for (int a = 0; a < k; ++a) {
-        int best = a;
-        for (int b = a + 1; b < k; ++b)
-          if (order_before(G[b][b], b, G[best][best], best)) best = b;
-        if (best != a) {
-          double t = G[a][a]; G[a][a] = G[best][best]; G[best][best] = t;
-          for (int i = 0; i < k; ++i) { double u = Y[i][a]; Y[i][a] = Y[i][best]; Y[i][best] = u; }
-        }
-        lam[s + a] = G[a][a];
+    // Y <- R^{-T} Y (back substitution, column b = tid)
+    if (tid < k) {
+      const int b = tid;
+      for (int i = k - 1; i >= 0; --i) {
+        double v = Y[i][b];
+        for (int t = i + 1; t < k; ++t) v -= Mm[t][i] * Y[t][b];
+        Y[i][b] = v / Mm[i][i];
       }
     }
     __syncthreads();
-    // Vout[:, s + t] = sum_a V[:, col[a]] Y[a][t], 32 rows per pass
-    const int rl = tid / 8, sub = tid % 8;
-    for (int64_t i0 = 0; i0 < n; i0 += NT / 8) {
-      const int64_t i = i0 + rl;
-      for (int a = sub; a < k; a += 8) rows[rl][a] = (i < n) ? V[i + (int64_t)col[a] * ldv] : 0.0;
-      __syncthreads();
-      if (i < n)
-        for (int t = sub; t < k; t += 8) {
-          double acc = 0.0;
-          for (int a = 0; a < k; ++a) acc += rows[rl][a] * Y[a][t];
-          Vout[i + (int64_t)(s + t) * ldvo] = acc;
-        }
-      __syncthreads();
+    // Ritz values ascending: the rank of each diagonal entry of G (distinct
+    // ranks under the total order), Y's columns placed at their ranks
+    if (tid < k) {
+      const double x = G[tid][tid];
+      int r = 0;
+      for (int b = 0; b < k; ++b) r += order_before(G[b][b], b, x, tid) ? 1 : 0;
+      rk[tid] = r;
     }
+    __syncthreads();
+    if (tid < k) lam[s + rk[tid]] = G[tid][tid];
+    for (int idx = tid; idx < k * k; idx += NT) {
+      const int i = idx % k, a = idx / k;
+      Mm[i][rk[a]] = Y[i][a];  // R is no longer needed
+    }
+    __syncthreads();
+    // Vout[:, s + t] = sum_a V[:, col[a]] Y[a][t]: one row per thread, the
+    // cluster's k entries of the row in registers
+    for (int64_t i = tid; i < n; i += NT) {
+      double v[KM];
+#pragma unroll
+      for (int a = 0; a < KM; ++a) v[a] = (a < k) ? V[i + (int64_t)col[a] * ldv] : 0.0;
+      for (int t = 0; t < k; ++t) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < KM; ++a)
+          if (a < k) acc += v[a] * Mm[a][t];
+        Vout[i + (int64_t)(s + t) * ldvo] = acc;
+      }
+    }
+    __syncthreads();
   }
 }
 
-__global__ void k_mirror_f32_to_f64(float* A32, double* A64, int64_t n) {
-  const int64_t j = blockIdx.y;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    float v = (i >= j) ? A32[i + j * n] : A32[j + i * n];
-    A64[i + j * n] = (double)v;
-  }
+// Symmetric completion from the lower triangle (i >= j) of A32: A64 = the
+// full symmetric matrix in FP64 and the upper triangle of A32 overwritten by
+// the mirrored lower one.  One block per 64 x 64 tile pair (I >= J), staged
+// through LDS so that both the direct and the mirrored accesses are
+// coalesced.
+constexpr int TT = 64;
+__device__ inline void tile_pair(int t, int& I, int& J) {  // t -> (I, J), I >= J, row-major lower triangle
+  int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  I = r;
+  J = t - r * (r + 1) / 2;
 }
-__global__ void k_fix_upper_f32(float* A32, int64_t n) {
-  const int64_t j = blockIdx.y;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < j; i += (int64_t)gridDim.x * blockDim.x)
-    A32[i + j * n] = A32[j + i * n];
+__global__ __launch_bounds__(256) void k_sym_from_lower(float* A32, double* A64, int64_t n) {
+  __shared__ float T[TT][TT + 1];
+  int I, J;
+  tile_pair(blockIdx.x, I, J);
+  const int64_t i0 = (int64_t)I * TT, j0 = (int64_t)J * TT;
+  const int a = threadIdx.x & 63, b0 = threadIdx.x >> 6;
+  // T[r][c] = A32(i0 + r, j0 + c) where that is in the lower triangle
+  for (int c = b0; c < TT; c += 4) {
+    const int64_t i = i0 + a, j = j0 + c;
+    T[a][c] = (i < n && j < n && i >= j) ? A32[i + j * n] : 0.f;
+  }
+  __syncthreads();
+  for (int c = b0; c < TT; c += 4) {
+    // tile (I, J): element (i0 + a, j0 + c)
+    {
+      const int64_t i = i0 + a, j = j0 + c;
+      if (i < n && j < n) {
+        const float v = (i >= j) ? T[a][c] : T[c][a];  // the latter only on the diagonal tile
+        A64[i + j * n] = (double)v;
+        if (I == J && i < j) A32[i + j * n] = v;
+      }
+    }
+    // mirrored tile (J, I): element (j0 + a, i0 + c) = A(i0 + c, j0 + a)
+    if (I != J) {
+      const int64_t i = j0 + a, j = i0 + c;
+      if (i < n && j < n) {
+        const float v = T[c][a];
+        A64[i + j * n] = (double)v;
+        A32[i + j * n] = v;
+      }
+    }
+  }
 }
 
 __global__ void k_f64_to_f32(const double* X, int64_t ldx, float* Y, int64_t ldy, int64_t m) {
@@ -390,12 +452,27 @@ __global__ __launch_bounds__(NT) void k_col_sign_f32(float* X, int64_t n, int64_
   if (threadIdx.x == 0 && sgn) sgn[j] = sg;
 }
 
-__global__ void k_series_d(const double* L, int64_t ldl, const float* U2, int64_t ldu, float* D, int64_t ldd,
-                           int64_t n) {
-  const int64_t j = blockIdx.y;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+// D = -U + U^2 on and above the diagonal, zero below (U = (L - I)^T, U2 the
+// product from the upper-tile GEMM, D may alias U2).  One block per 64 x 64
+// tile of D; L^T is read through an LDS transpose.
+__global__ __launch_bounds__(256) void k_series_d(const double* L, int64_t ldl, const float* U2, int64_t ldu, float* D,
+                                                  int64_t ldd, int64_t n) {
+  __shared__ double T[TT][TT + 1];
+  const int64_t i0 = (int64_t)blockIdx.x * TT, j0 = (int64_t)blockIdx.y * TT;
+  const int a = threadIdx.x & 63, b0 = threadIdx.x >> 6;
+  if (i0 <= j0 + TT - 1) {
+    // T[c][a'] = L(j0 + c, i0 + a') for the lower-triangle entries (j >= i)
+    for (int r = b0; r < TT; r += 4) {
+      const int64_t j = j0 + a, i = i0 + r;  // L(j, i): contiguous in j
+      T[a][r] = (i < n && j < n && j >= i) ? L[j + i * ldl] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int c = b0; c < TT; c += 4) {
+    const int64_t i = i0 + a, j = j0 + c;
+    if (i >= n || j >= n) continue;
     float v = 0.f;
-    if (i <= j) v = (float)(-(L[j + i * ldl] - (i == j ? 1.0 : 0.0)) + (double)U2[i + j * ldu]);
+    if (i <= j) v = (float)(-(T[c][a] - (i == j ? 1.0 : 0.0)) + (double)U2[i + j * ldu]);
     D[i + j * ldd] = v;
   }
 }
@@ -425,9 +502,9 @@ hipError_t refine_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz,
 }
 
 hipError_t f32_mirror_to_f64(float* At32, double* At64, int64_t n, hipStream_t s) {
-  dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 32), (unsigned)n);
-  hipLaunchKernelGGL(k_mirror_f32_to_f64, grid, dim3(256), 0, s, At32, At64, n);
-  hipLaunchKernelGGL(k_fix_upper_f32, grid, dim3(256), 0, s, At32, n);
+  if (n <= 0) return hipSuccess;
+  const int64_t t = (n + TT - 1) / TT;
+  hipLaunchKernelGGL(k_sym_from_lower, dim3((unsigned)(t * (t + 1) / 2)), dim3(256), 0, s, At32, At64, n);
   return hipGetLastError();
 }
 
@@ -451,8 +528,9 @@ hipError_t col_sign_f32(float* X, int64_t n, int64_t ldx, double* sgn, hipStream
 
 hipError_t series_d(const double* L, int64_t ldl, const float* U2, int64_t ldu, float* D, int64_t ldd, int64_t n,
                     hipStream_t s) {
-  dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 32), (unsigned)n);
-  hipLaunchKernelGGL(k_series_d, grid, dim3(256), 0, s, L, ldl, U2, ldu, D, ldd, n);
+  if (n <= 0) return hipSuccess;
+  const unsigned t = (unsigned)((n + TT - 1) / TT);
+  hipLaunchKernelGGL(k_series_d, dim3(t, t), dim3(256), 0, s, L, ldl, U2, ldu, D, ldd, n);
   return hipGetLastError();
 }
 

@@ -34,17 +34,32 @@ int pfsm_test_pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64
   return (int)pack_x3(X, src_double, m, n, ldx, flags, (bf16_t*)P, ldp, (hipStream_t)stream);
 }
 
-int pfsm_test_gemm_x3(int epi, int cfg, int tiles, int64_t M, int64_t N, int64_t K, const void* Ap, int64_t ldap,
-                      const void* Bp, int64_t ldbp, void* C, int64_t ldc, int c_double, double alpha, double beta,
-                      const float* B32, int64_t ldb32, const void* D, int64_t ldd, int d_double, const double* eps,
-                      double* part, void* stream) {
+int pfsm_test_gemm_x3_ws(int epi, int cfg, int tiles, int64_t M, int64_t N, int64_t K, const void* Ap, int64_t ldap,
+                         const void* Bp, int64_t ldbp, void* C, int64_t ldc, int c_double, double alpha, double beta,
+                         const float* B32, int64_t ldb32, const void* D, int64_t ldd, int d_double, const double* eps,
+                         double* part, void* split_ws, size_t split_bytes, void* stream) {
   X3Args g = {};
   g.M = M; g.N = N; g.K = K; g.Ap = (const bf16_t*)Ap; g.ldap = ldap; g.Bp = (const bf16_t*)Bp; g.ldbp = ldbp;
   g.C = C; g.ldc = ldc; g.c_double = c_double; g.alpha = alpha; g.beta = beta; g.B32 = B32; g.ldb32 = ldb32;
   g.D = D; g.ldd = ldd; g.d_double = d_double; g.eps = eps; g.part = part; g.tiles = tiles; g.cfg = cfg;
+  g.split_ws = (float*)split_ws; g.split_bytes = split_bytes;
   const hipError_t e = ensure_x3();
   if (e != hipSuccess) return (int)e;
   return (int)gemm_x3(epi, g, (hipStream_t)stream);
+}
+
+int pfsm_test_gemm_x3(int epi, int cfg, int tiles, int64_t M, int64_t N, int64_t K, const void* Ap, int64_t ldap,
+                      const void* Bp, int64_t ldbp, void* C, int64_t ldc, int c_double, double alpha, double beta,
+                      const float* B32, int64_t ldb32, const void* D, int64_t ldd, int d_double, const double* eps,
+                      double* part, void* stream) {
+  return pfsm_test_gemm_x3_ws(epi, cfg, tiles, M, N, K, Ap, ldap, Bp, ldbp, C, ldc, c_double, alpha, beta, B32, ldb32,
+                              D, ldd, d_double, eps, part, nullptr, 0, stream);
+}
+
+// K-split scratch bytes for an order-n lower-triangle product (0: no split).
+int64_t pfsm_test_x3_split_bytes(int64_t n) {
+  if (ensure_x3() != hipSuccess) return -1;
+  return (int64_t)x3_split_bytes(n);
 }
 
 int64_t pfsm_test_x3_row_stride(int64_t K) { return x3_row_stride(K); }
@@ -62,7 +77,7 @@ int pfsm_test_chol_near_identity(double* S, int64_t lds, int64_t n, void* pk, do
                                  double* colmax, double tol, int* info, void* stream) {
   const hipError_t e = ensure_x3();
   if (e != hipSuccess) return (int)e;
-  return (int)cholesky_near_identity(S, lds, n, (bf16_t*)pk, x3_row_stride(n), P, L1, ldw, colmax, tol, -1, info,
+  return (int)cholesky_near_identity(S, lds, n, (bf16_t*)pk, x3_row_stride(n), P, L1, ldw, colmax, tol, -1, nullptr, 0, info,
                                      (hipStream_t)stream);
 }
 

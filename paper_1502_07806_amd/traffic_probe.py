@@ -57,7 +57,7 @@ def summarize(fetch_csv: str, write_csv: str, n: int, out: str):
     res = {"_calibration": {"copy_bytes": 1 << 30, "fetch_scale": sf, "write_scale": sw,
                             "note": "FETCH_SIZE and WRITE_SIZE (KiB, summed over agents) per dispatch, each scaled "
                                     "by what the same counter reads for a 1 GiB device copy"}}
-    for key, name in (("gemm_x3_fsupd_n%d" % n, "gemm_x3_dl<2>"), ("gemm_f64_fsupd_n%d" % n, "gemm_f64_kernel"),
+    for key, name in (("gemm_x3_fsupd_n%d" % n, "gemm_x3_dl<2"), ("gemm_f64_fsupd_n%d" % n, "gemm_f64_kernel"),
                       ("gemm_oz_n%d" % n, "gemm_oz_fused")):
         f, w = pick(fe, name) * 1024 * sf, pick(wr, name) * 1024 * sw
         res[key] = {"kernel": name, "fetch_bytes": f, "write_bytes": w, "bytes_per_launch": f + w,

@@ -116,6 +116,55 @@ def test_pack_roundtrip(dev):
     assert np.array_equal(hi.T, h_ref) and np.array_equal(lo.T, l_ref)
 
 
+def _unpack(P, R, K, ldp):
+    raw = P.cpu().numpy().view(np.uint16).reshape(R, ldp).astype(np.uint32) << 16
+    vals = raw.view(np.float32).astype(np.float64)
+    nc = (K + 31) // 32
+    hi = np.concatenate([vals[:, 64 * c:64 * c + 32] for c in range(nc)], axis=1)
+    lo = np.concatenate([vals[:, 64 * c + 32:64 * c + 64] for c in range(nc)], axis=1)
+    return hi, lo
+
+
+@pytest.mark.parametrize("src_double", [0, 1])
+@pytest.mark.parametrize("by_rows", [False, True])
+@pytest.mark.parametrize("m,n,ld,flags", [(300, 300, 300, 2 | 4 | 16), (300, 300, 301, 2 | 8), (77, 130, 77, 0),
+                                          (257, 64, 259, 4)])
+def test_pack_flags_layouts(dev, src_double, by_rows, m, n, ld, flags):
+    """Both packing kernels (with and without transpose), FP32 and FP64
+    sources, aligned and unaligned leading dimensions, and the triangle /
+    identity / half-diagonal flags against the same transformation in numpy;
+    chunks past K hold zeros."""
+    L = lib()
+    g = np.random.default_rng(m + n + ld + flags)
+    x = g.standard_normal((m, n)) * np.exp(g.standard_normal((m, n)))
+    dt = torch.float64 if src_double else torch.float32
+    buf = torch.from_numpy(np.zeros((n, ld))).to(dt)
+    buf[:, :m] = torch.from_numpy(x.T).to(dt)
+    dx = buf.to(dev)  # column-major m x n with leading dimension ld
+    xs = buf[:, :m].numpy().T.astype(np.float64)  # the values as stored
+    ref = xs.copy()
+    rr, cc = np.indices((m, n))
+    if flags & 4:
+        ref[rr < cc] = 0.0
+    if flags & 8:
+        ref[rr > cc] = 0.0
+    d = np.arange(min(m, n))
+    if flags & 2:
+        ref[d, d] -= 1.0
+    if flags & 16:
+        ref[d, d] *= 0.5
+    R, K = (m, n) if by_rows else (n, m)
+    ldp = L.pfsm_test_x3_row_stride(K)
+    P = torch.full((R * ldp,), -1, dtype=torch.int16, device=dev)
+    assert L.pfsm_test_pack_x3(_p(dx), src_double, m, n, ld, (1 if by_rows else 0) | flags, _p(P), ldp,
+                               _stream()) == 0
+    hi, lo = _unpack(P, R, K, ldp)
+    want = ref if by_rows else ref.T  # packed row r, k along the row
+    h_ref, l_ref = split_hi_lo(want)
+    assert np.array_equal(hi[:, :K], h_ref) and np.array_equal(lo[:, :K], l_ref)
+    assert np.all(hi[:, K:] == 0) and np.all(lo[:, K:] == 0)
+
+
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("M,N,K", [(300, 270, 100), (256, 512, 64), (33, 600, 257)])
 def test_gemm_x3(dev, cfg, M, N, K):
@@ -134,6 +183,41 @@ def test_gemm_x3(dev, cfg, M, N, K):
     tol = 4 * K * 2.0 ** -24 * np.abs(A).max() * np.abs(B).max()
     assert np.max(np.abs(_np(C) - ref3)) <= tol
     assert np.max(np.abs(_np(C) - A @ B)) <= 2.0 ** -14 * np.sqrt(K) * np.abs(A).max() * np.abs(B).max() + tol
+
+
+@pytest.mark.parametrize("c_double,beta", [(1, 0.5), (0, 0.0)])
+def test_gemm_x3_lower_ksplit(dev, c_double, beta):
+    """Lower-triangle product whose last wave is split along K (23 x 23 tiles =
+    276 > 256 compute units): equal to the unsplit launch within FP32
+    accumulation, and the split tail tiles (the last tile row) equal to the
+    split-BF16 expansion; the upper tiles stay untouched."""
+    L = lib()
+    n = 5800
+    assert L.pfsm_test_x3_split_bytes(4096) == 0
+    nbytes = L.pfsm_test_x3_split_bytes(n)
+    assert nbytes > 0
+    ws = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    g = np.random.default_rng(77)
+    X = g.standard_normal((n, n))
+    Xp, ldx = _pack(X, False, dev)  # columns of X: C = X^T X
+    dt = torch.float64 if c_double else torch.float32
+    outs = []
+    for use_ws in (False, True):
+        C = torch.full((n, n), 1.0, dtype=dt, device=dev)  # symmetric fill: layout irrelevant
+        assert L.pfsm_test_gemm_x3_ws(0, 5, 1, n, n, n, _p(Xp), ldx, _p(Xp), ldx, _p(C), n, c_double, 1.0, beta, None,
+                                      0, None, 0, 0, None, None, _p(ws) if use_ws else None,
+                                      nbytes if use_ws else 0, _stream()) == 0
+        torch.cuda.synchronize()
+        outs.append(_np(C).T.astype(np.float64))  # column-major element (i, j) at [i, j]
+    ti = np.arange(n) // 256
+    lower = ti[:, None] >= ti[None, :]
+    tol = 4 * n * 2.0 ** -24 * np.abs(X).max() ** 2 + (0 if c_double else 2.0 ** -23 * n * 1.5)
+    assert np.all(outs[1][~lower] == 1.0)
+    assert np.max(np.abs(outs[1][lower] - outs[0][lower])) <= tol
+    xh, xl = split_hi_lo(X)
+    rows = np.arange(22 * 256, n)
+    ref = xh[:, rows].T @ xh + xh[:, rows].T @ xl + xl[:, rows].T @ xh + beta
+    assert np.max(np.abs(outs[1][rows] - ref)) <= tol
 
 
 # ------------------------------------------------------------ Cholesky (overlap factor)
