@@ -20,11 +20,13 @@ constexpr int TILE = BM * ROWB;      // 36864 bytes per operand per stage
 
 // Tile configurations (all 256 x 256 block tiles, 8 waves, two per SIMD):
 //   CFG 0: one launch for all weight groups, direct-to-LDS 4-stage ring,
-//          waves in 2 x 4 of 128 x 64 (gemm_oz_fused; the default)
+//          waves in 2 x 4 of 128 x 64 (gemm_oz_fused)
 //   CFG 1: CFG 0 with waves in 4 x 2 of 64 x 128
 //   CFG 2: one launch per weight group, direct-to-LDS ring (gemm_oz_dl), 4 x 2
 //   CFG 3: one launch per weight group, tiles staged through registers into
 //          double-buffered LDS (gemm_oz_kernel), 4 x 2
+//   CFG 4: CFG 0 with the fragments of the next k32 step read between the
+//          MFMAs of the current one (the default)
 // The per-group kernels keep the running sum in C (read-modify-write per
 // launch); the fused kernel pays that launch and epilogue cost once per tile.
 template <int CFG> struct OzCfg;
@@ -303,10 +305,11 @@ struct OzCursor {
   int g, p, kt;  // weight group, first digit index of the pair, k tile
 };
 
-template <int NT, int WGR, int WR, int WC>
+template <int NT, int WGR, int WR, int WC, bool PIPE>
 __global__ __launch_bounds__(NT, 1) void gemm_oz_fused(OzArgs a, int tiles_m, int tiles_n) {
   constexpr int NW = NT / 64;
   constexpr int CPW = 16 / NW;
+  constexpr int SUBS = DBK / 32;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   int tm, tn;
   {
@@ -372,26 +375,76 @@ __global__ __launch_bounds__(NT, 1) void gemm_oz_fused(OzArgs a, int tiles_m, in
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
   };
+  // Scaled group sum into C: stored by the first group, then added by
+  // no-return FP64 atomics, which need no registers or round trip for the
+  // old value (a read-modify-write would wait for every load, as C elements
+  // could alias as far as the compiler knows).  Each element is updated by
+  // one thread only, in program order, so the sums are the same as with
+  // plain loads and stores.
+  // The exponents of the tile's rows and columns sit in LDS: a global load
+  // there would wait for every atomic issued before it (one vmcnt counter).
+  __shared__ int s_ea[BM], s_eb[BN];
+  for (int i = tid; i < BM; i += NT) s_ea[i] = a.ea[min<int64_t>(m0 + i, a.M - 1)];
+  for (int j = tid; j < BN; j += NT) s_eb[j] = a.eb[min<int64_t>(n0 + j, a.N - 1)];
+  __syncthreads();
   auto flush = [&](int g, bool first) {
     const int shift = -12 - 7 * (g - 2);
+    // opaque copy of ldc: keeps the compiler from hoisting every output
+    // address out of the k loop into registers
+    int64_t ldc = a.ldc;
+    asm volatile("" : "+s"(ldc));
 #pragma unroll
     for (int ib = 0; ib < WR; ++ib) {
       const int64_t gi = m0 + wi0 + ib * 32 + l32;
       if (gi >= a.M) continue;
-      const int ei = a.ea[gi] + shift;
+      const int ei = s_ea[wi0 + ib * 32 + l32] + shift;
 #pragma unroll
       for (int jb = 0; jb < WC; ++jb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
+          const int jl = wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
+          const int64_t gj = n0 + jl;
           if (gj >= a.N) continue;
-          const double v = ldexp((double)acc[ib][jb][r], ei + a.eb[gj]);
-          double* cp = a.C + gi + gj * a.ldc;
-          *cp = first ? v : *cp + v;
+          const double v = ldexp((double)acc[ib][jb][r], ei + s_eb[jl]);
+          double* cp = a.C + gi + gj * ldc;
+          if (first) *cp = v;
+          else unsafeAtomicAdd(cp, v);
+          if (r % 8 == 7) __builtin_amdgcn_sched_barrier(0);  // bounds the registers the scheduler may hoist into
         }
     }
   };
   zero();
+
+  struct Frags {
+    v4i af[SUBS][WR], bf[SUBS][WC];
+  };
+  auto read_frags = [&](int t, Frags& f) {
+    const unsigned char* Ab = lds + (t % DST) * 2 * DTILE;
+    const unsigned char* Bb = Ab + DTILE;
+#pragma unroll
+    for (int sub = 0; sub < SUBS; ++sub) {
+      const int c = 2 * sub + lh;
+#pragma unroll
+      for (int ib = 0; ib < WR; ++ib) {
+        const int row = wi0 + ib * 32 + l32;
+        f.af[sub][ib] = *(const v4i*)(Ab + row * DBK + 16 * (c ^ dswz(row)));
+      }
+#pragma unroll
+      for (int jb = 0; jb < WC; ++jb) {
+        const int row = wj0 + jb * 32 + l32;
+        f.bf[sub][jb] = *(const v4i*)(Bb + row * DBK + 16 * (c ^ dswz(row)));
+      }
+    }
+  };
+  auto mma = [&](const Frags& f) {
+#pragma unroll
+    for (int sub = 0; sub < SUBS; ++sub)
+#pragma unroll
+      for (int ib = 0; ib < WR; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < WC; ++jb)
+          acc[ib][jb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.bf[sub][jb], f.af[sub][ib], acc[ib][jb], 0, 0, 0);
+  };
 
   OzCursor cc = {S + 1, plo(S + 1), 0};  // compute cursor
   OzCursor ic = cc;                       // issue cursor
@@ -399,43 +452,103 @@ __global__ __launch_bounds__(NT, 1) void gemm_oz_fused(OzArgs a, int tiles_m, in
     issue(ic, t);
     advance(ic);
   }
-  for (int t = 0; t < total; ++t) {
-    const int later = min(DST - 2, total - 1 - t);
-    if (later >= 2) wait_vm<2 * 2 * CPW>();
-    else if (later == 1) wait_vm<2 * CPW>();
-    else wait_vm<0>();
-    lds_barrier();  // as in gemm_oz_dl
-    if (t + DST - 1 < total) {
-      issue(ic, t + DST - 1);
-      advance(ic);
+  auto group_end = [&]() {  // after the MFMAs of the current k tile
+    const int g = cc.g;
+    advance(cc);
+    if (cc.g != g || cc.g < 2) {  // group g complete
+      flush(g, g == S + 1);
+      zero();
     }
-    const unsigned char* Ab = lds + (t % DST) * 2 * DTILE;
-    const unsigned char* Bb = Ab + DTILE;
-#pragma unroll
-    for (int sub = 0; sub < DBK / 32; ++sub) {
-      const int c = 2 * sub + lh;
+  };
+  if (!PIPE) {
+    for (int t = 0; t < total; ++t) {
+      const int later = min(DST - 2, total - 1 - t);
+      if (later >= 2) wait_vm<2 * 2 * CPW>();
+      else if (later == 1) wait_vm<2 * CPW>();
+      else wait_vm<0>();
+      lds_barrier();  // as in gemm_oz_dl
+      if (t + DST - 1 < total) {
+        issue(ic, t + DST - 1);
+        advance(ic);
+      }
+      Frags f;
+      read_frags(t, f);
+      mma(f);
+      group_end();
+    }
+  } else if (total > 0) {
+    // Fragments one k32 step ahead, read between the MFMAs of the current
+    // one (see the split-BF16 kernel).  Sub-step 0 of tile t prefetches
+    // sub-step 1 of the same tile; before sub-step 1 the barrier makes tile
+    // t + 1 visible, and its first fragments are read during sub-step 1.
+    // The slot refilled at that barrier, (t + 3) % 4, held tile t - 1, whose
+    // last fragments were read before it.  Flush atomics also count in
+    // vmcnt; issued after the loads being waited for, they only make the
+    // waits more conservative.
+    static_assert(SUBS == 2, "two k32 steps per k tile");
+    {
+      const int later0 = min(DST - 2, total - 1);
+      if (later0 >= 2) wait_vm<2 * 2 * CPW>();
+      else if (later0 == 1) wait_vm<2 * CPW>();
+      else wait_vm<0>();
+      lds_barrier();
+    }
+    struct Sub {
       v4i af[WR], bf[WC];
+    };
+    auto read_sub = [&](int t, int sub, Sub& f) {
+      const unsigned char* Ab = lds + (t % DST) * 2 * DTILE;
+      const unsigned char* Bb = Ab + DTILE;
+      const int c = 2 * sub + lh;
 #pragma unroll
       for (int ib = 0; ib < WR; ++ib) {
         const int row = wi0 + ib * 32 + l32;
-        af[ib] = *(const v4i*)(Ab + row * DBK + 16 * (c ^ dswz(row)));
+        f.af[ib] = *(const v4i*)(Ab + row * DBK + 16 * (c ^ dswz(row)));
       }
 #pragma unroll
       for (int jb = 0; jb < WC; ++jb) {
         const int row = wj0 + jb * 32 + l32;
-        bf[jb] = *(const v4i*)(Bb + row * DBK + 16 * (c ^ dswz(row)));
+        f.bf[jb] = *(const v4i*)(Bb + row * DBK + 16 * (c ^ dswz(row)));
       }
+    };
+    auto mma_sub = [&](const Sub& f) {
 #pragma unroll
       for (int ib = 0; ib < WR; ++ib)
 #pragma unroll
         for (int jb = 0; jb < WC; ++jb)
-          acc[ib][jb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[jb], af[ib], acc[ib][jb], 0, 0, 0);
-    }
-    const int g = cc.g;
-    advance(cc);
-    if (cc.g != g || t + 1 == total) {  // group g complete
-      flush(g, g == S + 1);
-      zero();
+          acc[ib][jb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.bf[jb], f.af[ib], acc[ib][jb], 0, 0, 0);
+    };
+    auto interleave = [&]() {
+#pragma unroll
+      for (int u = 0; u < WR + WC; ++u) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, WR * WC - (WR + WC), 0);
+    };
+    Sub F0, F1;
+    read_sub(0, 0, F0);
+    for (int t = 0; t < total; ++t) {
+      __builtin_amdgcn_sched_barrier(0);
+      read_sub(t, 1, F1);
+      mma_sub(F0);
+      interleave();
+      __builtin_amdgcn_sched_barrier(0);
+      if (t + 1 < total) {
+        if (t + 2 <= total - 1) wait_vm<2 * CPW>();
+        else wait_vm<0>();
+        lds_barrier();
+        if (t + DST - 1 < total) {
+          issue(ic, t + DST - 1);
+          advance(ic);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      read_sub(t + 1, 0, F0);  // past the last tile: a stale slot, never used
+      mma_sub(F1);
+      interleave();
+      __builtin_amdgcn_sched_barrier(0);
+      group_end();
     }
   }
 }
@@ -491,7 +604,7 @@ __global__ __launch_bounds__(256) void k_oz_split(const double* X, int64_t ldx, 
 
 }  // namespace
 
-int oz_default_cfg = 0;  // fastest measured at N = 8192
+int oz_default_cfg = 4;  // fastest measured at N = 8192
 
 hipError_t oz_init() {
   hipError_t e = hipFuncSetAttribute((const void*)gemm_oz_kernel<3>, hipFuncAttributeMaxDynamicSharedMemorySize, 4 * TILE);
@@ -499,11 +612,15 @@ hipError_t oz_init() {
     e = hipFuncSetAttribute((const void*)gemm_oz_dl<512, 4, 2, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             DST * 2 * DTILE);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)gemm_oz_fused<512, 2, 4, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void*)gemm_oz_fused<512, 2, 4, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             DST * 2 * DTILE);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)gemm_oz_fused<512, 4, 2, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void*)gemm_oz_fused<512, 4, 2, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             DST * 2 * DTILE);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)gemm_oz_fused<512, 2, 4, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            DST * 2 * DTILE);
+
   return e;
 }
 
@@ -520,7 +637,7 @@ hipError_t oz_split(const double* X, int64_t ldx, int64_t K, int64_t ncols, int 
 hipError_t gemm_oz(int64_t M, int64_t N, int64_t K, int s, const int8_t* Ap, const int* ea, const int8_t* Bp,
                    const int* eb, double* C, int64_t ldc, hipStream_t st, int cfg) {
   if (cfg < 0) cfg = oz_default_cfg;
-  if (cfg > 3) return hipErrorInvalidValue;
+  if (cfg > 4) return hipErrorInvalidValue;
   if (s < 1 || s > OZ_MAX_SLICES || K < 0 || (int64_t)s * K >= (1 << 19)) return hipErrorInvalidValue;
   if (M <= 0 || N <= 0) return hipSuccess;
   OzArgs a = {};
@@ -530,13 +647,18 @@ hipError_t gemm_oz(int64_t M, int64_t N, int64_t K, int s, const int8_t* Ap, con
   const int tm = (int)((M + BM - 1) / BM), tn = (int)((N + BN - 1) / BN);
   const dim3 grid((unsigned)(tm * tn));
   if (cfg == 0) {
-    hipLaunchKernelGGL((gemm_oz_fused<512, 2, 4, 2>), grid, dim3(512), DST * 2 * DTILE, st, a, tm, tn);
+    hipLaunchKernelGGL((gemm_oz_fused<512, 2, 4, 2, false>), grid, dim3(512), DST * 2 * DTILE, st, a, tm, tn);
     return hipGetLastError();
   }
   if (cfg == 1) {
-    hipLaunchKernelGGL((gemm_oz_fused<512, 4, 2, 4>), grid, dim3(512), DST * 2 * DTILE, st, a, tm, tn);
+    hipLaunchKernelGGL((gemm_oz_fused<512, 4, 2, 4, false>), grid, dim3(512), DST * 2 * DTILE, st, a, tm, tn);
     return hipGetLastError();
   }
+  if (cfg == 4) {
+    hipLaunchKernelGGL((gemm_oz_fused<512, 2, 4, 2, true>), grid, dim3(512), DST * 2 * DTILE, st, a, tm, tn);
+    return hipGetLastError();
+  }
+
   for (int g = s + 1; g >= 2; --g) {  // smallest weights first
     a.g = g;
     a.first = (g == s + 1);

@@ -427,14 +427,15 @@ __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int 
     }
   };
   auto mma = [&](const Frags& f) {
+    // product-major order: consecutive MFMAs update different accumulators
 #pragma unroll
-    for (int ib = 0; ib < WR; ++ib)
+    for (int pr = 0; pr < 3; ++pr)
 #pragma unroll
-      for (int jb = 0; jb < WC; ++jb) {
-        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bh[jb], f.ah[ib], acc[ib][jb], 0, 0, 0);
-        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bl[jb], f.ah[ib], acc[ib][jb], 0, 0, 0);
-        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bh[jb], f.al[ib], acc[ib][jb], 0, 0, 0);
-      }
+      for (int ib = 0; ib < WR; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < WC; ++jb)
+          acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pr == 1 ? f.bl[jb] : f.bh[jb],
+                                                                pr == 2 ? f.al[ib] : f.ah[ib], acc[ib][jb], 0, 0, 0);
   };
 
   for (int t = 0; t < DST - 1 && t < total; ++t) issue(t);
@@ -467,15 +468,29 @@ __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int 
     }
     Frags F0, F1;
     read_frags(0, F0);
+    // The fragment read is unconditional (past the last stage it reads a
+    // stale slot whose values are never used): with the same number of LDS
+    // reads on every path, the wait before the MFMAs covers only the
+    // previous step's reads instead of draining all of them.
     auto step = [&](int t, Frags& cur, Frags& nxt) {
       if (t + 1 < total) {
         if (t + 2 <= total - 1) wait_vm<2 * CPW>();  // stage t + 2 may still be in flight
         else wait_vm<0>();
         lds_barrier();
         if (t + DST - 1 < total) issue(t + DST - 1);
-        read_frags(t + 1, nxt);
       }
+      __builtin_amdgcn_sched_barrier(0);
+      read_frags(t + 1, nxt);
       mma(cur);
+      // interleave: two MFMAs of stage t, then one fragment read of stage
+      // t + 1, so the reads complete under this step's MFMAs and the wait at
+      // the next step finds them done
+#pragma unroll
+      for (int u = 0; u < 2 * (WR + WC); ++u) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 3 * WR * WC / (2 * (WR + WC)), 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     };
     for (int t = 0; t < total; t += 2) {
       step(t, F0, F1);

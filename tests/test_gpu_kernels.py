@@ -350,7 +350,7 @@ def test_oz_split_nonfinite(dev):
     assert np.all(planes[0, 0, :130] == 32) and np.all(planes[1:, 0, :] == 0)  # 1 = 32 * 2^(1 - 6)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("M,N,K,s", [(300, 270, 1000, 6), (256, 512, 128, 4), (33, 600, 257, 5)])
 def test_gemm_oz(dev, cfg, M, N, K, s):
     """C = A B from digits: equal (to FP64 rounding of the group sums) to the same
