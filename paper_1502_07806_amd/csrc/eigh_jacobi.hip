@@ -33,6 +33,13 @@ constexpr int LS = B2 + 1;       // LDS row stride
 constexpr double TOL = 1.1102230246251565e-16;  // 2^-53
 constexpr double TINY = 1e-300;
 constexpr double NOISE = 256.0 * TOL;
+// A pair-solver sweep whose rotations all had |sin| <= ANGLE ends the
+// iteration: Jacobi converges quadratically, so the inner products left after
+// such a sweep are of order ANGLE^2 relative (1e-16, below the 8u test), and
+// the sweep that would only confirm it is skipped.  The column norms of
+// W = S + sigma I differ by a factor of at most about 3, so small angles do
+// mean small relative inner products.
+constexpr double ANGLE = 1e-8;
 
 __device__ inline double noise_floor(const EighBatch& e) {
   return NOISE * fmax(fmax(fabs(e.scal[1]), fabs(e.scal[2])), TINY);
@@ -131,8 +138,10 @@ __device__ inline double rsq_d(double x) {
 // all columns are orthogonal.  Then W = W0 R = R diag(lambda + sigma) for
 // the accumulated rotation R, so the eigenvectors are the normalised final
 // columns of W and R is never accumulated.  Eight lanes own a column pair
-// (8 rows each) and reduce the 2x2 Gram entries with DPP, so a round needs
-// one barrier.  Padding indices (beyond the submatrix order) never rotate.
+// (8 rows each) and reduce its inner product with DPP, so a round needs one
+// barrier; the squared column norms are summed exactly in the first round of
+// each sweep and carried through the rotations in the others.  Padding
+// indices (beyond the submatrix order) never rotate.
 __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   const int npairs = e.nb / 2;
   const int p = blockIdx.x / npairs, k = blockIdx.x % npairs;
@@ -140,6 +149,7 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   if (e.state[2 * p]) { if (threadIdx.x == 0) *flagR = 0; return; }
   __shared__ double W[B2][LS];   // column-major: W[col][row]
   __shared__ double nrm[B2];
+  __shared__ double cn[B2];      // running squared column norms of W
   __shared__ int any_rot;
   __shared__ int sweep_rot;
   const int Mp = e.Mp;
@@ -184,41 +194,64 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
       const int a = rr_index(slot, r, B2), b = rr_index(B2 - 1 - slot, r, B2);
       const int pc = min(a, b), qc = max(a, b);
       double x[B2 / 8], y[B2 / 8];
-      double aa = 0.0, bb = 0.0, ab = 0.0;
+      double ab = 0.0, aa, bb;
+      if (r == 0) {
+        // exact squared column norms at the start of each sweep (every
+        // column is in exactly one pair of a round); later rounds use the
+        // running values in cn, updated with each rotation
+        double sa = 0.0, sb = 0.0;
 #pragma unroll
-      for (int m = 0; m < B2 / 8; ++m) {
-        const int row = sub + 8 * m;
-        x[m] = W[pc][row];
-        y[m] = W[qc][row];
-        aa += x[m] * x[m];
-        bb += y[m] * y[m];
-        ab += x[m] * y[m];
+        for (int m = 0; m < B2 / 8; ++m) {
+          const int row = sub + 8 * m;
+          x[m] = W[pc][row];
+          y[m] = W[qc][row];
+          sa += x[m] * x[m];
+          sb += y[m] * y[m];
+          ab += x[m] * y[m];
+        }
+        aa = sum8(sa);
+        bb = sum8(sb);
+      } else {
+#pragma unroll
+        for (int m = 0; m < B2 / 8; ++m) {
+          const int row = sub + 8 * m;
+          x[m] = W[pc][row];
+          y[m] = W[qc][row];
+          ab += x[m] * y[m];
+        }
+        aa = cn[pc];
+        bb = cn[qc];
       }
-      aa = sum8(aa);
-      bb = sum8(bb);
       ab = sum8(ab);
       const bool padpair = pair_idx(pc, I, J) >= msize || pair_idx(qc, I, J) >= msize;
-      // columns count as orthogonal below 8 u relative: the rounding noise of
-      // the dot products stays under it, so converged pairs stop rotating
-      if (!padpair && fabs(ab) > TINY && fabs(ab) > 8.0 * TOL * sqrt(aa * bb)) {
-        const double zeta = 0.5 * (bb - aa) * rcp_d(ab);
-        const double az = fabs(zeta);
-        double t;
-        if (az > 6.7e7) {
-          t = 0.5 * rcp_d(zeta);  // sqrt(1 + zeta^2) = |zeta| to working precision
-        } else {
-          const double q = 1.0 + zeta * zeta;
-          t = copysign(rcp_d(az + q * rsq_d(q)), zeta);
-        }
-        const double c = rsq_d(1.0 + t * t);
-        const double sn = t * c;
+      double na = aa, nb = bb;
+      // columns count as orthogonal below 8 u relative (|ab| <= 8u sqrt(aa bb),
+      // compared squared): the rounding noise of the dot products stays under
+      // it, so converged pairs stop rotating
+      if (!padpair && fabs(ab) > TINY && ab * ab > (64.0 * TOL * TOL) * (aa * bb)) {
+        // tan 2t = 2 ab / (bb - aa), |t| <= pi/4, from r = sqrt(d^2 + 4 ab^2):
+        // cos 2t = |d| / r, cos^2 t = (1 + cos 2t) / 2, sin t = sin 2t / (2 cos t)
+        const double d = bb - aa;
+        const double ir = rsq_d(fma(d, d, 4.0 * ab * ab));
+        const double h = fma(0.5 * fabs(d), ir, 0.5);
+        const double ic = rsq_d(h);
+        const double c = h * ic;
+        const double sn = (d >= 0.0 ? ab : -ab) * ir * ic;
 #pragma unroll
         for (int m = 0; m < B2 / 8; ++m) {
           const int row = sub + 8 * m;
           W[pc][row] = c * x[m] - sn * y[m];
           W[qc][row] = sn * x[m] + c * y[m];
         }
-        if (sub == 0) sweep_rot = 1;
+        const double cs2 = 2.0 * c * sn * ab;
+        na = c * c * aa - cs2 + sn * sn * bb;
+        nb = sn * sn * aa + cs2 + c * c * bb;
+        // only rotations by more than ANGLE keep the sweep going (see above)
+        if (sub == 0 && fabs(sn) > ANGLE) sweep_rot = 1;
+      }
+      if (sub == 0) {
+        cn[pc] = na;
+        cn[qc] = nb;
       }
       __syncthreads();
     }
