@@ -11,8 +11,6 @@
 // instead of N/64 times.
 #include "common.h"
 #include "chol.h"
-#include "gemm_x3.h"
-#include "refine.h"
 
 namespace pfsm {
 namespace {
@@ -146,57 +144,6 @@ __global__ __launch_bounds__(512) void potrf_diag(double* S, int64_t lds, int64_
   }
 }
 
-// One fixed-point step of the near-identity Cholesky, column j per block:
-// out = I + Phi(S - I - P) on the lower triangle (P = K K^T of the previous
-// iterate); with prev (the previous I + K), colmax[j] = max |out - prev|.
-// out may alias S (each element is read before it is written).
-__global__ __launch_bounds__(256) void k_chol_fp_step(const double* S, int64_t lds, const double* P, int64_t ldp,
-                                                      double* out, int64_t ldo, const double* prev, int64_t ldprev,
-                                                      double* colmax, int64_t n) {
-  __shared__ double sh[256];
-  const int64_t j = blockIdx.x;
-  double m = 0.0;
-  for (int64_t i = j + threadIdx.x; i < n; i += 256) {
-    const double e = S[i + j * lds] - (i == j ? 1.0 : 0.0) - P[i + j * ldp];
-    const double o = (i == j) ? 1.0 + 0.5 * e : e;
-    if (prev) {
-      const double d = fabs(o - prev[i + j * ldprev]);
-      m = (d > m || d != d) ? d : m;
-    }
-    out[i + j * ldo] = o;
-  }
-  if (!prev) return;
-  sh[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      const double o = sh[threadIdx.x + w];
-      sh[threadIdx.x] = (o > sh[threadIdx.x] || o != o) ? o : sh[threadIdx.x];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) colmax[j] = sh[0];
-}
-
-__global__ __launch_bounds__(256) void k_colmax_check(const double* colmax, int64_t n, double limit, int code,
-                                                      int* info) {
-  __shared__ double sh[256];
-  double m = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    const double v = colmax[i];
-    m = (v > m || v != v) ? v : m;
-  }
-  sh[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      const double o = sh[threadIdx.x + w];
-      sh[threadIdx.x] = (o > sh[threadIdx.x] || o != o) ? o : sh[threadIdx.x];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0 && !(sh[0] <= limit)) atomicCAS(info, 0, code);
-}
 
 hipError_t gemm_store(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, bool tb, const double* B,
                       int64_t ldb, double* C, int64_t ldc, double alpha, double beta, int lower, hipStream_t s) {
@@ -264,25 +211,5 @@ hipError_t cholesky_qr(double* S, int64_t lds, double* X, int64_t ldx, int64_t n
   return trsm_right_lt(S, lds, X, ldx, n, m, Tbuf, s);
 }
 
-hipError_t cholesky_near_identity(double* S, int64_t lds, int64_t n, bf16_t* pk, int64_t ldp, double* P, double* L1,
-                                  int64_t ldw, double* colmax, double tol, int x3_cfg, float* split_ws,
-                                  size_t split_bytes, int* info, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  X3Args g = {};
-  g.M = n; g.N = n; g.K = n; g.Ap = pk; g.ldap = ldp; g.Bp = pk; g.ldbp = ldp; g.C = P; g.ldc = ldw;
-  g.c_double = 1; g.alpha = 1.0; g.tiles = X3_LOWER; g.cfg = x3_cfg;
-  g.split_ws = split_ws; g.split_bytes = split_bytes;
-  // step 1: K0 = Phi(S - I) packed by rows; L1 = I + Phi(S - I - K0 K0^T)
-  CHK(pack_x3(S, 1, n, n, lds, PACK_BY_ROWS | PACK_LOWER | PACK_SUB_I | PACK_HALF_DIAG, pk, ldp, s));
-  CHK(gemm_x3(X3_STORE, g, s));
-  hipLaunchKernelGGL(k_chol_fp_step, dim3((unsigned)n), dim3(256), 0, s, S, lds, P, ldw, L1, ldw, nullptr, 0,
-                     nullptr, n);
-  // step 2: K1 = L1 - I; S <- I + Phi(S - I - K1 K1^T), change against L1 checked
-  CHK(pack_x3(L1, 1, n, n, ldw, PACK_BY_ROWS | PACK_LOWER | PACK_SUB_I, pk, ldp, s));
-  CHK(gemm_x3(X3_STORE, g, s));
-  hipLaunchKernelGGL(k_chol_fp_step, dim3((unsigned)n), dim3(256), 0, s, S, lds, P, ldw, S, lds, L1, ldw, colmax, n);
-  hipLaunchKernelGGL(k_colmax_check, dim3(1), dim3(256), 0, s, colmax, n, tol, PFSM_INFO_SERIES, info);
-  return hipGetLastError();
-}
 
 }  // namespace pfsm

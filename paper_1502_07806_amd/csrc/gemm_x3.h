@@ -25,11 +25,13 @@ enum X3Epi : int {
   X3_STORE = 0,  // C = alpha*acc + beta*C
   X3_SHIFT = 1,  // C = acc - B32(i,j) * eps[j]                (FP32 out)
   X3_FSUPD = 2,  // C = D32(i,j) - a*(acc - B32(i,j)*eps[j])    (FP32 out)
-  X3_ADD = 3,    // C = acc + D(i,j)   (D float or double)
+  X3_ADD = 3,    // C = alpha*acc + D(i,j)   (D float or double)
   X3_RQ = 4,     // part[tile_m][j] = sum_i acc(i,j) * D32(i,j)
 };
 
-enum X3Tiles : int { X3_FULL = 0, X3_LOWER = 1, X3_UPPER_TRI = 2, X3_KPREFIX = 3 };
+// LOWER: only tiles with tile row >= tile column (square C); KPREFIX: the k
+// range of column tile j ends at its last column (op(B) upper triangular).
+enum X3Tiles : int { X3_FULL = 0, X3_LOWER = 1, X3_KPREFIX = 3 };
 
 struct X3Args {
   int64_t M, N, K;

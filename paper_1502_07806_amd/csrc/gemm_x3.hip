@@ -56,30 +56,18 @@ __device__ inline v8bf as_bf(u32x4 v) { return __builtin_bit_cast(v8bf, v); }
 
 // Output tile of this block: XCD-grouped, lower / upper triangle enumeration
 // for the triangular modes, otherwise groups of 4 row tiles sharing column tiles.
-// KPREFIX and UPPER_TRI tiles differ in length (their K ranges follow the
-// triangle), so they are dealt longest first with consecutive blocks on
-// different XCDs, which balances the XCDs and fills the last wave with
-// short tiles.
+// KPREFIX tiles differ in length (their K ranges follow the triangle), so
+// they are dealt longest first with consecutive blocks on different XCDs,
+// which balances the XCDs and fills the last wave with short tiles.
 __device__ inline void x3_tile_coords(const X3Args& g, int tiles_m, int tiles_n, int& tm, int& tn) {
   int total;
-  if (g.tiles == X3_LOWER || g.tiles == X3_UPPER_TRI) total = tiles_m * (tiles_m + 1) / 2;
+  if (g.tiles == X3_LOWER) total = tiles_m * (tiles_m + 1) / 2;
   else total = tiles_m * tiles_n;
   if (g.split_s > 0) total = g.split_full;  // whole tiles only (the split ones follow)
   const int b = blockIdx.x;
   if (g.tiles == X3_KPREFIX) {  // K range [0, n0 + BN): longest column tiles first
     tn = tiles_n - 1 - b / tiles_m;
     tm = b % tiles_m;
-    return;
-  }
-  if (g.tiles == X3_UPPER_TRI) {  // K range [m0, n0 + BN): by diagonal, longest first
-    // diagonal d = tn - tm holds tiles_m - d tiles; d = tiles_m - 1 comes first
-    int d = tiles_m - 1, r = b;
-    while (r >= tiles_m - d) {
-      r -= tiles_m - d;
-      --d;
-    }
-    tm = r;
-    tn = r + d;
     return;
   }
   const int t = xcd_remap(b, total);
@@ -95,8 +83,7 @@ __device__ inline void x3_tile_coords(const X3Args& g, int tiles_m, int tiles_n,
 }
 
 // k range of a tile (multiples of 32): the optional per-column-tile range,
-// clipped by the triangular structure of the operands in the UPPER_TRI and
-// KPREFIX modes.
+// clipped in the KPREFIX mode (op(B) upper triangular).
 __device__ inline void x3_k_range(const X3Args& g, int tn, int64_t m0, int64_t n0, int64_t& kbeg, int64_t& kend) {
   kbeg = 0;
   kend = (g.K + 31) / 32 * 32;
@@ -104,12 +91,7 @@ __device__ inline void x3_k_range(const X3Args& g, int tn, int64_t m0, int64_t n
     kbeg = g.krange[2 * tn];
     kend = g.krange[2 * tn + 1];
   }
-  if (g.tiles == X3_UPPER_TRI) {
-    kbeg = max<int64_t>(kbeg, m0);
-    kend = min<int64_t>(kend, n0 + BN);
-  } else if (g.tiles == X3_KPREFIX) {
-    kend = min<int64_t>(kend, n0 + BN);
-  }
+  if (g.tiles == X3_KPREFIX) kend = min<int64_t>(kend, n0 + BN);
 }
 
 // Epilogue shared by the split-BF16 kernels: acc[ib][jb][r] is C(i, j) with
@@ -200,7 +182,7 @@ __device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t
           if (EPI == X3_STORE) outv = g.alpha * v + g.beta * in1[u];
           else if (EPI == X3_SHIFT) outv = v - in1[u] * ev[u];
           else if (EPI == X3_FSUPD) outv = in2[u] - a_eff * (v - in1[u] * ev[u]);
-          else outv = v + in1[u];
+          else outv = g.alpha * v + in1[u];
           if (g.c_double) ((double*)g.C)[gi + gj * g.ldc] = outv;
           else ((float*)g.C)[gi + gj * g.ldc] = (float)outv;
         }
@@ -666,7 +648,7 @@ __global__ __launch_bounds__(256) void k_pack_cols(const void* X, int64_t K, int
 
 template <int CFG>
 hipError_t launch_cfg(int epi, const X3Args& a, int tm, int tn, hipStream_t s) {
-  int total = (a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) ? tm * (tm + 1) / 2 : tm * tn;
+  int total = a.tiles == X3_LOWER ? tm * (tm + 1) / 2 : tm * tn;
   const size_t lds = 4 * (size_t)TILE_BYTES;
   dim3 grid(total), block(X3Cfg<CFG>::NT);
   switch (epi) {
@@ -745,7 +727,7 @@ hipError_t x3_init() {
 hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
   const int tm = (int)((a.M + BM - 1) / BM), tn = (int)((a.N + BN - 1) / BN);
   if (tm == 0 || tn == 0) return hipSuccess;
-  if ((a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) && tm != tn) return hipErrorInvalidValue;
+  if (a.tiles == X3_LOWER && tm != tn) return hipErrorInvalidValue;
   const int cfg = a.cfg >= 0 ? a.cfg : x3_default_cfg;
   switch (cfg) {
     case 0: return launch_cfg<0>(epi, a, tm, tn, s);
@@ -754,7 +736,7 @@ hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
     case 3: return launch_cfg<3>(epi, a, tm, tn, s);
     case 4:
     case 5: {
-      int total = (a.tiles == X3_LOWER || a.tiles == X3_UPPER_TRI) ? tm * (tm + 1) / 2 : tm * tn;
+      int total = a.tiles == X3_LOWER ? tm * (tm + 1) / 2 : tm * tn;
       const size_t dl = DST * 2 * DTILE;
       const bool pipe = cfg == 5;
       X3Args b = a;

@@ -452,31 +452,6 @@ __global__ __launch_bounds__(NT) void k_col_sign_f32(float* X, int64_t n, int64_
   if (threadIdx.x == 0 && sgn) sgn[j] = sg;
 }
 
-// D = -U + U^2 on and above the diagonal, zero below (U = (L - I)^T, U2 the
-// product from the upper-tile GEMM, D may alias U2).  One block per 64 x 64
-// tile of D; L^T is read through an LDS transpose.
-__global__ __launch_bounds__(256) void k_series_d(const double* L, int64_t ldl, const float* U2, int64_t ldu, float* D,
-                                                  int64_t ldd, int64_t n) {
-  __shared__ double T[TT][TT + 1];
-  const int64_t i0 = (int64_t)blockIdx.x * TT, j0 = (int64_t)blockIdx.y * TT;
-  const int a = threadIdx.x & 63, b0 = threadIdx.x >> 6;
-  if (i0 <= j0 + TT - 1) {
-    // T[c][a'] = L(j0 + c, i0 + a') for the lower-triangle entries (j >= i)
-    for (int r = b0; r < TT; r += 4) {
-      const int64_t j = j0 + a, i = i0 + r;  // L(j, i): contiguous in j
-      T[a][r] = (i < n && j < n && j >= i) ? L[j + i * ldl] : 0.0;
-    }
-  }
-  __syncthreads();
-  for (int c = b0; c < TT; c += 4) {
-    const int64_t i = i0 + a, j = j0 + c;
-    if (i >= n || j >= n) continue;
-    float v = 0.f;
-    if (i <= j) v = (float)(-(T[c][a] - (i == j ? 1.0 : 0.0)) + (double)U2[i + j * ldu]);
-    D[i + j * ldd] = v;
-  }
-}
-
 __global__ void k_permute_f64(const double* X, int64_t ldx, const int* rank, double* Y, int64_t ldy, int64_t m) {
   const int64_t j = blockIdx.y;
   double* dst = Y + (int64_t)rank[j] * ldy;
@@ -523,14 +498,6 @@ hipError_t lower_minus_identity_check(const double* L, int64_t ldl, int64_t n, d
 
 hipError_t col_sign_f32(float* X, int64_t n, int64_t ldx, double* sgn, hipStream_t s) {
   hipLaunchKernelGGL(k_col_sign_f32, dim3((unsigned)n), dim3(NT), 0, s, X, n, ldx, sgn);
-  return hipGetLastError();
-}
-
-hipError_t series_d(const double* L, int64_t ldl, const float* U2, int64_t ldu, float* D, int64_t ldd, int64_t n,
-                    hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const unsigned t = (unsigned)((n + TT - 1) / TT);
-  hipLaunchKernelGGL(k_series_d, dim3(t, t), dim3(256), 0, s, L, ldl, U2, ldu, D, ldd, n);
   return hipGetLastError();
 }
 

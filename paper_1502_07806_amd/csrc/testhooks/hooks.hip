@@ -73,13 +73,6 @@ int pfsm_test_trsm(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t
   return (int)trsm_right_lt(L, ldl, X, ldx, n, m, Tbuf, (hipStream_t)stream);
 }
 
-int pfsm_test_chol_near_identity(double* S, int64_t lds, int64_t n, void* pk, double* P, double* L1, int64_t ldw,
-                                 double* colmax, double tol, int* info, void* stream) {
-  const hipError_t e = ensure_x3();
-  if (e != hipSuccess) return (int)e;
-  return (int)cholesky_near_identity(S, lds, n, (bf16_t*)pk, x3_row_stride(n), P, L1, ldw, colmax, tol, -1, nullptr, 0, info,
-                                     (hipStream_t)stream);
-}
 
 int pfsm_test_oz_split(const double* X, int64_t ldx, int64_t K, int64_t ncols, int s, void* P, int* expo, int* info,
                        void* stream) {

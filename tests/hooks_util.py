@@ -35,8 +35,6 @@ def lib():
         L.pfsm_test_cholesky.restype = i32
         L.pfsm_test_trsm.argtypes = [vp, i64, vp, i64, i64, i64, vp, vp]
         L.pfsm_test_trsm.restype = i32
-        L.pfsm_test_chol_near_identity.argtypes = [vp, i64, i64, vp, vp, vp, i64, vp, dbl, vp, vp]
-        L.pfsm_test_chol_near_identity.restype = i32
         L.pfsm_test_oz_split.argtypes = [vp, i64, i64, i64, i32, vp, vp, vp, vp]
         L.pfsm_test_oz_split.restype = i32
         L.pfsm_test_gemm_oz.argtypes = [i64, i64, i64, i32, vp, vp, vp, vp, vp, i64, i32, vp]

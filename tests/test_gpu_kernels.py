@@ -267,45 +267,36 @@ def test_cholesky_breakdown_column(dev, n, k):
     assert int(info.item()) == cholesky_lower(S0)[1] == k + 1
 
 
-def _near_identity_run(S0, dev, tol=1e-7):
-    n = S0.shape[0]
-    S = _cm(S0, dev)
-    ldp = int(lib().pfsm_test_x3_row_stride(n))
-    pk = torch.empty(n * ldp, dtype=torch.int16, device=dev)
-    P = torch.empty((n, n), dtype=torch.float64, device=dev)
-    L1 = torch.empty((n, n), dtype=torch.float64, device=dev)
-    colmax = torch.empty(n, dtype=torch.float64, device=dev)
-    info = torch.zeros(1, dtype=torch.int32, device=dev)
-    assert lib().pfsm_test_chol_near_identity(_p(S), n, n, _p(pk), _p(P), _p(L1), n, _p(colmax), tol, _p(info),
-                                              _stream()) == 0
-    torch.cuda.synchronize()
-    return np.tril(_np(S)), int(info.item())
-
-
-@pytest.mark.parametrize("n,eps", [(300, 1e-4), (1000, 3e-5), (1000, 4e-4)])
-def test_cholesky_near_identity_vs_oracle(dev, n, eps):
-    """Fixed-point factor of S = X^T X with X = I + eps G (the overlap after the
-    folded-spectrum iterations is of this kind) against the oracle's Cholesky."""
-    from oracle.pfsm_ref import cholesky_lower
+@pytest.mark.parametrize("n,eps", [(600, 1e-4), (300, 1e-3)])
+def test_first_order_orthonormalisation(dev, n, eps):
+    """The mixed path's X <- X L^{-T} for S = X^T X near the identity: the rows
+    of Phi(S - I) packed straight from S (identity removed, lower triangle,
+    half diagonal), then X - X Phi(S - I)^T with the ADD epilogue (alpha = -1)
+    on KPREFIX tiles.  Equal to that expression in FP64 up to the split-BF16
+    rounding of the product, and orthonormal up to O(eps^2)."""
+    L = lib()
     g = np.random.default_rng(n)
-    X = np.eye(n) + eps * g.standard_normal((n, n)) / np.sqrt(n) * 10
-    S0 = X.T @ X
-    L_ref, info_ref = cholesky_lower(S0)
-    L, info = _near_identity_run(S0, dev)
-    assert info == info_ref == 0
-    K = np.abs(L_ref - np.eye(n)).max()
-    # fixed-point truncation after two steps (3e-10 at the largest case here, from
-    # an FP64 emulation) plus split-BF16 rounding of K K^T (relative 2^-16)
-    assert np.max(np.abs(L - L_ref)) <= 2e-9 + 2.0 ** -12 * np.sqrt(n) * K * K
-
-
-def test_cholesky_near_identity_flags_far_input(dev):
-    """An overlap matrix far from the identity does not converge in two steps: info -2."""
-    n = 300
-    g = np.random.default_rng(5)
-    X = np.eye(n) + 0.3 * g.standard_normal((n, n)) / np.sqrt(n)
-    L, info = _near_identity_run(X.T @ X, dev)
-    assert info == -2
+    X = np.eye(n) + eps * g.standard_normal((n, n)) / np.sqrt(n) * 3
+    S = X.T @ X
+    E = S - np.eye(n)
+    Phi = np.tril(E, -1) + 0.5 * np.diag(np.diag(E))
+    Xp, ldx = _pack(X, True, dev)                   # rows of X
+    Sp, lds = _pack(S, True, dev, 2 | 4 | 16)       # rows of Phi(S - I) = columns of Phi^T
+    dX = _cm(X, dev)
+    C = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+    assert L.pfsm_test_gemm_x3(3, 5, 3, n, n, n, _p(Xp), ldx, _p(Sp), lds, _p(C), n, 1, -1.0, 0.0, None, 0, _p(dX),
+                               n, 1, None, None, _stream()) == 0
+    torch.cuda.synchronize()
+    out = _np(C)
+    ref = X - X @ Phi.T
+    prod = np.abs(X) @ np.abs(Phi).T
+    assert np.max(np.abs(out - ref)) <= 2.0 ** -14 * prod.max() + 1e-15
+    # the first-order correction leaves an O(eps^2) overlap error, and the
+    # rounding of the product adds little to it
+    e1 = np.abs(E).max()
+    r_ref = np.abs(ref.T @ ref - np.eye(n)).max()
+    assert r_ref <= 0.05 * e1
+    assert np.abs(out.T @ out - np.eye(n)).max() <= r_ref + 2.0 ** -10 * e1
 
 
 # ------------------------------------------------------------ int8 digit GEMM (FP64-accurate products)
