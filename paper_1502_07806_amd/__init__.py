@@ -5,3 +5,4 @@ the C ABI declared in include/pfsm.h; this package is its Python binding.
 """
 from .binding import (BatchedPlan, Plan, PFSMFunction, load_library, solve, generalized_to_standard,  # noqa: F401
                       LIB_PATH)
+from .scf import FullDiag, SCFDriver, StepRecord  # noqa: F401,E402
