@@ -275,8 +275,8 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   }
   __syncthreads();
   double* Rg = e.Rw + ((int64_t)p * npairs + k) * B2 * B2;
-  for (int idx = tid; idx < B2 * B2; idx += NT) {
-    int r = idx % B2, c = idx / B2;
+  for (int idx = tid; idx < B2 * B2; idx += NT) {  // row-major: Rg[r * 2b + c] = R(r, c)
+    int r = idx / B2, c = idx % B2;
     Rg[idx] = W[c][r] * nrm[c];
   }
   if (tid == 0) {
@@ -286,34 +286,64 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   }
 }
 
-// 64x64x64 product in LDS with FP64 MFMA: Z = op(X) * Y, op(X) = X or X^T.
-// Wave w owns rows [32*(w&1), +32) and columns [32*(w>>1), +32).
-template <bool TX>
-__device__ inline void mm64(const double (*X)[LS], const double (*Y)[LS], v4d acc[2][2]) {
+// 64x64x64 products with FP64 MFMA.  Wave w owns rows [32*(w&1), +32) and
+// columns [32*(w>>1), +32) of Z.  The rotation operand R (row-major in global
+// memory, L2-resident) is read straight into registers, all 16 k-steps' worth
+// before the loop; only the tile operand sits in LDS, so a workgroup needs one
+// LDS tile.
+// Z = R^T Y: fragment (i, k) of R^T is R(k, i), contiguous over i.
+__device__ inline void mm64_rt_y(const double* __restrict__ R, const double (*Y)[LS], v4d acc[2][2]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
   const int i0 = (wave & 1) * 32, j0 = (wave >> 1) * 32;
+  double af[B2 / 4][2];
+#pragma unroll
+  for (int kk = 0; kk < B2 / 4; ++kk)
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib) af[kk][ib] = R[(4 * kk + lq) * B2 + i0 + ib * 16 + l16];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int k = 0; k < B2; k += 4) {
-    double af[2], bf[2];
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib) {
-      int i = i0 + ib * 16 + l16;
-      af[ib] = TX ? X[k + lq][i] : X[i][k + lq];
-    }
+  for (int kk = 0; kk < B2 / 4; ++kk) {
+    double bf[2];
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb) bf[jb] = Y[k + lq][j0 + jb * 16 + l16];
+    for (int jb = 0; jb < 2; ++jb) bf[jb] = Y[4 * kk + lq][j0 + jb * 16 + l16];
 #pragma unroll
     for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb)
-        acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[jb], af[ib], acc[ib][jb], 0, 0, 0);
+        acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[jb], af[kk][ib], acc[ib][jb], 0, 0, 0);
   }
 }
+// Z = X R: fragment (k, j) of R is contiguous over j.
+__device__ inline void mm64_x_r(const double (*X)[LS], const double* __restrict__ R, v4d acc[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int i0 = (wave & 1) * 32, j0 = (wave >> 1) * 32;
+  double bf[B2 / 4][2];
+#pragma unroll
+  for (int kk = 0; kk < B2 / 4; ++kk)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) bf[kk][jb] = R[(4 * kk + lq) * B2 + j0 + jb * 16 + l16];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < B2 / 4; ++kk) {
+    double af[2];
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib) af[ib] = X[i0 + ib * 16 + l16][4 * kk + lq];
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+        acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[kk][jb], af[ib], acc[ib][jb], 0, 0, 0);
+  }
+}
+
 __device__ inline void store_acc(double (*Z)[LS], v4d acc[2][2]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
@@ -329,9 +359,9 @@ __device__ inline void store_acc(double (*Z)[LS], v4d acc[2][2]) {
 // ------------------------------------------------------------------ apply
 // Work items per submatrix: npairs(npairs+1)/2 tiles (k1 <= k2) of B, each also
 // written transposed into (k2, k1) so B stays exactly symmetric, then
-// (Mp/2b)*npairs tiles of U.  Two 64 x 64 LDS tiles per workgroup (two
-// workgroups fit a CU); a product with an unrotated pair (identity R) is
-// skipped.
+// (Mp/2b)*npairs tiles of U.  One 64 x 64 LDS tile per workgroup (four
+// workgroups fit a CU; the rotations are read from L2 straight into
+// registers); a product with an unrotated pair (identity R) is skipped.
 __global__ __launch_bounds__(NT) void pair_apply(EighBatch e, int round) {
   const int npairs = e.nb / 2;
   const int nrc = e.Mp / B2;
@@ -343,7 +373,6 @@ __global__ __launch_bounds__(NT) void pair_apply(EighBatch e, int round) {
   const int* fl = e.rflag + (int64_t)p * npairs;
   const double* Rbase = e.Rw + (int64_t)p * npairs * B2 * B2;
   __shared__ double T[B2][LS];
-  __shared__ double X[B2][LS];
   const int tid = threadIdx.x;
   v4d acc[2][2];
   if (w < ntri) {
@@ -361,23 +390,16 @@ __global__ __launch_bounds__(NT) void pair_apply(EighBatch e, int round) {
     for (int idx = tid; idx < B2 * B2; idx += NT) {
       int r = idx % B2, c = idx / B2;
       T[r][c] = B[pair_idx(r, I1, J1) + (int64_t)pair_idx(c, I2, J2) * Mp];
-      if (f1) X[r][c] = R1[idx];
     }
     __syncthreads();
     if (f1) {
-      mm64<true>(X, T, acc);  // R1^T T
+      mm64_rt_y(R1, T, acc);  // R1^T T
       __syncthreads();
       store_acc(T, acc);
-      if (f2) {
-        for (int idx = tid; idx < B2 * B2; idx += NT) X[idx % B2][idx / B2] = R2[idx];
-      }
-      __syncthreads();
-    } else {
-      for (int idx = tid; idx < B2 * B2; idx += NT) X[idx % B2][idx / B2] = R2[idx];
       __syncthreads();
     }
     if (f2) {
-      mm64<false>(T, X, acc);  // (R1^T T) R2
+      mm64_x_r(T, R2, acc);  // (R1^T T) R2
       __syncthreads();
       store_acc(T, acc);
       __syncthreads();
@@ -403,10 +425,9 @@ __global__ __launch_bounds__(NT) void pair_apply(EighBatch e, int round) {
     for (int idx = tid; idx < B2 * B2; idx += NT) {
       int r = idx % B2, c = idx / B2;
       T[r][c] = U[(rc * B2 + r) + (int64_t)pair_idx(c, I2, J2) * Mp];
-      X[r][c] = R2[idx];
     }
     __syncthreads();
-    mm64<false>(T, X, acc);
+    mm64_x_r(T, R2, acc);
     __syncthreads();
     store_acc(T, acc);
     __syncthreads();
