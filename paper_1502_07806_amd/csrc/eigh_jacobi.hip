@@ -116,6 +116,18 @@ __device__ inline double sum8(double v) {
   v += dpp_d<0x141>(v);
   return v;
 }
+// Sum over an aligned group of 16 lanes: the 8-lane sums, then the row mirror
+// (lane i <-> 15 - i) adds the other half (bitwise the same in every lane).
+__device__ inline double sum16(double v) {
+  v = sum8(v);
+  v += dpp_d<0x140>(v);
+  return v;
+}
+// The pair solver gives each column pair PL lanes of B2 / PL rows each;
+// a workgroup has PS_NT = 32 PL threads.
+constexpr int PL = 16;
+constexpr int PS_NT = 32 * PL;
+__device__ inline double sum_pl(double v) { return PL == 16 ? sum16(v) : sum8(v); }
 // Reciprocal and reciprocal square root: the hardware estimates (relative
 // error about 5e-8) refined by two Newton steps, which converge
 // quadratically to one or two ulps (measured: 1.9e-16 and 2.3e-16).
@@ -137,12 +149,12 @@ __device__ inline double rsq_d(double x) {
 // bound| so that W is positive definite: column pairs of W are rotated until
 // all columns are orthogonal.  Then W = W0 R = R diag(lambda + sigma) for
 // the accumulated rotation R, so the eigenvectors are the normalised final
-// columns of W and R is never accumulated.  Eight lanes own a column pair
-// (8 rows each) and reduce its inner product with DPP, so a round needs one
-// barrier; the squared column norms are summed exactly in the first round of
+// columns of W and R is never accumulated.  PL = 16 lanes own a column pair
+// (4 rows each, two waves per SIMD) and reduce its inner product with DPP, so
+// a round needs one barrier; the squared column norms are summed exactly in the first round of
 // each sweep and carried through the rotations in the others.  Padding
 // indices (beyond the submatrix order) never rotate.
-__global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
+__global__ __launch_bounds__(PS_NT) void pair_solve(EighBatch e, int round) {
   const int npairs = e.nb / 2;
   const int p = blockIdx.x / npairs, k = blockIdx.x % npairs;
   int* flagR = e.rflag + (int64_t)p * npairs + k;
@@ -163,12 +175,12 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   if (tid == 0) any_rot = 0;
   __syncthreads();
   int need = 0;
-  for (int idx = tid; idx < B2 * B2; idx += NT) {
+  for (int idx = tid; idx < B2 * B2; idx += PS_NT) {
     int r = idx % B2, c = idx / B2;
     W[c][r] = B[pair_idx(r, I, J) + (int64_t)pair_idx(c, I, J) * Mp];
   }
   __syncthreads();
-  for (int idx = tid; idx < B2 * B2; idx += NT) {
+  for (int idx = tid; idx < B2 * B2; idx += PS_NT) {
     int r = idx % B2, c = idx / B2;
     if (r < c && must_rotate(W[c][r], W[r][r], W[c][c], fl)) need = 1;
   }
@@ -176,7 +188,7 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   __syncthreads();
   if (!any_rot) { if (tid == 0) *flagR = 0; return; }
   const double sigma = 2.0 * fmax(fabs(e.scal[1]), fabs(e.scal[2])) + TINY;
-  for (int t = tid; t < B2; t += NT) {
+  for (int t = tid; t < B2; t += PS_NT) {
     const bool pad = pair_idx(t, I, J) >= msize;
     if (pad) {  // a padding column becomes a unit vector (no overflow, never rotated)
       for (int r = 0; r < B2; ++r) W[t][r] = (r == t) ? 1.0 : 0.0;
@@ -185,7 +197,7 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
     }
   }
   __syncthreads();
-  const int slot = tid >> 3, sub = tid & 7;  // 32 column pairs x 8 lanes
+  const int slot = tid / PL, sub = tid % PL;  // 32 column pairs x PL lanes
   bool converged = false;
   for (int sweep = 0; sweep < e.inner_max_sweeps; ++sweep) {
     if (tid == 0) sweep_rot = 0;
@@ -193,7 +205,7 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
     for (int r = 0; r < B2 - 1; ++r) {
       const int a = rr_index(slot, r, B2), b = rr_index(B2 - 1 - slot, r, B2);
       const int pc = min(a, b), qc = max(a, b);
-      double x[B2 / 8], y[B2 / 8];
+      double x[B2 / PL], y[B2 / PL];
       double ab = 0.0, aa, bb;
       if (r == 0) {
         // exact squared column norms at the start of each sweep (every
@@ -201,20 +213,20 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
         // running values in cn, updated with each rotation
         double sa = 0.0, sb = 0.0;
 #pragma unroll
-        for (int m = 0; m < B2 / 8; ++m) {
-          const int row = sub + 8 * m;
+        for (int m = 0; m < B2 / PL; ++m) {
+          const int row = sub + PL * m;
           x[m] = W[pc][row];
           y[m] = W[qc][row];
           sa += x[m] * x[m];
           sb += y[m] * y[m];
           ab += x[m] * y[m];
         }
-        aa = sum8(sa);
-        bb = sum8(sb);
+        aa = sum_pl(sa);
+        bb = sum_pl(sb);
       } else {
 #pragma unroll
-        for (int m = 0; m < B2 / 8; ++m) {
-          const int row = sub + 8 * m;
+        for (int m = 0; m < B2 / PL; ++m) {
+          const int row = sub + PL * m;
           x[m] = W[pc][row];
           y[m] = W[qc][row];
           ab += x[m] * y[m];
@@ -222,7 +234,7 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
         aa = cn[pc];
         bb = cn[qc];
       }
-      ab = sum8(ab);
+      ab = sum_pl(ab);
       const bool padpair = pair_idx(pc, I, J) >= msize || pair_idx(qc, I, J) >= msize;
       double na = aa, nb = bb;
       // columns count as orthogonal below 8 u relative (|ab| <= 8u sqrt(aa bb),
@@ -238,8 +250,8 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
         const double c = h * ic;
         const double sn = (d >= 0.0 ? ab : -ab) * ir * ic;
 #pragma unroll
-        for (int m = 0; m < B2 / 8; ++m) {
-          const int row = sub + 8 * m;
+        for (int m = 0; m < B2 / PL; ++m) {
+          const int row = sub + PL * m;
           W[pc][row] = c * x[m] - sn * y[m];
           W[qc][row] = sn * x[m] + c * y[m];
         }
@@ -275,7 +287,7 @@ __global__ __launch_bounds__(NT) void pair_solve(EighBatch e, int round) {
   }
   __syncthreads();
   double* Rg = e.Rw + ((int64_t)p * npairs + k) * B2 * B2;
-  for (int idx = tid; idx < B2 * B2; idx += NT) {  // row-major: Rg[r * 2b + c] = R(r, c)
+  for (int idx = tid; idx < B2 * B2; idx += PS_NT) {  // row-major: Rg[r * 2b + c] = R(r, c)
     int r = idx / B2, c = idx % B2;
     Rg[idx] = W[c][r] * nrm[c];
   }
@@ -497,7 +509,7 @@ hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, 
   for (int sw = 0; sw < max_sweeps; ++sw) {
     hipLaunchKernelGGL(sweep_begin, dim3((e.P + 63) / 64), dim3(64), 0, s, e, sw);
     for (int r = 0; r < e.nb - 1; ++r) {
-      hipLaunchKernelGGL(pair_solve, dim3(e.P * npairs), dim3(NT), 0, s, e, r);
+      hipLaunchKernelGGL(pair_solve, dim3(e.P * npairs), dim3(PS_NT), 0, s, e, r);
       hipLaunchKernelGGL(pair_apply, dim3(e.P * (npairs * (npairs + 1) / 2 + nrc * npairs)), dim3(NT), 0, s, e, r);
     }
   }
