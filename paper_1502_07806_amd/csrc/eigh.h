@@ -31,5 +31,7 @@ struct EighBatch {
 
 hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, int max_sweeps, hipStream_t s);
 hipError_t embed_start_vectors(const EighBatch& e, double* X, int64_t ldx, double* eps, int64_t n, hipStream_t s);
+// The same with X0 rounded to FP32 (the mixed path's master copy).
+hipError_t embed_start_vectors(const EighBatch& e, float* X, int64_t ldx, double* eps, int64_t n, hipStream_t s);
 
 }  // namespace pfsm

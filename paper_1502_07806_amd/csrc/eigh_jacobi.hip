@@ -473,7 +473,8 @@ __global__ __launch_bounds__(NT) void rank_select(EighBatch e) {
     atomicCAS(e.info, 0, PFSM_INFO_EIGH_NOCONV);
 }
 
-__global__ void embed_x0(EighBatch e, double* __restrict__ X, int64_t ldx, double* __restrict__ eps, int64_t n) {
+template <typename T>
+__global__ void embed_x0(EighBatch e, T* __restrict__ X, int64_t ldx, double* __restrict__ eps, int64_t n) {
   // one workgroup per column c of X0
   const int64_t c = blockIdx.x;
   // find partition of column c (part offsets are ascending, P small)
@@ -489,7 +490,7 @@ __global__ void embed_x0(EighBatch e, double* __restrict__ X, int64_t ldx, doubl
   for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
     double v = 0.0;
     if (r >= w0 && r < w0 + M) v = U[r - w0];
-    X[r + c * ldx] = v;
+    X[r + c * ldx] = (T)v;
   }
   if (threadIdx.x == 0) {
     const double* B = e.Bw + (int64_t)p * Mp * Mp;
@@ -517,8 +518,13 @@ hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, 
   return hipGetLastError();
 }
 
+hipError_t embed_start_vectors(const EighBatch& e, float* X, int64_t ldx, double* eps, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(embed_x0<float>, dim3((unsigned)n), dim3(256), 0, s, e, X, ldx, eps, n);
+  return hipGetLastError();
+}
+
 hipError_t embed_start_vectors(const EighBatch& e, double* X, int64_t ldx, double* eps, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(embed_x0, dim3((unsigned)n), dim3(256), 0, s, e, X, ldx, eps, n);
+  hipLaunchKernelGGL(embed_x0<double>, dim3((unsigned)n), dim3(256), 0, s, e, X, ldx, eps, n);
   return hipGetLastError();
 }
 

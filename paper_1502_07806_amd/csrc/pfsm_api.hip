@@ -505,8 +505,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   // (2) submatrix eigensolver (FP64) and start vectors.
   EighBatch e = eigh_batch(pl, W, info, scal);
   PFSM_TRY(eigh_batched_run(e, At64, n, pl->max_sweeps, s));
-  PFSM_TRY(embed_start_vectors(e, B64a, n, eps, n, s));
-  PFSM_TRY(f64_to_f32(B64a, n, X32, n, n, n, s));
+  PFSM_TRY(embed_start_vectors(e, X32, n, eps, n, s));
   PFSM_TRY(pack_x3(X32, 0, n, n, n, 0, Xpk, ldp, s));
   clk.mark(3);
   // (3) folded-spectrum iterations (X master copy in FP32).

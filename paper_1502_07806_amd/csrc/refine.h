@@ -28,7 +28,6 @@ hipError_t refine_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz,
 
 // Mixed-path helpers.
 hipError_t f32_mirror_to_f64(float* At32, double* At64, int64_t n, hipStream_t s);   // lower -> both, FP64 copy
-hipError_t f64_to_f32(const double* X, int64_t ldx, float* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t s);
 // D = -U + U2 (upper triangle, zero below), U = (L - I)^T from the lower factor L.
 hipError_t lower_minus_identity_check(const double* L, int64_t ldl, int64_t n, double* scratch, int* info,
                                       hipStream_t s);

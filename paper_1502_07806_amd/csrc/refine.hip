@@ -375,12 +375,6 @@ __global__ __launch_bounds__(256) void k_sym_from_lower(float* A32, double* A64,
   }
 }
 
-__global__ void k_f64_to_f32(const double* X, int64_t ldx, float* Y, int64_t ldy, int64_t m) {
-  const int64_t j = blockIdx.y;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-    Y[i + j * ldy] = (float)X[i + j * ldx];
-}
-
 // max |L - I| over the lower triangle (one workgroup per column, then a max).
 __global__ __launch_bounds__(NT) void k_lmi_col(const double* L, int64_t ldl, int64_t n, double* out) {
   __shared__ double sh[NT];
@@ -480,12 +474,6 @@ hipError_t f32_mirror_to_f64(float* At32, double* At64, int64_t n, hipStream_t s
   if (n <= 0) return hipSuccess;
   const int64_t t = (n + TT - 1) / TT;
   hipLaunchKernelGGL(k_sym_from_lower, dim3((unsigned)(t * (t + 1) / 2)), dim3(256), 0, s, At32, At64, n);
-  return hipGetLastError();
-}
-
-hipError_t f64_to_f32(const double* X, int64_t ldx, float* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t s) {
-  dim3 grid((unsigned)std::min<int64_t>((m + 255) / 256, 32), (unsigned)n);
-  hipLaunchKernelGGL(k_f64_to_f32, grid, dim3(256), 0, s, X, ldx, Y, ldy, m);
   return hipGetLastError();
 }
 
