@@ -146,6 +146,35 @@ def bench_g2s(n: int, args, iterations: int = 8):
                                    "reduction launch)"}}
 
 
+def bench_wide(n, offs, A, V, lam_ex, n_it, q, args):
+    """Submatrices of the paper's width (gamma = M / N = 0.2 and 0.3, the slices
+    unchanged, halo widened): mixed-precision step time and eigenvalue error."""
+    import torch
+    import paper_1502_07806_amd as pf
+    m = offs[1] - offs[0]
+    res = []
+    for gamma in (0.2, 0.3):
+        halo = max(0, (int(round(gamma * n)) - m) // 2)
+        plan = pf.Plan(n, offs, halo=halo, iterations=n_it, fs_power=q, precision="mixed_bf16")
+        lam, Vo = plan.solve(A, V)
+        ts = []
+        for _ in range(2):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.solve(A, V, out=(lam, Vo), check=False)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        plan.check()
+        err = float(np.max(np.abs(lam.cpu().numpy() - lam_ex)) / np.max(np.abs(lam_ex)))
+        res.append({"gamma": gamma, "submatrix_order": m + 2 * halo, "halo": halo, "ms_per_step": min(ts),
+                    "eig_err_vs_prescribed": err})
+        del plan, lam, Vo
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +186,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-g2s", action="store_true", help="skip the generalized-to-standard conversion measurement")
+    ap.add_argument("--no-wide", action="store_true", help="skip the paper-width submatrix measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: multi-GPU sharding of the slices is not part of this "
@@ -282,6 +312,8 @@ def main():
         del pnr
     if not args.no_g2s:
         out["generalized_to_standard"] = bench_g2s(n, args)
+    if not args.no_wide:
+        out["paper_width_submatrices"] = bench_wide(n, offs, A, V, lam_ex, n_it, q, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out), flush=True)
