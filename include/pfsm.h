@@ -38,11 +38,10 @@
  *         previous vectors)
  *     -1  a non-finite eigenvalue (non-finite input propagates to it)
  *     -2  mixed precision: the overlap matrix is too far from the identity for
- *         its near-identity Cholesky iteration (last step changed L by more
- *         than 1e-7) or for the short series used for X L^{-T} (max |L - I| >
- *         1e-3): the start vectors are far from orthogonal, outside the
- *         diagonally dominant regime (this also covers what the FP64 path
- *         reports as k>0)
+ *         the first-order orthonormalisation X <- X - X Phi(S - I)^T
+ *         (max |S - I| > 1e-3): the start vectors are far from orthogonal,
+ *         outside the diagonally dominant regime (this also covers what the
+ *         FP64 path reports as k>0)
  *     -3  a submatrix eigensolver did not converge within its sweep limit
  *     -4  an output vector lost its length (squared norm outside [1/4, 4] before
  *         normalisation): V_prev does not have orthonormal columns
