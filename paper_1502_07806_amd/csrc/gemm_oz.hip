@@ -554,17 +554,60 @@ __global__ __launch_bounds__(NT, 1) void gemm_oz_fused(OzArgs a, int tiles_m, in
 }
 
 // One block per column: exponent of the column maximum, then the digits of
-// four consecutive k per thread (one 32-bit word per plane).
+// four consecutive k per thread (one 32-bit word per plane).  Columns of up
+// to 256 * 4 * SPLIT_REG entries are read once, into registers, with 16-byte
+// loads all in flight together; longer ones are read twice.
+constexpr int SPLIT_REG = 8;
+
+__device__ inline void oz_digits_store(double (&t)[4], int s, int8_t* out, int64_t pstride) {
+  for (int p = 0; p < s; ++p) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double d = rint(t[u]);  // |d| <= 64, |t - d| <= 1/2
+      word |= ((uint32_t)(int)d & 0xffu) << (8 * u);
+      t[u] = (t[u] - d) * 128.0;
+    }
+    *(uint32_t*)(out + p * pstride) = word;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_oz_split(const double* X, int64_t ldx, int64_t K, int64_t ldp,
                                                   int64_t pstride, int s, int8_t* P, int* expo, int* info) {
   __shared__ double sh[256];
   const int64_t c = blockIdx.x;
   const double* x = X + c * ldx;
   const int tid = threadIdx.x;
+  const int64_t nch = (ldp + 1023) / 1024;  // chunks of 4 entries per thread
+  const bool in_regs = nch <= SPLIT_REG;
+  // 16-byte loads need an even leading dimension and a 16-byte aligned base
+  const bool vec = ((ldx & 1) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  double r[SPLIT_REG][4];
   double m = 0.0;
-  for (int64_t k = tid; k < K; k += 256) {
-    const double v = fabs(x[k]);
-    m = (v > m || v != v) ? v : m;
+  if (in_regs) {
+#pragma unroll
+    for (int j = 0; j < SPLIT_REG; ++j) {
+      const int64_t k4 = 4 * (int64_t)tid + 1024 * (int64_t)j;
+      if (vec && k4 + 4 <= K) {
+        const double2 a = *(const double2*)(x + k4), b = *(const double2*)(x + k4 + 2);
+        r[j][0] = a.x; r[j][1] = a.y; r[j][2] = b.x; r[j][3] = b.y;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[j][u] = (k4 + u < K) ? x[k4 + u] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < SPLIT_REG; ++j)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double v = fabs(r[j][u]);
+        m = (v > m || v != v) ? v : m;
+      }
+  } else {
+    for (int64_t k = tid; k < K; k += 256) {
+      const double v = fabs(x[k]);
+      m = (v > m || v != v) ? v : m;
+    }
   }
   sh[tid] = m;
   __syncthreads();
@@ -584,20 +627,23 @@ __global__ __launch_bounds__(256) void k_oz_split(const double* X, int64_t ldx, 
     if (bad) atomicCAS(info, 0, -1);
   }
   int8_t* out = P + c * ldp;
+  if (in_regs) {
+#pragma unroll
+    for (int j = 0; j < SPLIT_REG; ++j) {
+      const int64_t k4 = 4 * (int64_t)tid + 1024 * (int64_t)j;
+      if (k4 >= ldp) break;
+      double t[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) t[u] = (!bad && k4 + u < K) ? ldexp(r[j][u], 6 - e) : 0.0;  // |t| < 64
+      oz_digits_store(t, s, out + k4, pstride);
+    }
+    return;
+  }
   for (int64_t k4 = 4 * (int64_t)tid; k4 < ldp; k4 += 4 * 256) {
     double t[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) t[u] = (!bad && k4 + u < K) ? ldexp(x[k4 + u], 6 - e) : 0.0;  // |t| < 64
-    for (int p = 0; p < s; ++p) {
-      uint32_t word = 0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double d = rint(t[u]);  // |d| <= 64, |t - d| <= 1/2
-        word |= ((uint32_t)(int)d & 0xffu) << (8 * u);
-        t[u] = (t[u] - d) * 128.0;
-      }
-      *(uint32_t*)(out + p * pstride + k4) = word;
-    }
+    oz_digits_store(t, s, out + k4, pstride);
   }
 }
 

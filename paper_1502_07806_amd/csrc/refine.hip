@@ -18,6 +18,9 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int KM = REFINE_KMAX;
+constexpr int KS = 4;  // clusters up to this size take the one-pass Gram and output paths
+constexpr int GU = 2;  // rows per thread in flight in the one-pass Gram
+constexpr int RU = 4;  // rows per thread in flight in the output copies
 
 __device__ inline double block_sum(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -113,7 +116,7 @@ __global__ __launch_bounds__(1024) void k_clusters(const double* lam_s, int64_t 
 
 // One workgroup per (natural) cluster; clusters longer than KM are processed
 // as consecutive pieces of at most KM estimates.
-__global__ __launch_bounds__(NT) void k_cluster_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz, int64_t n,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_cluster_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz, int64_t n,
                                                    const int* count, const int* cstart, const int* csize, const int* inv,
                                                    const double* lam_s, const double* nn, double* lam, double* Vout,
                                                    int64_t ldvo) {
@@ -125,6 +128,7 @@ __global__ __launch_bounds__(NT) void k_cluster_rr(const double* V, int64_t ldv,
   __shared__ int pp[KM / 2], qq[KM / 2];
   __shared__ int rk[KM];
   __shared__ int rot;
+  __shared__ double red[NT / 64][2 * KS * KS];
   const int tid = threadIdx.x;
   const int s_all = cstart[c], k_all = csize[c];
   for (int piece = 0; piece < k_all; piece += KM) {
@@ -134,15 +138,83 @@ __global__ __launch_bounds__(NT) void k_cluster_rr(const double* V, int64_t ldv,
       if (tid == 0) lam[s] = lam_s[s];
       const int j = inv[s];
       const double inv_norm = 1.0 / sqrt(nn[j]);
-      for (int64_t i = tid; i < n; i += NT) Vout[i + (int64_t)s * ldvo] = V[i + (int64_t)j * ldv] * inv_norm;
+      const double* vj = V + (int64_t)j * ldv;
+      double* out = Vout + (int64_t)s * ldvo;
+      for (int64_t i0 = tid; i0 < n; i0 += NT * RU) {  // RU rows per thread in flight
+        double x[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) x[u] = vj[min<int64_t>(i0 + NT * u, n - 1)];
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+          if (i0 + NT * u < n) out[i0 + NT * u] = x[u] * inv_norm;
+      }
       __syncthreads();
       continue;
     }
     if (tid < KM) col[tid] = inv[s + min(tid, k - 1)];  // entries past k repeat a valid column
     __syncthreads();
-    // G = V_c^T Z_c, Mm = V_c^T V_c: each wave takes (a, b) pairs
     const int lane = tid & 63, wave = tid >> 6;
-    for (int pidx = wave; pidx < k * k; pidx += NT / 64) {
+    if (k <= KS) {
+      // Small cluster: one pass of the whole workgroup over the rows, every
+      // product v_a^T z_b and v_a^T v_b of the cluster accumulated at once
+      // (columns past k repeat column k - 1 and their sums are not used).
+      double pz[KS][KS], mv[KS][KS];
+#pragma unroll
+      for (int a = 0; a < KS; ++a)
+#pragma unroll
+        for (int b = 0; b < KS; ++b) pz[a][b] = mv[a][b] = 0.0;
+      for (int64_t i0 = tid; i0 < n; i0 += NT * GU) {
+        double x[GU][KS], y[GU][KS];
+#pragma unroll
+        for (int u = 0; u < GU; ++u)
+#pragma unroll
+          for (int a = 0; a < KS; ++a) {
+            const int64_t i = min<int64_t>(i0 + NT * u, n - 1);
+            x[u][a] = V[i + (int64_t)col[a] * ldv];
+            y[u][a] = Z[i + (int64_t)col[a] * ldz];
+          }
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+          if (i0 + NT * u >= n) continue;
+#pragma unroll
+          for (int a = 0; a < KS; ++a)
+#pragma unroll
+            for (int b = 0; b < KS; ++b) {
+              pz[a][b] += x[u][a] * y[u][b];
+              if (b >= a) mv[a][b] += x[u][a] * x[u][b];
+            }
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < KS; ++a)
+#pragma unroll
+        for (int b = 0; b < KS; ++b) {
+          double p = pz[a][b], m = (b >= a) ? mv[a][b] : 0.0;
+          for (int off = 32; off > 0; off >>= 1) {
+            p += __shfl_xor(p, off, 64);
+            if (b >= a) m += __shfl_xor(m, off, 64);
+          }
+          if (lane == 0) {
+            red[wave][a * KS + b] = p;
+            red[wave][KS * KS + a * KS + b] = m;
+          }
+        }
+      __syncthreads();
+      if (tid < k * k) {
+        const int a = tid % k, b = tid / k;
+        double p_ab = 0.0, p_ba = 0.0, m = 0.0;
+        const int lo = min(a, b), hi = max(a, b);
+        for (int w = 0; w < NT / 64; ++w) {
+          p_ab += red[w][a * KS + b];
+          p_ba += red[w][b * KS + a];
+          m += red[w][KS * KS + lo * KS + hi];
+        }
+        G[a][b] = 0.5 * (p_ab + p_ba);
+        Mm[a][b] = m;
+      }
+    }
+    // G = V_c^T Z_c, Mm = V_c^T V_c: each wave takes (a, b) pairs
+    for (int pidx = wave; k > KS && pidx < k * k; pidx += NT / 64) {
       const int a = pidx % k, b = pidx / k;
       if (a > b) continue;
       const double* va = V + (int64_t)col[a] * ldv;
@@ -312,6 +384,28 @@ __global__ __launch_bounds__(NT) void k_cluster_rr(const double* V, int64_t ldv,
     __syncthreads();
     // Vout[:, s + t] = sum_a V[:, col[a]] Y[a][t]: one row per thread, the
     // cluster's k entries of the row in registers
+    if (k <= KS) {
+      for (int64_t i0 = tid; i0 < n; i0 += NT * RU) {
+        double v[RU][KS];
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+#pragma unroll
+          for (int a = 0; a < KS; ++a) v[u][a] = V[min<int64_t>(i0 + NT * u, n - 1) + (int64_t)col[a] * ldv];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          if (i0 + NT * u >= n) continue;
+          for (int t = 0; t < k; ++t) {
+            double acc = 0.0;
+#pragma unroll
+            for (int a = 0; a < KS; ++a)
+              if (a < k) acc += v[u][a] * Mm[a][t];
+            Vout[i0 + NT * u + (int64_t)(s + t) * ldvo] = acc;
+          }
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     for (int64_t i = tid; i < n; i += NT) {
       double v[KM];
 #pragma unroll

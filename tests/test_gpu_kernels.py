@@ -313,10 +313,15 @@ def _oz_split_dev(X, s, dev):
     return P, P.cpu().numpy().reshape(s, nc, ldp), ex.cpu().numpy(), int(info.item()), ldp, ex
 
 
-def test_oz_split_digits(dev):
+@pytest.mark.parametrize("K,nc", [
+    (300, 70),   # columns held in registers, 16-byte loads, ragged tail
+    (301, 9),    # odd leading dimension: 8-byte loads
+    (8200, 7),   # longer than the register-held column: two reads
+])
+def test_oz_split_digits(dev, K, nc):
     from hooks_util import oz_digits
-    g = np.random.default_rng(21)
-    K, nc, s = 300, 70, 6
+    g = np.random.default_rng(21 + K)
+    s = 6
     X = g.standard_normal((K, nc)) * np.exp(3 * g.standard_normal((1, nc))) * np.exp(g.standard_normal((K, nc)))
     X[:, 5] = 0.0
     X[:, 6] = 0.5  # exact power of two at the maximum
