@@ -19,7 +19,7 @@ namespace {
 constexpr int NT = 256;
 constexpr int KM = REFINE_KMAX;
 constexpr int KS = 4;  // clusters up to this size take the one-pass Gram and output paths
-constexpr int GU = 2;  // rows per thread in flight in the one-pass Gram
+constexpr int GU = 1;  // rows per thread per step of the one-pass Gram
 constexpr int RU = 4;  // rows per thread in flight in the output copies
 
 __device__ inline double block_sum(double v, double* sh) {
@@ -153,105 +153,85 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
     if (tid < KM) col[tid] = inv[s + min(tid, k - 1)];  // entries past k repeat a valid column
     __syncthreads();
+    // G = (V_c^T Z_c + Z_c^T V_c) / 2 and Mm = V_c^T V_c, by blocks of KS x KS
+    // entries: for each block pair the whole workgroup makes one pass over
+    // the rows with every product of the pair accumulated at once (columns
+    // past k repeat column k - 1; their sums are not stored).  V_c^T Z_c is
+    // gathered in Y, which is free until the Jacobi iteration.
     const int lane = tid & 63, wave = tid >> 6;
-    if (k <= KS) {
-      // Small cluster: one pass of the whole workgroup over the rows, every
-      // product v_a^T z_b and v_a^T v_b of the cluster accumulated at once
-      // (columns past k repeat column k - 1 and their sums are not used).
+    const int nblk = (k + KS - 1) / KS;
+    for (int bp = 0; bp < nblk * nblk; ++bp) {
+      const int ca = bp % nblk, cb = bp / nblk;
+      int64_t oa[KS], ob[KS], oz[KS];
+#pragma unroll
+      for (int t = 0; t < KS; ++t) {
+        oa[t] = (int64_t)__builtin_amdgcn_readfirstlane(col[ca * KS + t]) * ldv;
+        const int cbt = __builtin_amdgcn_readfirstlane(col[cb * KS + t]);
+        ob[t] = (int64_t)cbt * ldv;
+        oz[t] = (int64_t)cbt * ldz;
+      }
       double pz[KS][KS], mv[KS][KS];
 #pragma unroll
-      for (int a = 0; a < KS; ++a)
+      for (int x = 0; x < KS; ++x)
 #pragma unroll
-        for (int b = 0; b < KS; ++b) pz[a][b] = mv[a][b] = 0.0;
+        for (int y = 0; y < KS; ++y) pz[x][y] = mv[x][y] = 0.0;
       for (int64_t i0 = tid; i0 < n; i0 += NT * GU) {
-        double x[GU][KS], y[GU][KS];
+        double xa[GU][KS], xb[GU][KS], yb[GU][KS];
 #pragma unroll
         for (int u = 0; u < GU; ++u)
 #pragma unroll
-          for (int a = 0; a < KS; ++a) {
+          for (int t = 0; t < KS; ++t) {
             const int64_t i = min<int64_t>(i0 + NT * u, n - 1);
-            x[u][a] = V[i + (int64_t)col[a] * ldv];
-            y[u][a] = Z[i + (int64_t)col[a] * ldz];
+            xa[u][t] = V[i + oa[t]];
+            xb[u][t] = (ca == cb) ? 0.0 : V[i + ob[t]];
+            yb[u][t] = Z[i + oz[t]];
           }
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
           if (i0 + NT * u >= n) continue;
 #pragma unroll
-          for (int a = 0; a < KS; ++a)
+          for (int x = 0; x < KS; ++x)
 #pragma unroll
-            for (int b = 0; b < KS; ++b) {
-              pz[a][b] += x[u][a] * y[u][b];
-              if (b >= a) mv[a][b] += x[u][a] * x[u][b];
+            for (int y = 0; y < KS; ++y) {
+              pz[x][y] += xa[u][x] * yb[u][y];
+              mv[x][y] += xa[u][x] * ((ca == cb) ? xa[u][y] : xb[u][y]);
             }
         }
       }
 #pragma unroll
-      for (int a = 0; a < KS; ++a)
+      for (int x = 0; x < KS; ++x)
 #pragma unroll
-        for (int b = 0; b < KS; ++b) {
-          double p = pz[a][b], m = (b >= a) ? mv[a][b] : 0.0;
+        for (int y = 0; y < KS; ++y) {
+          double p = pz[x][y], m = mv[x][y];
           for (int off = 32; off > 0; off >>= 1) {
             p += __shfl_xor(p, off, 64);
-            if (b >= a) m += __shfl_xor(m, off, 64);
+            m += __shfl_xor(m, off, 64);
           }
           if (lane == 0) {
-            red[wave][a * KS + b] = p;
-            red[wave][KS * KS + a * KS + b] = m;
+            red[wave][x * KS + y] = p;
+            red[wave][KS * KS + x * KS + y] = m;
           }
         }
       __syncthreads();
-      if (tid < k * k) {
-        const int a = tid % k, b = tid / k;
-        double p_ab = 0.0, p_ba = 0.0, m = 0.0;
-        const int lo = min(a, b), hi = max(a, b);
+      if (tid < KS * KS) {
+        const int x = tid / KS, y = tid % KS;
+        const int ga = ca * KS + x, gb = cb * KS + y;
+        double p = 0.0, m = 0.0;
         for (int w = 0; w < NT / 64; ++w) {
-          p_ab += red[w][a * KS + b];
-          p_ba += red[w][b * KS + a];
-          m += red[w][KS * KS + lo * KS + hi];
+          p += red[w][x * KS + y];
+          m += red[w][KS * KS + x * KS + y];
         }
-        G[a][b] = 0.5 * (p_ab + p_ba);
-        Mm[a][b] = m;
+        if (ga < k && gb < k) {
+          Y[ga][gb] = p;  // v_ga^T z_gb
+          Mm[ga][gb] = m;
+        }
       }
+      __syncthreads();
     }
-    // G = V_c^T Z_c, Mm = V_c^T V_c: each wave takes (a, b) pairs
-    for (int pidx = wave; k > KS && pidx < k * k; pidx += NT / 64) {
-      const int a = pidx % k, b = pidx / k;
-      if (a > b) continue;
-      const double* va = V + (int64_t)col[a] * ldv;
-      const double* vb = V + (int64_t)col[b] * ldv;
-      const double* za = Z + (int64_t)col[a] * ldz;
-      const double* zb = Z + (int64_t)col[b] * ldz;
-      double g1 = 0.0, g2 = 0.0, m = 0.0;
-      constexpr int U = 8;  // rows per lane and pass: 4 U independent loads in flight
-      for (int64_t i0 = lane; i0 < n; i0 += 64 * U) {
-        double x[U], y[U], zx[U], zy[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int64_t i = min<int64_t>(i0 + 64 * u, n - 1);
-          x[u] = va[i];
-          y[u] = vb[i];
-          zx[u] = za[i];
-          zy[u] = zb[i];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (i0 + 64 * u < n) {
-            g1 += x[u] * zy[u];
-            g2 += y[u] * zx[u];
-            m += x[u] * y[u];
-          }
-        }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        g1 += __shfl_xor(g1, off, 64);
-        g2 += __shfl_xor(g2, off, 64);
-        m += __shfl_xor(m, off, 64);
-      }
-      if (lane == 0) {
-        double g = 0.5 * (g1 + g2);
-        G[a][b] = g; G[b][a] = g;
-        Mm[a][b] = m; Mm[b][a] = m;
-      }
+    for (int idx = tid; idx < k * k; idx += NT) {
+      const int x = idx % k, y = idx / k;
+      G[x][y] = 0.5 * (Y[x][y] + Y[y][x]);
+      if (x > y) Mm[x][y] = Mm[y][x];  // the same sum in both triangles
     }
     __syncthreads();
     // Cholesky Mm = R R^T (lower R, in Mm; right-looking, rows in parallel),
@@ -382,40 +362,42 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       Mm[i][rk[a]] = Y[i][a];  // R is no longer needed
     }
     __syncthreads();
-    // Vout[:, s + t] = sum_a V[:, col[a]] Y[a][t]: one row per thread, the
-    // cluster's k entries of the row in registers
-    if (k <= KS) {
+    // Vout[:, s + t] = sum_a V[:, col[a]] Mm[a][t], by blocks of KS output
+    // columns: RU rows per thread, the row's entries of one block of KS
+    // input columns in registers at a time.
+    for (int tb = 0; tb < nblk; ++tb) {
       for (int64_t i0 = tid; i0 < n; i0 += NT * RU) {
-        double v[RU][KS];
+        double acc[RU][KS];
 #pragma unroll
         for (int u = 0; u < RU; ++u)
 #pragma unroll
-          for (int a = 0; a < KS; ++a) v[u][a] = V[min<int64_t>(i0 + NT * u, n - 1) + (int64_t)col[a] * ldv];
+          for (int t = 0; t < KS; ++t) acc[u][t] = 0.0;
+        for (int ab = 0; ab < nblk; ++ab) {
+          double v[RU][KS];
+#pragma unroll
+          for (int t = 0; t < KS; ++t) {
+            const int64_t oc = (int64_t)__builtin_amdgcn_readfirstlane(col[ab * KS + t]) * ldv;
+#pragma unroll
+            for (int u = 0; u < RU; ++u) v[u][t] = V[min<int64_t>(i0 + NT * u, n - 1) + oc];
+          }
+#pragma unroll
+          for (int x = 0; x < KS; ++x) {
+            if (ab * KS + x >= k) continue;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+              const double c = Mm[ab * KS + x][tb * KS + t];
+#pragma unroll
+              for (int u = 0; u < RU; ++u) acc[u][t] += v[u][x] * c;
+            }
+          }
+        }
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
           if (i0 + NT * u >= n) continue;
-          for (int t = 0; t < k; ++t) {
-            double acc = 0.0;
 #pragma unroll
-            for (int a = 0; a < KS; ++a)
-              if (a < k) acc += v[u][a] * Mm[a][t];
-            Vout[i0 + NT * u + (int64_t)(s + t) * ldvo] = acc;
-          }
+          for (int t = 0; t < KS; ++t)
+            if (tb * KS + t < k) Vout[i0 + NT * u + (int64_t)(s + tb * KS + t) * ldvo] = acc[u][t];
         }
-      }
-      __syncthreads();
-      continue;
-    }
-    for (int64_t i = tid; i < n; i += NT) {
-      double v[KM];
-#pragma unroll
-      for (int a = 0; a < KM; ++a) v[a] = (a < k) ? V[i + (int64_t)col[a] * ldv] : 0.0;
-      for (int t = 0; t < k; ++t) {
-        double acc = 0.0;
-#pragma unroll
-        for (int a = 0; a < KM; ++a)
-          if (a < k) acc += v[a] * Mm[a][t];
-        Vout[i + (int64_t)(s + t) * ldvo] = acc;
       }
     }
     __syncthreads();

@@ -94,6 +94,20 @@ def test_mixed_full_size(pf):
     # digits: about 2^-42 sqrt(n) max|A| max|V| per entry, 1e-11 here)
     rq = torch.sum(Vs * (A @ Vs), dim=0).cpu().numpy()
     assert np.max(np.abs(rq - lam_np[cols.cpu().numpy()])) <= 1e-10
+    # the largest groups of close estimates (refined together by a Rayleigh-Ritz
+    # solve, several blocks of columns wide): Ritz vectors orthonormal to FP64
+    # rounding, eigenvalues equal to their Rayleigh quotients
+    thr = 1e-4 * np.abs(lam_np).max()
+    starts = np.flatnonzero(np.r_[True, np.diff(lam_np) > thr])
+    sizes = np.diff(np.r_[starts, cfg.n])
+    big = np.argsort(-sizes, kind="stable")[:3]
+    assert sizes[big[0]] >= 5
+    for b in big:
+        cl = torch.arange(int(starts[b]), int(starts[b] + sizes[b]), device=dev)
+        Vc = Vo[:, cl]
+        assert torch.max(torch.abs(Vc.T @ Vc - torch.eye(len(cl), dtype=Vc.dtype, device=dev))).item() <= 1e-12
+        rq = torch.sum(Vc * (A @ Vc), dim=0).cpu().numpy()
+        assert np.max(np.abs(rq - lam_np[cl.cpu().numpy()])) <= 1e-10
 
 
 def test_mixed_failure_modes(pf):
