@@ -277,15 +277,11 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     pl->m_rb = w; w = align256(w + (size_t)(7 * n + 8) * sizeof(double));
     pl->split_bytes = x3_split_bytes(n);
     pl->m_split = w; w = align256(w + pl->split_bytes);
-    // The refinement runs after the packed copies of A, V and At are dead:
-    // its digit planes reuse that span when they fit (they do when n is a
-    // multiple of 128), else they get their own region.
+    // The digit planes of the refinement (two sets of s planes plus 2n
+    // exponents) always exceed the span of the three packed copies of A, V
+    // and At (3 * 4 n ceil32(n) bytes), so they get a region of their own.
     const size_t oz = align256(2 * oz_plane_bytes(n, n, REFINE_OZ_SLICES)) + 2 * n * sizeof(int);
-    if (oz <= pl->m_Xpk - pl->m_Apk) {
-      pl->m_oz = pl->m_Apk;
-    } else {
-      pl->m_oz = w; w = align256(w + oz);
-    }
+    pl->m_oz = w; w = align256(w + oz);
   }
   pl->total = w;
   *out = pl;
