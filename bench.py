@@ -149,6 +149,157 @@ def bench_g2s(n: int, args, iterations: int = 8):
                                    "reduction launch)"}}
 
 
+def _graph_replay_ms(fn, outs, reps):
+    """Capture fn() (which writes into the tensors `outs`) once into a HIP graph,
+    replay it `reps` times and return (ms per replay, every replay equal to the
+    eager result bit for bit)."""
+    import torch
+    ref = [x.clone() for x in outs]
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        with torch.cuda.graph(g, stream=cs):
+            fn()
+    torch.cuda.current_stream().wait_stream(cs)
+    g.replay()
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(outs, ref))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    same = same and all(torch.equal(a, b) for a, b in zip(outs, ref))
+    del g
+    return ms, same
+
+
+def bench_batched(args, count: int = 64):
+    """Batched uneven instances: `count` independent problems of order N_b drawn
+    from {384, 512, 768, 1024, 1536, 2048} (seeded), each with its own spectrum
+    and V_prev perturbation (||K||_F = 1e-2), slices of 128, submatrices of
+    order 256, 3 iterations, mixed precision; the whole batch is one call,
+    captured into one HIP graph and replayed.  Flops = sum of the per-instance
+    step flops."""
+    import torch
+    import paper_1502_07806_amd as pf
+    from pfsm_workloads import CONFIGS, batch_instance, batch_sizes, uniform_layout
+    cfg = CONFIGS["c4_batched"]
+    dev = torch.device("cuda:0")
+    ns = batch_sizes(count)
+    As, Vs, lex = [], [], []
+    for b, nb in enumerate(ns):
+        A, V, lam, _ = batch_instance(b, nb, cfg.kappa, cfg.seed_base, device=dev)
+        As.append(A.t().contiguous().t())
+        Vs.append(V.t().contiguous().t())
+        lex.append(lam)
+    specs = [dict(n=nb, part_offsets=uniform_layout(nb, cfg.slice_size), halo=cfg.halo,
+                  iterations=cfg.iterations, precision="mixed_bf16") for nb in ns]
+    bp = pf.BatchedPlan(specs)
+    lams, Vouts = bp.outputs(dev)
+    bp.solve(As, Vs, out=(lams, Vouts))  # eager: allocates the workspace; device info checked
+    for _ in range(max(1, args.warmup)):
+        bp.solve(As, Vs, out=(lams, Vouts), check=False)
+    ms, same = _graph_replay_ms(lambda: bp.solve(As, Vs, out=(lams, Vouts), check=False), lams + Vouts,
+                                max(2, args.steps // 2))
+    bp.check()
+    if not same:
+        raise RuntimeError("batched graph replay differs from the eager call")
+    F = sum(algorithmic_flops(nb, min(nb, cfg.slice_size + 2 * cfg.halo), 2, cfg.iterations) for nb in ns)
+    err = max(float(np.max(np.abs(l.cpu().numpy() - e)) / np.max(np.abs(e))) for l, e in zip(lams, lex))
+    out = {"workload": "%d instances, N_b in {384..2048} (sum %d), slices of %d, submatrix order %d, %d FS "
+                       "iterations, mixed precision; one graph replay per batch" %
+                       (count, sum(ns), cfg.slice_size, cfg.slice_size + 2 * cfg.halo, cfg.iterations),
+           "ms_per_batch": ms, "instances_per_s": count * 1e3 / ms, "tflops": F / (ms * 1e-3) / 1e12,
+           "eig_err_vs_prescribed_max": err}
+    del bp, As, Vs, lams, Vouts
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_backward(args):
+    """Differentiation workload: N = 4096, 16 slices of 256, submatrices of
+    order 512; forward step then the adjoint dA = sym(V (diag(dlam) + F o (V^T dV)) V^T)
+    for the loss sum_{i <= n_occ} w_i lam_i + sum_{j <= n_occ} <v_j, D v_j>
+    (w ~ U[0,1), D = diag(d), d ~ N(0,1)); FP64 plan and mixed plan (split-BF16
+    products).  Backward flops: 2N^3 (V^T dV) + 2N^3 + N^3 (V M V^T, symmetric)."""
+    import torch
+    import paper_1502_07806_amd as pf
+    from pfsm_workloads import CONFIGS, loss_weights, prescribed_problem, uniform_layout
+    cfg = CONFIGS["c5_grad_n4096"]
+    dev = torch.device("cuda:0")
+    n, k = cfg.n, cfg.n_occ
+    A, V, _, _ = prescribed_problem(n, k, cfg.kappa, cfg.seed_base, cfg.clusters, device=dev)
+    A, V = A.t().contiguous().t(), V.t().contiguous().t()
+    w, d = loss_weights(k, n, cfg.seed_base)
+    w_t, d_t = torch.from_numpy(w).to(dev), torch.from_numpy(d).to(dev)
+    res = {"workload": "N=%d, %d slices of %d, submatrix order %d, loss over the %d lowest eigenpairs" %
+                       (n, n // cfg.slice_size, cfg.slice_size, cfg.slice_size + 2 * cfg.halo, k)}
+    for precision in ("fp64", "mixed_bf16"):
+        plan = pf.Plan(n, uniform_layout(n, cfg.slice_size), halo=cfg.halo, iterations=cfg.iterations,
+                       precision=precision)
+        lam, Vo = plan.solve(A, V)
+        # gradients of the loss with respect to lam and V (the loss definition itself)
+        glam = torch.zeros(n, dtype=torch.float64, device=dev)
+        glam[:k] = w_t
+        gV = torch.zeros_like(Vo)
+        gV[:, :k] = 2.0 * d_t[:, None] * Vo[:, :k]
+        for _ in range(max(1, args.warmup)):
+            gA = plan.backward(lam, Vo, glam, gV, eta=1e-8)
+        ts = []
+        for _ in range(max(2, args.steps // 2)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            gA = plan.backward(lam, Vo, glam, gV, eta=1e-8)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        plan.check()
+        ms = float(np.median(ts))
+        res[precision] = {"backward_ms": ms, "tflops": 5.0 * n ** 3 / (ms * 1e-3) / 1e12,
+                          "symmetric": bool(torch.equal(gA, gA.t()))}
+        del plan, lam, Vo, gA, gV
+        torch.cuda.empty_cache()
+    return res
+
+
+def bench_scf_sequence(args, steps: int = 10):
+    """SCF-like sequence at N = 2048 (8 slices of 256, submatrices of order 512,
+    FP64 path): A_k = A_{k-1} + E_k, ||E_k||_F = 1e-2 2^-k, each solve started
+    from the previous solve's vectors (chained on the GPU); per-step time and
+    the eigenvalue error of the last step against the exact eigenvalues of A_k."""
+    import torch
+    import paper_1502_07806_amd as pf
+    from pfsm_workloads import CONFIGS, prescribed_problem, scf_sequence, uniform_layout
+    cfg = CONFIGS["c2_n2048_seq"]
+    dev = torch.device("cuda:0")
+    n = cfg.n
+    A0, V0, _, _ = prescribed_problem(n, cfg.n_occ, cfg.kappa, cfg.seed_base, cfg.clusters, device=dev)
+    seq = [a.t().contiguous().t() for a in scf_sequence(A0, steps, cfg.seed_base)]
+    plan = pf.Plan(n, uniform_layout(n, cfg.slice_size), halo=cfg.halo, iterations=cfg.iterations, precision="fp64")
+    V = V0.t().contiguous().t()
+    plan.solve(seq[0], V)  # warm-up
+    ts = []
+    for Ak in seq:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lam, V = plan.solve(Ak, V, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    plan.check()
+    exact = torch.linalg.eigvalsh(seq[-1].cpu()).numpy()
+    err = float(np.max(np.abs(lam.cpu().numpy() - exact)) / np.max(np.abs(exact)))
+    F = algorithmic_flops(n, cfg.slice_size + 2 * cfg.halo, 2, cfg.iterations)
+    return {"workload": "N=%d, %d steps, 8 slices of %d, submatrix order %d, FP64 path, chained" %
+                        (n, steps, cfg.slice_size, cfg.slice_size + 2 * cfg.halo),
+            "ms_per_step": [round(t, 3) for t in ts], "total_ms": float(sum(ts)),
+            "tflops": F * steps / (sum(ts) * 1e-3) / 1e12, "last_step_eig_err_vs_exact": err}
+
+
 def bench_wide(n, offs, A, V, lam_ex, n_it, q, args):
     """Submatrices of the paper's width (gamma = M / N = 0.2 and 0.3, the slices
     unchanged, halo widened): mixed-precision step time and eigenvalue error."""
@@ -190,6 +341,8 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-g2s", action="store_true", help="skip the generalized-to-standard conversion measurement")
     ap.add_argument("--no-wide", action="store_true", help="skip the paper-width submatrix measurement")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched, backward and SCF-sequence measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: multi-GPU sharding of the slices is not part of this "
@@ -347,6 +500,12 @@ def main():
         out["generalized_to_standard"] = bench_g2s(n, args)
     if not args.no_wide:
         out["paper_width_submatrices"] = bench_wide(n, offs, A, V, lam_ex, n_it, q, args)
+    if not args.no_extra:
+        del A, V
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(args)
+        out["backward"] = bench_backward(args)
+        out["scf_sequence"] = bench_scf_sequence(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out), flush=True)
