@@ -70,10 +70,12 @@ typedef enum pfsm_status {
 
 typedef enum pfsm_precision {
   PFSM_PREC_FP64 = 0,       /* every product in FP64 on matrix cores */
-  PFSM_PREC_MIXED_BF16 = 1  /* products on BF16 matrix cores with every operand split into
-                               hi + lo BF16 parts (three products, FP32 accumulation); FP64 for
-                               the submatrix eigensolver, the Cholesky of the overlap and the
-                               final Rayleigh quotients / cluster Rayleigh-Ritz against A */
+  PFSM_PREC_MIXED_BF16 = 1  /* products on BF16 matrix cores, FP32 accumulation: the basis change,
+                               overlap and back-rotation with every operand split into hi + lo
+                               BF16 parts (three products), the folded-spectrum products on plain
+                               BF16 operands (one product; see PFSM_FLAG_FS_SPLIT); FP64 for the
+                               submatrix eigensolver, the Cholesky of the overlap and the final
+                               Rayleigh quotients / cluster Rayleigh-Ritz against A */
 } pfsm_precision;
 
 typedef enum pfsm_shift_mode {
@@ -101,6 +103,14 @@ typedef struct pfsm_desc {
  * eigenvalue estimates of the reduced-precision step (Rayleigh quotients in the
  * rotated basis) -- the "FP32 result" of the mixed path. */
 #define PFSM_FLAG_NO_REFINE 1
+/* Mixed precision, fs_power 2: run the two products of each folded-spectrum
+ * iteration on hi/lo split operands (three BF16 products, FP32 accumulation)
+ * instead of the default plain BF16 operands (one product, FP32 accumulation).
+ * The FP64 refinement against A removes what the plain products leave (at
+ * N = 8192 the refined eigenvalues are 3.3e-10 from an FP64 computation either
+ * way); the unrefined estimates (PFSM_FLAG_NO_REFINE) are about 4 % closer
+ * with the split. */
+#define PFSM_FLAG_FS_SPLIT 2
 
 typedef struct pfsm_plan pfsm_plan;
 

@@ -29,6 +29,7 @@ INFO_TEXT = {0: "ok", -1: "non-finite eigenvalue",
              -4: "an output vector lost its length: V_prev is not orthonormal",
              -5: "a diagonal entry of B is not a positive finite number"}
 FLAG_NO_REFINE = 1
+FLAG_FS_SPLIT = 2
 
 
 class PfsmDesc(ctypes.Structure):
@@ -123,10 +124,11 @@ def _stream_handle() -> int:
 
 
 def _desc(n, part_offsets, halo=-1, iterations=3, fs_power=2, alpha=0.0, shift_mode="fixed", precision="fp64",
-          max_sweeps=0, refine=True):
+          max_sweeps=0, refine=True, fs_split=False):
     offs = (ctypes.c_int64 * len(part_offsets))(*[int(x) for x in part_offsets])
+    flags = (0 if refine else FLAG_NO_REFINE) | (FLAG_FS_SPLIT if fs_split else 0)
     d = PfsmDesc(int(n), len(part_offsets) - 1, offs, int(halo), int(iterations), int(fs_power), float(alpha),
-                 PFSM_SHIFT[shift_mode], PFSM_PREC[precision], int(max_sweeps), 0 if refine else FLAG_NO_REFINE)
+                 PFSM_SHIFT[shift_mode], PFSM_PREC[precision], int(max_sweeps), flags)
     return d, offs  # keep offs alive while d is used
 
 
@@ -135,10 +137,10 @@ class Plan:
 
     def __init__(self, n: int, part_offsets: Sequence[int], halo: int = -1, iterations: int = 3,
                  fs_power: int = 2, alpha: float = 0.0, shift_mode: str = "fixed", precision: str = "fp64",
-                 max_sweeps: int = 0, refine: bool = True):
+                 max_sweeps: int = 0, refine: bool = True, fs_split: bool = False):
         lib = load_library()
         d, _keep = _desc(n, part_offsets, halo, iterations, fs_power, alpha, shift_mode, precision, max_sweeps,
-                         refine)
+                         refine, fs_split)
         h = ctypes.c_void_p()
         _check(lib.pfsm_plan_create(ctypes.byref(h), ctypes.byref(d)))
         self._h = h

@@ -326,7 +326,11 @@ template <int W> __device__ inline void wait_vm() {
   __builtin_amdgcn_s_waitcnt((W & 15) | (7 << 4) | (15 << 8) | (((W >> 4) & 3) << 14));
 }
 
-template <int EPI, bool PIPE>
+// NP = 3: the three split products of k16 stages of the split layout.
+// NP = 1: one product from operands in the plain layout; a stage then holds
+// 32 k values per row (the same 64 bytes, four 16-byte chunks of 8 k), and
+// the two fragment slots (hi, lo) carry the first and second 16 k of it.
+template <int EPI, bool PIPE, int NP = 3>
 __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int tiles_n) {
   constexpr int NW = 8, WGR = 4, WR = 2, WC = 4, CPW = 16 / NW;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -351,21 +355,24 @@ __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int 
     kbeg = b0;
     kend = b1;
   }
-  const int total = kend > kbeg ? (int)((kend - kbeg) / 16) : 0;
+  constexpr int SK = NP == 1 ? 32 : 16;  // k values per stage
+  const int total = kend > kbeg ? (int)((kend - kbeg) / SK) : 0;
 
   // byte offsets of this lane's 16-byte chunk in each 1 KB row group it loads
   int64_t offA[CPW], offB[CPW];
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
     const int row = 16 * (wave * CPW + j) + (lane >> 2);
-    const int c = (lane & 3) ^ dswz(row);          // logical chunk: hi k0-7, hi k8-15, lo k0-7, lo k8-15
-    const int coff = (c >> 1) * 64 + (c & 1) * 16;
+    // logical chunk: split layout hi k0-7, hi k8-15, lo k0-7, lo k8-15;
+    // plain layout k0-7, k8-15, k16-23, k24-31
+    const int c = (lane & 3) ^ dswz(row);
+    const int coff = NP == 1 ? 16 * c : (c >> 1) * 64 + (c & 1) * 16;
     offA[j] = min<int64_t>(m0 + row, g.M - 1) * g.ldap * 2 + coff;
     offB[j] = min<int64_t>(n0 + row, g.N - 1) * g.ldbp * 2 + coff;
   }
   auto issue = [&](int t) {
-    const int64_t k0 = kbeg + 16 * (int64_t)t;
-    const int64_t koff = (k0 >> 5) * 128 + ((k0 >> 4) & 1) * 32;
+    const int64_t k0 = kbeg + SK * (int64_t)t;
+    const int64_t koff = NP == 1 ? 2 * k0 : (k0 >> 5) * 128 + ((k0 >> 4) & 1) * 32;
     const unsigned char* A = (const unsigned char*)g.Ap + koff;
     const unsigned char* B = (const unsigned char*)g.Bp + koff;
     unsigned char* sA = lds + (t % DST) * 2 * DTILE;
@@ -410,14 +417,25 @@ __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int 
   };
   auto mma = [&](const Frags& f) {
     // product-major order: consecutive MFMAs update different accumulators
+    if (NP == 3) {
 #pragma unroll
-    for (int pr = 0; pr < 3; ++pr)
+      for (int pr = 0; pr < 3; ++pr)
 #pragma unroll
-      for (int ib = 0; ib < WR; ++ib)
+        for (int ib = 0; ib < WR; ++ib)
 #pragma unroll
-        for (int jb = 0; jb < WC; ++jb)
-          acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pr == 1 ? f.bl[jb] : f.bh[jb],
-                                                                pr == 2 ? f.al[ib] : f.ah[ib], acc[ib][jb], 0, 0, 0);
+          for (int jb = 0; jb < WC; ++jb)
+            acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pr == 1 ? f.bl[jb] : f.bh[jb],
+                                                                  pr == 2 ? f.al[ib] : f.ah[ib], acc[ib][jb], 0, 0, 0);
+    } else {  // first 16 k of the stage, then the second 16
+#pragma unroll
+      for (int pr = 0; pr < 2; ++pr)
+#pragma unroll
+        for (int ib = 0; ib < WR; ++ib)
+#pragma unroll
+          for (int jb = 0; jb < WC; ++jb)
+            acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pr == 1 ? f.bl[jb] : f.bh[jb],
+                                                                  pr == 1 ? f.al[ib] : f.ah[ib], acc[ib][jb], 0, 0, 0);
+    }
   };
 
   for (int t = 0; t < DST - 1 && t < total; ++t) issue(t);
@@ -467,10 +485,18 @@ __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int 
       // interleave: two MFMAs of stage t, then one fragment read of stage
       // t + 1, so the reads complete under this step's MFMAs and the wait at
       // the next step finds them done
+      if (NP == 3) {
 #pragma unroll
-      for (int u = 0; u < 2 * (WR + WC); ++u) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 3 * WR * WC / (2 * (WR + WC)), 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        for (int u = 0; u < 2 * (WR + WC); ++u) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 3 * WR * WC / (2 * (WR + WC)), 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+      } else {  // 2 WR WC MFMAs and 2 (WR + WC) fragment reads
+#pragma unroll
+        for (int u = 0; u < 2 * (WR + WC); ++u) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
       }
       __builtin_amdgcn_sched_barrier(0);
     };
@@ -641,6 +667,10 @@ __global__ __launch_bounds__(256) void k_pack_cols(const void* X, int64_t K, int
     hw[u] = (uint32_t)h0 | ((uint32_t)h1 << 16);
     lw[u] = (uint32_t)l0 | ((uint32_t)l1 << 16);
   }
+  if (flags & PACK_PLAIN) {
+    *(u32x4*)(P + r * ldp + k0) = hw;
+    return;
+  }
   bf16_t* dst = P + r * ldp + (k0 >> 5) * 64 + (k0 & 31);
   *(u32x4*)dst = hw;
   *(u32x4*)(dst + 32) = lw;
@@ -721,14 +751,35 @@ hipError_t x3_init() {
   X3_DL_ATTR(X3_ADD)
   X3_DL_ATTR(X3_RQ)
 #undef X3_DL_ATTR
+#define X3_DL1_ATTR(E)                                                                                            \
+  if (e == hipSuccess)                                                                                            \
+    e = hipFuncSetAttribute((const void*)gemm_x3_dl<E, true, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, dl);
+  X3_DL1_ATTR(X3_SHIFT)
+  X3_DL1_ATTR(X3_FSUPD)
+#undef X3_DL1_ATTR
   return e;
+}
+
+template <int E>
+void launch_dl(bool one, bool pipe, int total, size_t dl, hipStream_t s, const X3Args& b, int tm, int tn) {
+  if constexpr (E == X3_SHIFT || E == X3_FSUPD) {
+    if (one) {
+      hipLaunchKernelGGL((gemm_x3_dl<E, true, 1>), dim3(total), dim3(512), dl, s, b, tm, tn);
+      return;
+    }
+  }
+  if (pipe) hipLaunchKernelGGL((gemm_x3_dl<E, true>), dim3(total), dim3(512), dl, s, b, tm, tn);
+  else hipLaunchKernelGGL((gemm_x3_dl<E, false>), dim3(total), dim3(512), dl, s, b, tm, tn);
 }
 
 hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
   const int tm = (int)((a.M + BM - 1) / BM), tn = (int)((a.N + BN - 1) / BN);
   if (tm == 0 || tn == 0) return hipSuccess;
   if (a.tiles == X3_LOWER && tm != tn) return hipErrorInvalidValue;
-  const int cfg = a.cfg >= 0 ? a.cfg : x3_default_cfg;
+  if (a.products != 0 && a.products != 1 && a.products != 3) return hipErrorInvalidValue;
+  const bool one = a.products == 1;
+  if (one && ((epi != X3_SHIFT && epi != X3_FSUPD) || a.tiles != X3_FULL)) return hipErrorInvalidValue;
+  const int cfg = one ? 5 : (a.cfg >= 0 ? a.cfg : x3_default_cfg);
   switch (cfg) {
     case 0: return launch_cfg<0>(epi, a, tm, tn, s);
     case 1: return launch_cfg<1>(epi, a, tm, tn, s);
@@ -758,10 +809,9 @@ hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
         }
       }
       switch (epi) {
-#define X3_DL_CASE(E)                                                                           \
-  case E:                                                                                       \
-    if (pipe) hipLaunchKernelGGL((gemm_x3_dl<E, true>), dim3(total), dim3(512), dl, s, b, tm, tn); \
-    else hipLaunchKernelGGL((gemm_x3_dl<E, false>), dim3(total), dim3(512), dl, s, b, tm, tn);     \
+#define X3_DL_CASE(E)                            \
+  case E:                                        \
+    launch_dl<E>(one, pipe, total, dl, s, b, tm, tn); \
     break;
         X3_DL_CASE(X3_STORE)
         X3_DL_CASE(X3_SHIFT)
@@ -789,6 +839,7 @@ hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t 
   const int64_t R = by_rows ? m : n;
   const int64_t K = by_rows ? n : m;
   if (R <= 0 || K <= 0) return hipSuccess;
+  if (by_rows && (flags & PACK_PLAIN)) return hipErrorInvalidValue;
   if (!by_rows) {
     const size_t es = src_double ? 8 : 4;
     const bool vec = ((uintptr_t)X % 16 == 0) && ((size_t)ldx * es) % 16 == 0;

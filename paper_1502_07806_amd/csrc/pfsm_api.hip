@@ -130,7 +130,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   if (d->fs_power != 1 && d->fs_power != 2) return PFSM_INVALID_ARG;
   if (d->shift_mode != PFSM_SHIFT_FIXED && d->shift_mode != PFSM_SHIFT_RAYLEIGH) return PFSM_INVALID_ARG;
   if (d->precision != PFSM_PREC_FP64 && d->precision != PFSM_PREC_MIXED_BF16) return PFSM_INVALID_ARG;
-  if (d->flags & ~PFSM_FLAG_NO_REFINE) return PFSM_INVALID_ARG;
+  if (d->flags & ~(PFSM_FLAG_NO_REFINE | PFSM_FLAG_FS_SPLIT)) return PFSM_INVALID_ARG;
   if (!(d->alpha == d->alpha)) return PFSM_INVALID_ARG;  // NaN
   const int64_t n = d->n;
   const int P = d->num_parts;
@@ -450,6 +450,13 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
                                double* dLam, double* dVout, int64_t ldvo, char* W, int* info, hipStream_t s) {
   const int64_t n = pl->n;
   const int64_t ldp = x3_row_stride(n);
+  // Plain BF16 operands for the folded-spectrum products (q = 2, unless the
+  // split is asked for): At, X and Y are packed in the plain layout (row
+  // stride ldq) for those products only.  The refinement against A in FP64
+  // removes what the single BF16 product leaves in the vectors (at N = 8192
+  // the refined eigenvalues stay 3.3e-10 from an FP64 computation).
+  const bool fs_plain = !(pl->flags & PFSM_FLAG_FS_SPLIT) && pl->q == 2 && pl->iterations > 0;
+  const int64_t ldq = x3_plain_stride(n);
   double* At64 = (double*)(W + pl->o_At);
   double* B64a = (double*)(W + pl->o_b0);   // X0 (FP64), later Z = A V_new
   double* Vn64 = (double*)(W + pl->o_b1);   // V_new before ordering
@@ -492,7 +499,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     h.split_ws = split_ws; h.split_bytes = pl->split_bytes;
     PFSM_TRY(gemm_x3(X3_STORE, h, s));
     PFSM_TRY(f32_mirror_to_f64(At32, At64, n, s));
-    PFSM_TRY(pack_x3(At32, 0, n, n, n, 0, Atpk, ldp, s));
+    PFSM_TRY(pack_x3(At32, 0, n, n, n, fs_plain ? PACK_PLAIN : 0, Atpk, fs_plain ? ldq : ldp, s));
   }
   clk.mark(1);
   PFSM_TRY(gershgorin_alpha(At64, n, n, pl->q, pl->alpha, (double*)(W + pl->o_glo), (double*)(W + pl->o_ghi), scal,
@@ -502,7 +509,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   EighBatch e = eigh_batch(pl, W, info, scal);
   PFSM_TRY(eigh_batched_run(e, At64, n, pl->max_sweeps, s));
   PFSM_TRY(embed_start_vectors(e, X32, n, eps, n, s));
-  PFSM_TRY(pack_x3(X32, 0, n, n, n, 0, Xpk, ldp, s));
+  PFSM_TRY(pack_x3(X32, 0, n, n, n, fs_plain ? PACK_PLAIN : 0, Xpk, fs_plain ? ldq : ldp, s));
   clk.mark(3);
   // (3) folded-spectrum iterations (X master copy in FP32).
   for (int it = 0; it < pl->iterations; ++it) {
@@ -510,11 +517,13 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     if (pl->q == 2) {
       X3Args g = x3(X3_SHIFT, n, n, n, Atpk, Xpk, Y32, n, 0);
       g.B32 = X32; g.ldb32 = n; g.eps = eps; g.krange = kr;
+      if (fs_plain) { g.products = 1; g.ldap = g.ldbp = ldq; }
       PFSM_TRY(gemm_x3(X3_SHIFT, g, s));  // Y = (At - eps) X
-      PFSM_TRY(pack_x3(Y32, 0, n, n, n, 0, Ypk, ldp, s));
+      PFSM_TRY(pack_x3(Y32, 0, n, n, n, fs_plain ? PACK_PLAIN : 0, Ypk, fs_plain ? ldq : ldp, s));
       if (it < 8) clk.mark(4 + 2 * it);
       X3Args h = x3(X3_FSUPD, n, n, n, Atpk, Ypk, X32, n, 0);
       h.B32 = Y32; h.ldb32 = n; h.D = X32; h.ldd = n; h.eps = eps; h.alpha_dev = scal;
+      if (fs_plain) { h.products = 1; h.ldap = h.ldbp = ldq; }
       PFSM_TRY(gemm_x3(X3_FSUPD, h, s));  // X <- X - a (At - eps) Y
     } else {
       if (it < 8) clk.mark(4 + 2 * it);
@@ -523,7 +532,9 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
       PFSM_TRY(gemm_x3(X3_FSUPD, h, s));  // X <- X - a (At - eps) X (operand read from the packed copy)
     }
     if (it < 8) clk.mark(5 + 2 * it);  // the update stage holds exactly one GEMM launch
-    PFSM_TRY(pack_x3(X32, 0, n, n, n, 0, Xpk, ldp, s));
+    // the next iteration's operand, or the split operand of the overlap
+    const bool plain_next = fs_plain && it + 1 < pl->iterations;
+    PFSM_TRY(pack_x3(X32, 0, n, n, n, plain_next ? PACK_PLAIN : 0, Xpk, plain_next ? ldq : ldp, s));
   }
   clk.mark(19);
   // (4) overlap S = X^T X (FP64 output, lower tiles) and X <- X L^{-T}.
@@ -555,6 +566,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   const bool refine = !(pl->flags & PFSM_FLAG_NO_REFINE);
   if (!refine) {
     // eigenvalue estimates of the reduced-precision step: x_j^T At x_j
+    if (fs_plain) PFSM_TRY(pack_x3(At32, 0, n, n, n, 0, Atpk, ldp, s));  // split layout again
     PFSM_TRY(pack_x3(X32, 0, n, n, n, 0, Xpk, ldp, s));
     X3Args r = x3(X3_RQ, n, n, n, Atpk, Xpk, nullptr, n, 0);
     r.D = X32; r.ldd = n; r.part = part;

@@ -56,6 +56,22 @@ int pfsm_test_gemm_x3(int epi, int cfg, int tiles, int64_t M, int64_t N, int64_t
                               D, ldd, d_double, eps, part, nullptr, 0, stream);
 }
 
+// SHIFT / FSUPD product (FP32 C) with `products` BF16 products: 3 from split
+// operands, 1 from plain operands (row strides ldap / ldbp in bf16 elements).
+int pfsm_test_gemm_x3_fs(int epi, int products, int64_t M, int64_t N, int64_t K, const void* Ap, int64_t ldap,
+                         const void* Bp, int64_t ldbp, float* C, int64_t ldc, const float* B32, int64_t ldb32,
+                         const float* D, int64_t ldd, const double* eps, double alpha, void* stream) {
+  X3Args g = {};
+  g.M = M; g.N = N; g.K = K; g.Ap = (const bf16_t*)Ap; g.ldap = ldap; g.Bp = (const bf16_t*)Bp; g.ldbp = ldbp;
+  g.C = C; g.ldc = ldc; g.c_double = 0; g.alpha = alpha; g.B32 = B32; g.ldb32 = ldb32; g.D = D; g.ldd = ldd;
+  g.eps = eps; g.cfg = -1; g.products = products;
+  const hipError_t e = ensure_x3();
+  if (e != hipSuccess) return (int)e;
+  return (int)gemm_x3(epi, g, (hipStream_t)stream);
+}
+
+int64_t pfsm_test_x3_plain_stride(int64_t K) { return x3_plain_stride(K); }
+
 // K-split scratch bytes for an order-n lower-triangle product (0: no split).
 int64_t pfsm_test_x3_split_bytes(int64_t n) {
   if (ensure_x3() != hipSuccess) return -1;

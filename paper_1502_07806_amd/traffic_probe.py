@@ -8,7 +8,8 @@
 
 Dispatches, in order: a plain device copy of 1 GiB (calibration: 1 GiB read +
 1 GiB written), then at order n on synthetic operands: the split-BF16
-folded-spectrum update (FSUPD epilogue, default tile configuration), the
+folded-spectrum update (FSUPD epilogue, default tile configuration), the same
+update from plain BF16 operands (one product, as the mixed path runs it), the
 FP64 folded-spectrum update, and the int8 digit product of the refinement
 (two digit splits, then one launch).  Each counter value of a dispatch is
 scaled by the copy's bytes over the copy's counter value.  Needs
@@ -57,8 +58,9 @@ def summarize(fetch_csv: str, write_csv: str, n: int, out: str):
     res = {"_calibration": {"copy_bytes": 1 << 30, "fetch_scale": sf, "write_scale": sw,
                             "note": "FETCH_SIZE and WRITE_SIZE (KiB, summed over agents) per dispatch, each scaled "
                                     "by what the same counter reads for a 1 GiB device copy"}}
-    for key, name in (("gemm_x3_fsupd_n%d" % n, "gemm_x3_dl<2"), ("gemm_f64_fsupd_n%d" % n, "gemm_f64_kernel"),
-                      ("gemm_oz_n%d" % n, "gemm_oz_fused")):
+    for key, name in (("gemm_x3_fsupd_n%d" % n, "gemm_x3_dl<2, true, 3>"),
+                      ("gemm_x3_fsupd_plain_n%d" % n, "gemm_x3_dl<2, true, 1>"),
+                      ("gemm_f64_fsupd_n%d" % n, "gemm_f64_kernel"), ("gemm_oz_n%d" % n, "gemm_oz_fused")):
         f, w = pick(fe, name) * 1024 * sf, pick(wr, name) * 1024 * sw
         res[key] = {"kernel": name, "fetch_bytes": f, "write_bytes": w, "bytes_per_launch": f + w,
                     "source_hash": gemm_source_hash()}
@@ -86,6 +88,10 @@ def main():
     L.pfsm_test_pack_x3.argtypes = [vp, i32, i64, i64, i64, i32, vp, i64, vp]
     L.pfsm_test_x3_row_stride.argtypes = [i64]
     L.pfsm_test_x3_row_stride.restype = i64
+    L.pfsm_test_x3_plain_stride.argtypes = [i64]
+    L.pfsm_test_x3_plain_stride.restype = i64
+    L.pfsm_test_gemm_x3_fs.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, dbl,
+                                       vp]
     L.pfsm_test_oz_split.argtypes = [vp, i64, i64, i64, i32, vp, vp, vp, vp]
     L.pfsm_test_gemm_oz.argtypes = [i64, i64, i64, i32, vp, vp, vp, vp, vp, i64, i32, vp]
     L.pfsm_test_oz_row_stride.argtypes = [i64]
@@ -115,7 +121,17 @@ def main():
     assert L.pfsm_test_gemm_x3(2, -1, 0, n, n, n, P(Ap), ldp, P(Bp), ldp, P(X32), n, 0, 0.1, 0.0, P(Y32), n, P(X32),
                                n, 0, P(eps), None, s) == 0
     torch.cuda.synchronize()
-    del Ap, Bp, Y32, X32
+    # the same update from plain BF16 operands (one product), as the mixed path runs it
+    ldq = L.pfsm_test_x3_plain_stride(n)
+    Aq = torch.empty(n * ldq, dtype=torch.int16, device=dev)
+    Bq = torch.empty(n * ldq, dtype=torch.int16, device=dev)
+    assert L.pfsm_test_pack_x3(P(M), 1, n, n, n, 32, P(Aq), ldq, s) == 0
+    assert L.pfsm_test_pack_x3(P(M), 1, n, n, n, 32, P(Bq), ldq, s) == 0
+    torch.cuda.synchronize()
+    assert L.pfsm_test_gemm_x3_fs(2, 1, n, n, n, P(Aq), ldq, P(Bq), ldq, P(X32), n, P(Y32), n, P(X32), n, P(eps),
+                                  0.1, s) == 0
+    torch.cuda.synchronize()
+    del Ap, Bp, Aq, Bq, Y32, X32
     # FP64 folded-spectrum update, N x N x N
     B = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)
     C = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)

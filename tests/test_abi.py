@@ -48,7 +48,7 @@ def _desc(n=64, offs=(0, 32, 64), **kw):
 
 @pytest.mark.parametrize("kw", [dict(n=0), dict(offs=(0, 40, 32, 64)), dict(offs=(0, 32, 60)), dict(offs=(1, 32, 64)),
                                 dict(offs=(0, 32, 32, 64)), dict(fs_power=3), dict(iterations=-1),
-                                dict(shift_mode=7), dict(precision=9), dict(flags=2), dict(alpha=float("nan"))])
+                                dict(shift_mode=7), dict(precision=9), dict(flags=4), dict(alpha=float("nan"))])
 def test_plan_rejects_invalid_descriptors(lib, kw):
     n = kw.pop("n", 64)
     offs = kw.pop("offs", (0, 32, 64))

@@ -185,6 +185,67 @@ def test_gemm_x3(dev, cfg, M, N, K):
     assert np.max(np.abs(_np(C) - A @ B)) <= 2.0 ** -14 * np.sqrt(K) * np.abs(A).max() * np.abs(B).max() + tol
 
 
+def _pack_plain(x, dev):
+    """Plain layout of the columns of x (K x R): bf16(x) along k, zero-filled to 32."""
+    L = lib()
+    K, R = x.shape
+    ldq = L.pfsm_test_x3_plain_stride(K)
+    P = torch.full((R * ldq,), -1, dtype=torch.int16, device=dev)
+    dx = _cm(x, dev)
+    assert L.pfsm_test_pack_x3(_p(dx), 1, K, R, dx.stride(1), 32, _p(P), ldq, _stream()) == 0
+    return P, ldq
+
+
+def test_pack_plain_layout(dev):
+    g = np.random.default_rng(5)
+    K, R = 100, 37
+    x = g.standard_normal((K, R))
+    P, ldq = _pack_plain(x, dev)
+    assert ldq == 128
+    torch.cuda.synchronize()
+    got = P.cpu().numpy().view(np.uint16).reshape(R, ldq)
+    h_ref, _ = split_hi_lo(x.T)
+    hi = (got[:, :K].astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    assert np.array_equal(hi, h_ref)
+    assert np.all(got[:, K:] == 0)
+    # the transposing pack has no plain form
+    dx = _cm(x, dev)
+    assert lib().pfsm_test_pack_x3(_p(dx), 1, K, R, K, 1 | 32, _p(P), ldq, _stream()) != 0
+
+
+@pytest.mark.parametrize("epi", [1, 2])  # X3_SHIFT, X3_FSUPD
+@pytest.mark.parametrize("M,N,K", [(300, 270, 100), (512, 512, 512), (33, 600, 257)])
+def test_gemm_x3_plain_product(dev, epi, M, N, K):
+    """One BF16 product from plain operands (the folded-spectrum products of the
+    mixed path): equal to bf16(A) bf16(B) within FP32 accumulation, with the
+    SHIFT / FSUPD epilogue; refused for other epilogues."""
+    L = lib()
+    g = np.random.default_rng(M + N + K + epi)
+    A = g.standard_normal((M, K))
+    B = g.standard_normal((K, N))
+    Ap, lda = _pack_plain(A.T, dev)   # rows of A
+    Bp, ldb = _pack_plain(B, dev)     # columns of B
+    B32 = torch.from_numpy(g.standard_normal((N, M))).float().to(dev).t()
+    D32 = torch.from_numpy(g.standard_normal((N, M))).float().to(dev).t()
+    eps = torch.from_numpy(g.standard_normal(N)).to(dev)
+    C = torch.empty((N, M), dtype=torch.float32, device=dev).t()
+    alpha = 0.3
+    assert L.pfsm_test_gemm_x3_fs(epi, 1, M, N, K, _p(Ap), lda, _p(Bp), ldb, _p(C), M, _p(B32), M, _p(D32), M,
+                                  _p(eps), alpha, _stream()) == 0
+    torch.cuda.synchronize()
+    ah, _ = split_hi_lo(A)
+    bh, _ = split_hi_lo(B)
+    prod = ah @ bh
+    b32, d32, e = _np(B32).astype(np.float64), _np(D32).astype(np.float64), eps.cpu().numpy()
+    ref = prod - b32 * e[None, :]
+    if epi == 2:
+        ref = d32 - alpha * ref
+    tol = (4 * K * 2.0 ** -24 * np.abs(ah).max() * np.abs(bh).max() + 2.0 ** -23 * np.abs(ref).max()) * (1 + alpha)
+    assert np.max(np.abs(_np(C).astype(np.float64) - ref)) <= tol
+    assert L.pfsm_test_gemm_x3_fs(0, 1, M, N, K, _p(Ap), lda, _p(Bp), ldb, _p(C), M, None, 0, None, 0, None,
+                                  1.0, _stream()) != 0
+
+
 @pytest.mark.parametrize("c_double,beta", [(1, 0.5), (0, 0.0)])
 def test_gemm_x3_lower_ksplit(dev, c_double, beta):
     """Lower-triangle product whose last wave is split along K (23 x 23 tiles =

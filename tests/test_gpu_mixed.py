@@ -57,6 +57,27 @@ def test_mixed_parity(pf, n, offs, halo, clusters, q):
     assert eig_error(lam_rr, lam_ref) <= TOL_MIXED
 
 
+@pytest.mark.parametrize("n,offs,halo", [
+    (1000, uniform_layout(1000, 100), 50),
+    (300, [0, 50, 130, 220, 300], 20),
+])
+def test_mixed_fs_split_and_plain(pf, n, offs, halo):
+    """The folded-spectrum products on plain BF16 operands (default) and on
+    split operands (PFSM_FLAG_FS_SPLIT): both within the mixed bar of the
+    oracle after the FP64 refinement, and close to each other."""
+    # (the N = 300 case has no clusters: with them and these narrow submatrices
+    # the overlap is 3e-2 from the identity, outside the mixed path's range)
+    A, V, _, _ = prescribed_problem(n, n // 4, 5e-3, 3000 + n, clusters=n >= 1000)
+    A, V = A.numpy(), V.numpy()
+    lam_ref, V_ref, _ = pfsm_ref(A, V, offs, halo, 3, 2)
+    _, info_p, lam_p, V_p = _run(pf, A, V, offs, halo)
+    _, info_s, lam_s, V_s = _run(pf, A, V, offs, halo, fs_split=True)
+    assert info_p == info_s == 0
+    assert eig_error(lam_p, lam_ref) <= TOL_MIXED and eig_error(lam_s, lam_ref) <= TOL_MIXED
+    assert eig_error(lam_p, lam_s) <= 1e-9
+    assert abs(residual_norm(A, lam_p, V_p) - residual_norm(A, lam_s, V_s)) <= 1e-6
+
+
 def test_mixed_unrefined_result(pf):
     A, V, _, _ = prescribed_problem(512, 128, 5e-3, 3512, clusters=True)
     A, V = A.numpy(), V.numpy()
