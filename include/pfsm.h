@@ -104,8 +104,10 @@ typedef struct pfsm_desc {
  * rotated basis) -- the "FP32 result" of the mixed path. */
 #define PFSM_FLAG_NO_REFINE 1
 /* Mixed precision, fs_power 2: run the two products of each folded-spectrum
- * iteration on hi/lo split operands (three BF16 products, FP32 accumulation)
- * instead of the default plain BF16 operands (one product, FP32 accumulation).
+ * iteration, and the small correction product of the orthonormalisation
+ * (X Phi(S - I)^T), on hi/lo split operands (three BF16 products, FP32
+ * accumulation) instead of the default plain BF16 operands (one product, FP32
+ * accumulation).
  * The FP64 refinement against A removes what the plain products leave (at
  * N = 8192 the refined eigenvalues are 3.3e-10 from an FP64 computation either
  * way); the unrefined estimates (PFSM_FLAG_NO_REFINE) are about 4 % closer

@@ -53,8 +53,8 @@ struct X3Args {
   // along K over the whole chip and summed by a second kernel.
   float* split_ws; size_t split_bytes;
   int split_full, split_s;          // set inside gemm_x3
-  // 0 or 3: hi*hi + hi*lo + lo*hi from the split layout; 1 (SHIFT and FSUPD
-  // only): one BF16 product from operands in the plain layout (PACK_PLAIN,
+  // 0 or 3: hi*hi + hi*lo + lo*hi from the split layout; 1 (SHIFT, FSUPD and
+  // ADD, not LOWER tiles): one BF16 product from operands in the plain layout (PACK_PLAIN,
   // ldap / ldbp = their row strides), FP32 accumulation, in the direct-to-LDS
   // configuration whatever cfg says
   int products;
@@ -75,9 +75,9 @@ size_t x3_split_bytes(int64_t n);
 // PACK_SUB_I packs X - I; PACK_LOWER / PACK_UPPER keep only the lower / upper
 // triangle of X (row >= col / row <= col), zeros elsewhere; PACK_HALF_DIAG
 // halves the diagonal (after PACK_SUB_I).
-// PACK_PLAIN (without PACK_BY_ROWS only) writes the plain layout: row r holds
-// bf16(x) for k = 0 .. K-1 contiguously (no lo values), zero-filled to a
-// multiple of 32, row stride at least x3_plain_stride(K).
+// PACK_PLAIN writes the plain layout: row r holds bf16(x) for k = 0 .. K-1
+// contiguously (no lo values), zero-filled to a multiple of 32, row stride at
+// least x3_plain_stride(K).
 enum PackFlags : int { PACK_BY_ROWS = 1, PACK_SUB_I = 2, PACK_LOWER = 4, PACK_UPPER = 8, PACK_HALF_DIAG = 16,
                        PACK_PLAIN = 32 };
 inline int64_t x3_plain_stride(int64_t K) { return 32 * ((K + 31) / 32); }

@@ -602,6 +602,10 @@ __global__ __launch_bounds__(256) void k_pack(const void* X, int src_double, int
       hw[u] = (uint32_t)h0 | ((uint32_t)h1 << 16);
       lw[u] = (uint32_t)l0 | ((uint32_t)l1 << 16);
     }
+    if (flags & PACK_PLAIN) {  // 64-byte aligned: ldp is a multiple of 32
+      *(u32x4*)(P + r * ldp + kc * 32 + 8 * c) = hw;
+      return;
+    }
     bf16_t* dst = P + r * ldp + kc * 64;  // 128-byte aligned: ldp is a multiple of 64
     *(u32x4*)(dst + 8 * c) = hw;
     *(u32x4*)(dst + 32 + 8 * c) = lw;
@@ -756,13 +760,14 @@ hipError_t x3_init() {
     e = hipFuncSetAttribute((const void*)gemm_x3_dl<E, true, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, dl);
   X3_DL1_ATTR(X3_SHIFT)
   X3_DL1_ATTR(X3_FSUPD)
+  X3_DL1_ATTR(X3_ADD)
 #undef X3_DL1_ATTR
   return e;
 }
 
 template <int E>
 void launch_dl(bool one, bool pipe, int total, size_t dl, hipStream_t s, const X3Args& b, int tm, int tn) {
-  if constexpr (E == X3_SHIFT || E == X3_FSUPD) {
+  if constexpr (E == X3_SHIFT || E == X3_FSUPD || E == X3_ADD) {
     if (one) {
       hipLaunchKernelGGL((gemm_x3_dl<E, true, 1>), dim3(total), dim3(512), dl, s, b, tm, tn);
       return;
@@ -778,7 +783,7 @@ hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
   if (a.tiles == X3_LOWER && tm != tn) return hipErrorInvalidValue;
   if (a.products != 0 && a.products != 1 && a.products != 3) return hipErrorInvalidValue;
   const bool one = a.products == 1;
-  if (one && ((epi != X3_SHIFT && epi != X3_FSUPD) || a.tiles != X3_FULL)) return hipErrorInvalidValue;
+  if (one && ((epi != X3_SHIFT && epi != X3_FSUPD && epi != X3_ADD) || a.tiles == X3_LOWER)) return hipErrorInvalidValue;
   const int cfg = one ? 5 : (a.cfg >= 0 ? a.cfg : x3_default_cfg);
   switch (cfg) {
     case 0: return launch_cfg<0>(epi, a, tm, tn, s);
@@ -839,7 +844,6 @@ hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t 
   const int64_t R = by_rows ? m : n;
   const int64_t K = by_rows ? n : m;
   if (R <= 0 || K <= 0) return hipSuccess;
-  if (by_rows && (flags & PACK_PLAIN)) return hipErrorInvalidValue;
   if (!by_rows) {
     const size_t es = src_double ? 8 : 4;
     const bool vec = ((uintptr_t)X % 16 == 0) && ((size_t)ldx * es) % 16 == 0;

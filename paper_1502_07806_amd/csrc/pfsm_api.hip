@@ -552,12 +552,18 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   // terms lie below the rounding of the split-BF16 products themselves, and
   // the FP64 refinement against A sees them only to second order.  The
   // product X Phi(E)^T is upper triangular in its k range (KPREFIX tiles).
+  // Its size is of order |E| (3e-6 at N = 8192), so with the plain
+  // folded-spectrum products it takes plain BF16 operands too: the single
+  // product's rounding, 2^-9 of that, is far below the split products' own.
   PFSM_TRY(lower_minus_identity_check(S64, n, n, rb, info, s));
   {
-    PFSM_TRY(pack_x3(S64, 1, n, n, n, PACK_SUB_I | PACK_LOWER | PACK_HALF_DIAG | PACK_BY_ROWS, Ypk, ldp, s));
-    PFSM_TRY(pack_x3(X32, 0, n, n, n, PACK_BY_ROWS, Rpk, ldp, s));  // rows of X
+    const int pf = fs_plain ? PACK_PLAIN : 0;
+    const int64_t ldc = fs_plain ? ldq : ldp;
+    PFSM_TRY(pack_x3(S64, 1, n, n, n, PACK_SUB_I | PACK_LOWER | PACK_HALF_DIAG | PACK_BY_ROWS | pf, Ypk, ldc, s));
+    PFSM_TRY(pack_x3(X32, 0, n, n, n, PACK_BY_ROWS | pf, Rpk, ldc, s));  // rows of X
     X3Args h = x3(X3_ADD, n, n, n, Rpk, Ypk, X32, n, 0);  // Ypk: columns of Phi(E)^T = rows of Phi(E)
     h.alpha = -1.0; h.D = X32; h.ldd = n; h.d_double = 0; h.tiles = X3_KPREFIX;
+    if (fs_plain) { h.products = 1; h.ldap = h.ldbp = ldq; }
     PFSM_TRY(gemm_x3(X3_ADD, h, s));  // X <- X - X Phi(E)^T (in place: the operand comes from the packed copy)
   }
   clk.mark(21);

@@ -56,12 +56,14 @@ int pfsm_test_gemm_x3(int epi, int cfg, int tiles, int64_t M, int64_t N, int64_t
                               D, ldd, d_double, eps, part, nullptr, 0, stream);
 }
 
-// SHIFT / FSUPD product (FP32 C) with `products` BF16 products: 3 from split
-// operands, 1 from plain operands (row strides ldap / ldbp in bf16 elements).
-int pfsm_test_gemm_x3_fs(int epi, int products, int64_t M, int64_t N, int64_t K, const void* Ap, int64_t ldap,
-                         const void* Bp, int64_t ldbp, float* C, int64_t ldc, const float* B32, int64_t ldb32,
-                         const float* D, int64_t ldd, const double* eps, double alpha, void* stream) {
+// SHIFT / FSUPD / ADD product (FP32 C and D) with `products` BF16 products: 3
+// from split operands, 1 from plain operands (row strides ldap / ldbp in bf16
+// elements); tiles as in X3Args.
+int pfsm_test_gemm_x3_fs(int epi, int products, int tiles, int64_t M, int64_t N, int64_t K, const void* Ap,
+                         int64_t ldap, const void* Bp, int64_t ldbp, float* C, int64_t ldc, const float* B32,
+                         int64_t ldb32, const float* D, int64_t ldd, const double* eps, double alpha, void* stream) {
   X3Args g = {};
+  g.tiles = tiles;
   g.M = M; g.N = N; g.K = K; g.Ap = (const bf16_t*)Ap; g.ldap = ldap; g.Bp = (const bf16_t*)Bp; g.ldbp = ldbp;
   g.C = C; g.ldc = ldc; g.c_double = 0; g.alpha = alpha; g.B32 = B32; g.ldb32 = ldb32; g.D = D; g.ldd = ldd;
   g.eps = eps; g.cfg = -1; g.products = products;

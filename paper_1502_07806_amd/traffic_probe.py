@@ -90,8 +90,8 @@ def main():
     L.pfsm_test_x3_row_stride.restype = i64
     L.pfsm_test_x3_plain_stride.argtypes = [i64]
     L.pfsm_test_x3_plain_stride.restype = i64
-    L.pfsm_test_gemm_x3_fs.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, dbl,
-                                       vp]
+    L.pfsm_test_gemm_x3_fs.argtypes = [i32, i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
+                                       dbl, vp]
     L.pfsm_test_oz_split.argtypes = [vp, i64, i64, i64, i32, vp, vp, vp, vp]
     L.pfsm_test_gemm_oz.argtypes = [i64, i64, i64, i32, vp, vp, vp, vp, vp, i64, i32, vp]
     L.pfsm_test_oz_row_stride.argtypes = [i64]
@@ -128,7 +128,7 @@ def main():
     assert L.pfsm_test_pack_x3(P(M), 1, n, n, n, 32, P(Aq), ldq, s) == 0
     assert L.pfsm_test_pack_x3(P(M), 1, n, n, n, 32, P(Bq), ldq, s) == 0
     torch.cuda.synchronize()
-    assert L.pfsm_test_gemm_x3_fs(2, 1, n, n, n, P(Aq), ldq, P(Bq), ldq, P(X32), n, P(Y32), n, P(X32), n, P(eps),
+    assert L.pfsm_test_gemm_x3_fs(2, 1, 0, n, n, n, P(Aq), ldq, P(Bq), ldq, P(X32), n, P(Y32), n, P(X32), n, P(eps),
                                   0.1, s) == 0
     torch.cuda.synchronize()
     del Ap, Bp, Aq, Bq, Y32, X32

@@ -27,8 +27,8 @@ def lib():
         L.pfsm_test_gemm_x3_ws.argtypes = [i32, i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, dbl, dbl, vp,
                                            i64, vp, i64, i32, vp, vp, vp, ctypes.c_size_t, vp]
         L.pfsm_test_gemm_x3_ws.restype = i32
-        L.pfsm_test_gemm_x3_fs.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
-                                           vp, dbl, vp]
+        L.pfsm_test_gemm_x3_fs.argtypes = [i32, i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
+                                           i64, vp, dbl, vp]
         L.pfsm_test_gemm_x3_fs.restype = i32
         L.pfsm_test_x3_plain_stride.argtypes = [i64]
         L.pfsm_test_x3_plain_stride.restype = i64

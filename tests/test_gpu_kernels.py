@@ -208,9 +208,16 @@ def test_pack_plain_layout(dev):
     hi = (got[:, :K].astype(np.uint32) << 16).view(np.float32).astype(np.float64)
     assert np.array_equal(hi, h_ref)
     assert np.all(got[:, K:] == 0)
-    # the transposing pack has no plain form
+    # the transposing pack in the plain layout: rows of x (K rows of length R)
+    ldr = lib().pfsm_test_x3_plain_stride(R)
+    Q = torch.full((K * ldr,), -1, dtype=torch.int16, device=dev)
     dx = _cm(x, dev)
-    assert lib().pfsm_test_pack_x3(_p(dx), 1, K, R, K, 1 | 32, _p(P), ldq, _stream()) != 0
+    assert lib().pfsm_test_pack_x3(_p(dx), 1, K, R, K, 1 | 32, _p(Q), ldr, _stream()) == 0
+    torch.cuda.synchronize()
+    got = Q.cpu().numpy().view(np.uint16).reshape(K, ldr)
+    h_ref, _ = split_hi_lo(x)
+    assert np.array_equal((got[:, :R].astype(np.uint32) << 16).view(np.float32).astype(np.float64), h_ref)
+    assert np.all(got[:, R:] == 0)
 
 
 @pytest.mark.parametrize("epi", [1, 2])  # X3_SHIFT, X3_FSUPD
@@ -230,7 +237,7 @@ def test_gemm_x3_plain_product(dev, epi, M, N, K):
     eps = torch.from_numpy(g.standard_normal(N)).to(dev)
     C = torch.empty((N, M), dtype=torch.float32, device=dev).t()
     alpha = 0.3
-    assert L.pfsm_test_gemm_x3_fs(epi, 1, M, N, K, _p(Ap), lda, _p(Bp), ldb, _p(C), M, _p(B32), M, _p(D32), M,
+    assert L.pfsm_test_gemm_x3_fs(epi, 1, 0, M, N, K, _p(Ap), lda, _p(Bp), ldb, _p(C), M, _p(B32), M, _p(D32), M,
                                   _p(eps), alpha, _stream()) == 0
     torch.cuda.synchronize()
     ah, _ = split_hi_lo(A)
@@ -242,8 +249,42 @@ def test_gemm_x3_plain_product(dev, epi, M, N, K):
         ref = d32 - alpha * ref
     tol = (4 * K * 2.0 ** -24 * np.abs(ah).max() * np.abs(bh).max() + 2.0 ** -23 * np.abs(ref).max()) * (1 + alpha)
     assert np.max(np.abs(_np(C).astype(np.float64) - ref)) <= tol
-    assert L.pfsm_test_gemm_x3_fs(0, 1, M, N, K, _p(Ap), lda, _p(Bp), ldb, _p(C), M, None, 0, None, 0, None,
+    assert L.pfsm_test_gemm_x3_fs(0, 1, 0, M, N, K, _p(Ap), lda, _p(Bp), ldb, _p(C), M, None, 0, None, 0, None,
                                   1.0, _stream()) != 0
+    assert L.pfsm_test_gemm_x3_fs(epi, 1, 1, M, N, K, _p(Ap), lda, _p(Bp), ldb, _p(C), M, _p(B32), M, _p(D32), M,
+                                  _p(eps), alpha, _stream()) != 0  # no lower-triangle tiles
+
+
+@pytest.mark.parametrize("n", [600, 512])
+def test_gemm_x3_plain_correction(dev, n):
+    """The orthonormalisation correction X <- X - X Phi^T of the mixed path from
+    plain operands packed by rows (transposing pack), k-prefix tiles: equal to
+    D - bf16(X) bf16(Phi)^T within FP32 accumulation for a lower-triangular Phi."""
+    L = lib()
+    g = np.random.default_rng(n)
+    X = g.standard_normal((n, n))
+    Phi = np.tril(g.standard_normal((n, n))) * 1e-3
+    ldq = L.pfsm_test_x3_plain_stride(n)
+    dX, dPhi = _cm(X, dev), _cm(Phi, dev)
+    Xp = torch.full((n * ldq,), -1, dtype=torch.int16, device=dev)
+    Pp = torch.full((n * ldq,), -1, dtype=torch.int16, device=dev)
+    assert L.pfsm_test_pack_x3(_p(dX), 1, n, n, n, 1 | 32, _p(Xp), ldq, _stream()) == 0    # rows of X
+    assert L.pfsm_test_pack_x3(_p(dPhi), 1, n, n, n, 1 | 32, _p(Pp), ldq, _stream()) == 0  # rows of Phi
+    torch.cuda.synchronize()
+    rows = Xp.cpu().numpy().view(np.uint16).reshape(n, ldq)
+    h_ref, _ = split_hi_lo(X)
+    assert np.array_equal((rows[:, :n].astype(np.uint32) << 16).view(np.float32).astype(np.float64), h_ref)
+    assert np.all(rows[:, n:] == 0)
+    D = torch.from_numpy(g.standard_normal((n, n))).float().to(dev).t().contiguous().t()
+    C = torch.empty((n, n), dtype=torch.float32, device=dev).t()
+    assert L.pfsm_test_gemm_x3_fs(3, 1, 3, n, n, n, _p(Xp), ldq, _p(Pp), ldq, _p(C), n, None, 0, _p(D), n, None,
+                                  -1.0, _stream()) == 0
+    torch.cuda.synchronize()
+    xh, _ = split_hi_lo(X)
+    ph, _ = split_hi_lo(Phi)
+    ref = _np(D).astype(np.float64) - xh @ ph.T
+    tol = 4 * n * 2.0 ** -24 * np.abs(xh).max() * np.abs(ph).max() + 2.0 ** -23 * np.abs(ref).max()
+    assert np.max(np.abs(_np(C).astype(np.float64) - ref)) <= tol
 
 
 @pytest.mark.parametrize("c_double,beta", [(1, 0.5), (0, 0.0)])
