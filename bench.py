@@ -398,8 +398,8 @@ def main():
         acc["residual"] = r
         acc["orthogonality"] = o
         st = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
-        ms_graph = time_graph(plan, lam, Vo)
-        return plan, ms, st, acc, ms_graph
+        ms_graph, spread = time_graph(plan, lam, Vo)
+        return plan, ms, st, acc, ms_graph, spread
 
     def time_graph(plan, lam, Vo):
         """The same step captured once into a HIP graph and replayed K times
@@ -415,22 +415,29 @@ def main():
         torch.cuda.current_stream().wait_stream(cs)
         g.replay()
         torch.cuda.synchronize()
+        # events between the replays give the per-step spread (median, IQR)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        ev[0].record()
+        for k in range(args.steps):
             g.replay()
+            ev[k + 1].record()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         plan.check()
         if not (torch.equal(lam_g, lam) and torch.equal(Vo_g, Vo)):
             raise RuntimeError("graph replay differs from the eager step")
         del g
-        return (t1 - t0) * 1e3 / args.steps
+        per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+        spread = {"median_ms": float(np.median(per)),
+                  "iqr_ms": float(np.percentile(per, 75) - np.percentile(per, 25))}
+        return (t1 - t0) * 1e3 / args.steps, spread
 
     precision = args.precision
     if precision == "auto":
         precision = "mixed_bf16"
     F = algorithmic_flops(n, M, q, n_it)
-    plan, ms_eager, st, acc, ms = run(precision)
+    plan, ms_eager, st, acc, ms, spread = run(precision)
     upd_ms = float(np.mean([st["fs_update_%d" % i] for i in range(n_it)]))
     if precision == "fp64":
         dom_flops, peak, unit_dtype = 2.0 * n ** 3, PEAK_TFLOPS["fp64"], "f64"
@@ -455,6 +462,7 @@ def main():
         "timing": "the step captured once into a HIP graph and replayed K times (every replay equal to the "
                   "eager step bit for bit); eager_ms_per_step launches the same kernels one by one",
         "eager_ms_per_step": ms_eager,
+        "step_ms_median_iqr": spread,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -487,15 +495,16 @@ def main():
             "fp64_equivalent_tflops": 2.0 * n ** 3 / (oz_ms * 1e-3) / 1e12}
     del plan
     if precision != "fp64" and not args.no_fp64_compare:
-        p64, ms64_eager, st64, acc64, ms64 = run("fp64")
+        p64, ms64_eager, st64, acc64, ms64, spread64 = run("fp64")
         upd64 = float(np.mean([st64["fs_update_%d" % i] for i in range(n_it)]))
         out["fp64_path"] = {"solves_per_s": 1e3 / ms64, "ms_per_step": ms64, "eager_ms_per_step": ms64_eager,
+                            "step_ms_median_iqr": spread64,
                             "tflops": F / (ms64 * 1e-3) / 1e12,
                             "accuracy": acc64, "speedup_of_mixed": ms64 / ms,
                             "fs_update_gemm_tflops": 2.0 * n ** 3 / (upd64 * 1e-3) / 1e12,
                             "stages_ms": {k: round(v, 4) for k, v in st64.items() if v > 0.01}}
         del p64
-        pnr, msnr_eager, stnr, accnr, msnr = run(precision, refine=False)
+        pnr, msnr_eager, stnr, accnr, msnr, _ = run(precision, refine=False)
         out["fp32_result"] = {"note": "mixed path without the FP64 refinement against A", "ms_per_step": msnr,
                               "accuracy": accnr}
         del pnr
