@@ -98,7 +98,16 @@ def cpu_baseline(n_full: int, sample_n: int = 4096):
         pr.jacobi_eigh = orig
     r = n_full / sample_n
     est = spent["eigh"] * r + (total - spent["eigh"]) * r ** 3
-    threads = max([x.get("num_threads", 1) for x in threadpool_info() if x.get("user_api") == "blas"] or [1])
+    blas = [x for x in threadpool_info() if x.get("user_api") == "blas"]
+    threads = max([x.get("num_threads", 1) for x in blas] or [1])
+    cpu_model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            names = [ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")]
+        if names:
+            cpu_model = names[0]
+    except OSError:
+        pass
     return {
         "value": 1.0 / est,
         "unit": "solves/s",
@@ -107,8 +116,8 @@ def cpu_baseline(n_full: int, sample_n: int = 4096):
         "sample": ("one N=%d instance of the same recipe (P=%d, M=512, 3 iterations) took %.2f s "
                    "(submatrix Jacobi %.2f s); scaled to N=%d by x%d (Jacobi, slice count) and x%d (rest, N^3); "
                    "host %s, %d cores visible" % (sample_n, len(offs) - 1, total, spent["eigh"], n_full, r, r ** 3,
-                                                  platform.processor() or platform.machine(),
-                                                  len(os.sched_getaffinity(0)))),
+                                                  cpu_model, len(os.sched_getaffinity(0)))),
+        "blas": ", ".join(sorted({"%s %s" % (x.get("internal_api", "?"), x.get("version", "")) for x in blas})),
     }
 
 
