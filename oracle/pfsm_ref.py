@@ -97,6 +97,31 @@ def sign_normalize(X: np.ndarray) -> np.ndarray:
     return X * sgn[None, :]
 
 
+def fs_iterate(At: np.ndarray, X: np.ndarray, eps: np.ndarray, alpha: float, iterations: int,
+               fs_power: int = 2, shift_mode: str = "fixed") -> np.ndarray:
+    """Folded-spectrum iterations x <- x - alpha (At - eps I)^q x on every column
+    (Eq. 11 for q = 2, applied as two shifted products; q = 1 is the
+    one-product variant).  shift_mode "fixed" keeps each column's shift (the
+    submatrix eigenvalue, Methodology); "rayleigh" replaces it before every
+    iteration by the column's Rayleigh quotient x^T At x / x^T x."""
+    X = np.array(X, dtype=np.float64, copy=True)
+    eps = np.array(eps, dtype=np.float64, copy=True)
+    for _ in range(iterations):
+        if shift_mode == "rayleigh":
+            eps = np.sum(X * (At @ X), axis=0) / np.sum(X * X, axis=0)
+        elif shift_mode != "fixed":
+            raise ValueError("shift_mode must be 'fixed' or 'rayleigh'")
+        if fs_power == 2:
+            Y1 = At @ X - X * eps[None, :]
+            Y2 = At @ Y1 - Y1 * eps[None, :]
+            X = X - alpha * Y2
+        elif fs_power == 1:
+            X = X - alpha * (At @ X - X * eps[None, :])
+        else:
+            raise ValueError("fs_power must be 1 or 2")
+    return X
+
+
 def pfsm_ref(A: np.ndarray, V: np.ndarray, part_offsets: Sequence[int], halo: Optional[int] = None,
              iterations: int = 3, fs_power: int = 2, alpha: Optional[float] = None,
              shift_mode: str = "fixed", details: bool = False):
@@ -153,17 +178,7 @@ def pfsm_ref(A: np.ndarray, V: np.ndarray, part_offsets: Sequence[int], halo: Op
     det["eps"] = eps.copy()
 
     # O5: folded-spectrum iterations, each column with its own shift.
-    for _ in range(iterations):
-        if shift_mode == "rayleigh":
-            eps = np.sum(X * (At @ X), axis=0) / np.sum(X * X, axis=0)
-        if fs_power == 2:
-            Y1 = At @ X - X * eps[None, :]
-            Y2 = At @ Y1 - Y1 * eps[None, :]
-            X = X - alpha_v * Y2
-        elif fs_power == 1:
-            X = X - alpha_v * (At @ X - X * eps[None, :])
-        else:
-            raise ValueError("fs_power must be 1 or 2")
+    X = fs_iterate(At, X, eps, alpha_v, iterations, fs_power, shift_mode)
     det["X_fs"] = X.copy()
 
     # O6: Gram-Schmidt in column order, computed as Cholesky-QR: X <- X L^{-T}.

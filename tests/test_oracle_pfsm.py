@@ -12,8 +12,10 @@ import pytest
 import scipy.linalg
 
 from oracle.jacobi import jacobi_eigh
-from oracle.pfsm_ref import (clusters, eig_error, gershgorin_alpha, max_subspace_angle, orthogonality,
-                             pfsm_ref, residual_norm, window_layout)
+from fractions import Fraction
+
+from oracle.pfsm_ref import (clusters, eig_error, fs_iterate, gershgorin_alpha, max_subspace_angle, orthogonality,
+                             pfsm_ref, residual_norm, sign_normalize, window_layout)
 from pfsm_workloads import antisym_k, householder_q, prescribed_problem, spectrum, uniform_layout
 
 
@@ -70,8 +72,10 @@ def test_unperturbed_basis_is_exact(c1):
     A, V, lam, Q = c1
     lam_p, Vn, info, det = pfsm_ref(A, Q, uniform_layout(256, 64), 32, details=True)
     assert info == 0 and eig_error(lam_p, lam) <= 1e-14
-    # every output vector is +-(a column of Q)
-    assert np.abs(np.abs(np.sum(Vn * Q, axis=0)) - 1.0).max() <= 1e-13
+    # every output vector is a column of Q with its sign: in the rotated basis the
+    # vectors are unit vectors e_j (up to rounding), whose largest entry the sign
+    # convention makes positive, so V_new = Q X = Q without any sign flip
+    assert np.abs(np.sum(Vn * Q, axis=0) - 1.0).max() <= 1e-13
 
 
 def test_block_diagonal_operator_is_exact():
@@ -146,6 +150,71 @@ def test_rayleigh_shift_mode_runs(c1):
     A, V, lam, Q = c1
     lam_p, Vn, info = pfsm_ref(A, V, uniform_layout(256, 64), 32, shift_mode="rayleigh")
     assert info == 0 and eig_error(lam_p, lam) < 1e-6
+
+
+def _fs_exact(w, x0, alpha, iterations, q, rayleigh):
+    """Folded-spectrum iterations on a diagonal operator diag(w) in exact rational
+    arithmetic: component k of x is multiplied by 1 - alpha (w_k - eps)^q, the
+    shift being the Rayleigh quotient sum w_k x_k^2 / sum x_k^2 of the current
+    vector (refreshed shift) or the given one (fixed shift)."""
+    x = [Fraction(v) for v in x0]
+    eps = Fraction(rayleigh[1]) if not rayleigh[0] else None
+    for _ in range(iterations):
+        if rayleigh[0]:
+            eps = sum(wk * xk * xk for wk, xk in zip(w, x)) / sum(xk * xk for xk in x)
+        x = [(1 - alpha * (wk - eps) ** q) * xk for wk, xk in zip(w, x)]
+    return [float(v) for v in x]
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_rayleigh_shift_hand_case(q):
+    # At = diag(0, 1, 3), x0 = (1, 1, 1): the refreshed shift of the first
+    # iteration is 4/3; alpha = 1/10.  After one q = 2 iteration the vector is
+    # (74, 89, 65)/90 and the next shift 20596/17622.
+    w = [Fraction(0), Fraction(1), Fraction(3)]
+    alpha = Fraction(1, 10)
+    At = np.diag([0.0, 1.0, 3.0])
+    x0 = np.ones((3, 1))
+    X1 = fs_iterate(At, x0, np.array([0.5]), 0.1, 1, q, "rayleigh")  # the given shift is replaced
+    if q == 2:
+        assert np.allclose(X1[:, 0], [74 / 90, 89 / 90, 65 / 90], rtol=0, atol=1e-15)
+    for it in (1, 2, 4):
+        X = fs_iterate(At, x0, np.array([0.5]), 0.1, it, q, "rayleigh")
+        ref = _fs_exact(w, [1, 1, 1], alpha, it, q, (True, None))
+        assert np.abs(X[:, 0] - ref).max() <= 1e-14
+        # the fixed shift keeps 0.5 for every iteration
+        Xf = fs_iterate(At, x0, np.array([0.5]), 0.1, it, q, "fixed")
+        assert np.abs(Xf[:, 0] - _fs_exact(w, [1, 1, 1], alpha, it, q, (False, Fraction(1, 2)))).max() <= 1e-14
+        assert np.abs(Xf - X).max() > 1e-3  # the two shift rules differ on this vector
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_rayleigh_shift_closed_form(c1, q):
+    A, V, lam, Q = c1
+    nit = 3
+    _, _, _, det = pfsm_ref(A, V, uniform_layout(256, 64), 32, iterations=nit, fs_power=q, shift_mode="rayleigh",
+                            details=True)
+    At, X0, alpha = det["At"], det["X0"], det["alpha"]
+    w, U = np.linalg.eigh(At)
+    # in At's eigenbasis the Rayleigh quotient of a column c is sum w_k c_k^2 / sum c_k^2, and the
+    # iteration scales component k by 1 - alpha (w_k - eps)^q
+    C = U.T @ X0
+    for _ in range(nit):
+        eps = np.sum(w[:, None] * C * C, axis=0) / np.sum(C * C, axis=0)
+        C = (1.0 - alpha * (w[:, None] - eps[None, :]) ** q) * C
+    assert np.abs(det["X_fs"] - U @ C).max() <= 1e-12
+
+
+def test_sign_convention_hand_built_columns():
+    # largest |entry| positive; among equal magnitudes the lowest row decides
+    X = np.array([[1.0, -3.0, 2.0, -2.0, 0.0, 0.0],
+                  [-2.0, 1.0, -2.0, 2.0, 0.0, 0.0],
+                  [0.5, 2.0, 1.0, 0.0, -1e-300, 0.0]])
+    Y = sign_normalize(X)
+    assert np.array_equal(Y, X * np.array([-1.0, -1.0, 1.0, -1.0, -1.0, 1.0])[None, :])
+    # idempotent, and a column and its negative map to the same column
+    assert np.array_equal(sign_normalize(Y), Y)
+    assert np.array_equal(sign_normalize(-X), Y)
 
 
 def test_uneven_slices(c1):
