@@ -62,23 +62,23 @@ def load_traffic(kernel_key: str):
         return None
 
 
-def cpu_baseline(n_full: int, sample_n: int = 4096):
-    """Time the FP64 CPU oracle on a bounded sample of the same recipe and scale it to N = n_full.
+def _host_cpu_model() -> str:
+    cpu_model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            names = [ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")]
+        if names:
+            cpu_model = names[0]
+    except OSError:
+        pass
+    return cpu_model
 
-    The sample is one N = sample_n instance (same spectrum recipe, slices of 256, halo 128).
-    Stage times scale separately: the submatrix eigensolver by the slice count (n_full/sample_n),
-    everything else (dense O(N^3) products and the Cholesky) by (n_full/sample_n)^3."""
-    import torch
-    from threadpoolctl import threadpool_info
-    from oracle.pfsm_ref import pfsm_ref
+
+def _timed_oracle(A, V, offs, halo):
+    """One run of the FP64 oracle; returns (seconds, seconds inside its submatrix Jacobi solves, info)."""
     from oracle import jacobi as oj
-    from pfsm_workloads import prescribed_problem, uniform_layout
-
+    from oracle.pfsm_ref import pfsm_ref
     import oracle.pfsm_ref  # noqa: F401  (registers the submodule)
-    A, V, _, _ = prescribed_problem(sample_n, sample_n // 4, 5e-3, 3000, clusters=True)
-    A, V = A.numpy(), V.numpy()
-    offs = uniform_layout(sample_n, 256)
-    # time the submatrix eigensolver part separately by wrapping the oracle's Jacobi
     spent = {"eigh": 0.0}
     orig = oj.jacobi_eigh
 
@@ -92,31 +92,42 @@ def cpu_baseline(n_full: int, sample_n: int = 4096):
     pr.jacobi_eigh = timed
     try:
         t0 = time.perf_counter()
-        pfsm_ref(A, V, offs, 128, 3, 2)
+        info = pfsm_ref(A, V, offs, halo, 3, 2)[2]
         total = time.perf_counter() - t0
     finally:
         pr.jacobi_eigh = orig
-    r = n_full / sample_n
-    est = spent["eigh"] * r + (total - spent["eigh"]) * r ** 3
+    return total, spent["eigh"], info
+
+
+def cpu_baseline(A_dev, V_dev, n: int, slice_size: int, halo: int, small_n: int = 2048):
+    """The FP64 CPU oracle timed on the host cores: once on the benchmark's own N = n
+    input (the same matrices as the GPU step, all BLAS threads), and once on an
+    N = small_n instance of the same recipe with one BLAS thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from pfsm_workloads import prescribed_problem, uniform_layout
+
+    A, V = A_dev.cpu().numpy(), V_dev.cpu().numpy()
+    print("cpu baseline: FP64 oracle at N=%d (all BLAS threads)" % n, flush=True)
+    total, eigh, info = _timed_oracle(A, V, uniform_layout(n, slice_size), halo)
+    assert info == 0
+    print("cpu baseline: %.1f s; FP64 oracle at N=%d, one thread" % (total, small_n), flush=True)
+    As, Vs, _, _ = prescribed_problem(small_n, small_n // 4, 5e-3, 3000, clusters=True)
+    with threadpool_limits(limits=1, user_api="blas"):
+        total1, eigh1, _ = _timed_oracle(As.numpy(), Vs.numpy(), uniform_layout(small_n, slice_size), halo)
+    print("cpu baseline: %.1f s" % total1, flush=True)
     blas = [x for x in threadpool_info() if x.get("user_api") == "blas"]
     threads = max([x.get("num_threads", 1) for x in blas] or [1])
-    cpu_model = platform.processor() or platform.machine()
-    try:
-        with open("/proc/cpuinfo") as fh:
-            names = [ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")]
-        if names:
-            cpu_model = names[0]
-    except OSError:
-        pass
     return {
-        "value": 1.0 / est,
+        "value": 1.0 / total,
         "unit": "solves/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": ("one N=%d instance of the same recipe (P=%d, M=512, 3 iterations) took %.2f s "
-                   "(submatrix Jacobi %.2f s); scaled to N=%d by x%d (Jacobi, slice count) and x%d (rest, N^3); "
-                   "host %s, %d cores visible" % (sample_n, len(offs) - 1, total, spent["eigh"], n_full, r, r ** 3,
-                                                  cpu_model, len(os.sched_getaffinity(0)))),
+        "sample": ("measured at N=%d on the benchmark's own input (P=%d, M=%d, 3 iterations), no scaling: "
+                   "%.2f s (submatrix Jacobi %.2f s), %d BLAS threads; host %s, %d cores visible"
+                   % (n, n // slice_size, slice_size + 2 * halo, total, eigh, threads, _host_cpu_model(),
+                      len(os.sched_getaffinity(0)))),
+        "single_thread_small": {"n": small_n, "seconds": total1, "submatrix_jacobi_s": eigh1,
+                                "solves_per_s": 1.0 / total1, "blas_threads": 1},
         "blas": ", ".join(sorted({"%s %s" % (x.get("internal_api", "?"), x.get("version", "")) for x in blas})),
     }
 
@@ -380,6 +391,33 @@ def main():
     gp = os.path.join(ROOT, "tests", "golden", "c3_n8192_oracle_lambda.txt")
     if n == 8192 and os.path.exists(gp):
         golden = np.loadtxt(gp)
+    gv = None
+    gvc = os.path.join(ROOT, "tests", "golden", "c3_n8192_oracle_vec_cols.txt")
+    gvv = os.path.join(ROOT, "tests", "golden", "c3_n8192_oracle_vectors.npy")
+    if n == 8192 and os.path.exists(gvc) and os.path.exists(gvv):
+        gv = (np.loadtxt(gvc), np.load(gvv).T)
+
+    def vec_err(Vo):
+        """Eigenvector error against the oracle's stored columns: sin of the angle for 8
+        well separated eigenvalues (sign included) and for one 3-fold cluster (subspace),
+        and the largest sin * gap / ||A||_2 (the Davis-Kahan-normalised error)."""
+        rows, Vref = gv
+        cols = rows[:, 0].astype(np.int64)
+        Vg = Vo[:, torch.from_numpy(cols).to(Vo.device)].cpu().numpy()
+        a2 = np.max(np.abs(golden))
+        worst, worst_dk = 0.0, 0.0
+        for grp in np.unique(rows[:, 1]):
+            sel = np.flatnonzero(rows[:, 1] == grp)
+            for j in (sel if grp < 0 else [sel]):
+                j = np.atleast_1d(j)
+                if grp < 0:
+                    e = float(np.linalg.norm(Vg[:, j[0]] - Vref[:, j[0]])) / np.sqrt(2.0)
+                else:
+                    Q1, Q2 = Vg[:, j], Vref[:, j]
+                    e = float(np.linalg.norm(Q1 - Q2 @ (Q2.T @ Q1), 2))
+                worst = max(worst, e)
+                worst_dk = max(worst_dk, e * rows[j[0], 2] / a2)
+        return {"max_sin": worst, "max_sin_gap_over_norm": worst_dk, "columns": int(len(cols))}
 
     def run(precision, refine=True):
         plan = pf.Plan(n, offs, halo=halo, iterations=n_it, fs_power=q, precision=precision, refine=refine)
@@ -403,6 +441,8 @@ def main():
         acc = {"eig_err_vs_prescribed": float(np.max(np.abs(lam_np - lam_ex)) / scale)}
         if golden is not None:
             acc["eig_err_vs_oracle"] = float(np.max(np.abs(lam_np - golden)) / np.max(np.abs(golden)))
+        if gv is not None:
+            acc["vec_err_vs_oracle"] = vec_err(Vo)
         r, o = plan.diagnostics(A, lam, Vo)
         acc["residual"] = r
         acc["orthogonality"] = o
@@ -528,7 +568,7 @@ def main():
         out["backward"] = bench_backward(args)
         out["scf_sequence"] = bench_scf_sequence(args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n)
+        out["cpu_baseline"] = cpu_baseline(A, V, n, m, halo)
     print(json.dumps(out), flush=True)
 
 

@@ -32,16 +32,10 @@
  * only.  Conditions found on the device are written to *dInfo (int32, device
  * memory, cleared by the call itself):
  *      0  success
- *    k>0  FP64 path: the overlap matrix is not positive definite at column k
- *         (the start vectors do not span: a randomly mixed, non-diagonally-
- *         dominant input as the Methodology section warns, or duplicated
- *         previous vectors)
+ *    k>0  the overlap matrix is not positive definite at column k (the start
+ *         vectors do not span: a randomly mixed, non-diagonally-dominant input
+ *         as the Methodology section warns, or duplicated previous vectors)
  *     -1  a non-finite eigenvalue (non-finite input propagates to it)
- *     -2  mixed precision: the overlap matrix is too far from the identity for
- *         the first-order orthonormalisation X <- X - X Phi(S - I)^T
- *         (max |S - I| > 1e-3): the start vectors are far from orthogonal,
- *         outside the diagonally dominant regime (this also covers what the
- *         FP64 path reports as k>0)
  *     -3  a submatrix eigensolver did not converge within its sweep limit
  *     -4  an output vector lost its length (squared norm outside [1/4, 4] before
  *         normalisation): V_prev does not have orthonormal columns
@@ -74,8 +68,11 @@ typedef enum pfsm_precision {
                                overlap and back-rotation with every operand split into hi + lo
                                BF16 parts (three products), the folded-spectrum products on plain
                                BF16 operands (one product; see PFSM_FLAG_FS_SPLIT); FP64 for the
-                               submatrix eigensolver, the Cholesky of the overlap and the final
-                               Rayleigh quotients / cluster Rayleigh-Ritz against A */
+                               submatrix eigensolver and the final Rayleigh quotients / cluster
+                               Rayleigh-Ritz against A (from an FP64-accurate int8 digit product).
+                               Orthonormalisation: to first order in S - I while max |S - I| <=
+                               1e-3 (a correction product on the matrix cores), otherwise the FP64
+                               Cholesky-QR of the overlap, chosen on the device */
 } pfsm_precision;
 
 typedef enum pfsm_shift_mode {

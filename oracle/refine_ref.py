@@ -9,6 +9,18 @@ re-evaluated against A in FP64.
   order the estimates; runs of neighbours with gaps <= tau max|lambda| form
   clusters; each cluster's estimates are replaced by the Ritz pairs of the
   pencil (V_c^T Z_c, V_c^T V_c); isolated vectors are normalised.
+
+Readings (the refinement is not in the paper; these choices define it):
+  * tau = 1e-4: estimates closer than this (relative to max|lambda|) may have
+    been mixed by the reduced-precision products, whose eigenvector error
+    grows like (product error) / gap; wider clusters cost more Rayleigh-Ritz
+    work without changing the eigenvalues at the 1e-8 level;
+  * kmax = 32: a run longer than kmax is refined in consecutive pieces of at
+    most kmax estimates (the Rayleigh-Ritz block size; vectors inside one
+    piece are mixed freely, across pieces they are not);
+  * each Ritz vector's sign makes its largest-magnitude coefficient on the
+    piece's input vectors positive (lowest index on ties), so the output does
+    not depend on the signs an eigensolver happens to return.
 """
 from __future__ import annotations
 
@@ -45,6 +57,8 @@ def refine_ref(A: np.ndarray, V: np.ndarray, tau: float = 1e-4, kmax: int = 32):
             G = 0.5 * (G + G.T)
             M = Vc.T @ Vc
             mu, Y = scipy.linalg.eigh(G, M)
+            big = np.argmax(np.abs(Y), axis=0)  # first maximum: lowest index
+            Y = Y * np.where(Y[big, np.arange(Y.shape[1])] < 0.0, -1.0, 1.0)[None, :]
             out_l[p0:p1] = mu
             out_V[:, p0:p1] = Vc @ Y
     return out_l, out_V

@@ -24,7 +24,6 @@ LIB_PATH = os.path.join(_HERE, "libpfsm.so")
 PFSM_PREC = {"fp64": 0, "mixed_bf16": 1}
 PFSM_SHIFT = {"fixed": 0, "rayleigh": 1}
 INFO_TEXT = {0: "ok", -1: "non-finite eigenvalue",
-             -2: "overlap factor too far from the identity for the mixed-precision orthonormalisation",
              -3: "submatrix eigensolver did not converge",
              -4: "an output vector lost its length: V_prev is not orthonormal",
              -5: "a diagonal entry of B is not a positive finite number"}

@@ -53,6 +53,7 @@ struct pfsm_plan {
   size_t m_At32, m_X32, m_Y32, m_S64, m_Apk, m_Vpk, m_Atpk, m_Xpk, m_Ypk, m_Rpk, m_rb;
   size_t m_oz;  // digit planes of A and V_new for the refinement product, then 2n exponents
   size_t m_split = 0, split_bytes = 0;  // K-split scratch of the lower-triangle split-BF16 products
+  size_t m_gate = 0, m_bcopy = 0;  // orthonormalisation: fallback gate word, Cholesky block copies
 };
 
 namespace {
@@ -282,6 +283,8 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     // and At (3 * 4 n ceil32(n) bytes), so they get a region of their own.
     const size_t oz = align256(2 * oz_plane_bytes(n, n, REFINE_OZ_SLICES)) + 2 * n * sizeof(int);
     pl->m_oz = w; w = align256(w + oz);
+    pl->m_gate = w; w = align256(w + sizeof(int));
+    pl->m_bcopy = w; w = align256(w + (size_t)((n + CHOL_NB - 1) / CHOL_NB) * CHOL_NB * CHOL_NB * sizeof(double));
   }
   pl->total = w;
   *out = pl;
@@ -443,9 +446,13 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
 }
 
 
-// Mixed precision: every large product on BF16 matrix cores with hi/lo split
-// operands (FP32 accumulation); FP64 submatrix eigensolver, FP64 Cholesky of
-// the overlap, FP64 Rayleigh quotients and cluster Rayleigh-Ritz against A.
+// Mixed precision: the large products on BF16 matrix cores with FP32
+// accumulation (basis change, overlap and back-rotation on hi/lo split
+// operands, the folded-spectrum products on plain operands unless
+// PFSM_FLAG_FS_SPLIT); FP64 submatrix eigensolver; orthonormalisation to first
+// order in S - I, or the FP64 Cholesky-QR of the overlap when S is farther
+// from the identity; FP64 Rayleigh quotients and cluster Rayleigh-Ritz against
+// A from an FP64-accurate product on the int8 matrix cores.
 static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv,
                                double* dLam, double* dVout, int64_t ldvo, char* W, int* info, hipStream_t s) {
   const int64_t n = pl->n;
@@ -546,16 +553,24 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   }
   clk.mark(20);
   // X <- X L^{-T} with S = L L^T.  S is the identity up to the folded-spectrum
-  // residual E = S - I (max |E| <= 1e-3 checked, info = -2 above that), so
-  // L = I + Phi(E) + O(|E|^2) (Phi: strictly lower part plus half the
-  // diagonal) and L^{-T} = I - Phi(E)^T + O(|E|^2).  For such E the dropped
-  // terms lie below the rounding of the split-BF16 products themselves, and
-  // the FP64 refinement against A sees them only to second order.  The
-  // product X Phi(E)^T is upper triangular in its k range (KPREFIX tiles).
-  // Its size is of order |E| (3e-6 at N = 8192), so with the plain
-  // folded-spectrum products it takes plain BF16 operands too: the single
-  // product's rounding, 2^-9 of that, is far below the split products' own.
-  PFSM_TRY(lower_minus_identity_check(S64, n, n, rb, info, s));
+  // residual E = S - I, so L = I + Phi(E) + O(|E|^2) (Phi: strictly lower part
+  // plus half the diagonal) and L^{-T} = I - Phi(E)^T + O(|E|^2).  While
+  // max |E| <= 1e-3 the dropped terms lie below the rounding of the split-BF16
+  // products themselves, and the FP64 refinement against A sees them only to
+  // second order: that first-order step is the fast path.  The product
+  // X Phi(E)^T is upper triangular in its k range (KPREFIX tiles).  Its size
+  // is of order |E| (3e-6 at N = 8192), so with the plain folded-spectrum
+  // products it takes plain BF16 operands too: the single product's rounding,
+  // 2^-9 of that, is far below the split products' own.
+  // When max |E| > 1e-3 (start vectors far from orthogonal) a device gate
+  // switches on the FP64 Cholesky-QR of S: an FP64 copy of X taken before the
+  // first-order step is factored with S (one launch per 64-wide block column,
+  // every launch returning at once when the gate is off, so the launch
+  // sequence does not depend on the data) and replaces X.
+  int* gate = (int*)(W + pl->m_gate);
+  double* X64 = B64a;  // free until the refinement product
+  PFSM_TRY(lower_minus_identity_check(S64, n, n, ORTHO_FIRST_ORDER_MAX, rb, gate, s));
+  PFSM_TRY(convert_f32_f64_gated(X32, n, X64, n, n, n, 1, gate, s));
   {
     const int pf = fs_plain ? PACK_PLAIN : 0;
     const int64_t ldc = fs_plain ? ldq : ldp;
@@ -566,6 +581,8 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     if (fs_plain) { h.products = 1; h.ldap = h.ldbp = ldq; }
     PFSM_TRY(gemm_x3(X3_ADD, h, s));  // X <- X - X Phi(E)^T (in place: the operand comes from the packed copy)
   }
+  PFSM_TRY(cholesky_qr_gated(S64, n, X64, n, n, n, (double*)(W + pl->o_T), (double*)(W + pl->m_bcopy), info, gate, s));
+  PFSM_TRY(convert_f32_f64_gated(X32, n, X64, n, n, n, 0, gate, s));
   clk.mark(21);
   // (5) sign convention; V_new = V + V (X - I) (FP64 output).
   PFSM_TRY(col_sign_f32(X32, n, n, (double*)(W + pl->o_sgn), s));

@@ -3,7 +3,10 @@
 namespace pfsm {
 constexpr int REFINE_KMAX = 32;         // largest cluster handled by one Rayleigh-Ritz block
 constexpr double REFINE_TAU = 1e-4;     // relative gap below which neighbours are refined together
-constexpr int PFSM_INFO_SERIES = -2;    // orthonormalisation series outside its range (mixed path)
+// Largest |S - I| (overlap of the folded-spectrum vectors) for which the
+// mixed path keeps the first-order orthonormalisation; above it the FP64
+// Cholesky-QR of the overlap runs instead.
+constexpr double ORTHO_FIRST_ORDER_MAX = 1e-3;
 // Digits per operand of the refinement product Z = A V_new on the int8 matrix
 // cores (error about 2^-42 sqrt(n) of the row and column maxima).
 constexpr int REFINE_OZ_SLICES = 6;
@@ -28,9 +31,10 @@ hipError_t refine_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz,
 
 // Mixed-path helpers.
 hipError_t f32_mirror_to_f64(float* At32, double* At64, int64_t n, hipStream_t s);   // lower -> both, FP64 copy
-// D = -U + U2 (upper triangle, zero below), U = (L - I)^T from the lower factor L.
-hipError_t lower_minus_identity_check(const double* L, int64_t ldl, int64_t n, double* scratch, int* info,
-                                      hipStream_t s);
+// *gate = 1 when max |L - I| over the lower triangle exceeds limit (or is not
+// a number), else 0; scratch: n doubles.
+hipError_t lower_minus_identity_check(const double* L, int64_t ldl, int64_t n, double limit, double* scratch,
+                                      int* gate, hipStream_t s);
 hipError_t col_sign_f32(float* X, int64_t n, int64_t ldx, double* sgn, hipStream_t s);  // flips in place
 hipError_t permute_f64_cols(const double* X, int64_t ldx, const int* rank, double* Y, int64_t ldy, int64_t m,
                             int64_t n, hipStream_t s);

@@ -345,6 +345,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         for (int t = i + 1; t < k; ++t) v -= Mm[t][i] * Y[t][b];
         Y[i][b] = v / Mm[i][i];
       }
+      // sign of the Ritz vector: its largest-magnitude coefficient on the
+      // cluster's input vectors (lowest index on ties) is positive
+      double big = -1.0, sg = 1.0;
+      for (int i = 0; i < k; ++i) {
+        const double a = fabs(Y[i][b]);
+        if (a > big) {
+          big = a;
+          sg = Y[i][b] < 0.0 ? -1.0 : 1.0;
+        }
+      }
+      for (int i = 0; i < k; ++i) Y[i][b] *= sg;
     }
     __syncthreads();
     // Ritz values ascending: the rank of each diagonal entry of G (distinct
@@ -471,7 +482,7 @@ __global__ __launch_bounds__(NT) void k_lmi_col(const double* L, int64_t ldl, in
   }
   if (threadIdx.x == 0) out[j] = sh[0];
 }
-__global__ __launch_bounds__(NT) void k_lmi_final(const double* col, int64_t n, double limit, int* info) {
+__global__ __launch_bounds__(NT) void k_lmi_final(const double* col, int64_t n, double limit, int* gate) {
   __shared__ double sh[NT];
   double m = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += NT) {
@@ -487,7 +498,7 @@ __global__ __launch_bounds__(NT) void k_lmi_final(const double* col, int64_t n, 
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && !(sh[0] <= limit)) atomicCAS(info, 0, PFSM_INFO_SERIES);
+  if (threadIdx.x == 0) *gate = (sh[0] <= limit) ? 0 : 1;  // NaN: 1
 }
 
 __global__ __launch_bounds__(NT) void k_col_sign_f32(float* X, int64_t n, int64_t ldx, double* sgn) {
@@ -553,10 +564,10 @@ hipError_t f32_mirror_to_f64(float* At32, double* At64, int64_t n, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t lower_minus_identity_check(const double* L, int64_t ldl, int64_t n, double* scratch, int* info,
-                                      hipStream_t s) {
+hipError_t lower_minus_identity_check(const double* L, int64_t ldl, int64_t n, double limit, double* scratch,
+                                      int* gate, hipStream_t s) {
   hipLaunchKernelGGL(k_lmi_col, dim3((unsigned)n), dim3(NT), 0, s, L, ldl, n, scratch);
-  hipLaunchKernelGGL(k_lmi_final, dim3(1), dim3(NT), 0, s, scratch, n, 1e-3, info);
+  hipLaunchKernelGGL(k_lmi_final, dim3(1), dim3(NT), 0, s, scratch, n, limit, gate);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include "../gemm_x3.h"
 #include "../chol.h"
 #include "../gemm_oz.h"
+#include "../refine.h"
 
 using namespace pfsm;
 
@@ -91,6 +92,15 @@ int pfsm_test_trsm(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t
   return (int)trsm_right_lt(L, ldl, X, ldx, n, m, Tbuf, (hipStream_t)stream);
 }
 
+int pfsm_test_cholesky_qr_gated(double* S, int64_t lds, double* X, int64_t ldx, int64_t n, int64_t m, double* Tbuf,
+                                double* Bcopy, int* info, const int* gate, void* stream) {
+  return (int)cholesky_qr_gated(S, lds, X, ldx, n, m, Tbuf, Bcopy, info, gate, (hipStream_t)stream);
+}
+
+int pfsm_test_convert_gated(void* X32, int64_t ld32, double* X64, int64_t ld64, int64_t m, int64_t n, int to_f64,
+                            const int* gate, void* stream) {
+  return (int)convert_f32_f64_gated((const float*)X32, ld32, X64, ld64, m, n, to_f64, gate, (hipStream_t)stream);
+}
 
 int pfsm_test_oz_split(const double* X, int64_t ldx, int64_t K, int64_t ncols, int s, void* P, int* expo, int* info,
                        void* stream) {
@@ -109,5 +119,37 @@ int pfsm_test_gemm_oz(int64_t M, int64_t N, int64_t K, int s, const void* Ap, co
 }
 
 int64_t pfsm_test_oz_row_stride(int64_t K) { return oz_row_stride(K); }
+
+int64_t pfsm_test_oz_plane_bytes(int64_t n, int s) { return (int64_t)oz_plane_bytes(n, n, s); }
+int pfsm_test_refine_slices() { return REFINE_OZ_SLICES; }
+double pfsm_test_refine_tau() { return REFINE_TAU; }
+int pfsm_test_refine_kmax() { return REFINE_KMAX; }
+
+// The mixed path's refinement on given FP64 estimates V (n x n, ldv): digits
+// of A and V, Z = A V on the int8 matrix cores, then refine_rr.  planes:
+// 2 * pfsm_test_oz_plane_bytes(n, s) bytes; expo: 2n ints; Z: n x n doubles
+// (ld n); rb: 7n + 8 doubles.
+int pfsm_test_refine(int64_t n, const double* A, int64_t lda, const double* V, int64_t ldv, void* planes, int* expo,
+                     double* Z, double* rb, double* lam, double* Vout, int64_t ldvo, int* info, void* stream) {
+  static bool init = false;
+  if (!init) {
+    const hipError_t e = oz_init();
+    if (e != hipSuccess) return (int)e;
+    init = true;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int s = REFINE_OZ_SLICES;
+  int8_t* pA = (int8_t*)planes;
+  int8_t* pV = pA + oz_plane_bytes(n, n, s);
+  hipError_t e = oz_split(A, lda, n, n, s, pA, expo, info, st);
+  if (e == hipSuccess) e = oz_split(V, ldv, n, n, s, pV, expo + n, info, st);
+  if (e == hipSuccess) e = gemm_oz(n, n, n, s, pA, expo, pV, expo + n, Z, n, st);
+  if (e != hipSuccess) return (int)e;
+  RefineBufs b;
+  b.d = rb; b.nn = rb + n; b.lam_s = rb + 2 * n;
+  b.rank = (int*)(rb + 3 * n); b.inv = (int*)(rb + 4 * n); b.cstart = (int*)(rb + 5 * n);
+  b.csize = (int*)(rb + 6 * n); b.clus = (int*)(rb + 7 * n);
+  return (int)refine_rr(V, ldv, Z, n, n, REFINE_TAU, lam, Vout, ldvo, b, info, st);
+}
 
 }  // extern "C"

@@ -196,3 +196,4 @@ def overlap_matrix(n: int, delta: float, seed: int, device="cpu") -> torch.Tenso
     B = 0.5 * (B + B.T)
     B.diagonal().add_(1.0)
     return B
+

@@ -40,12 +40,26 @@ def lib():
         L.pfsm_test_cholesky.restype = i32
         L.pfsm_test_trsm.argtypes = [vp, i64, vp, i64, i64, i64, vp, vp]
         L.pfsm_test_trsm.restype = i32
+        L.pfsm_test_cholesky_qr_gated.argtypes = [vp, i64, vp, i64, i64, i64, vp, vp, vp, vp, vp]
+        L.pfsm_test_cholesky_qr_gated.restype = i32
+        L.pfsm_test_convert_gated.argtypes = [vp, i64, vp, i64, i64, i64, i32, vp, vp]
+        L.pfsm_test_convert_gated.restype = i32
         L.pfsm_test_oz_split.argtypes = [vp, i64, i64, i64, i32, vp, vp, vp, vp]
         L.pfsm_test_oz_split.restype = i32
         L.pfsm_test_gemm_oz.argtypes = [i64, i64, i64, i32, vp, vp, vp, vp, vp, i64, i32, vp]
         L.pfsm_test_gemm_oz.restype = i32
         L.pfsm_test_oz_row_stride.argtypes = [i64]
         L.pfsm_test_oz_row_stride.restype = i64
+        L.pfsm_test_oz_plane_bytes.argtypes = [i64, i32]
+        L.pfsm_test_oz_plane_bytes.restype = i64
+        L.pfsm_test_refine_slices.argtypes = []
+        L.pfsm_test_refine_slices.restype = i32
+        L.pfsm_test_refine_tau.argtypes = []
+        L.pfsm_test_refine_tau.restype = dbl
+        L.pfsm_test_refine_kmax.argtypes = []
+        L.pfsm_test_refine_kmax.restype = i32
+        L.pfsm_test_refine.argtypes = [i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp, i64, vp, vp]
+        L.pfsm_test_refine.restype = i32
         _lib = L
     return _lib
 

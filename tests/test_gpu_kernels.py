@@ -354,6 +354,58 @@ def test_cholesky_blocked_vs_oracle(dev, n):
     assert np.max(np.abs(_np(X) - ref)) <= 1e-10 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("n,m", [(64, 64), (200, 200), (300, 150), (1100, 1100)])
+def test_cholesky_qr_gated_vs_oracle(dev, n, m):
+    """Fallback orthonormalisation of the mixed path: one launch per 64-wide block
+    column factors [S; X] left-looking, giving L in place of S and X L^{-T} in
+    place of X.  Against the oracle's column Cholesky and a solve with its
+    factor, on ragged sizes; with the gate off nothing is written."""
+    from oracle.pfsm_ref import cholesky_lower
+    S0 = _spd(n, n)
+    X0 = np.random.default_rng(n + 7).standard_normal((m, n))
+    L_ref, info_ref = cholesky_lower(S0)
+    assert info_ref == 0
+    ref = np.linalg.solve(L_ref, X0.T).T
+    nblk = (n + 63) // 64
+    for g in (0, 1):
+        S = _cm(S0, dev)
+        X = _cm(X0, dev)
+        T = torch.zeros(nblk * 4096, dtype=torch.float64, device=dev)
+        Bc = torch.zeros(nblk * 4096, dtype=torch.float64, device=dev)
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+        gate = torch.tensor([g], dtype=torch.int32, device=dev)
+        assert lib().pfsm_test_cholesky_qr_gated(_p(S), n, _p(X), m, n, m, _p(T), _p(Bc), _p(info), _p(gate),
+                                                 _stream()) == 0
+        torch.cuda.synchronize()
+        if g == 0:
+            assert np.array_equal(_np(S), S0) and np.array_equal(_np(X), X0)
+            continue
+        assert int(info.item()) == 0
+        L = np.tril(_np(S))
+        assert np.max(np.abs(L - L_ref)) <= 64 * n * U64 * np.abs(L_ref).max()
+        assert np.max(np.abs(_np(X) - ref)) <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,k", [(200, 0), (200, 130), (1100, 777)])
+def test_cholesky_qr_gated_breakdown(dev, n, k):
+    """The fallback reports a non-positive pivot at global column k as info = k + 1."""
+    from oracle.pfsm_ref import cholesky_lower
+    S0 = np.eye(n)
+    S0[k, k] = -1.0
+    S0[min(k + 5, n - 1), min(k + 5, n - 1)] = -2.0
+    nblk = (n + 63) // 64
+    S = _cm(S0, dev)
+    X = _cm(np.eye(n), dev)
+    T = torch.zeros(nblk * 4096, dtype=torch.float64, device=dev)
+    Bc = torch.zeros(nblk * 4096, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    gate = torch.ones(1, dtype=torch.int32, device=dev)
+    assert lib().pfsm_test_cholesky_qr_gated(_p(S), n, _p(X), n, n, n, _p(T), _p(Bc), _p(info), _p(gate),
+                                             _stream()) == 0
+    torch.cuda.synchronize()
+    assert int(info.item()) == cholesky_lower(S0)[1] == k + 1
+
+
 @pytest.mark.parametrize("n,k", [(200, 0), (200, 130), (1100, 777)])
 def test_cholesky_breakdown_column(dev, n, k):
     """A non-positive pivot at global column k reports info = k + 1 (first one wins)."""
