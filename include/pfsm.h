@@ -137,6 +137,29 @@ pfsm_status pfsm_solve(pfsm_plan* plan, const double* dA, int64_t lda, const dou
                        double* dLambda, double* dVout, int64_t ldvo, void* dWork, size_t work_bytes,
                        int32_t* dInfo, void* stream);
 
+/* Bytes of the library-owned device workspace behind pfsm_solve_static
+ * (64 MiB; every GPU the library runs on holds one copy until the process
+ * ends). */
+#define PFSM_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* pfsm_solve without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The workspace is a
+ * fixed device array of PFSM_STATIC_SCRATCH_BYTES owned by the library, one
+ * per device; its address is looked up once per device (at the first plan
+ * creation or static solve on it).  Arguments, layout and device info codes
+ * as pfsm_solve; the outputs must not overlap the inputs.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents (the solve clears what it needs itself): calls that overlap
+ * in time on one device -- on different streams or from different threads --
+ * race and must be serialised by the caller.
+ * Errors: WORKSPACE_TOO_SMALL when pfsm_workspace_size(plan) exceeds
+ * PFSM_STATIC_SCRATCH_BYTES (nothing is enqueued; e.g. FP64 plans up to
+ * n ~ 1400, mixed-precision plans up to n ~ 800), INVALID_ARG (batched plan,
+ * as pfsm_solve), HIP_ERROR. */
+pfsm_status pfsm_solve_static(pfsm_plan* plan, const double* dA, int64_t lda, const double* dVprev, int64_t ldv,
+                              double* dLambda, double* dVout, int64_t ldvo, int32_t* dInfo, void* stream);
+
 /* Reverse-mode gradient of a symmetric eigendecomposition A = V diag(lambda) V^T
  * (eigen-adjoint: dA = sym(V (diag(gLambda) + F o (V^T gV)) V^T), F_ij =
  * d/(d^2 + eta^2), d = lambda_j - lambda_i, F_ii = 0; the Lorentzian keeps an

@@ -62,6 +62,8 @@ def load_library(path: str = LIB_PATH):
     vp, i64, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
     lib.pfsm_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PfsmDesc)]
     lib.pfsm_plan_create.restype = ctypes.c_int
+    lib.pfsm_solve_static.argtypes = [vp, vp, i64, vp, i64, vp, vp, i64, vp, vp]
+    lib.pfsm_solve_static.restype = ctypes.c_int
     lib.pfsm_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
     lib.pfsm_workspace_size.restype = ctypes.c_int
     lib.pfsm_solve.argtypes = [vp, vp, i64, vp, i64, vp, vp, i64, vp, sz, vp, vp]
@@ -180,6 +182,31 @@ class Plan:
         _check(load_library().pfsm_solve(self._h, Ac.data_ptr(), lda, Vc.data_ptr(), ldv, lam.data_ptr(),
                                           Vout.data_ptr(), Vout.stride(1), work.data_ptr(), self.workspace_bytes,
                                           self._info.data_ptr(), _stream_handle()))
+        if check:
+            self.check()
+        return lam, Vout
+
+    def solve_static(self, A: torch.Tensor, V_prev: torch.Tensor,
+                     out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, check: bool = True):
+        """solve() through pfsm_solve_static: the library's own device workspace
+        (PFSM_STATIC_SCRATCH_BYTES), no allocation inside the call."""
+        n = self.n
+        if A.shape != (n, n) or V_prev.shape != (n, n):
+            raise ValueError("A and V_prev must be %d x %d" % (n, n))
+        Ac, lda = _colmajor(A)
+        Vc, ldv = _colmajor(V_prev)
+        if self._info is None or self._info.device != A.device:
+            self._info = torch.zeros(1, dtype=torch.int32, device=A.device)
+        if out is None:
+            lam = torch.empty(n, dtype=torch.float64, device=A.device)
+            Vout = torch.empty((n, n), dtype=torch.float64, device=A.device).t()
+        else:
+            lam, Vout = out
+        if Vout.stride(0) != 1:
+            raise ValueError("out V must be column-major (stride(0) == 1)")
+        _check(load_library().pfsm_solve_static(self._h, Ac.data_ptr(), lda, Vc.data_ptr(), ldv, lam.data_ptr(),
+                                                 Vout.data_ptr(), Vout.stride(1), self._info.data_ptr(),
+                                                 _stream_handle()))
         if check:
             self.check()
         return lam, Vout

@@ -11,10 +11,17 @@
 #include "g2s.h"
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
 using namespace pfsm;
+
+// Workspace of pfsm_solve_static: one copy per device, held until the process
+// ends.  Host code never passes this name to a kernel (on the host it is only
+// a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[PFSM_STATIC_SCRATCH_BYTES];
 
 struct pfsm_plan {
   int64_t n = 0;
@@ -67,6 +74,28 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
 }
 
 pfsm_status hip_status(hipError_t e) { return e == hipSuccess ? PFSM_OK : PFSM_HIP_ERROR; }
+
+// Device address of `scratch` on the current device, looked up once per
+// device (at the first plan creation or static solve there) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 // Records the boundary event k of the current timed solve (no-op when timing is off).
 struct StageClock {
@@ -211,8 +240,9 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   size_t o_ps = tb; tb = align256(tb + P * sizeof(int64_t));
   size_t o_kr = tb; tb = align256(tb + pl->krange.size() * sizeof(int32_t));
   size_t o_k3 = tb; tb = align256(tb + pl->krange_x3.size() * sizeof(int32_t));
+  void* sp = nullptr;
   if (hipGetDevice(&pl->device) != hipSuccess || x3_init() != hipSuccess || oz_init() != hipSuccess ||
-      hipMalloc(&pl->dtab, tb) != hipSuccess) {
+      scratch_address(&sp) != hipSuccess || hipMalloc(&pl->dtab, tb) != hipSuccess) {
     delete pl;
     return PFSM_HIP_ERROR;
   }
@@ -314,6 +344,17 @@ void pfsm_plan_destroy(pfsm_plan* pl) {
 
 static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv,
                                double* dLam, double* dVout, int64_t ldvo, char* W, int* info, hipStream_t s);
+
+pfsm_status pfsm_solve_static(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv,
+                              double* dLam, double* dVout, int64_t ldvo, int32_t* dInfo, void* stream) {
+  if (!pl || !pl->sub.empty()) return PFSM_INVALID_ARG;
+  if (pl->total > (size_t)PFSM_STATIC_SCRATCH_BYTES) return PFSM_WORKSPACE_TOO_SMALL;
+  void* work = nullptr;
+  if (scratch_address(&work) != hipSuccess) return PFSM_HIP_ERROR;
+  // pfsm_solve clears what it needs cleared (the info word) with kernels and
+  // allocates nothing; the scratch keeps the previous call's contents.
+  return pfsm_solve(pl, dA, lda, dV, ldv, dLam, dVout, ldvo, work, PFSM_STATIC_SCRATCH_BYTES, dInfo, stream);
+}
 
 pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv, double* dLam,
                        double* dVout, int64_t ldvo, void* dWork, size_t work_bytes, int32_t* dInfo, void* stream) {
