@@ -561,14 +561,17 @@ def main():
         out["generalized_to_standard"] = bench_g2s(n, args)
     if not args.no_wide:
         out["paper_width_submatrices"] = bench_wide(n, offs, A, V, lam_ex, n_it, q, args)
+    host_inputs = None
+    if not args.no_cpu_baseline:
+        host_inputs = (A.cpu(), V.cpu())
     if not args.no_extra:
         del A, V
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(args)
         out["backward"] = bench_backward(args)
         out["scf_sequence"] = bench_scf_sequence(args)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, V, n, m, halo)
+    if host_inputs is not None:
+        out["cpu_baseline"] = cpu_baseline(host_inputs[0], host_inputs[1], n, m, halo)
     print(json.dumps(out), flush=True)
 
 
