@@ -54,7 +54,7 @@ def load_traffic(kernel_key: str):
     try:
         d = json.load(open(p))
         e = d.get(kernel_key)
-        from paper_1502_07806_amd.traffic_probe import gemm_source_hash
+        from traffic_probe import gemm_source_hash
         if not e or e.get("source_hash") != gemm_source_hash():
             return None
         return float(e["bytes_per_launch"])
@@ -228,11 +228,24 @@ def bench_batched(args, count: int = 64):
         raise RuntimeError("batched graph replay differs from the eager call")
     F = sum(algorithmic_flops(nb, min(nb, cfg.slice_size + 2 * cfg.halo), 2, cfg.iterations) for nb in ns)
     err = max(float(np.max(np.abs(l.cpu().numpy() - e)) / np.max(np.abs(e))) for l, e in zip(lams, lex))
+    # against the oracle: the first instance of every order (stored by tests/golden/make_golden.py)
+    err_o = None
+    gp = os.path.join(ROOT, "tests", "golden", "c4_batch_oracle_lambda.txt")
+    if count == 64 and os.path.exists(gp):
+        err_o = {}
+        for line in open(gp):
+            if line.startswith("#"):
+                continue
+            f = line.split()
+            b, nb, ref = int(f[0]), int(f[1]), np.array([float(x) for x in f[2:]])
+            assert ns[b] == nb and len(ref) == nb
+            err_o[str(nb)] = float(np.max(np.abs(lams[b].cpu().numpy() - ref)) / np.max(np.abs(ref)))
     out = {"workload": "%d instances, N_b in {384..2048} (sum %d), slices of %d, submatrix order %d, %d FS "
                        "iterations, mixed precision; one graph replay per batch" %
                        (count, sum(ns), cfg.slice_size, cfg.slice_size + 2 * cfg.halo, cfg.iterations),
            "ms_per_batch": ms, "instances_per_s": count * 1e3 / ms, "tflops": F / (ms * 1e-3) / 1e12,
-           "eig_err_vs_prescribed_max": err}
+           "eig_err_vs_prescribed_max": err,
+           "eig_err_vs_oracle_by_order": err_o}
     del bp, As, Vs, lams, Vouts
     torch.cuda.empty_cache()
     return out
@@ -530,16 +543,18 @@ def main():
     }
     if precision != "fp64":
         # The dominant kernel of the mixed step is the FP64-accurate refinement
-        # product Z = A V_new (21 int8 digit products of 2N^3 ops, one launch);
-        # the folded-spectrum update is reported beside it.
+        # product Z = A V_new (s (s + 1) / 2 int8 digit products of 2N^3 ops, one
+        # launch); the folded-spectrum update is reported beside it.
         oz_ms = st["refine_product"]
-        oz_ops = 21 * 2.0 * n ** 3
+        s_dig = int(pf.load_library().pfsm_refine_digit_count())
+        pairs = s_dig * (s_dig + 1) // 2
+        oz_ops = pairs * 2.0 * n ** 3
         out["roofline_fs_update"] = out["roofline"]
         out["roofline"] = {
             "bound": "mfma", "achieved": oz_ops / (oz_ms * 1e-3) / 1e12, "peak": PEAK_TOPS_INT8, "unit": "TOP/s",
             "frac": oz_ops / (oz_ms * 1e-3) / 1e12 / PEAK_TOPS_INT8, "traffic": load_traffic("gemm_oz_n%d" % n),
-            "kernel": "gemm_oz_fused (Z = A V_new from six 7-bit digits per operand, 21 int8 products, "
-                      "exact int32 accumulation, FP64 sum)",
+            "kernel": "gemm_oz_fused (Z = A V_new from %d 7-bit digits per operand, %d int8 products, "
+                      "exact int32 accumulation, FP64 sum)" % (s_dig, pairs),
             "launch_ms": oz_ms, "ops_per_launch": oz_ops,
             "fp64_equivalent_tflops": 2.0 * n ** 3 / (oz_ms * 1e-3) / 1e12}
     del plan

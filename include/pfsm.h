@@ -190,9 +190,13 @@ pfsm_status pfsm_plan_create_batched(pfsm_plan** plan, const pfsm_desc* descs, i
  * The instances are enqueued largest first over internal streams forked from
  * and joined back into `stream` with events, so the call is capturable: a
  * hipStreamBeginCapture / EndCapture around it yields one graph whose
- * branches run the instances concurrently.  Errors: INVALID_ARG (non-batched
- * plan, null pointer, bad leading dimension; nothing is enqueued),
- * WORKSPACE_TOO_SMALL, HIP_ERROR. */
+ * branches run the instances concurrently.  Every instance is checked as
+ * pfsm_solve checks it, and the outputs of one instance must not overlap the
+ * inputs or outputs of another, the info array or the workspace; any such
+ * error returns before anything is enqueued.  Errors: INVALID_ARG
+ * (non-batched plan, null pointer, bad leading dimension, overlap),
+ * WORKSPACE_TOO_SMALL, HIP_ERROR (a failed launch: the internal streams are
+ * still joined back into `stream`). */
 pfsm_status pfsm_solve_batched(pfsm_plan* plan, const double* const* dA, const int64_t* lda,
                                const double* const* dVprev, const int64_t* ldv, double* const* dLambda,
                                double* const* dVout, const int64_t* ldvo, void* dWork, size_t work_bytes,
@@ -200,6 +204,12 @@ pfsm_status pfsm_solve_batched(pfsm_plan* plan, const double* const* dA, const i
 
 /* Number of instances of a batched plan (0 for a single plan or NULL). */
 int32_t pfsm_batch_count(const pfsm_plan* plan);
+
+/* Mixed precision: signed 7-bit digits per operand row in the FP64-accurate
+ * refinement product Z = A V_new on the int8 matrix cores (s; the product
+ * sums the s (s + 1) / 2 digit products of weight up to s + 1, error about
+ * (s + 1) 2^-7s sqrt(n) times the row and column maxima per entry). */
+int32_t pfsm_refine_digit_count(void);
 
 /* Tile autotuning of the split-BF16 products (mixed precision): times each
  * tile configuration on an N x N x N product in the plan's workspace (on

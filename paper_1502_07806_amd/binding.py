@@ -64,6 +64,8 @@ def load_library(path: str = LIB_PATH):
     lib.pfsm_plan_create.restype = ctypes.c_int
     lib.pfsm_solve_static.argtypes = [vp, vp, i64, vp, i64, vp, vp, i64, vp, vp]
     lib.pfsm_solve_static.restype = ctypes.c_int
+    lib.pfsm_refine_digit_count.argtypes = []
+    lib.pfsm_refine_digit_count.restype = i32
     lib.pfsm_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
     lib.pfsm_workspace_size.restype = ctypes.c_int
     lib.pfsm_solve.argtypes = [vp, vp, i64, vp, i64, vp, vp, i64, vp, sz, vp, vp]

@@ -12,8 +12,8 @@
 //     C(i, j) = 2^(e_i + f_j) * sum_{g = 2}^{s + 1} 2^(-12 - 7 (g - 2)) * sum_{p + q = g} (D_p E_q^T)(i, j).
 // The dropped groups (p + q > s + 1) and the digit remainders (below
 // 2^(-7 s) relative to the row maximum) bound the error by about
-// s K 2^(-7 s) 2^(e_i + f_j), and by sqrt(K) in place of K for entries of
-// random sign (s = 6: 2^-42 per unit of K).
+// (s + 1) K 2^(-7 s) 2^(e_i + f_j), and by sqrt(K) in place of K for entries of
+// random sign (s = 5: 6 * 2^-35 per unit of K).
 #include "common.h"
 
 namespace pfsm {

@@ -356,8 +356,12 @@ pfsm_status pfsm_solve_static(pfsm_plan* pl, const double* dA, int64_t lda, cons
   return pfsm_solve(pl, dA, lda, dV, ldv, dLam, dVout, ldvo, work, PFSM_STATIC_SCRATCH_BYTES, dInfo, stream);
 }
 
-pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv, double* dLam,
-                       double* dVout, int64_t ldvo, void* dWork, size_t work_bytes, int32_t* dInfo, void* stream) {
+// Argument checks of one (single-instance) solve: pointers, leading
+// dimensions, workspace size and alignment, outputs not overlapping the inputs,
+// each other or the workspace.
+static pfsm_status check_solve_args(const pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv,
+                                    const double* dLam, const double* dVout, int64_t ldvo, const void* dWork,
+                                    size_t work_bytes, const int32_t* dInfo) {
   if (!pl || !dA || !dV || !dLam || !dVout || !dWork || !dInfo) return PFSM_INVALID_ARG;
   if (!pl->sub.empty()) return PFSM_INVALID_ARG;  // batched plans go through pfsm_solve_batched
   const int64_t n = pl->n;
@@ -371,6 +375,14 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
   if (overlaps(dVout, bVo, dWork, pl->total) || overlaps(dLam, n * sizeof(double), dWork, pl->total) ||
       overlaps(dLam, n * sizeof(double), dVout, bVo))
     return PFSM_INVALID_ARG;
+  return PFSM_OK;
+}
+
+pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv, double* dLam,
+                       double* dVout, int64_t ldvo, void* dWork, size_t work_bytes, int32_t* dInfo, void* stream) {
+  const pfsm_status chk = check_solve_args(pl, dA, lda, dV, ldv, dLam, dVout, ldvo, dWork, work_bytes, dInfo);
+  if (chk != PFSM_OK) return chk;
+  const int64_t n = pl->n;
   hipStream_t s = (hipStream_t)stream;
   char* W = (char*)dWork;
   double* At = (double*)(W + pl->o_At);
@@ -791,10 +803,35 @@ pfsm_status pfsm_solve_batched(pfsm_plan* pl, const double* const* dA, const int
   if (((uintptr_t)dWork) % 256 != 0) return PFSM_INVALID_ARG;
   if (work_bytes < pl->total) return PFSM_WORKSPACE_TOO_SMALL;
   const int count = (int)pl->sub.size();
-  // validate every instance before enqueuing anything
+  // Validate every instance before enqueuing anything: each instance's own
+  // checks (as pfsm_solve), and no output range of one instance overlapping an
+  // output or input range of another (the instances run concurrently).
+  struct Range {
+    const char* p;
+    size_t b;
+  };
+  std::vector<Range> outs, ins;
   for (int i = 0; i < count; ++i) {
-    const int64_t n = pl->sub[i]->n;
-    if (!dA[i] || !dV[i] || !dLam[i] || !dVout[i] || lda[i] < n || ldv[i] < n || ldvo[i] < n) return PFSM_INVALID_ARG;
+    const pfsm_plan* q = pl->sub[i];
+    const int64_t n = q->n;
+    if (!dA[i] || !dV[i] || !dLam[i] || !dVout[i]) return PFSM_INVALID_ARG;
+    const pfsm_status st = check_solve_args(q, dA[i], lda[i], dV[i], ldv[i], dLam[i], dVout[i], ldvo[i],
+                                            (char*)dWork + pl->sub_off[i], q->total, dInfo + i);
+    if (st != PFSM_OK) return st;
+    outs.push_back({(const char*)dLam[i], (size_t)n * sizeof(double)});
+    outs.push_back({(const char*)dVout[i], (size_t)(ldvo[i] * (n - 1) + n) * sizeof(double)});
+    ins.push_back({(const char*)dA[i], (size_t)(lda[i] * (n - 1) + n) * sizeof(double)});
+    ins.push_back({(const char*)dV[i], (size_t)(ldv[i] * (n - 1) + n) * sizeof(double)});
+  }
+  for (size_t a = 0; a < outs.size(); ++a) {
+    const int ia = (int)(a / 2);
+    if (overlaps(outs[a].p, outs[a].b, dInfo, count * sizeof(int32_t)) ||
+        overlaps(outs[a].p, outs[a].b, dWork, pl->total))
+      return PFSM_INVALID_ARG;
+    for (size_t b = 0; b < outs.size(); ++b)
+      if ((int)(b / 2) != ia && overlaps(outs[a].p, outs[a].b, outs[b].p, outs[b].b)) return PFSM_INVALID_ARG;
+    for (size_t b = 0; b < ins.size(); ++b)
+      if ((int)(b / 2) != ia && overlaps(outs[a].p, outs[a].b, ins[b].p, ins[b].b)) return PFSM_INVALID_ARG;
   }
   hipStream_t s = (hipStream_t)stream;
   const int ns = (int)pl->streams.size();
@@ -806,20 +843,25 @@ pfsm_status pfsm_solve_batched(pfsm_plan* pl, const double* const* dA, const int
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pl->sub[a]->n > pl->sub[b]->n; });
-  for (int t = 0; t < count; ++t) {
+  pfsm_status result = PFSM_OK;
+  for (int t = 0; t < count && result == PFSM_OK; ++t) {
     const int i = order[t];
-    pfsm_status st = pfsm_solve(pl->sub[i], dA[i], lda[i], dV[i], ldv[i], dLam[i], dVout[i], ldvo[i],
-                                (char*)dWork + pl->sub_off[i], pl->sub[i]->total, dInfo + i, pl->streams[t % ns]);
-    if (st != PFSM_OK) return st;
+    result = pfsm_solve(pl->sub[i], dA[i], lda[i], dV[i], ldv[i], dLam[i], dVout[i], ldvo[i],
+                        (char*)dWork + pl->sub_off[i], pl->sub[i]->total, dInfo + i, pl->streams[t % ns]);
   }
+  // join every internal stream back into the caller's stream, also after a
+  // failed enqueue, so that nothing enqueued so far is left unjoined
   for (int k = 0; k < ns; ++k) {
-    PFSM_TRY(hipEventRecord(pl->join_ev[k], pl->streams[k]));
-    PFSM_TRY(hipStreamWaitEvent(s, pl->join_ev[k], 0));
+    const hipError_t e1 = hipEventRecord(pl->join_ev[k], pl->streams[k]);
+    const hipError_t e2 = hipStreamWaitEvent(s, pl->join_ev[k], 0);
+    if (result == PFSM_OK && (e1 != hipSuccess || e2 != hipSuccess)) result = PFSM_HIP_ERROR;
   }
-  return PFSM_OK;
+  return result;
 }
 
 int32_t pfsm_batch_count(const pfsm_plan* pl) { return pl ? (int32_t)pl->sub.size() : 0; }
+
+int32_t pfsm_refine_digit_count(void) { return REFINE_OZ_SLICES; }
 
 // Tile autotuning for the split-BF16 products: time each configuration of
 // the N x N x N product on the plan's workspace and keep the fastest.

@@ -8,8 +8,14 @@ constexpr double REFINE_TAU = 1e-4;     // relative gap below which neighbours a
 // Cholesky-QR of the overlap runs instead.
 constexpr double ORTHO_FIRST_ORDER_MAX = 1e-3;
 // Digits per operand of the refinement product Z = A V_new on the int8 matrix
-// cores (error about 2^-42 sqrt(n) of the row and column maxima).
-constexpr int REFINE_OZ_SLICES = 6;
+// cores: the fewest for which the Rayleigh quotients stay well inside 1e-8 of
+// max|lambda| (s = 5, s (s + 1) / 2 = 15 digit products).  Each entry of Z
+// errs by at most (s + 1) 2^-7s 2^(e_i + f_j) per term of its sum (e_i, f_j:
+// exponents of the row and column maxima), about sqrt(n) times that for
+// errors of random sign; the Rayleigh quotient of a unit vector inherits
+// about the same size: at n = 8192 (2^e_i ~ 1, 2^f_j ~ 1/16) that is
+// 6 * 2^-35 * 90.5 / 16 ~ 1e-9, against 7e-8 for s = 4 and 6e-12 for s = 6.
+constexpr int REFINE_OZ_SLICES = 5;
 
 struct RefineBufs {
   double* d;       // [n] v_j^T z_j

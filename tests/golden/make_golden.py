@@ -1,6 +1,6 @@
 """Write oracle-only expected values for the GPU parity tests.
 
-    python tests/golden/make_golden.py [c3]
+    python tests/golden/make_golden.py [c3] [c4]
 
 Calls only the seeded workload generator and the CPU oracle (never the GPU
 library).  Outputs, for the N=8192 mixed-precision workload (2048 occupied +
@@ -25,7 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle.pfsm_ref import pfsm_ref, eig_error  # noqa: E402
-from pfsm_workloads import CONFIGS, prescribed_problem, uniform_layout  # noqa: E402
+from pfsm_workloads import CONFIGS, batch_instance, batch_sizes, prescribed_problem, uniform_layout  # noqa: E402
 
 SINGLE_COLS = 8
 
@@ -72,7 +72,31 @@ def make_c3():
     print("wrote", path)
 
 
+def make_c4():
+    """c4_batch_oracle_lambda.txt: oracle eigenvalues of the first instance of every
+    order in the 64-instance batched workload (slices of 128, halo 64, 3
+    iterations, q = 2); one line per instance: index b, order n, n eigenvalues."""
+    cfg = CONFIGS["c4_batched"]
+    ns = batch_sizes(64)
+    path = os.path.join(HERE, "c4_batch_oracle_lambda.txt")
+    with open(path, "w") as f:
+        f.write("# oracle PFSM eigenvalues of batched instances (see make_golden.py): b n lambda_0 .. lambda_{n-1}\n")
+        for n in sorted(set(ns)):
+            b = ns.index(n)
+            A, V, lam_ex, _ = batch_instance(b, n, cfg.kappa, cfg.seed_base)
+            t = time.time()
+            lam, _, info = pfsm_ref(A.numpy(), V.numpy(), uniform_layout(n, cfg.slice_size), cfg.halo,
+                                    cfg.iterations, 2)
+            assert info == 0
+            print("instance %d (n=%d): oracle in %.1f s, error vs prescribed %.3e" %
+                  (b, n, time.time() - t, eig_error(lam, lam_ex)), flush=True)
+            f.write("%d %d " % (b, n) + " ".join("%.17e" % x for x in lam) + "\n")
+    print("wrote", path)
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c3"]
+    which = sys.argv[1:] or ["c3", "c4"]
     if "c3" in which:
         make_c3()
+    if "c4" in which:
+        make_c4()

@@ -43,6 +43,55 @@ def test_batched_matches_single_and_oracle(pf):
         assert eig_error(lams[b].cpu().numpy(), lam_ref) <= 1e-8
 
 
+def test_batched_every_order_vs_oracle(pf):
+    """One instance of every order of the batched workload (384 ... 2048, slices
+    of 128, submatrices of 256) in one batched call, each against the oracle."""
+    from pfsm_workloads.gen import BATCH_SIZES
+    dev = torch.device("cuda:0")
+    ns = list(BATCH_SIZES)
+    inst = [batch_instance(20 + b, n) for b, n in enumerate(ns)]
+    bp = pf.BatchedPlan(_specs(ns))
+    lams, _ = bp.solve([x[0].to(dev) for x in inst], [x[1].to(dev) for x in inst])
+    for b, n in enumerate(ns):
+        lam_ref, _, info = pfsm_ref(inst[b][0].numpy(), inst[b][1].numpy(), uniform_layout(n, 128), 64, 3, 2)
+        err = eig_error(lams[b].cpu().numpy(), lam_ref)
+        print("batched instance n=%d: eigenvalue error vs oracle %.3e" % (n, err))
+        assert info == 0 and err <= 1e-8
+
+
+def test_batched_rejects_overlapping_outputs(pf):
+    """Outputs of one instance overlapping another instance's input or output are
+    refused before anything is enqueued; the same call with separate outputs runs."""
+    import ctypes
+    lib = pf.load_library()
+    dev = torch.device("cuda:0")
+    ns = [384, 512]
+    inst = [batch_instance(40 + b, n) for b, n in enumerate(ns)]
+    As = [x[0].to(dev).t().contiguous().t() for x in inst]
+    Vs = [x[1].to(dev).t().contiguous().t() for x in inst]
+    bp = pf.BatchedPlan(_specs(ns))
+    lams, Vos = bp.outputs(dev)
+    work = torch.empty(bp.workspace_bytes, dtype=torch.uint8, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+
+    def call(vout1):
+        arrA = (P * 2)(*[a.data_ptr() for a in As])
+        arrV = (P * 2)(*[v.data_ptr() for v in Vs])
+        arrL = (P * 2)(*[x.data_ptr() for x in lams])
+        arrO = (P * 2)(Vos[0].data_ptr(), vout1)
+        ld = (I64 * 2)(*ns)
+        return lib.pfsm_solve_batched(bp._h, arrA, ld, arrV, ld, arrL, arrO, ld, work.data_ptr(), bp.workspace_bytes,
+                                      info.data_ptr(), torch.cuda.current_stream().cuda_stream)
+
+    assert call(Vos[0].data_ptr()) == 1   # instance 1 writes over instance 0's vectors
+    assert call(As[0].data_ptr()) == 1    # instance 1 writes over instance 0's matrix
+    assert call(Vos[1].data_ptr()) == 0
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, 0]
+
+
 def test_batched_graph_replay(pf):
     dev = torch.device("cuda:0")
     ns = batch_sizes(64)[:8]

@@ -1,9 +1,9 @@
 """Counter probe for the HBM traffic of the dominant kernels.
 
-    python -m paper_1502_07806_amd.traffic_probe [--n 8192]
+    python traffic_probe.py [--n 8192]
         dispatches the kernels; run it under `rocprofv3 --pmc FETCH_SIZE` and,
         separately, `rocprofv3 --pmc WRITE_SIZE` (CSV output)
-    python -m paper_1502_07806_amd.traffic_probe --summarize FETCH.csv WRITE.csv --out profiles/traffic.json
+    python traffic_probe.py --summarize FETCH.csv WRITE.csv --out profiles/traffic.json
         turns the two counter files into HBM bytes per launch
 
 Dispatches, in order: a plain device copy of 1 GiB (calibration: 1 GiB read +
@@ -11,7 +11,7 @@ Dispatches, in order: a plain device copy of 1 GiB (calibration: 1 GiB read +
 folded-spectrum update (FSUPD epilogue, default tile configuration), the same
 update from plain BF16 operands (one product, as the mixed path runs it), the
 FP64 folded-spectrum update, and the int8 digit product of the refinement
-(two digit splits, then one launch).  Each counter value of a dispatch is
+(two digit splits with the refinement's digit count, then one launch).  Each counter value of a dispatch is
 scaled by the copy's bytes over the copy's counter value.  Needs
 libpfsm_testhooks.so (the internal kernels' test entry points).
 """
@@ -24,8 +24,9 @@ import os
 
 import torch
 
-HERE = os.path.dirname(os.path.abspath(__file__))
-GEMM_SOURCES = ("gemm_f64.hip", "gemm_x3.hip", "gemm_x3.h", "gemm_oz.hip", "gemm_oz.h", "common.h")
+ROOT = os.path.dirname(os.path.abspath(__file__))
+PKG = os.path.join(ROOT, "paper_1502_07806_amd")
+GEMM_SOURCES = ("gemm_f64.hip", "gemm_x3.hip", "gemm_x3.h", "gemm_oz.hip", "gemm_oz.h", "common.h", "refine.h")
 
 
 def gemm_source_hash() -> str:
@@ -33,7 +34,7 @@ def gemm_source_hash() -> str:
     kernels they were measured on."""
     h = hashlib.sha256()
     for f in GEMM_SOURCES:
-        p = os.path.join(HERE, "csrc", f)
+        p = os.path.join(PKG, "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
@@ -73,13 +74,13 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
-    ap.add_argument("--out", default=os.path.join(os.path.dirname(HERE), "profiles", "traffic.json"))
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     a = ap.parse_args()
     n = a.n
     if a.summarize:
         summarize(a.summarize[0], a.summarize[1], n, a.out)
         return
-    L = ctypes.CDLL(os.path.join(HERE, "libpfsm_testhooks.so"))
+    L = ctypes.CDLL(os.path.join(PKG, "libpfsm_testhooks.so"))
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     L.pfsm_test_gemm_x3.argtypes = [i32, i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, dbl, dbl, vp, i64,
                                     vp, i64, i32, vp, vp, vp]
@@ -96,6 +97,7 @@ def main():
     L.pfsm_test_gemm_oz.argtypes = [i64, i64, i64, i32, vp, vp, vp, vp, vp, i64, i32, vp]
     L.pfsm_test_oz_row_stride.argtypes = [i64]
     L.pfsm_test_oz_row_stride.restype = i64
+    L.pfsm_test_refine_slices.restype = i32
     dev = torch.device("cuda:0")
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     P = lambda t: ctypes.c_void_p(t.data_ptr())
@@ -139,8 +141,8 @@ def main():
     assert L.pfsm_test_gemm_f64(0, 0, 2, n, n, n, P(M), n, P(B), n, P(C), n, 0.1, 0.0, P(eps), P(C), n, None, 0,
                                 s) == 0
     torch.cuda.synchronize()
-    # int8 digit product (six digits), C = M B
-    s6 = 6
+    # int8 digit product with the refinement's digit count, C = M B
+    s6 = L.pfsm_test_refine_slices()
     ldo = L.pfsm_test_oz_row_stride(n)
     Ad = torch.empty(s6 * n * ldo, dtype=torch.int8, device=dev)
     Bd = torch.empty(s6 * n * ldo, dtype=torch.int8, device=dev)
