@@ -341,26 +341,36 @@ __global__ __launch_bounds__(NT, 1) void gemm_oz_fused(OzArgs a, int tiles_m, in
     }
   };
 
-  int64_t offA[CPW], offB[CPW];
+  // Lane offsets inside the tile's rows (32-bit: rows past the edge read the
+  // last row), added to a uniform 64-bit base per load: two registers per
+  // load instead of four, so nothing in the k loop is spilled (a reload from
+  // scratch would wait on the vector-memory counter, i.e. on every load of
+  // the ring still in flight).
+  uint32_t offA[CPW], offB[CPW];
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
     const int row = 16 * (wave * CPW + j) + (lane >> 2);
     const int c = (lane & 3) ^ dswz(row);
-    offA[j] = min<int64_t>(m0 + row, a.M - 1) * a.ldp + 16 * c;
-    offB[j] = min<int64_t>(n0 + row, a.N - 1) * a.ldp + 16 * c;
+    offA[j] = (uint32_t)((min<int64_t>(m0 + row, a.M - 1) - m0) * a.ldp + 16 * c);
+    offB[j] = (uint32_t)((min<int64_t>(n0 + row, a.N - 1) - n0) * a.ldp + 16 * c);
   }
   auto issue = [&](const OzCursor& c, int t) {
     const int q = c.g - c.p;
-    const int8_t* A = a.Ap + (int64_t)(c.p - 1) * a.pa + (int64_t)c.kt * DBK;
-    const int8_t* B = a.Bp + (int64_t)(q - 1) * a.pb + (int64_t)c.kt * DBK;
+    const int8_t* A = a.Ap + (int64_t)(c.p - 1) * a.pa + (int64_t)c.kt * DBK + m0 * a.ldp;
+    const int8_t* B = a.Bp + (int64_t)(q - 1) * a.pb + (int64_t)c.kt * DBK + n0 * a.ldp;
     unsigned char* sA = lds + (t % DST) * 2 * DTILE;
     unsigned char* sB = sA + DTILE;
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
-      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(A + offA[j]),
+      // opaque 32-bit copies: the address stays (uniform base) + (32-bit lane
+      // offset), the scalar-base form of the load, instead of a 64-bit
+      // per-lane address kept live across the loop
+      uint32_t oa = offA[j], ob = offB[j];
+      asm volatile("" : "+v"(oa), "+v"(ob));
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(A + oa),
                                        (void __attribute__((address_space(3)))*)(sA + (wave * CPW + j) * 1024), 16, 0,
                                        0);
-      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(B + offB[j]),
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(B + ob),
                                        (void __attribute__((address_space(3)))*)(sB + (wave * CPW + j) * 1024), 16, 0,
                                        0);
     }
