@@ -255,8 +255,9 @@ def bench_backward(args):
     """Differentiation workload: N = 4096, 16 slices of 256, submatrices of
     order 512; forward step then the adjoint dA = sym(V (diag(dlam) + F o (V^T dV)) V^T)
     for the loss sum_{i <= n_occ} w_i lam_i + sum_{j <= n_occ} <v_j, D v_j>
-    (w ~ U[0,1), D = diag(d), d ~ N(0,1)); FP64 plan and mixed plan (split-BF16
-    products).  Backward flops: 2N^3 (V^T dV) + 2N^3 + N^3 (V M V^T, symmetric)."""
+    (w ~ U[0,1), D = diag(d), d ~ N(0,1)); FP64 plan, mixed plan (FP64 products
+    in the adjoint, the default) and mixed plan with split-BF16 adjoint products.
+    Backward flops: 2N^3 (V^T dV) + 2N^3 + N^3 (V M V^T, symmetric)."""
     import torch
     import paper_1502_07806_amd as pf
     from pfsm_workloads import CONFIGS, loss_weights, prescribed_problem, uniform_layout
@@ -269,9 +270,10 @@ def bench_backward(args):
     w_t, d_t = torch.from_numpy(w).to(dev), torch.from_numpy(d).to(dev)
     res = {"workload": "N=%d, %d slices of %d, submatrix order %d, loss over the %d lowest eigenpairs" %
                        (n, n // cfg.slice_size, cfg.slice_size, cfg.slice_size + 2 * cfg.halo, k)}
-    for precision in ("fp64", "mixed_bf16"):
+    for key, precision, split in (("fp64", "fp64", False), ("mixed_bf16", "mixed_bf16", False),
+                                  ("mixed_bf16_split_adjoint", "mixed_bf16", True)):
         plan = pf.Plan(n, uniform_layout(n, cfg.slice_size), halo=cfg.halo, iterations=cfg.iterations,
-                       precision=precision)
+                       precision=precision, backward_split=split)
         lam, Vo = plan.solve(A, V)
         # gradients of the loss with respect to lam and V (the loss definition itself)
         glam = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -291,7 +293,7 @@ def bench_backward(args):
             ts.append(e0.elapsed_time(e1))
         plan.check()
         ms = float(np.median(ts))
-        res[precision] = {"backward_ms": ms, "tflops": 5.0 * n ** 3 / (ms * 1e-3) / 1e12,
+        res[key] = {"backward_ms": ms, "tflops": 5.0 * n ** 3 / (ms * 1e-3) / 1e12,
                           "symmetric": bool(torch.equal(gA, gA.t()))}
         del plan, lam, Vo, gA, gV
         torch.cuda.empty_cache()

@@ -36,6 +36,8 @@
  *         vectors do not span: a randomly mixed, non-diagonally-dominant input
  *         as the Methodology section warns, or duplicated previous vectors)
  *     -1  a non-finite eigenvalue (non-finite input propagates to it)
+ *     -2  a returned eigenpair's residual ||A v_i - lambda_i v_i|| exceeds the
+ *         plan's threshold resid_tol * max_j |lambda_j| (plans with resid_tol > 0)
  *     -3  a submatrix eigensolver did not converge within its sweep limit
  *     -4  an output vector lost its length (squared norm outside [1/4, 4] before
  *         normalisation): V_prev does not have orthonormal columns
@@ -94,6 +96,9 @@ typedef struct pfsm_desc {
   int32_t precision;           /* pfsm_precision */
   int32_t max_sweeps;          /* submatrix Jacobi sweep limit; <= 0: 10 */
   int32_t flags;               /* PFSM_FLAG_* bits; 0 = defaults */
+  double resid_tol;            /* > 0: per-column residuals are computed and info = -2 when
+                                  max_i ||A v_i - lambda_i v_i|| > resid_tol * max_j |lambda_j|;
+                                  0: no check */
 } pfsm_desc;
 
 /* Mixed precision only: skip the FP64 refinement against A and return the
@@ -110,6 +115,18 @@ typedef struct pfsm_desc {
  * way); the unrefined estimates (PFSM_FLAG_NO_REFINE) are about 4 % closer
  * with the split. */
 #define PFSM_FLAG_FS_SPLIT 2
+/* Compute the per-column residuals r_i = ||A v_i - lambda_i v_i||_2 of the
+ * returned eigenpairs during the solve (read them with pfsm_residuals).  FP64
+ * path: from the Rayleigh-quotient product, r_i^2 = ||At x_i||^2 - lambda_i^2;
+ * mixed path: from the refinement product Z = A V_new (for the Ritz vectors
+ * of a cluster, from y^T (Z_c^T Z_c) y - mu^2).  The difference of squares
+ * loses digits for residuals below about 1e-8 |lambda|.  Implied by
+ * resid_tol > 0; not available with PFSM_FLAG_NO_REFINE. */
+#define PFSM_FLAG_RESIDUALS 4
+/* Mixed precision: run the two n x n products of pfsm_backward with V on
+ * split-BF16 operands (about 16 significant bits, gradients to about 1e-4
+ * relative) instead of the default FP64 products. */
+#define PFSM_FLAG_BACKWARD_SPLIT 8
 
 typedef struct pfsm_plan pfsm_plan;
 
@@ -170,8 +187,8 @@ pfsm_status pfsm_solve_static(pfsm_plan* plan, const double* dA, int64_t lda, co
  *   dGradA        output n x n symmetric, ldga >= n; must not overlap the inputs
  * The middle factor is symmetrised in FP64 before the products
  * (M_ij = F_ij (T_ij - T_ji) / 2, T = V^T gV in FP64), so dA = V M V^T; the two
- * n x n products with V run in FP64 for an FP64 plan and as split-BF16
- * matrix-core products (FP32-class accuracy) for a mixed-precision plan.
+ * n x n products with V run in FP64 (also for a mixed-precision plan, unless
+ * it sets PFSM_FLAG_BACKWARD_SPLIT: split-BF16 matrix-core products).
  * Errors: INVALID_ARG, WORKSPACE_TOO_SMALL, HIP_ERROR. */
 pfsm_status pfsm_backward(pfsm_plan* plan, const double* dLambda, const double* dV, int64_t ldv,
                           const double* dGradLambda, const double* dGradV, int64_t ldg, double eta,
@@ -201,6 +218,12 @@ pfsm_status pfsm_solve_batched(pfsm_plan* plan, const double* const* dA, const i
                                const double* const* dVprev, const int64_t* ldv, double* const* dLambda,
                                double* const* dVout, const int64_t* ldvo, void* dWork, size_t work_bytes,
                                int32_t* dInfo, void* stream);
+
+/* Copy the per-column residuals of the last solve (output order, n doubles)
+ * from the workspace to dR (device) on `stream`.  Errors: INVALID_ARG,
+ * NOT_SUPPORTED (the plan does not compute residuals: see
+ * PFSM_FLAG_RESIDUALS), WORKSPACE_TOO_SMALL, HIP_ERROR. */
+pfsm_status pfsm_residuals(const pfsm_plan* plan, const void* dWork, size_t work_bytes, double* dR, void* stream);
 
 /* Number of instances of a batched plan (0 for a single plan or NULL). */
 int32_t pfsm_batch_count(const pfsm_plan* plan);

@@ -24,11 +24,14 @@ LIB_PATH = os.path.join(_HERE, "libpfsm.so")
 PFSM_PREC = {"fp64": 0, "mixed_bf16": 1}
 PFSM_SHIFT = {"fixed": 0, "rayleigh": 1}
 INFO_TEXT = {0: "ok", -1: "non-finite eigenvalue",
+             -2: "an eigenpair's residual exceeds the plan's threshold",
              -3: "submatrix eigensolver did not converge",
              -4: "an output vector lost its length: V_prev is not orthonormal",
              -5: "a diagonal entry of B is not a positive finite number"}
 FLAG_NO_REFINE = 1
 FLAG_FS_SPLIT = 2
+FLAG_RESIDUALS = 4
+FLAG_BACKWARD_SPLIT = 8
 
 
 class PfsmDesc(ctypes.Structure):
@@ -44,6 +47,7 @@ class PfsmDesc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("max_sweeps", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("resid_tol", ctypes.c_double),
     ]
 
 
@@ -64,6 +68,8 @@ def load_library(path: str = LIB_PATH):
     lib.pfsm_plan_create.restype = ctypes.c_int
     lib.pfsm_solve_static.argtypes = [vp, vp, i64, vp, i64, vp, vp, i64, vp, vp]
     lib.pfsm_solve_static.restype = ctypes.c_int
+    lib.pfsm_residuals.argtypes = [vp, vp, sz, vp, vp]
+    lib.pfsm_residuals.restype = ctypes.c_int
     lib.pfsm_refine_digit_count.argtypes = []
     lib.pfsm_refine_digit_count.restype = i32
     lib.pfsm_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
@@ -127,11 +133,12 @@ def _stream_handle() -> int:
 
 
 def _desc(n, part_offsets, halo=-1, iterations=3, fs_power=2, alpha=0.0, shift_mode="fixed", precision="fp64",
-          max_sweeps=0, refine=True, fs_split=False):
+          max_sweeps=0, refine=True, fs_split=False, residuals=False, resid_tol=0.0, backward_split=False):
     offs = (ctypes.c_int64 * len(part_offsets))(*[int(x) for x in part_offsets])
-    flags = (0 if refine else FLAG_NO_REFINE) | (FLAG_FS_SPLIT if fs_split else 0)
+    flags = ((0 if refine else FLAG_NO_REFINE) | (FLAG_FS_SPLIT if fs_split else 0) |
+             (FLAG_RESIDUALS if residuals else 0) | (FLAG_BACKWARD_SPLIT if backward_split else 0))
     d = PfsmDesc(int(n), len(part_offsets) - 1, offs, int(halo), int(iterations), int(fs_power), float(alpha),
-                 PFSM_SHIFT[shift_mode], PFSM_PREC[precision], int(max_sweeps), flags)
+                 PFSM_SHIFT[shift_mode], PFSM_PREC[precision], int(max_sweeps), flags, float(resid_tol))
     return d, offs  # keep offs alive while d is used
 
 
@@ -140,10 +147,11 @@ class Plan:
 
     def __init__(self, n: int, part_offsets: Sequence[int], halo: int = -1, iterations: int = 3,
                  fs_power: int = 2, alpha: float = 0.0, shift_mode: str = "fixed", precision: str = "fp64",
-                 max_sweeps: int = 0, refine: bool = True, fs_split: bool = False):
+                 max_sweeps: int = 0, refine: bool = True, fs_split: bool = False, residuals: bool = False,
+                 resid_tol: float = 0.0, backward_split: bool = False):
         lib = load_library()
         d, _keep = _desc(n, part_offsets, halo, iterations, fs_power, alpha, shift_mode, precision, max_sweeps,
-                         refine, fs_split)
+                         refine, fs_split, residuals, resid_tol, backward_split)
         h = ctypes.c_void_p()
         _check(lib.pfsm_plan_create(ctypes.byref(h), ctypes.byref(d)))
         self._h = h
@@ -212,6 +220,16 @@ class Plan:
         if check:
             self.check()
         return lam, Vout
+
+    def residuals(self) -> torch.Tensor:
+        """Per-column residuals ||A v_i - lambda_i v_i|| of the last solve (output order);
+        the plan must have been made with residuals=True or resid_tol > 0."""
+        if self._work is None:
+            raise RuntimeError("no solve has run with this plan's workspace")
+        r = torch.empty(self.n, dtype=torch.float64, device=self._work.device)
+        _check(load_library().pfsm_residuals(self._h, self._work.data_ptr(), self.workspace_bytes, r.data_ptr(),
+                                             _stream_handle()))
+        return r
 
     def check(self):
         """Synchronise and raise if the device reported a failure."""

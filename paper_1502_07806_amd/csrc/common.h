@@ -17,7 +17,8 @@ enum GemmEpi : int {
   EPI_STORE = 0,   // C = alpha*acc + beta*C
   EPI_SHIFT = 1,   // C = acc - B(i,j) * eps[j]            (B square operand, not transposed)
   EPI_FSUPD = 2,   // C = D(i,j) - a * (acc - B(i,j)*eps[j]), a = *alpha_dev or alpha
-  EPI_RQ = 3,      // part[tile_m][j] = sum_{i in tile} acc(i,j) * D(i,j)   (C untouched)
+  EPI_RQ = 3,      // part[tile_m][j] = sum_{i in tile} acc(i,j) * D(i,j)   (C untouched); and
+                   // part2[tile_m][j] = sum_{i in tile} acc(i,j)^2 when part2 is set
   EPI_G2S = 4,     // C = B(i,j) + eps[i] * (D(i,j) - acc); part[tile_m][j] = sum_i (D(i,j) - acc)^2
                    // when part is set (B square operand, not transposed; C must not alias B)
 };
@@ -32,6 +33,7 @@ struct GemmArgs {
   const double* eps;         // column shifts for EPI_SHIFT / EPI_FSUPD, row scales for EPI_G2S
   const double* D; int64_t ldd;  // FSUPD base matrix / RQ partner matrix
   double* part;              // RQ partial sums [tiles_m x N]
+  double* part2;             // RQ, optional: partial sums of acc^2 [tiles_m x N] (squared column norms of A X)
   const int32_t* krange;     // optional [tiles_n][2] K range per column tile
   int lower_only;            // skip tiles strictly above the diagonal
 };

@@ -193,6 +193,35 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m
       int64_t gj = n0 + tid;
       if (gj < g.N) g.part[(int64_t)tm * g.N + gj] = red[0][tid] + red[1][tid];
     }
+    if (!g.part2) return;
+    // the same for acc^2 (squared norms of the columns of A X over this tile's rows)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double s = 0.0;
+        const int64_t gj = n0 + wj0 + jb * 16 + lq + 4 * r;
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+          const int64_t gi = m0 + wi0 + ib * 16 + l16;
+          if (gi < g.M && gj < g.N) s += acc[ib][jb][r] * acc[ib][jb][r];
+        }
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off, 64);
+        cs[jb][r] = s;
+      }
+    __syncthreads();  // red is read above
+    if (l16 == 0) {
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[wave & 1][wj0 + jb * 16 + lq + 4 * r] = cs[jb][r];
+    }
+    __syncthreads();
+    if (tid < BN) {
+      const int64_t gj = n0 + tid;
+      if (gj < g.N) g.part2[(int64_t)tm * g.N + gj] = red[0][tid] + red[1][tid];
+    }
     return;
   }
 

@@ -29,6 +29,8 @@ struct pfsm_plan {
   int64_t halo = 0;
   int iterations = 0, q = 2, shift_mode = 0, precision = 0, max_sweeps = 10, flags = 0;
   double alpha = 0.0;
+  bool residuals = false;  // per-column residuals computed (PFSM_FLAG_RESIDUALS or resid_tol > 0)
+  double resid_tol = 0.0;  // > 0: info -2 when a residual exceeds resid_tol * max|lambda|
   std::vector<int64_t> part_start, wstart;
   std::vector<int32_t> part_size, wsize, offset;
   std::vector<int32_t> krange;  // [tiles_n][2] K range of the first folded-spectrum product (128-column tiles)
@@ -55,7 +57,7 @@ struct pfsm_plan {
   int t_max = 0, t_count = 0;
   size_t o_stats = 0;
   size_t o_At, o_b0, o_b1, o_Bw, o_Uw, o_Rw, o_rflag, o_state, o_sel, o_T, o_part, o_eps, o_lamu, o_sgn, o_rank,
-      o_scal, o_glo, o_ghi, o_den, total;
+      o_scal, o_glo, o_ghi, o_den, o_resid = 0, o_zz = 0, o_part2 = 0, total;
   // mixed-precision workspace (byte offsets)
   size_t m_At32, m_X32, m_Y32, m_S64, m_Apk, m_Vpk, m_Atpk, m_Xpk, m_Ypk, m_Rpk, m_rb;
   size_t m_oz;  // digit planes of A and V_new for the refinement product, then 2n exponents
@@ -160,8 +162,10 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   if (d->fs_power != 1 && d->fs_power != 2) return PFSM_INVALID_ARG;
   if (d->shift_mode != PFSM_SHIFT_FIXED && d->shift_mode != PFSM_SHIFT_RAYLEIGH) return PFSM_INVALID_ARG;
   if (d->precision != PFSM_PREC_FP64 && d->precision != PFSM_PREC_MIXED_BF16) return PFSM_INVALID_ARG;
-  if (d->flags & ~(PFSM_FLAG_NO_REFINE | PFSM_FLAG_FS_SPLIT)) return PFSM_INVALID_ARG;
+  if (d->flags & ~(PFSM_FLAG_NO_REFINE | PFSM_FLAG_FS_SPLIT | PFSM_FLAG_RESIDUALS | PFSM_FLAG_BACKWARD_SPLIT))
+    return PFSM_INVALID_ARG;
   if (!(d->alpha == d->alpha)) return PFSM_INVALID_ARG;  // NaN
+  if (!(d->resid_tol >= 0.0)) return PFSM_INVALID_ARG;   // negative or NaN
   const int64_t n = d->n;
   const int P = d->num_parts;
   if (d->part_offsets[0] != 0 || d->part_offsets[P] != n) return PFSM_INVALID_ARG;
@@ -172,6 +176,9 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     mmax = std::max(mmax, m);
   }
   if (d->precision == PFSM_PREC_MIXED_BF16 && d->shift_mode != PFSM_SHIFT_FIXED) return PFSM_NOT_SUPPORTED;
+  const bool want_resid = (d->flags & PFSM_FLAG_RESIDUALS) || d->resid_tol > 0.0;
+  // the mixed path's residuals come from the refinement product
+  if (want_resid && d->precision == PFSM_PREC_MIXED_BF16 && (d->flags & PFSM_FLAG_NO_REFINE)) return PFSM_NOT_SUPPORTED;
 
   pfsm_plan* pl = new (std::nothrow) pfsm_plan();
   if (!pl) return PFSM_OOM;
@@ -185,6 +192,8 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   pl->precision = d->precision;
   pl->max_sweeps = d->max_sweeps > 0 ? d->max_sweeps : 10;
   pl->flags = d->flags;
+  pl->residuals = want_resid;
+  pl->resid_tol = d->resid_tol;
   int Mmax = 0;
   for (int p = 0; p < P; ++p) {
     int64_t s = d->part_offsets[p], m = d->part_offsets[p + 1] - s;
@@ -292,6 +301,11 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   pl->o_glo = w; w = align256(w + n * sizeof(double));
   pl->o_ghi = w; w = align256(w + n * sizeof(double));
   pl->o_den = w; w = align256(w + n * sizeof(double));
+  if (pl->residuals) {
+    pl->o_resid = w; w = align256(w + n * sizeof(double));
+    pl->o_zz = w; w = align256(w + n * sizeof(double));
+    pl->o_part2 = w; w = align256(w + (size_t)std::max<int64_t>(tiles_m, 3) * n * sizeof(double));
+  }
   if (pl->precision == PFSM_PREC_MIXED_BF16) {
     const size_t N4 = (size_t)n * n * sizeof(float);
     const size_t PK = (size_t)n * x3_row_stride(n) * sizeof(bf16_t);
@@ -305,7 +319,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     pl->m_Xpk = w; w = align256(w + PK);
     pl->m_Ypk = w; w = align256(w + PK);
     pl->m_Rpk = w; w = align256(w + PK);
-    pl->m_rb = w; w = align256(w + (size_t)(7 * n + 8) * sizeof(double));
+    pl->m_rb = w; w = align256(w + (size_t)(8 * n + 8) * sizeof(double));
     pl->split_bytes = x3_split_bytes(n);
     pl->m_split = w; w = align256(w + pl->split_bytes);
     // The digit planes of the refinement (two sets of s planes plus 2n
@@ -472,18 +486,27 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
     PFSM_TRY(cholesky_qr(S, n, X, n, n, n, (double*)(W + pl->o_T), info, s));
   }
   clk.mark(21);
-  // (7) Rayleigh quotients x_j^T At x_j.
+  // (7) Rayleigh quotients x_j^T At x_j (and, for the residuals, ||At x_j||^2:
+  // the residual of the unit vector x_j is sqrt(||At x_j||^2 - lambda_j^2),
+  // equal to ||A v_j - lambda_j v_j|| for v_j = V_prev x_j).
   {
     GemmArgs r = {};
     r.M = n; r.N = n; r.K = n; r.A = At; r.lda = n; r.B = X; r.ldb = n; r.D = X; r.ldd = n; r.part = part;
     r.alpha = 1.0;
+    if (pl->residuals) r.part2 = (double*)(W + pl->o_part2);
     PFSM_TRY(gemm_f64(true, false, EPI_RQ, r, s));
     PFSM_TRY(rq_reduce(part, tiles_m, n, nullptr, lamu, s));
+    if (pl->residuals) PFSM_TRY(rq_reduce(r.part2, tiles_m, n, nullptr, (double*)(W + pl->o_zz), s));
   }
   clk.mark(22);
   // (8) sign convention, ascending order, back-rotation V_out = V X_perm.
   double* Xp = S;
   PFSM_TRY(finalize_order(lamu, X, n, n, Xp, n, dLam, (int*)(W + pl->o_rank), (double*)(W + pl->o_sgn), info, s));
+  if (pl->residuals) {
+    double* resid = (double*)(W + pl->o_resid);
+    PFSM_TRY(residuals_from_rq((double*)(W + pl->o_zz), lamu, (int*)(W + pl->o_rank), n, resid, s));
+    if (pl->resid_tol > 0.0) PFSM_TRY(residual_check(resid, dLam, n, pl->resid_tol, info, s));
+  }
   clk.mark(23);
   {
     GemmArgs g = {};
@@ -685,7 +708,12 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     b.d = rb; b.nn = rb + n; b.lam_s = rb + 2 * n;
     b.rank = (int*)(rb + 3 * n); b.inv = (int*)(rb + 4 * n); b.cstart = (int*)(rb + 5 * n);
     b.csize = (int*)(rb + 6 * n); b.clus = (int*)(rb + 7 * n);
+    if (pl->residuals) {
+      b.zz = rb + 7 * n + 8;
+      b.resid = (double*)(W + pl->o_resid);
+    }
     PFSM_TRY(refine_rr(Vn64, n, B64a, n, n, REFINE_TAU, dLam, dVout, ldvo, b, info, s));
+    if (pl->resid_tol > 0.0) PFSM_TRY(residual_check(b.resid, dLam, n, pl->resid_tol, info, s));
   }
   clk.mark(26);
   return hip_status(hipGetLastError());
@@ -863,6 +891,16 @@ int32_t pfsm_batch_count(const pfsm_plan* pl) { return pl ? (int32_t)pl->sub.siz
 
 int32_t pfsm_refine_digit_count(void) { return REFINE_OZ_SLICES; }
 
+pfsm_status pfsm_residuals(const pfsm_plan* pl, const void* dWork, size_t work_bytes, double* dR, void* stream) {
+  if (!pl || !dWork || !dR || !pl->sub.empty()) return PFSM_INVALID_ARG;
+  if (!pl->residuals) return PFSM_NOT_SUPPORTED;
+  if (work_bytes < pl->total) return PFSM_WORKSPACE_TOO_SMALL;
+  const size_t bytes = (size_t)pl->n * sizeof(double);
+  if (overlaps(dR, bytes, dWork, pl->total)) return PFSM_INVALID_ARG;
+  return hip_status(hipMemcpyAsync(dR, (const char*)dWork + pl->o_resid, bytes, hipMemcpyDeviceToDevice,
+                                   (hipStream_t)stream));
+}
+
 // Tile autotuning for the split-BF16 products: time each configuration of
 // the N x N x N product on the plan's workspace and keep the fastest.
 pfsm_status pfsm_autotune(pfsm_plan* pl, void* dWork, size_t work_bytes, int32_t* chosen, void* stream) {
@@ -978,8 +1016,8 @@ pfsm_status pfsm_backward(pfsm_plan* pl, const double* dLam, const double* dV, i
   double* T = (double*)(W + pl->o_b0);
   double* G = (double*)(W + pl->o_b1);
   PFSM_TRY(fill_i32((int*)dInfo, 1, 0, s));
-  if (pl->precision == PFSM_PREC_MIXED_BF16) {
-    // split-BF16 products (FP32-class accuracy); the middle factor in FP64
+  if (pl->precision == PFSM_PREC_MIXED_BF16 && (pl->flags & PFSM_FLAG_BACKWARD_SPLIT)) {
+    // split-BF16 products (about 16 significant bits); the middle factor in FP64
     const int64_t ldp = x3_row_stride(n);
     bf16_t* Pa = (bf16_t*)(W + pl->m_Apk);
     bf16_t* Pb = (bf16_t*)(W + pl->m_Vpk);

@@ -17,6 +17,8 @@ constexpr double ORTHO_FIRST_ORDER_MAX = 1e-3;
 // 6 * 2^-35 * 90.5 / 16 ~ 1e-9, against 7e-8 for s = 4 and 6e-12 for s = 6.
 constexpr int REFINE_OZ_SLICES = 5;
 
+constexpr int PFSM_INFO_RESIDUAL = -2;  // a residual above the plan's threshold
+
 struct RefineBufs {
   double* d;       // [n] v_j^T z_j
   double* nn;      // [n] v_j^T v_j
@@ -26,6 +28,8 @@ struct RefineBufs {
   int* clus;       // [1] number of clusters
   int* cstart;     // [n] cluster starts
   int* csize;      // [n] cluster sizes
+  double* zz = nullptr;     // [n] z_j^T z_j (with resid)
+  double* resid = nullptr;  // [n] optional: residuals ||A v - lambda v|| of the outputs, output order
 };
 
 // FP64 refinement of the eigenpair estimates (columns of V, Z = A V):
@@ -34,6 +38,12 @@ struct RefineBufs {
 // Vout (column-major, ldvo).
 hipError_t refine_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz, int64_t n, double tau,
                      double* lam, double* Vout, int64_t ldvo, RefineBufs b, int* info, hipStream_t s);
+
+// info = -2 when max_i r[i] > tol * max_i |lam[i]| (or not a number).
+hipError_t residual_check(const double* r, const double* lam, int64_t n, double tol, int* info, hipStream_t s);
+// FP64 path: r_out[rank[j]] = sqrt(max(zz[j] - lam[j]^2, 0)).
+hipError_t residuals_from_rq(const double* zz, const double* lam, const int* rank, int64_t n, double* r_out,
+                             hipStream_t s);
 
 // Mixed-path helpers.
 hipError_t f32_mirror_to_f64(float* At32, double* At64, int64_t n, hipStream_t s);   // lower -> both, FP64 copy

@@ -34,20 +34,23 @@ __device__ inline double block_sum(double v, double* sh) {
 }
 
 __global__ __launch_bounds__(NT) void k_dots(const double* V, int64_t ldv, const double* Z, int64_t ldz, int64_t n,
-                                             double* d, double* nn) {
+                                             double* d, double* nn, double* zz) {
   __shared__ double sh[NT / 64];
   const int64_t j = blockIdx.x;
-  double a = 0.0, b = 0.0;
+  double a = 0.0, b = 0.0, c = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += NT) {
-    double v = V[i + j * ldv];
-    a += v * Z[i + j * ldz];
+    const double v = V[i + j * ldv], z = Z[i + j * ldz];
+    a += v * z;
     b += v * v;
+    c += z * z;
   }
   a = block_sum(a, sh);
   b = block_sum(b, sh);
+  if (zz) c = block_sum(c, sh);
   if (threadIdx.x == 0) {
     d[j] = a;
     nn[j] = b;
+    if (zz) zz[j] = c;
   }
 }
 
@@ -119,7 +122,7 @@ __global__ __launch_bounds__(1024) void k_clusters(const double* lam_s, int64_t 
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_cluster_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz, int64_t n,
                                                    const int* count, const int* cstart, const int* csize, const int* inv,
                                                    const double* lam_s, const double* nn, double* lam, double* Vout,
-                                                   int64_t ldvo) {
+                                                   int64_t ldvo, const double* zz, double* resid) {
   const int c = blockIdx.x;
   if (c >= *count) return;
   __shared__ double G[KM][KM + 1], Mm[KM][KM + 1], Y[KM][KM + 1];
@@ -137,6 +140,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (k == 1) {
       if (tid == 0) lam[s] = lam_s[s];
       const int j = inv[s];
+      // residual of the normalised vector: ||z||^2 / v^T v - lambda^2
+      if (resid && tid == 0) resid[s] = sqrt(fmax(zz[j] / nn[j] - lam_s[s] * lam_s[s], 0.0));
       const double inv_norm = 1.0 / sqrt(nn[j]);
       const double* vj = V + (int64_t)j * ldv;
       double* out = Vout + (int64_t)s * ldvo;
@@ -412,7 +417,100 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       }
     }
     __syncthreads();
+    if (resid) {
+      // Residuals of the Ritz pairs: A u_t = Z_c y_t, so ||A u_t - mu_t u_t||^2 =
+      // y_t^T (Z_c^T Z_c) y_t - mu_t^2 (u_t has unit length and Rayleigh quotient
+      // mu_t).  H = Z_c^T Z_c by KS x KS blocks (one pass over the rows per block
+      // pair), into G, which is free now.
+      for (int bp = 0; bp < nblk * nblk; ++bp) {
+        const int ca = bp % nblk, cb = bp / nblk;
+        int64_t oza[KS], ozb[KS];
+#pragma unroll
+        for (int t = 0; t < KS; ++t) {
+          oza[t] = (int64_t)__builtin_amdgcn_readfirstlane(col[ca * KS + t]) * ldz;
+          ozb[t] = (int64_t)__builtin_amdgcn_readfirstlane(col[cb * KS + t]) * ldz;
+        }
+        double hz[KS][KS];
+#pragma unroll
+        for (int x = 0; x < KS; ++x)
+#pragma unroll
+          for (int y = 0; y < KS; ++y) hz[x][y] = 0.0;
+        for (int64_t i = tid; i < n; i += NT) {
+          double za[KS], zb[KS];
+#pragma unroll
+          for (int t = 0; t < KS; ++t) {
+            za[t] = Z[i + oza[t]];
+            zb[t] = Z[i + ozb[t]];
+          }
+#pragma unroll
+          for (int x = 0; x < KS; ++x)
+#pragma unroll
+            for (int y = 0; y < KS; ++y) hz[x][y] += za[x] * zb[y];
+        }
+#pragma unroll
+        for (int x = 0; x < KS; ++x)
+#pragma unroll
+          for (int y = 0; y < KS; ++y) {
+            double h = hz[x][y];
+            for (int off = 32; off > 0; off >>= 1) h += __shfl_xor(h, off, 64);
+            if (lane == 0) red[wave][x * KS + y] = h;
+          }
+        __syncthreads();
+        if (tid < KS * KS) {
+          const int x = tid / KS, y = tid % KS;
+          const int ga = ca * KS + x, gb = cb * KS + y;
+          double h = 0.0;
+          for (int w = 0; w < NT / 64; ++w) h += red[w][x * KS + y];
+          if (ga < k && gb < k) G[ga][gb] = h;
+        }
+        __syncthreads();
+      }
+      if (tid < k) {
+        double q = 0.0;
+        for (int a = 0; a < k; ++a) {
+          double ha = 0.0;
+          for (int b = 0; b < k; ++b) ha += G[a][b] * Mm[b][tid];
+          q += Mm[a][tid] * ha;
+        }
+        const double mu = lam[s + tid];
+        resid[s + tid] = sqrt(fmax(q - mu * mu, 0.0));
+      }
+      __syncthreads();
+    }
   }
+}
+
+// info = -2 when some residual exceeds tol * max|lambda| (one workgroup).
+__global__ __launch_bounds__(1024) void k_resid_check(const double* r, const double* lam, int64_t n, double tol,
+                                                      int* info) {
+  __shared__ double sr[1024], sl[1024];
+  double mr = 0.0, ml = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double a = r[i], b = fabs(lam[i]);
+    mr = (a > mr || a != a) ? a : mr;
+    ml = (b > ml || b != b) ? b : ml;
+  }
+  sr[threadIdx.x] = mr;
+  sl[threadIdx.x] = ml;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double a = sr[threadIdx.x + w], b = sl[threadIdx.x + w];
+      sr[threadIdx.x] = (a > sr[threadIdx.x] || a != a) ? a : sr[threadIdx.x];
+      sl[threadIdx.x] = (b > sl[threadIdx.x] || b != b) ? b : sl[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && !(sr[0] <= tol * sl[0])) atomicCAS(info, 0, PFSM_INFO_RESIDUAL);
+}
+
+// FP64 path: r_out[rank[j]] = sqrt(max(zz[j] - lam[j]^2, 0)) for unit vectors
+// x_j with Rayleigh quotients lam[j] and squared norms zz[j] of At x_j.
+__global__ __launch_bounds__(256) void k_resid_rq(const double* zz, const double* lam, const int* rank, int64_t n,
+                                                  double* r_out) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  r_out[rank[j]] = sqrt(fmax(zz[j] - lam[j] * lam[j], 0.0));
 }
 
 // Symmetric completion from the lower triangle (i >= j) of A32: A64 = the
@@ -544,7 +642,7 @@ __global__ void k_permute_f64(const double* X, int64_t ldx, const int* rank, dou
 
 hipError_t refine_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz, int64_t n, double tau, double* lam,
                      double* Vout, int64_t ldvo, RefineBufs b, int* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_dots, dim3((unsigned)n), dim3(NT), 0, s, V, ldv, Z, ldz, n, b.d, b.nn);
+  hipLaunchKernelGGL(k_dots, dim3((unsigned)n), dim3(NT), 0, s, V, ldv, Z, ldz, n, b.d, b.nn, b.resid ? b.zz : nullptr);
   hipError_t e = norm_check(b.nn, n, info, s);
   if (e != hipSuccess) return e;
   e = rank_ascending(b.d, b.nn, n, b.rank, s);
@@ -553,7 +651,18 @@ hipError_t refine_rr(const double* V, int64_t ldv, const double* Z, int64_t ldz,
                      b.lam_s, info);
   hipLaunchKernelGGL(k_clusters, dim3(1), dim3(1024), 0, s, b.lam_s, n, tau, b.clus, b.cstart, b.csize);
   hipLaunchKernelGGL(k_cluster_rr, dim3((unsigned)n), dim3(NT), 0, s, V, ldv, Z, ldz, n, b.clus, b.cstart, b.csize,
-                     b.inv, b.lam_s, b.nn, lam, Vout, ldvo);
+                     b.inv, b.lam_s, b.nn, lam, Vout, ldvo, b.zz, b.resid);
+  return hipGetLastError();
+}
+
+hipError_t residual_check(const double* r, const double* lam, int64_t n, double tol, int* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_resid_check, dim3(1), dim3(1024), 0, s, r, lam, n, tol, info);
+  return hipGetLastError();
+}
+
+hipError_t residuals_from_rq(const double* zz, const double* lam, const int* rank, int64_t n, double* r_out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_resid_rq, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, zz, lam, rank, n, r_out);
   return hipGetLastError();
 }
 

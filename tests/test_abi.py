@@ -42,13 +42,15 @@ def _desc(n=64, offs=(0, 32, 64), **kw):
     from paper_1502_07806_amd.binding import PfsmDesc
     arr = (ctypes.c_int64 * len(offs))(*offs)
     d = PfsmDesc(n, len(offs) - 1, arr, kw.get("halo", -1), kw.get("iterations", 3), kw.get("fs_power", 2),
-                 kw.get("alpha", 0.0), kw.get("shift_mode", 0), kw.get("precision", 0), 0, kw.get("flags", 0))
+                 kw.get("alpha", 0.0), kw.get("shift_mode", 0), kw.get("precision", 0), 0, kw.get("flags", 0),
+                 kw.get("resid_tol", 0.0))
     return d, arr
 
 
 @pytest.mark.parametrize("kw", [dict(n=0), dict(offs=(0, 40, 32, 64)), dict(offs=(0, 32, 60)), dict(offs=(1, 32, 64)),
                                 dict(offs=(0, 32, 32, 64)), dict(fs_power=3), dict(iterations=-1),
-                                dict(shift_mode=7), dict(precision=9), dict(flags=4), dict(alpha=float("nan"))])
+                                dict(shift_mode=7), dict(precision=9), dict(flags=64), dict(alpha=float("nan")),
+                                dict(resid_tol=-1.0), dict(resid_tol=float("nan"))])
 def test_plan_rejects_invalid_descriptors(lib, kw):
     n = kw.pop("n", 64)
     offs = kw.pop("offs", (0, 32, 64))
@@ -62,6 +64,15 @@ def test_mixed_with_rayleigh_shift_not_supported(lib):
     d, keep = _desc(64, (0, 32, 64), precision=1, shift_mode=1)
     h = ctypes.c_void_p()
     assert lib.pfsm_plan_create(ctypes.byref(h), ctypes.byref(d)) == 2  # PFSM_NOT_SUPPORTED
+
+
+def test_mixed_residuals_need_the_refinement(lib):
+    """The mixed path's residuals come from its refinement product: asking for
+    them without the refinement is refused before touching a device."""
+    for kw in (dict(flags=1 | 4), dict(flags=1, resid_tol=1e-3)):
+        d, keep = _desc(64, (0, 32, 64), precision=1, **kw)
+        h = ctypes.c_void_p()
+        assert lib.pfsm_plan_create(ctypes.byref(h), ctypes.byref(d)) == 2  # PFSM_NOT_SUPPORTED
 
 
 def test_null_arguments(lib):

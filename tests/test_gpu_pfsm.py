@@ -272,15 +272,19 @@ def test_timing_stages(pf):
     assert sm["back_rotation"] > 0 and sm["refine_product"] > 0 and sm["refine_rr"] > 0
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed_bf16", 1e-4)])
-def test_backward_c5_full_size(pf, precision, tol):
+@pytest.mark.parametrize("precision,split,tol", [("fp64", False, 1e-10), ("mixed_bf16", False, 1e-10),
+                                                 ("mixed_bf16", True, 1e-4)])
+def test_backward_c5_full_size(pf, precision, split, tol):
     """Differentiation workload at N = 4096 (16 slices of 256): the library's
     adjoint against the FP64 CPU formula on the same (lambda, V); loss =
-    weighted occupied eigenvalues + <v_j, D v_j> over the occupied set."""
+    weighted occupied eigenvalues + <v_j, D v_j> over the occupied set.  The
+    products with V run in FP64 (both plans) or, on request, on split-BF16
+    operands (about 16 significant bits)."""
     cfg = CONFIGS["c5_grad_n4096"]
     dev = torch.device("cuda:0")
     A, V, _, _ = prescribed_problem(cfg.n, cfg.n_occ, cfg.kappa, cfg.seed_base, cfg.clusters, device=dev)
-    plan = pf.Plan(cfg.n, uniform_layout(cfg.n, cfg.slice_size), halo=cfg.halo, precision=precision)
+    plan = pf.Plan(cfg.n, uniform_layout(cfg.n, cfg.slice_size), halo=cfg.halo, precision=precision,
+                   backward_split=split)
     lam, Vo = plan.solve(A, V)
     w, d = loss_weights(cfg.n_occ, cfg.n, cfg.seed_base)
     lam_np, V_np = lam.cpu().numpy(), Vo.cpu().numpy()
@@ -314,3 +318,29 @@ def test_paper_width_windows(pf, precision):
     else:
         assert eig_error(lam, lam_ref) <= 1e-8
         assert orthogonality(Vo) <= 1e-3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_bf16"])
+def test_residuals_and_threshold(pf, precision):
+    """Per-column residuals r_i = ||A v_i - lambda_i v_i|| returned by the solve
+    against the same norms computed in FP64 from its outputs (clusters of close
+    eigenvalues included); a plan threshold below the largest residual reports
+    info -2, one above it reports 0 and leaves the results unchanged."""
+    n = 1000
+    A, V, _, _ = prescribed_problem(n, n // 4, 5e-3, 3000 + n, clusters=True)
+    dev = torch.device("cuda:0")
+    A, V = A.to(dev), V.to(dev)
+    offs = uniform_layout(n, 100)
+    plan = pf.Plan(n, offs, halo=50, precision=precision, residuals=True)
+    lam, Vo = plan.solve(A, V)
+    r = plan.residuals().cpu().numpy()
+    ref = torch.linalg.vector_norm(A @ Vo - Vo * lam[None, :], dim=0).cpu().numpy()
+    scale = torch.max(torch.abs(lam)).item()
+    # the difference of squares loses about sqrt(u) |lambda| absolute
+    assert np.max(np.abs(r - ref)) <= 1e-3 * np.max(ref) + 4e-8 * scale
+    rmax = float(np.max(ref))
+    for tol, code in ((0.5 * rmax / scale, -2), (2.0 * rmax / scale, 0)):
+        p2 = pf.Plan(n, offs, halo=50, precision=precision, resid_tol=tol)
+        l2, V2 = p2.solve(A, V, check=False)
+        assert int(p2.info.item()) == code
+        assert torch.equal(l2, lam) and torch.equal(V2, Vo)
