@@ -27,6 +27,16 @@ struct EighBatch {
   const int64_t* part_start;  // [P] first global column of the slice
   int* info;               // device info word (first error wins)
   const double* scal;      // device scalars; scal[1], scal[2] = Gershgorin interval of the full matrix
+  // Submatrices of several independent instances solved together (all null
+  // for one instance): submatrix p reads its matrix at wbase + src_off[p]
+  // (bytes; leading dimension src_ld[p]), its Gershgorin scalars at
+  // wbase + scal_off[p], and reports to info_base[info_idx[p]].
+  const char* wbase;
+  const int64_t* src_off;
+  const int32_t* src_ld;
+  const int64_t* scal_off;
+  int* info_base;
+  const int32_t* info_idx;
 };
 
 hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, int max_sweeps, hipStream_t s);

@@ -41,8 +41,17 @@ constexpr double NOISE = 256.0 * TOL;
 // mean small relative inner products.
 constexpr double ANGLE = 1e-8;
 
-__device__ inline double noise_floor(const EighBatch& e) {
-  return NOISE * fmax(fmax(fabs(e.scal[1]), fabs(e.scal[2])), TINY);
+// Gershgorin scalars and info word of submatrix p (its own instance's when
+// several instances are solved together).
+__device__ inline const double* scal_of(const EighBatch& e, int p) {
+  return e.scal_off ? (const double*)(e.wbase + e.scal_off[p]) : e.scal;
+}
+__device__ inline int* info_of(const EighBatch& e, int p) {
+  return e.info_idx ? e.info_base + e.info_idx[p] : e.info;
+}
+__device__ inline double noise_floor(const EighBatch& e, int p) {
+  const double* sc = scal_of(e, p);
+  return NOISE * fmax(fmax(fabs(sc[1]), fabs(sc[2])), TINY);
 }
 __device__ inline bool must_rotate(double apq, double app, double aqq, double floor_abs) {
   double a = fabs(apq);
@@ -65,6 +74,10 @@ __device__ inline int pair_idx(int t, int I, int J) { return t < EIGH_B ? I * EI
 // ------------------------------------------------------------------ gather
 __global__ void gather_windows(EighBatch e, const double* __restrict__ At, int64_t ldat) {
   const int p = blockIdx.y;
+  if (e.src_off) {  // this submatrix's own instance
+    At = (const double*)(e.wbase + e.src_off[p]);
+    ldat = e.src_ld[p];
+  }
   const int Mp = e.Mp;
   const int64_t w0 = e.wstart[p];
   const int M = e.wsize[p];
@@ -170,7 +183,7 @@ __global__ __launch_bounds__(PS_NT) void pair_solve(EighBatch e, int round) {
   pair_blocks(k, round, e.nb, I, J);
   const double* B = e.Bw + (int64_t)p * Mp * Mp;
   const int tid = threadIdx.x;
-  const double fl = noise_floor(e);
+  const double fl = noise_floor(e, p);
   // pass 1: copy S (as columns) and decide whether any rotation is needed
   if (tid == 0) any_rot = 0;
   __syncthreads();
@@ -187,7 +200,8 @@ __global__ __launch_bounds__(PS_NT) void pair_solve(EighBatch e, int round) {
   if (need) any_rot = 1;
   __syncthreads();
   if (!any_rot) { if (tid == 0) *flagR = 0; return; }
-  const double sigma = 2.0 * fmax(fabs(e.scal[1]), fabs(e.scal[2])) + TINY;
+  const double* sc = scal_of(e, p);
+  const double sigma = 2.0 * fmax(fabs(sc[1]), fabs(sc[2])) + TINY;
   for (int t = tid; t < B2; t += PS_NT) {
     const bool pad = pair_idx(t, I, J) >= msize;
     if (pad) {  // a padding column becomes a unit vector (no overflow, never rotated)
@@ -278,7 +292,8 @@ __global__ __launch_bounds__(PS_NT) void pair_solve(EighBatch e, int round) {
   // The normalised columns are orthonormal eigenvectors only once every
   // column pair is orthogonal; a pair problem that did not get there is a
   // convergence failure of the eigensolver.
-  if (!converged && tid == 0 && e.info) atomicCAS(e.info, 0, PFSM_INFO_EIGH_NOCONV);
+  int* inf = info_of(e, p);
+  if (!converged && tid == 0 && inf) atomicCAS(inf, 0, PFSM_INFO_EIGH_NOCONV);
   // eigenvectors: normalised columns of W
   if (tid < B2) {
     double s2 = 0.0;
@@ -469,8 +484,9 @@ __global__ __launch_bounds__(NT) void rank_select(EighBatch e) {
     sel[rank] = i;  // rank -> local index; ranks are a permutation even with NaN
   }
   // not converged: the last sweep still rotated and no sweep was rotation-free
-  if (threadIdx.x == 0 && e.state[2 * p] == 0 && e.state[2 * p + 1] != 0 && e.info)
-    atomicCAS(e.info, 0, PFSM_INFO_EIGH_NOCONV);
+  int* inf = info_of(e, p);
+  if (threadIdx.x == 0 && e.state[2 * p] == 0 && e.state[2 * p + 1] != 0 && inf)
+    atomicCAS(inf, 0, PFSM_INFO_EIGH_NOCONV);
 }
 
 template <typename T>

@@ -52,6 +52,18 @@ struct pfsm_plan {
   std::vector<size_t> sub_off;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> fork_ev, join_ev;
+  // batched plans: the submatrices of all instances with the same padded
+  // order and sweep limit are solved by one eigensolver run (one launch per
+  // stage for the whole group instead of one per instance)
+  struct EighGroup {
+    std::vector<int> members, p0;  // instances, and each one's first submatrix in the group
+    int P = 0, Mp = 0, nb = 0, max_sweeps = 0;
+    void* dtab = nullptr;
+    int64_t *d_wstart = nullptr, *d_part_start = nullptr, *d_src_off = nullptr, *d_scal_off = nullptr;
+    int32_t *d_wsize = nullptr, *d_offset = nullptr, *d_src_ld = nullptr, *d_info_idx = nullptr;
+    size_t o_Bw = 0, o_Uw = 0, o_Rw = 0, o_rflag = 0, o_state = 0, o_stats = 0, o_sel = 0;  // in the workspace
+  };
+  std::vector<EighGroup> groups;
   // stage timing
   std::vector<hipEvent_t> tev;
   int t_max = 0, t_count = 0;
@@ -349,6 +361,8 @@ void pfsm_plan_destroy(pfsm_plan* pl) {
   for (hipStream_t st : pl->streams) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : pl->fork_ev) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : pl->join_ev) (void)hipEventDestroy(ev);
+  for (auto& g : pl->groups)
+    if (g.dtab) (void)hipFree(g.dtab);
   if (pl->dtab) {
     (void)hipDeviceSynchronize();
     (void)hipFree(pl->dtab);
@@ -356,8 +370,18 @@ void pfsm_plan_destroy(pfsm_plan* pl) {
   delete pl;
 }
 
+// A solve in two halves around the submatrix eigensolver, so that a batched
+// call can run the eigensolver of all its instances together: PH_BEGIN runs
+// up to the step length, PH_END from the start vectors on, with the
+// eigensolver's results in `ext` (a view of the instance's submatrices);
+// PH_ALL runs everything with the plan's own eigensolver arrays.
+enum SolvePhase { PH_ALL = 0, PH_BEGIN = 1, PH_END = 2 };
+static pfsm_status solve_fp64(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv,
+                              double* dLam, double* dVout, int64_t ldvo, char* W, int* info, hipStream_t s,
+                              int phase, const EighBatch* ext);
 static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv,
-                               double* dLam, double* dVout, int64_t ldvo, char* W, int* info, hipStream_t s);
+                               double* dLam, double* dVout, int64_t ldvo, char* W, int* info, hipStream_t s,
+                               int phase, const EighBatch* ext);
 
 pfsm_status pfsm_solve_static(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv,
                               double* dLam, double* dVout, int64_t ldvo, int32_t* dInfo, void* stream) {
@@ -396,9 +420,18 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
                        double* dVout, int64_t ldvo, void* dWork, size_t work_bytes, int32_t* dInfo, void* stream) {
   const pfsm_status chk = check_solve_args(pl, dA, lda, dV, ldv, dLam, dVout, ldvo, dWork, work_bytes, dInfo);
   if (chk != PFSM_OK) return chk;
-  const int64_t n = pl->n;
   hipStream_t s = (hipStream_t)stream;
   char* W = (char*)dWork;
+  int* info = (int*)dInfo;
+  if (pl->precision == PFSM_PREC_MIXED_BF16)
+    return solve_mixed(pl, dA, lda, dV, ldv, dLam, dVout, ldvo, W, info, s, PH_ALL, nullptr);
+  return solve_fp64(pl, dA, lda, dV, ldv, dLam, dVout, ldvo, W, info, s, PH_ALL, nullptr);
+}
+
+static pfsm_status solve_fp64(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv,
+                              double* dLam, double* dVout, int64_t ldvo, char* W, int* info, hipStream_t s,
+                              int phase, const EighBatch* ext) {
+  const int64_t n = pl->n;
   double* At = (double*)(W + pl->o_At);
   double* buf0 = (double*)(W + pl->o_b0);
   double* buf1 = (double*)(W + pl->o_b1);
@@ -407,10 +440,9 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
   double* part = (double*)(W + pl->o_part);
   double* scal = (double*)(W + pl->o_scal);
   const int tiles_m = (int)((n + GEMM_BM - 1) / GEMM_BM);
-  int* info = (int*)dInfo;
-  if (pl->precision == PFSM_PREC_MIXED_BF16) return solve_mixed(pl, dA, lda, dV, ldv, dLam, dVout, ldvo, W, info, s);
 
   StageClock clk(pl, s);
+  if (phase != PH_END) {
   PFSM_TRY(fill_i32(info, 1, 0, s));
   clk.mark(0);
 
@@ -432,10 +464,12 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
   // (2) step length from the Gershgorin interval (or the caller's alpha).
   PFSM_TRY(gershgorin_alpha(At, n, n, pl->q, pl->alpha, (double*)(W + pl->o_glo), (double*)(W + pl->o_ghi), scal, info, s));
   clk.mark(2);
+  }
+  if (phase == PH_BEGIN) return hip_status(hipGetLastError());
 
   // (3) submatrix eigenproblems, (4) zero-padded start vectors and shifts.
-  EighBatch e = eigh_batch(pl, W, info, scal);
-  PFSM_TRY(eigh_batched_run(e, At, n, pl->max_sweeps, s));
+  const EighBatch e = ext ? *ext : eigh_batch(pl, W, info, scal);
+  if (phase == PH_ALL) PFSM_TRY(eigh_batched_run(e, At, n, pl->max_sweeps, s));
   double* X = buf1;
   double* Wt = buf0;
   PFSM_TRY(embed_start_vectors(e, X, n, eps, n, s));
@@ -530,7 +564,8 @@ pfsm_status pfsm_solve(pfsm_plan* pl, const double* dA, int64_t lda, const doubl
 // from the identity; FP64 Rayleigh quotients and cluster Rayleigh-Ritz against
 // A from an FP64-accurate product on the int8 matrix cores.
 static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, const double* dV, int64_t ldv,
-                               double* dLam, double* dVout, int64_t ldvo, char* W, int* info, hipStream_t s) {
+                               double* dLam, double* dVout, int64_t ldvo, char* W, int* info, hipStream_t s,
+                               int phase, const EighBatch* ext) {
   const int64_t n = pl->n;
   const int64_t ldp = x3_row_stride(n);
   // Plain BF16 operands for the folded-spectrum products (q = 2, unless the
@@ -559,8 +594,6 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   double* rb = (double*)(W + pl->m_rb);
   float* split_ws = pl->split_bytes ? (float*)(W + pl->m_split) : nullptr;
   StageClock clk(pl, s);
-  PFSM_TRY(fill_i32(info, 1, 0, s));
-  clk.mark(0);
 
   auto x3 = [&](int epi, int64_t M, int64_t N, int64_t K, const bf16_t* Ap, const bf16_t* Bp, void* C, int64_t ldc,
                 int c_double) {
@@ -570,6 +603,9 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     return g;
   };
 
+  if (phase != PH_END) {
+  PFSM_TRY(fill_i32(info, 1, 0, s));
+  clk.mark(0);
   // (1) basis change: W = A V, At = V^T W (lower tiles), FP64 copy for the eigensolver.
   PFSM_TRY(pack_x3(dA, 1, n, n, lda, 0, Apk, ldp, s));        // rows of A (= columns, A symmetric)
   PFSM_TRY(pack_x3(dV, 1, n, n, ldv, 0, Vpk, ldp, s));        // columns of V
@@ -588,9 +624,11 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   PFSM_TRY(gershgorin_alpha(At64, n, n, pl->q, pl->alpha, (double*)(W + pl->o_glo), (double*)(W + pl->o_ghi), scal,
                             info, s));
   clk.mark(2);
+  }
+  if (phase == PH_BEGIN) return hip_status(hipGetLastError());
   // (2) submatrix eigensolver (FP64) and start vectors.
-  EighBatch e = eigh_batch(pl, W, info, scal);
-  PFSM_TRY(eigh_batched_run(e, At64, n, pl->max_sweeps, s));
+  const EighBatch e = ext ? *ext : eigh_batch(pl, W, info, scal);
+  if (phase == PH_ALL) PFSM_TRY(eigh_batched_run(e, At64, n, pl->max_sweeps, s));
   PFSM_TRY(embed_start_vectors(e, X32, n, eps, n, s));
   PFSM_TRY(pack_x3(X32, 0, n, n, n, fs_plain ? PACK_PLAIN : 0, Xpk, fs_plain ? ldq : ldp, s));
   clk.mark(3);
@@ -796,12 +834,88 @@ pfsm_status pfsm_plan_create_batched(pfsm_plan** out, const pfsm_desc* descs, in
     pl->sub_off.push_back(w);
     w = align256(w + q->total);
   }
-  pl->total = w;
   pl->n = 0;
   if (hipGetDevice(&pl->device) != hipSuccess) {
     pfsm_plan_destroy(pl);
     return PFSM_HIP_ERROR;
   }
+  // eigensolver groups: instances with the same padded submatrix order and
+  // sweep limit, their submatrices numbered consecutively
+  for (int32_t i = 0; i < count; ++i) {
+    const pfsm_plan* q = pl->sub[i];
+    pfsm_plan::EighGroup* g = nullptr;
+    for (auto& h : pl->groups)
+      if (h.Mp == q->Mp && h.max_sweeps == q->max_sweeps) g = &h;
+    if (!g) {
+      pl->groups.emplace_back();
+      g = &pl->groups.back();
+      g->Mp = q->Mp;
+      g->nb = q->nb;
+      g->max_sweeps = q->max_sweeps;
+    }
+    g->members.push_back(i);
+    g->p0.push_back(g->P);
+    g->P += q->P;
+  }
+  const int B2 = 2 * EIGH_B;
+  for (auto& g : pl->groups) {
+    std::vector<int64_t> ws, ps, so, sc;
+    std::vector<int32_t> wz, of, sl, ii;
+    for (size_t m = 0; m < g.members.size(); ++m) {
+      const int i = g.members[m];
+      const pfsm_plan* q = pl->sub[i];
+      for (int p = 0; p < q->P; ++p) {
+        ws.push_back(q->wstart[p]);
+        ps.push_back(q->part_start[p]);
+        wz.push_back(q->wsize[p]);
+        of.push_back(q->offset[p]);
+        so.push_back((int64_t)(pl->sub_off[i] + q->o_At));
+        sl.push_back((int32_t)q->n);
+        sc.push_back((int64_t)(pl->sub_off[i] + q->o_scal));
+        ii.push_back(i);
+      }
+    }
+    const size_t P = (size_t)g.P;
+    size_t tb = 0;
+    const size_t t_ws = tb; tb = align256(tb + P * sizeof(int64_t));
+    const size_t t_ps = tb; tb = align256(tb + P * sizeof(int64_t));
+    const size_t t_so = tb; tb = align256(tb + P * sizeof(int64_t));
+    const size_t t_sc = tb; tb = align256(tb + P * sizeof(int64_t));
+    const size_t t_wz = tb; tb = align256(tb + P * sizeof(int32_t));
+    const size_t t_of = tb; tb = align256(tb + P * sizeof(int32_t));
+    const size_t t_sl = tb; tb = align256(tb + P * sizeof(int32_t));
+    const size_t t_ii = tb; tb = align256(tb + P * sizeof(int32_t));
+    if (hipMalloc(&g.dtab, tb) != hipSuccess) {
+      pfsm_plan_destroy(pl);
+      return PFSM_HIP_ERROR;
+    }
+    char* b = (char*)g.dtab;
+    g.d_wstart = (int64_t*)(b + t_ws); g.d_part_start = (int64_t*)(b + t_ps);
+    g.d_src_off = (int64_t*)(b + t_so); g.d_scal_off = (int64_t*)(b + t_sc);
+    g.d_wsize = (int32_t*)(b + t_wz); g.d_offset = (int32_t*)(b + t_of);
+    g.d_src_ld = (int32_t*)(b + t_sl); g.d_info_idx = (int32_t*)(b + t_ii);
+    const bool ok = hipMemcpy(g.d_wstart, ws.data(), P * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
+                    hipMemcpy(g.d_part_start, ps.data(), P * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
+                    hipMemcpy(g.d_src_off, so.data(), P * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
+                    hipMemcpy(g.d_scal_off, sc.data(), P * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
+                    hipMemcpy(g.d_wsize, wz.data(), P * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+                    hipMemcpy(g.d_offset, of.data(), P * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+                    hipMemcpy(g.d_src_ld, sl.data(), P * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+                    hipMemcpy(g.d_info_idx, ii.data(), P * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+      pfsm_plan_destroy(pl);
+      return PFSM_HIP_ERROR;
+    }
+    const size_t Mp2 = (size_t)g.Mp * g.Mp * sizeof(double);
+    g.o_Bw = w; w = align256(w + P * Mp2);
+    g.o_Uw = w; w = align256(w + P * Mp2);
+    g.o_Rw = w; w = align256(w + P * (g.nb / 2) * B2 * B2 * sizeof(double));
+    g.o_rflag = w; w = align256(w + P * (g.nb / 2) * sizeof(int));
+    g.o_state = w; w = align256(w + P * 2 * sizeof(int));
+    g.o_stats = w; w = align256(w + P * 2 * sizeof(int));
+    g.o_sel = w; w = align256(w + P * g.Mp * sizeof(int));
+  }
+  pl->total = w;
   // Instances run concurrently on a few internal streams (default priority),
   // joined back into the caller's stream with events, so that a stream
   // capture of pfsm_solve_batched yields one graph with parallel branches.
@@ -871,20 +985,73 @@ pfsm_status pfsm_solve_batched(pfsm_plan* pl, const double* const* dA, const int
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pl->sub[a]->n > pl->sub[b]->n; });
+  char* W = (char*)dWork;
+  auto half = [&](int i, int phase, const EighBatch* view, hipStream_t st) {
+    pfsm_plan* q = pl->sub[i];
+    char* Wi = W + pl->sub_off[i];
+    if (q->precision == PFSM_PREC_MIXED_BF16)
+      return solve_mixed(q, dA[i], lda[i], dV[i], ldv[i], dLam[i], dVout[i], ldvo[i], Wi, dInfo + i, st, phase,
+                         view);
+    return solve_fp64(q, dA[i], lda[i], dV[i], ldv[i], dLam[i], dVout[i], ldvo[i], Wi, dInfo + i, st, phase, view);
+  };
+  // join every internal stream back into the caller's stream (also after a
+  // failed enqueue, so that nothing enqueued so far is left unjoined)
+  auto join = [&](pfsm_status r) {
+    for (int k = 0; k < ns; ++k) {
+      const hipError_t e1 = hipEventRecord(pl->join_ev[k], pl->streams[k]);
+      const hipError_t e2 = hipStreamWaitEvent(s, pl->join_ev[k], 0);
+      if (r == PFSM_OK && (e1 != hipSuccess || e2 != hipSuccess)) r = PFSM_HIP_ERROR;
+    }
+    return r;
+  };
+  // 1. every instance up to its submatrices (basis change, step length)
   pfsm_status result = PFSM_OK;
+  for (int t = 0; t < count && result == PFSM_OK; ++t) result = half(order[t], PH_BEGIN, nullptr, pl->streams[t % ns]);
+  result = join(result);
+  if (result != PFSM_OK) return result;
+  // 2. one eigensolver run per group of instances, on the caller's stream
+  for (const auto& g : pl->groups) {
+    EighBatch e = {};
+    e.P = g.P; e.Mp = g.Mp; e.nb = g.nb; e.inner_max_sweeps = EIGH_INNER_SWEEPS;
+    e.Bw = (double*)(W + g.o_Bw); e.Uw = (double*)(W + g.o_Uw); e.Rw = (double*)(W + g.o_Rw);
+    e.rflag = (int*)(W + g.o_rflag); e.state = (int*)(W + g.o_state); e.stats = (int*)(W + g.o_stats);
+    e.sel = (int*)(W + g.o_sel);
+    e.wstart = g.d_wstart; e.wsize = g.d_wsize; e.offset = g.d_offset; e.part_start = g.d_part_start;
+    e.wbase = W; e.src_off = g.d_src_off; e.src_ld = g.d_src_ld; e.scal_off = g.d_scal_off;
+    e.info_base = dInfo; e.info_idx = g.d_info_idx;
+    PFSM_TRY(eigh_batched_run(e, nullptr, 0, g.max_sweeps, s));
+  }
+  // 3. every instance from its start vectors on, reading its submatrices'
+  // eigenpairs through a view of its group's arrays
+  for (int k = 0; k < ns; ++k) {
+    PFSM_TRY(hipEventRecord(pl->fork_ev[k], s));
+    PFSM_TRY(hipStreamWaitEvent(pl->streams[k], pl->fork_ev[k], 0));
+  }
+  std::vector<EighBatch> views(count);
+  for (const auto& g : pl->groups)
+    for (size_t m = 0; m < g.members.size(); ++m) {
+      const int i = g.members[m];
+      const pfsm_plan* q = pl->sub[i];
+      const size_t p0 = (size_t)g.p0[m];
+      EighBatch& v = views[i];
+      v = {};
+      v.P = q->P; v.Mp = g.Mp; v.nb = g.nb; v.inner_max_sweeps = EIGH_INNER_SWEEPS;
+      v.Bw = (double*)(W + g.o_Bw) + p0 * g.Mp * g.Mp;
+      v.Uw = (double*)(W + g.o_Uw) + p0 * g.Mp * g.Mp;
+      v.Rw = (double*)(W + g.o_Rw) + p0 * (g.nb / 2) * (2 * EIGH_B) * (2 * EIGH_B);
+      v.rflag = (int*)(W + g.o_rflag) + p0 * (g.nb / 2);
+      v.state = (int*)(W + g.o_state) + 2 * p0;
+      v.stats = (int*)(W + g.o_stats) + 2 * p0;
+      v.sel = (int*)(W + g.o_sel) + p0 * g.Mp;
+      v.wstart = q->d_wstart; v.wsize = q->d_wsize; v.offset = q->d_offset; v.part_start = q->d_part_start;
+      v.info = dInfo + i;
+      v.scal = (const double*)(W + pl->sub_off[i] + q->o_scal);
+    }
   for (int t = 0; t < count && result == PFSM_OK; ++t) {
     const int i = order[t];
-    result = pfsm_solve(pl->sub[i], dA[i], lda[i], dV[i], ldv[i], dLam[i], dVout[i], ldvo[i],
-                        (char*)dWork + pl->sub_off[i], pl->sub[i]->total, dInfo + i, pl->streams[t % ns]);
+    result = half(i, PH_END, &views[i], pl->streams[t % ns]);
   }
-  // join every internal stream back into the caller's stream, also after a
-  // failed enqueue, so that nothing enqueued so far is left unjoined
-  for (int k = 0; k < ns; ++k) {
-    const hipError_t e1 = hipEventRecord(pl->join_ev[k], pl->streams[k]);
-    const hipError_t e2 = hipStreamWaitEvent(s, pl->join_ev[k], 0);
-    if (result == PFSM_OK && (e1 != hipSuccess || e2 != hipSuccess)) result = PFSM_HIP_ERROR;
-  }
-  return result;
+  return join(result);
 }
 
 int32_t pfsm_batch_count(const pfsm_plan* pl) { return pl ? (int32_t)pl->sub.size() : 0; }
