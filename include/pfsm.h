@@ -235,14 +235,20 @@ int32_t pfsm_batch_count(const pfsm_plan* plan);
 int32_t pfsm_refine_digit_count(void);
 
 /* Tile autotuning of the split-BF16 products (mixed precision): times each
- * tile configuration on an N x N x N product in the plan's workspace (on
- * `stream`, synchronising it) and keeps the fastest in the plan (for a batched
- * plan, per instance).  *chosen (nullable) receives the configuration, -1 when
- * nothing was tuned (FP64 plans, batched plans).  Call it outside any stream
- * capture.  Errors: INVALID_ARG, HIP_ERROR. */
+ * tile configuration on an N x N x N product of pseudo-random operands in the
+ * plan's workspace (on `stream`, synchronising it) and keeps the fastest in
+ * the plan (for a batched plan, per instance).  Choices are remembered per
+ * process and order; when the environment variable PFSM_TUNE_CACHE names a
+ * file, they are also read from and appended to it as lines
+ * "<gfx arch> <HIP runtime version> x3 <n> <cfg> <ms>", and a stored choice
+ * for the same architecture, runtime and order is taken without timing.
+ * *chosen (nullable) receives the configuration, -1 when nothing was tuned
+ * (FP64 plans, batched plans).  The folded-spectrum products on plain
+ * operands have a single configuration and are not tuned.  Call it outside
+ * any stream capture.  Errors: INVALID_ARG, HIP_ERROR. */
 pfsm_status pfsm_autotune(pfsm_plan* plan, void* dWork, size_t work_bytes, int32_t* chosen, void* stream);
 
-/* Fix the split-BF16 tile configuration (-1: library default, 0..3: see
+/* Fix the split-BF16 tile configuration (-1: library default, 0..5: see
  * pfsm_autotune) for a plan and its instances.  Errors: INVALID_ARG. */
 pfsm_status pfsm_set_tile_config(pfsm_plan* plan, int32_t cfg);
 

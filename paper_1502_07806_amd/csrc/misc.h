@@ -2,6 +2,8 @@
 #include "common.h"
 namespace pfsm {
 hipError_t fill_i32(int* p, int64_t count, int value, hipStream_t s);
+// y[i] = deterministic pseudo-random values in [-1, 1) (hash of i and seed).
+hipError_t fill_hash_f32(float* y, int64_t count, uint32_t seed, hipStream_t s);
 hipError_t gershgorin_alpha(const double* At, int64_t n, int64_t ld, int q, double user_alpha,
                             double* part_lo, double* part_hi, double* scal, int* info, hipStream_t s);
 hipError_t rq_reduce(const double* part, int tiles_m, int64_t n, const double* den, double* out, hipStream_t s);

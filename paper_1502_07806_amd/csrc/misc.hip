@@ -315,6 +315,27 @@ hipError_t norm_check(const double* nn, int64_t n, int* info, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Deterministic pseudo-random values in [-1, 1) (a 32-bit integer hash of the
+// index and seed), for timing products on realistic, non-zero operands.
+__global__ void k_fill_hash_f32(float* y, int64_t count, uint32_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t h = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(i >> 32) ^ seed;
+    h ^= h >> 16;
+    h *= 0x7FEB352Du;
+    h ^= h >> 15;
+    h *= 0x846CA68Bu;
+    h ^= h >> 16;
+    y[i] = (float)((double)h * (2.0 / 4294967296.0) - 1.0);
+  }
+}
+
+hipError_t fill_hash_f32(float* y, int64_t count, uint32_t seed, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_hash_f32, dim3((unsigned)std::min<int64_t>((count + 255) / 256, 4096)), dim3(256), 0, s, y,
+                     count, seed);
+  return hipGetLastError();
+}
+
 hipError_t fill_i32(int* p, int64_t count, int value, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 1024))),
                      dim3(256), 0, s, p, count, value);

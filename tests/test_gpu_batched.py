@@ -131,3 +131,35 @@ def test_batched_fp64_and_autotune(pf):
     p = pf.Plan(1024, uniform_layout(1024, 128), halo=64, precision="mixed_bf16")
     cfg = p.autotune()
     assert cfg in (0, 1, 2, 3, 4, 5)
+
+
+def test_autotune_cache_file(pf, tmp_path):
+    """The tile choice is stored in the file PFSM_TUNE_CACHE names, keyed by GPU
+    architecture, runtime version and order; a stored choice is taken without
+    timing (the file is not appended).  Each step runs in a child process, since
+    the cache file is read once per process."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    code = ("import sys; sys.path.insert(0, %r); import paper_1502_07806_amd as pf; "
+            "from pfsm_workloads import uniform_layout; n = int(sys.argv[1]); "
+            "p = pf.Plan(n, uniform_layout(n, 128), halo=64, precision='mixed_bf16'); print(p.autotune())" % root)
+    env = dict(os.environ, PFSM_TUNE_CACHE=str(cache))
+
+    def child(n):
+        r = subprocess.run([sys.executable, "-c", code, str(n)], env=env, capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return int(r.stdout.strip().splitlines()[-1])
+
+    c512 = child(512)
+    lines = [ln.split() for ln in cache.read_text().splitlines()]
+    assert len(lines) == 1 and lines[0][2:4] == ["x3", "512"] and int(lines[0][4]) == c512
+    arch, ver = lines[0][0], lines[0][1]
+    stored = (c512 + 1) % 6  # a choice the timing did not make for 512; stored for 640
+    with open(cache, "a") as f:
+        f.write("%s %s x3 640 %d 1.0\n" % (arch, ver, stored))
+    assert child(640) == stored
+    assert child(512) == c512
+    assert len(cache.read_text().splitlines()) == 2  # nothing timed, nothing appended
