@@ -8,12 +8,19 @@ constexpr int EIGH_B = 32;                 // column-block width; pair problems 
 constexpr double EIGH_PAD_DIAG = 1e200;    // decoupled padding eigenvalue (sorts last)
 constexpr int PFSM_INFO_EIGH_NOCONV = -3;  // a submatrix needed rotations in its last sweep
 constexpr int EIGH_INNER_SWEEPS = 30;      // sweep limit of the in-LDS pair solver (4-6 are typical)
+// Rotation floor of the mixed path, relative to the Gershgorin bound of the
+// full matrix: 2^-24, the unit roundoff of FP32.  That path forms the
+// projected matrix with split-BF16 products, whose rounding (about 2^-16
+// relative) lies far above this floor, and rounds its start vectors to FP32;
+// rotating entries below 2^-24 ||B|| would resolve nothing the inputs hold.
+constexpr double EIGH_FLOOR_MIXED = 5.9604644775390625e-08;  // 2^-24
 
 struct EighBatch {
   int P;                   // number of submatrices
   int Mp;                  // padded order (multiple of 2b), common to all
   int nb;                  // Mp / b (even)
   int inner_max_sweeps;    // sweeps of the in-LDS pair solver
+  double floor_rel;        // rotation floor relative to the Gershgorin bound (0: the FP64 rounding floor)
   double* Bw;              // [P][Mp][Mp] working matrices (column-major)
   double* Uw;              // [P][Mp][Mp] accumulated eigenvectors
   double* Rw;              // [P][nb/2][2b][2b] pair rotations of the current round

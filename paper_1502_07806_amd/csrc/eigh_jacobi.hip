@@ -19,7 +19,8 @@
 // |b_pq| > 256 * 2^-53 * ||B|| (rounding floor of the block products, with
 // ||B|| bounded by the Gershgorin interval of the full matrix).  Without the
 // floor, the rounding error of the MFMA block updates would keep rotating
-// exactly degenerate pairs forever.
+// exactly degenerate pairs forever.  A caller that rounds the eigenvectors
+// to a shorter format raises the floor (EighBatch::floor_rel).
 #include "common.h"
 #include "eigh.h"
 #include "order_key.h"
@@ -51,7 +52,7 @@ __device__ inline int* info_of(const EighBatch& e, int p) {
 }
 __device__ inline double noise_floor(const EighBatch& e, int p) {
   const double* sc = scal_of(e, p);
-  return NOISE * fmax(fmax(fabs(sc[1]), fabs(sc[2])), TINY);
+  return fmax(NOISE, e.floor_rel) * fmax(fmax(fabs(sc[1]), fabs(sc[2])), TINY);
 }
 __device__ inline bool must_rotate(double apq, double app, double aqq, double floor_abs) {
   double a = fabs(apq);

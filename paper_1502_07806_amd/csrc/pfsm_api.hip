@@ -61,6 +61,7 @@ struct pfsm_plan {
   struct EighGroup {
     std::vector<int> members, p0;  // instances, and each one's first submatrix in the group
     int P = 0, Mp = 0, nb = 0, max_sweeps = 0;
+    double floor_rel = 0.0;
     void* dtab = nullptr;
     int64_t *d_wstart = nullptr, *d_part_start = nullptr, *d_src_off = nullptr, *d_scal_off = nullptr;
     int32_t *d_wsize = nullptr, *d_offset = nullptr, *d_src_ld = nullptr, *d_info_idx = nullptr;
@@ -139,6 +140,10 @@ struct StageClock {
     if (_e != hipSuccess) return PFSM_HIP_ERROR; \
   } while (0)
 
+// Rotation floor of the submatrix eigensolver: the FP64 rounding floor, or the
+// looser one of the mixed path, whose start vectors are stored in FP32.
+double eigh_floor(const pfsm_plan* pl) { return pl->precision == PFSM_PREC_MIXED_BF16 ? EIGH_FLOOR_MIXED : 0.0; }
+
 // Submatrix eigensolver arguments: every pointer into the plan's workspace layout.
 EighBatch eigh_batch(const pfsm_plan* pl, char* W, int* info, const double* scal) {
   EighBatch e = {};
@@ -149,6 +154,7 @@ EighBatch eigh_batch(const pfsm_plan* pl, char* W, int* info, const double* scal
   e.wstart = pl->d_wstart; e.wsize = pl->d_wsize; e.offset = pl->d_offset; e.part_start = pl->d_part_start;
   e.info = info;
   e.scal = scal;
+  e.floor_rel = eigh_floor(pl);
   return e;
 }
 
@@ -842,19 +848,20 @@ pfsm_status pfsm_plan_create_batched(pfsm_plan** out, const pfsm_desc* descs, in
     pfsm_plan_destroy(pl);
     return PFSM_HIP_ERROR;
   }
-  // eigensolver groups: instances with the same padded submatrix order and
-  // sweep limit, their submatrices numbered consecutively
+  // eigensolver groups: instances with the same padded submatrix order, sweep
+  // limit and rotation floor, their submatrices numbered consecutively
   for (int32_t i = 0; i < count; ++i) {
     const pfsm_plan* q = pl->sub[i];
     pfsm_plan::EighGroup* g = nullptr;
     for (auto& h : pl->groups)
-      if (h.Mp == q->Mp && h.max_sweeps == q->max_sweeps) g = &h;
+      if (h.Mp == q->Mp && h.max_sweeps == q->max_sweeps && h.floor_rel == eigh_floor(q)) g = &h;
     if (!g) {
       pl->groups.emplace_back();
       g = &pl->groups.back();
       g->Mp = q->Mp;
       g->nb = q->nb;
       g->max_sweeps = q->max_sweeps;
+      g->floor_rel = eigh_floor(q);
     }
     g->members.push_back(i);
     g->p0.push_back(g->P);
@@ -1022,6 +1029,7 @@ pfsm_status pfsm_solve_batched(pfsm_plan* pl, const double* const* dA, const int
     e.wstart = g.d_wstart; e.wsize = g.d_wsize; e.offset = g.d_offset; e.part_start = g.d_part_start;
     e.wbase = W; e.src_off = g.d_src_off; e.src_ld = g.d_src_ld; e.scal_off = g.d_scal_off;
     e.info_base = dInfo; e.info_idx = g.d_info_idx;
+    e.floor_rel = g.floor_rel;
     PFSM_TRY(eigh_batched_run(e, nullptr, 0, g.max_sweeps, s));
   }
   // 3. every instance from its start vectors on, reading its submatrices'
@@ -1038,7 +1046,7 @@ pfsm_status pfsm_solve_batched(pfsm_plan* pl, const double* const* dA, const int
       const size_t p0 = (size_t)g.p0[m];
       EighBatch& v = views[i];
       v = {};
-      v.P = q->P; v.Mp = g.Mp; v.nb = g.nb; v.inner_max_sweeps = EIGH_INNER_SWEEPS;
+      v.P = q->P; v.Mp = g.Mp; v.nb = g.nb; v.inner_max_sweeps = EIGH_INNER_SWEEPS; v.floor_rel = g.floor_rel;
       v.Bw = (double*)(W + g.o_Bw) + p0 * g.Mp * g.Mp;
       v.Uw = (double*)(W + g.o_Uw) + p0 * g.Mp * g.Mp;
       v.Rw = (double*)(W + g.o_Rw) + p0 * (g.nb / 2) * (2 * EIGH_B) * (2 * EIGH_B);
