@@ -560,7 +560,7 @@ def main():
         out["roofline"] = {
             "bound": "mfma", "achieved": oz_ops / (oz_ms * 1e-3) / 1e12, "peak": PEAK_TOPS_INT8, "unit": "TOP/s",
             "frac": oz_ops / (oz_ms * 1e-3) / 1e12 / PEAK_TOPS_INT8, "traffic": load_traffic("gemm_oz_n%d" % n),
-            "kernel": "gemm_oz_fused (Z = A V_new from %d 7-bit digits per operand, %d int8 products, "
+            "kernel": "gemm_oz_multi (Z = A V_new from %d 7-bit digits per operand, %d int8 products, "
                       "exact int32 accumulation, FP64 sum)" % (s_dig, pairs),
             "launch_ms": oz_ms, "ops_per_launch": oz_ops,
             "fp64_equivalent_tflops": 2.0 * n ** 3 / (oz_ms * 1e-3) / 1e12}

@@ -35,8 +35,9 @@ hipError_t oz_split(const double* X, int64_t ldx, int64_t K, int64_t ncols, int 
 
 // C (M x N, column-major, ldc) = A B from the digit planes of the rows of A
 // (Ap, ea: M operand rows) and of the columns of B (Bp, eb: N operand rows),
-// both split with the same s and K.  One launch per weight group, smallest
-// weights first, the first one storing and the others adding.
+// both split with the same s and K.  The weight groups' FP64 values are
+// added smallest weights first, C(i, j) = ((v_{s+1} + v_s) + ...) + v_2, in every
+// tile configuration (cfg < 0: the default), so all give the same bits.
 hipError_t gemm_oz(int64_t M, int64_t N, int64_t K, int s, const int8_t* Ap, const int* ea, const int8_t* Bp,
                    const int* eb, double* C, int64_t ldc, hipStream_t st, int cfg = -1);
 extern int oz_default_cfg;  // tile configuration used when cfg < 0

@@ -26,7 +26,11 @@ constexpr int TILE = BM * ROWB;      // 36864 bytes per operand per stage
 //   CFG 3: one launch per weight group, tiles staged through registers into
 //          double-buffered LDS (gemm_oz_kernel), 4 x 2
 //   CFG 4: CFG 0 with the fragments of the next k32 step read between the
-//          MFMAs of the current one (the default)
+//          MFMAs of the current one
+//   CFG 5: all weight groups at once from one staging of every plane
+//          (gemm_oz_multi; 128 x 128 block tiles, 8 waves of 64 x 32, a
+//          four-slot ring of 32-byte k stages), s = 3 .. 5
+//   CFG 6: CFG 5 with a two-slot ring of 64-byte k stages (the default)
 // The per-group kernels keep the running sum in C (read-modify-write per
 // launch); the fused kernel pays that launch and epilogue cost once per tile.
 template <int CFG> struct OzCfg;
@@ -563,6 +567,159 @@ __global__ __launch_bounds__(NT, 1) void gemm_oz_fused(OzArgs a, int tiles_m, in
   }
 }
 
+// All weight groups at once.  The fused kernel above walks the digit pairs one
+// after the other: every plane is staged and read from LDS once per pair it
+// takes part in (s times for the first planes).  Here a workgroup of eight
+// waves (128 x 128 block tile, 64 x 32 per wave) stages the k32 slice of all s
+// planes of both operands once, reads each plane's fragments once and issues
+// every pair (p, q), p + q <= s + 1, from them into the int32 accumulator of
+// its weight group.  The s group sums (s x 32 registers a lane) are scaled and
+// added in FP64 at the end, smallest weights first: the same additions in the
+// same order as the fused kernel's store and atomic adds, so C is the same bit
+// for bit, and it is written once.
+constexpr int MT = 128;
+
+// Stage of MBK k bytes per row (32 or 64), MST = 128 KB / ... stages in the ring.
+// 32-byte rows: the two 16-byte chunks of rows 8..15 (mod 16) swap places; 64-byte
+// rows: chunk c of row r sits at c ^ dswz(r).  Either way the fragment reads of
+// 16 consecutive rows cover all 64 banks once.
+template <int MBK> __device__ inline int mswz(int r) { return MBK == 32 ? (r >> 3) & 1 : dswz(r); }
+template <int MBK> constexpr int multi_stages(int S) { return (MBK == 32 ? 4 : 2) + 0 * S; }
+
+template <int S, int MBK>
+__global__ __launch_bounds__(512, 1) void gemm_oz_multi(OzArgs a, int tiles_m, int tiles_n) {
+  constexpr int WR = 2, WC = 1;          // 32 x 32 blocks per wave: 64 x 32
+  constexpr int MPLANE = MT * MBK;       // the k slice of one plane of one operand
+  constexpr int MST = multi_stages<MBK>(S);
+  constexpr int STAGE = 2 * S * MPLANE;  // A planes, then B planes
+  constexpr int RG = MT * MBK / 1024;    // 1 KB row groups per plane
+  constexpr int LPW = 2 * S * RG / 8;    // 1 KB loads per wave and stage
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  int64_t m0, n0;
+  {
+    const int t = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+    const int GROUP = 4;
+    const int first_m = (t / (GROUP * tiles_n)) * GROUP;
+    const int gsz = min(tiles_m - first_m, GROUP);
+    m0 = (int64_t)(first_m + (t % (GROUP * tiles_n)) % gsz) * MT;
+    n0 = (int64_t)((t % (GROUP * tiles_n)) / gsz) * MT;
+  }
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wi0 = (wave & 1) * 64, wj0 = (wave >> 1) * 32;
+  const int l32 = lane & 31, lh = lane >> 5;
+  const int ntk = (int)(a.ldp / MBK);
+  // Wave w stages row group w % 4 (rows 32 (w % 4) .. + 31) of the planes
+  // w / 4, w / 4 + 2, ... of the list A_1 .. A_s, B_1 .. B_s: lane L holds row
+  // 32 (w % 4) + L / 2, stored chunk L % 2.  Rows past the edge read the last
+  // row (their outputs are not stored).
+  // (32-byte rows: wave w stages row group w % 4 of the planes w / 4, w / 4 + 2, ...;
+  // 64-byte rows: row group w of every plane, lane L holding row 16 w + L / 4)
+  const int rg = wave % RG, po0 = wave / RG, pstep = 8 / RG;
+  uint32_t offA, offB;
+  {
+    constexpr int LPR = MBK / 16;  // lanes per row
+    const int row = (1024 / MBK) * rg + lane / LPR;
+    const int c = (lane % LPR) ^ mswz<MBK>(row);
+    offA = (uint32_t)((min<int64_t>(m0 + row, a.M - 1) - m0) * a.ldp + 16 * c);
+    offB = (uint32_t)((min<int64_t>(n0 + row, a.N - 1) - n0) * a.ldp + 16 * c);
+  }
+  auto issue = [&](int kt) {
+    unsigned char* st = lds + (kt % MST) * STAGE + rg * 1024;
+#pragma unroll
+    for (int i = 0; i < LPW; ++i) {
+      const int po = po0 + pstep * i;  // wave-uniform
+      const bool isA = po < S;
+      const int8_t* base = isA ? a.Ap + (int64_t)po * a.pa + m0 * a.ldp : a.Bp + (int64_t)(po - S) * a.pb + n0 * a.ldp;
+      uint32_t o = isA ? offA : offB;
+      asm volatile("" : "+v"(o));  // keep the scalar-base load form (see gemm_oz_fused)
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(base + (int64_t)kt * MBK + o),
+                                       (void __attribute__((address_space(3)))*)(st + po * MPLANE), 16, 0, 0);
+    }
+  };
+
+  v16i acc[S][WR][WC];  // acc[g - 2]: weight group g
+#pragma unroll
+  for (int g = 0; g < S; ++g)
+#pragma unroll
+    for (int i = 0; i < WR; ++i)
+#pragma unroll
+      for (int j = 0; j < WC; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[g][i][j][r] = 0;
+
+  for (int t = 0; t < MST - 1 && t < ntk; ++t) issue(t);
+  for (int t = 0; t < ntk; ++t) {
+    // this wave's part of stage t has landed once at most the loads of the
+    // later stages already issued are outstanding
+    const int later = min(MST - 2, ntk - 1 - t);
+    static_assert(MST <= 4, "wait counts below");
+    if (later >= 2) wait_vm<2 * LPW>();
+    else if (later == 1) wait_vm<LPW>();
+    else wait_vm<0>();
+    // After the barrier every wave's part of stage t is in LDS, and the slot of
+    // stage t - 1 is free (its fragments fed MFMAs before the barrier).
+    lds_barrier();
+    if (t + MST - 1 < ntk) issue(t + MST - 1);
+    const unsigned char* st = lds + (t % MST) * STAGE;
+#pragma unroll
+    for (int sub = 0; sub < MBK / 32; ++sub) {
+    v4i af[S][WR], bf[S][WC];
+    const int c = 2 * sub + lh;
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+#pragma unroll
+      for (int ib = 0; ib < WR; ++ib) {
+        const int row = wi0 + ib * 32 + l32;
+        af[p][ib] = *(const v4i*)(st + p * MPLANE + row * MBK + 16 * (c ^ mswz<MBK>(row)));
+      }
+#pragma unroll
+      for (int jb = 0; jb < WC; ++jb) {
+        const int row = wj0 + jb * 32 + l32;
+        bf[p][jb] = *(const v4i*)(st + (S + p) * MPLANE + row * MBK + 16 * (c ^ mswz<MBK>(row)));
+      }
+    }
+    // pairs in order of their larger digit index, so the first MFMAs need only
+    // the first fragments read
+#pragma unroll
+    for (int mx = 1; mx <= S; ++mx)
+#pragma unroll
+      for (int p = 1; p <= S; ++p)
+#pragma unroll
+        for (int q = 1; q <= S; ++q) {
+          if (p + q > S + 1 || (p > q ? p : q) != mx) continue;
+#pragma unroll
+          for (int ib = 0; ib < WR; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < WC; ++jb)
+              acc[p + q - 2][ib][jb] =
+                  __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[q - 1][jb], af[p - 1][ib], acc[p + q - 2][ib][jb], 0, 0, 0);
+        }
+    }
+  }
+
+  // acc[g - 2][ib][jb][r] is group g's sum for C(i, j), i = wi0 + 32 ib + lane % 32,
+  // j = wj0 + 32 jb + 8 (r / 4) + 4 (lane / 32) + r % 4.
+#pragma unroll
+  for (int ib = 0; ib < WR; ++ib) {
+    const int64_t gi = m0 + wi0 + ib * 32 + l32;
+    if (gi >= a.M) continue;
+    const int ei = a.ea[gi];
+#pragma unroll
+    for (int jb = 0; jb < WC; ++jb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t gj = n0 + wj0 + jb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
+        if (gj >= a.N) continue;
+        const int e = ei + a.eb[gj];
+        double v = ldexp((double)acc[S - 1][ib][jb][r], e - 12 - 7 * (S - 1));  // group S + 1
+#pragma unroll
+        for (int g = S; g >= 2; --g) v += ldexp((double)acc[g - 2][ib][jb][r], e - 12 - 7 * (g - 2));
+        a.C[gi + gj * a.ldc] = v;
+      }
+  }
+}
+
 // One block per column: exponent of the column maximum, then the digits of
 // four consecutive k per thread (one 32-bit word per plane).  Columns of up
 // to 256 * 4 * SPLIT_REG entries are read once, into registers, with 16-byte
@@ -658,9 +815,20 @@ __global__ __launch_bounds__(256) void k_oz_split(const double* X, int64_t ldx, 
 }
 
 
+template <int S, int MBK> constexpr int multi_lds() { return multi_stages<MBK>(S) * 2 * S * MT * MBK; }
+template <int S, int MBK> hipError_t oz_multi_init() {
+  return hipFuncSetAttribute((const void*)gemm_oz_multi<S, MBK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             multi_lds<S, MBK>());
+}
+template <int S, int MBK> void oz_multi_launch(const OzArgs& a, hipStream_t st) {
+  const int tm = (int)((a.M + MT - 1) / MT), tn = (int)((a.N + MT - 1) / MT);
+  constexpr int lds = multi_lds<S, MBK>();
+  hipLaunchKernelGGL((gemm_oz_multi<S, MBK>), dim3((unsigned)(tm * tn)), dim3(512), lds, st, a, tm, tn);
+}
+
 }  // namespace
 
-int oz_default_cfg = 4;  // fastest measured at N = 8192
+int oz_default_cfg = 6;  // fastest measured at N = 8192 (configuration 4 where s is outside 3 .. 5)
 
 hipError_t oz_init() {
   hipError_t e = hipFuncSetAttribute((const void*)gemm_oz_kernel<3>, hipFuncAttributeMaxDynamicSharedMemorySize, 4 * TILE);
@@ -676,6 +844,12 @@ hipError_t oz_init() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)gemm_oz_fused<512, 2, 4, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             DST * 2 * DTILE);
+  if (e == hipSuccess) e = oz_multi_init<3, 32>();
+  if (e == hipSuccess) e = oz_multi_init<4, 32>();
+  if (e == hipSuccess) e = oz_multi_init<5, 32>();
+  if (e == hipSuccess) e = oz_multi_init<3, 64>();
+  if (e == hipSuccess) e = oz_multi_init<4, 64>();
+  if (e == hipSuccess) e = oz_multi_init<5, 64>();
 
   return e;
 }
@@ -693,7 +867,8 @@ hipError_t oz_split(const double* X, int64_t ldx, int64_t K, int64_t ncols, int 
 hipError_t gemm_oz(int64_t M, int64_t N, int64_t K, int s, const int8_t* Ap, const int* ea, const int8_t* Bp,
                    const int* eb, double* C, int64_t ldc, hipStream_t st, int cfg) {
   if (cfg < 0) cfg = oz_default_cfg;
-  if (cfg > 4) return hipErrorInvalidValue;
+  if (cfg > 6) return hipErrorInvalidValue;
+  if (cfg >= 5 && (s < 3 || s > 5)) cfg = 4;  // the all-groups kernels are built for 3 to 5 digits
   if (s < 1 || s > OZ_MAX_SLICES || K < 0 || (int64_t)s * K >= (1 << 19)) return hipErrorInvalidValue;
   if (M <= 0 || N <= 0) return hipSuccess;
   OzArgs a = {};
@@ -712,6 +887,18 @@ hipError_t gemm_oz(int64_t M, int64_t N, int64_t K, int s, const int8_t* Ap, con
   }
   if (cfg == 4) {
     hipLaunchKernelGGL((gemm_oz_fused<512, 2, 4, 2, true>), grid, dim3(512), DST * 2 * DTILE, st, a, tm, tn);
+    return hipGetLastError();
+  }
+  if (cfg == 5) {
+    if (s == 3) oz_multi_launch<3, 32>(a, st);
+    else if (s == 4) oz_multi_launch<4, 32>(a, st);
+    else oz_multi_launch<5, 32>(a, st);
+    return hipGetLastError();
+  }
+  if (cfg == 6) {
+    if (s == 3) oz_multi_launch<3, 64>(a, st);
+    else if (s == 4) oz_multi_launch<4, 64>(a, st);
+    else oz_multi_launch<5, 64>(a, st);
     return hipGetLastError();
   }
 

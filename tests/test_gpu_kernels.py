@@ -500,8 +500,8 @@ def test_oz_split_nonfinite(dev):
     assert np.all(planes[0, 0, :130] == 32) and np.all(planes[1:, 0, :] == 0)  # 1 = 32 * 2^(1 - 6)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
-@pytest.mark.parametrize("M,N,K,s", [(300, 270, 1000, 6), (256, 512, 128, 4), (33, 600, 257, 5)])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("M,N,K,s", [(300, 270, 1000, 6), (256, 512, 128, 4), (33, 600, 257, 5), (520, 130, 700, 5)])
 def test_gemm_oz(dev, cfg, M, N, K, s):
     """C = A B from digits: equal (to FP64 rounding of the group sums) to the same
     truncated digit expansion evaluated in FP64 from digits made on the host, and
@@ -527,3 +527,23 @@ def test_gemm_oz(dev, cfg, M, N, K, s):
     scale = np.ldexp(1.0, e_a)[:, None] * np.ldexp(1.0, e_b)[None, :]
     assert np.max(np.abs(out - ref) / scale) <= 8 * U64 * K
     assert np.max(np.abs(out - A @ B) / scale) <= 2 * s * K * 2.0 ** (-7 * s)
+
+
+@pytest.mark.parametrize("M,N,K,s", [(300, 270, 1000, 5), (640, 384, 2048, 5), (200, 333, 512, 4), (129, 64, 128, 3)])
+def test_gemm_oz_multi_matches_fused(dev, M, N, K, s):
+    """The all-groups kernel (configuration 5) performs the fused kernel's FP64
+    additions in the same order: the two products agree bit for bit."""
+    g = np.random.default_rng(7 * M + N + K + s)
+    A = g.standard_normal((M, K)) * np.exp(g.standard_normal((M, 1)))
+    B = g.standard_normal((K, N)) * np.exp(g.standard_normal((1, N)))
+    Ap, _, _, info_a, _, ea = _oz_split_dev(A.T, s, dev)
+    Bp, _, _, info_b, _, eb = _oz_split_dev(B, s, dev)
+    assert info_a == info_b == 0
+    out = []
+    for cfg in (4, 5, 6):
+        C = torch.full((N, M), np.nan, dtype=torch.float64, device=dev).t()
+        assert lib().pfsm_test_gemm_oz(M, N, K, s, _p(Ap), _p(ea), _p(Bp), _p(eb), _p(C), M, cfg, _stream()) == 0
+        torch.cuda.synchronize()
+        out.append(_np(C))
+    assert np.all(np.isfinite(out[1]))
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])

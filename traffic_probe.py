@@ -1,10 +1,15 @@
-"""Counter probe for the HBM traffic of the dominant kernels.
+"""Measurement helpers for the profiles: HBM traffic of the dominant kernels,
+and the per-kernel table of one solve from a kernel trace.
 
     python traffic_probe.py [--n 8192]
         dispatches the kernels; run it under `rocprofv3 --pmc FETCH_SIZE` and,
         separately, `rocprofv3 --pmc WRITE_SIZE` (CSV output)
     python traffic_probe.py --summarize FETCH.csv WRITE.csv --out profiles/traffic.json
         turns the two counter files into HBM bytes per launch
+    python traffic_probe.py --trace-summary KERNEL_TRACE.csv --out OUT.md
+        per-kernel table of one solve of a `rocprofv3 --kernel-trace` run of
+        bench.py (the launches between the last two int8 refinement products),
+        and the submatrix eigensolver's kernel time per sweep
 
 Dispatches, in order: a plain device copy of 1 GiB (calibration: 1 GiB read +
 1 GiB written), then at order n on synthetic operands: the split-BF16
@@ -21,12 +26,14 @@ import ctypes
 import hashlib
 import json
 import os
+import re
 
 import torch
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.join(ROOT, "paper_1502_07806_amd")
 GEMM_SOURCES = ("gemm_f64.hip", "gemm_x3.hip", "gemm_x3.h", "gemm_oz.hip", "gemm_oz.h", "common.h", "refine.h")
+OZ_PRODUCT = "gemm_oz_multi"  # the int8 digit product's default kernel
 
 
 def gemm_source_hash() -> str:
@@ -61,7 +68,7 @@ def summarize(fetch_csv: str, write_csv: str, n: int, out: str):
                                     "by what the same counter reads for a 1 GiB device copy"}}
     for key, name in (("gemm_x3_fsupd_n%d" % n, "gemm_x3_dl<2, true, 3>"),
                       ("gemm_x3_fsupd_plain_n%d" % n, "gemm_x3_dl<2, true, 1>"),
-                      ("gemm_f64_fsupd_n%d" % n, "gemm_f64_kernel"), ("gemm_oz_n%d" % n, "gemm_oz_fused")):
+                      ("gemm_f64_fsupd_n%d" % n, "gemm_f64_kernel"), ("gemm_oz_n%d" % n, OZ_PRODUCT)):
         f, w = pick(fe, name) * 1024 * sf, pick(wr, name) * 1024 * sw
         res[key] = {"kernel": name, "fetch_bytes": f, "write_bytes": w, "bytes_per_launch": f + w,
                     "source_hash": gemm_source_hash()}
@@ -70,13 +77,61 @@ def summarize(fetch_csv: str, write_csv: str, n: int, out: str):
     print(json.dumps(res, indent=1))
 
 
+def _short(name: str) -> str:
+    name = name.replace("pfsm::(anonymous namespace)::", "").replace("void ", "")
+    m = re.match(r"([A-Za-z_0-9]+(<[^()]*>)?)", name)
+    return m.group(1) if m else name[:40]
+
+
+def trace_summary(trace_csv: str, out: str):
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    idx = [i for i, r in enumerate(rows) if OZ_PRODUCT in r["Kernel_Name"]]
+    seq = rows[idx[-2] + 1:idx[-1] + 1]
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in seq]
+    span = (int(seq[-1]["End_Timestamp"]) - int(seq[0]["Start_Timestamp"])) / 1e6
+    agg = {}
+    for r, d in zip(seq, dur):
+        a = agg.setdefault(_short(r["Kernel_Name"]), [0, 0.0, 1e30, 0.0])
+        a[0] += 1
+        a[1] += d
+        a[2] = min(a[2], d)
+        a[3] = max(a[3], d)
+    busy = sum(dur)
+    lines = ["One solve taken from the kernel trace (the launches between the last two int8 refinement "
+             "products): span %.2f ms, kernels busy %.2f ms, %d launches." % (span, busy / 1e3, len(seq)), "",
+             "| kernel | launches | total ms | avg us | min us | max us | share |", "|---|---|---|---|---|---|---|"]
+    for name, a in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        lines.append("| `%s` | %d | %.3f | %.1f | %.1f | %.1f | %.1f%% |"
+                     % (name, a[0], a[1] / 1e3, a[1] / a[0], a[2], a[3], 100.0 * a[1] / busy))
+    sweeps, cur = [], None
+    for r, d in zip(seq, dur):
+        name = _short(r["Kernel_Name"])
+        if name == "sweep_begin":
+            cur = [0.0, 0]
+            sweeps.append(cur)
+        if cur is not None and name in ("sweep_begin", "pair_solve", "pair_apply"):
+            cur[0] += d
+            cur[1] += 1
+        if name == "rank_select":
+            cur = None
+    lines += ["", "Submatrix eigensolver, kernel time per sweep (us / launches): "
+              + ", ".join("%.0f / %d" % (t, c) for t, c in sweeps)]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     a = ap.parse_args()
     n = a.n
+    if a.trace_summary:
+        trace_summary(a.trace_summary, a.out)
+        return
     if a.summarize:
         summarize(a.summarize[0], a.summarize[1], n, a.out)
         return
