@@ -70,8 +70,10 @@ typedef enum pfsm_precision {
                                overlap and back-rotation with every operand split into hi + lo
                                BF16 parts (three products), the folded-spectrum products on plain
                                BF16 operands (one product; see PFSM_FLAG_FS_SPLIT); FP64 for the
-                               submatrix eigensolver and the final Rayleigh quotients / cluster
-                               Rayleigh-Ritz against A (from an FP64-accurate int8 digit product).
+                               submatrix eigensolver (its rotation floor 2^-24 of the Gershgorin
+                               bound, the unit roundoff of the FP32 start vectors) and the final
+                               Rayleigh quotients / cluster Rayleigh-Ritz against A (from an
+                               FP64-accurate int8 digit product).
                                Orthonormalisation: to first order in S - I while max |S - I| <=
                                1e-3 (a correction product on the matrix cores), otherwise the FP64
                                Cholesky-QR of the overlap, chosen on the device */
@@ -110,10 +112,10 @@ typedef struct pfsm_desc {
  * (X Phi(S - I)^T), on hi/lo split operands (three BF16 products, FP32
  * accumulation) instead of the default plain BF16 operands (one product, FP32
  * accumulation).
- * The FP64 refinement against A removes what the plain products leave (at
- * N = 8192 the refined eigenvalues are 3.3e-10 from an FP64 computation either
- * way); the unrefined estimates (PFSM_FLAG_NO_REFINE) are about 4 % closer
- * with the split. */
+ * The FP64 refinement against A removes what the plain products leave: the
+ * refined eigenvalues of the two forms agree to 1e-9 of max |lambda| and both
+ * stay within 1e-8 of an FP64 computation; only the unrefined estimates
+ * (PFSM_FLAG_NO_REFINE) move. */
 #define PFSM_FLAG_FS_SPLIT 2
 /* Compute the per-column residuals r_i = ||A v_i - lambda_i v_i||_2 of the
  * returned eigenpairs during the solve (read them with pfsm_residuals).  FP64
