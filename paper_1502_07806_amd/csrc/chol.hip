@@ -292,16 +292,16 @@ __global__ __launch_bounds__(512) void k_chol_ll(double* S, int64_t lds, double*
 __global__ __launch_bounds__(256) void k_f32_to_f64_gated(const float* X, int64_t ldx, double* Y, int64_t ldy, int64_t m,
                                                           int64_t n, const int* gate) {
   if (*gate == 0) return;
-  const int64_t j = blockIdx.y;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
-    Y[i + j * ldy] = (double)X[i + j * ldx];
+  for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
+      Y[i + j * ldy] = (double)X[i + j * ldx];
 }
 __global__ __launch_bounds__(256) void k_f64_to_f32_gated(const double* Y, int64_t ldy, float* X, int64_t ldx, int64_t m,
                                                           int64_t n, const int* gate) {
   if (*gate == 0) return;
-  const int64_t j = blockIdx.y;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
-    X[i + j * ldx] = (float)Y[i + j * ldy];
+  for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
+      X[i + j * ldx] = (float)Y[i + j * ldy];
 }
 
 
@@ -387,7 +387,8 @@ hipError_t cholesky_qr_gated(double* S, int64_t lds, double* X, int64_t ldx, int
 hipError_t convert_f32_f64_gated(const float* X32, int64_t ld32, double* X64, int64_t ld64, int64_t m, int64_t n,
                                  int to_f64, const int* gate, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  const dim3 grid((unsigned)std::min<int64_t>((m + 255) / 256, 16), (unsigned)n);
+  // a modest grid, columns in a stride loop: when the gate is off every workgroup only reads it
+  const dim3 grid((unsigned)std::min<int64_t>((m + 255) / 256, 16), (unsigned)std::min<int64_t>(n, 128));
   if (to_f64)
     hipLaunchKernelGGL(k_f32_to_f64_gated, grid, dim3(256), 0, s, X32, ld32, X64, ld64, m, n, gate);
   else

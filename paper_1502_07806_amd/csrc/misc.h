@@ -4,6 +4,11 @@ namespace pfsm {
 hipError_t fill_i32(int* p, int64_t count, int value, hipStream_t s);
 // y[i] = deterministic pseudo-random values in [-1, 1) (hash of i and seed).
 hipError_t fill_hash_f32(float* y, int64_t count, uint32_t seed, hipStream_t s);
+// Zero rows [krange[2 t], krange[2 t + 1]) (clipped to m) of every column c of
+// X (m x n, column-major), t = c / tile_n: what remains is X outside the K
+// range a per-column-tile product with that krange covers.
+hipError_t zero_krange_rows(float* X, int64_t ldx, int64_t m, int64_t n, const int32_t* krange, int64_t tile_n,
+                            hipStream_t s);
 hipError_t gershgorin_alpha(const double* At, int64_t n, int64_t ld, int q, double user_alpha,
                             double* part_lo, double* part_hi, double* scal, int* info, hipStream_t s);
 hipError_t rq_reduce(const double* part, int tiles_m, int64_t n, const double* den, double* out, hipStream_t s);

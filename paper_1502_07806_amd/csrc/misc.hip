@@ -336,6 +336,20 @@ hipError_t fill_hash_f32(float* y, int64_t count, uint32_t seed, hipStream_t s) 
   return hipGetLastError();
 }
 
+__global__ void k_zero_krange_rows(float* X, int64_t ldx, int64_t m, const int32_t* krange, int64_t tile_n) {
+  const int64_t c = blockIdx.x;
+  const int64_t t = c / tile_n;
+  const int64_t r0 = krange[2 * t], r1 = min<int64_t>(krange[2 * t + 1], m);
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) X[r + c * ldx] = 0.0f;
+}
+
+hipError_t zero_krange_rows(float* X, int64_t ldx, int64_t m, int64_t n, const int32_t* krange, int64_t tile_n,
+                            hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_krange_rows, dim3((unsigned)n), dim3(256), 0, s, X, ldx, m, krange, tile_n);
+  return hipGetLastError();
+}
+
 hipError_t fill_i32(int* p, int64_t count, int value, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 1024))),
                      dim3(256), 0, s, p, count, value);

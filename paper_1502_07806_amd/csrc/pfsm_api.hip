@@ -721,12 +721,29 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   }
   clk.mark(22);
   clk.mark(23);  // the ordering comes with the refinement, after the back-rotation
+  // V_new = V + V (X - I), the sum over k split in two: the rows of X that
+  // belong to the submatrices of a column tile (the K range of the first
+  // folded-spectrum product) on split operands, where X - I holds the
+  // rotations, which are of order one inside clusters; the other rows on
+  // plain operands, where X holds only the small components the folded-spectrum
+  // iterations added outside the submatrices (about 1e-4 per column at
+  // N = 8192), so the plain product's rounding, 2^-9 of those, stays far
+  // below the split product's on the first part.  The identity lies inside
+  // the first part, so the second is X itself with those rows zeroed.
   PFSM_TRY(pack_x3(X32, 0, n, n, n, PACK_SUB_I, Xpk, ldp, s));  // columns of X - I
   PFSM_TRY(pack_x3(dV, 1, n, n, ldv, PACK_BY_ROWS, Rpk, ldp, s));  // rows of V
   {
     X3Args g = x3(X3_ADD, n, n, n, Rpk, Xpk, Vn64, n, 1);
-    g.D = dV; g.ldd = ldv; g.d_double = 1;
+    g.D = dV; g.ldd = ldv; g.d_double = 1; g.krange = pl->d_krange_x3;
     PFSM_TRY(gemm_x3(X3_ADD, g, s));
+  }
+  PFSM_TRY(zero_krange_rows(X32, n, n, n, pl->d_krange_x3, X3_BN, s));
+  PFSM_TRY(pack_x3(X32, 0, n, n, n, PACK_PLAIN, Ypk, ldq, s));                  // columns of X outside those rows
+  PFSM_TRY(pack_x3(dV, 1, n, n, ldv, PACK_BY_ROWS | PACK_PLAIN, Atpk, ldq, s));  // rows of V, plain
+  {
+    X3Args h = x3(X3_ADD, n, n, n, Atpk, Ypk, Vn64, n, 1);
+    h.D = Vn64; h.ldd = n; h.d_double = 1; h.products = 1; h.ldap = h.ldbp = ldq;
+    PFSM_TRY(gemm_x3(X3_ADD, h, s));
   }
   if (!refine) {
     clk.mark(24);
