@@ -520,6 +520,9 @@ def main():
         kernel_key = "gemm_x3_fsupd_plain_n%d" % n
     achieved = dom_flops / (upd_ms * 1e-3) / 1e12
     traffic = load_traffic(kernel_key)
+    band_products = None
+    if precision != "fp64":
+        band_products = plan.debug_stats()["fs_band_products"]
     out = {
         "metric": "PFSM solves/s + TFLOP/s at N=8192, mixed vs FP64 GPU path, eig err <=1e-8",
         "value": 1e3 / ms,
@@ -542,6 +545,9 @@ def main():
                    "n": n, "slices": len(offs) - 1, "submatrix_order": M, "iterations": n_it,
                    "precision": precision, "split_bf16_tile_config": tuned.get(precision)},
         "tflops": F / (ms * 1e-3) / 1e12,
+        "tflops_note": "the method's product flops (dense folded-spectrum products, 19.33 N^3 + 2 N^2 M) per "
+                       "second; the band form of the folded-spectrum products and the back-rotation's split "
+                       "perform fewer",
         "accuracy": acc,
         "stages_ms": {k: round(v, 4) for k, v in st.items() if v > 0.01},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -556,7 +562,27 @@ def main():
         s_dig = int(pf.load_library().pfsm_refine_digit_count())
         pairs = s_dig * (s_dig + 1) // 2
         oz_ops = pairs * 2.0 * n ** 3
-        out["roofline_fs_update"] = out["roofline"]
+        if band_products == q * n_it:
+            # Band form (every folded-spectrum product took it): the product on
+            # the off-diagonal part of At over the submatrix rows of each
+            # 256-column tile (K = M rows), the diagonal term and the update
+            # in the epilogue.  Bound by HBM: the FP32 epilogue reads Y and X
+            # and writes X (12 N^2 bytes), the tiles read their columns of the
+            # off-diagonal At (N/256 tiles x N x M bf16) and their rows of Y.
+            kb = min(n, M)
+            band_bytes = 12.0 * n * n + (n / 256.0) * n * kb * 2.0 + n * kb * 2.0
+            gbs = band_bytes / (upd_ms * 1e-3) / 1e9
+            out["roofline_fs_update"] = {
+                "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                "traffic": None,
+                "kernel": "gemm_x3_dl<X3_FSUPD, plain>, band form (off-diagonal At times the submatrix rows of Y, "
+                          "K = %d per column tile; diagonal term and update in the FP32 epilogue), and the gated-off "
+                          "full form" % kb,
+                "launch_ms": upd_ms, "bytes_per_launch": band_bytes,
+                "flops_per_launch": 2.0 * n * n * kb}
+        else:
+            out["roofline_fs_update"] = out["roofline"]
+        out["fs_band_products"] = band_products
         out["roofline"] = {
             "bound": "mfma", "achieved": oz_ops / (oz_ms * 1e-3) / 1e12, "peak": PEAK_TOPS_INT8, "unit": "TOP/s",
             "frac": oz_ops / (oz_ms * 1e-3) / 1e12 / PEAK_TOPS_INT8, "traffic": load_traffic("gemm_oz_n%d" % n),

@@ -58,6 +58,22 @@ struct X3Args {
   // ldap / ldbp = their row strides), FP32 accumulation, in the direct-to-LDS
   // configuration whatever cfg says
   int products;
+  // Band form of the folded-spectrum products (SHIFT / FSUPD).  diag: the
+  // diagonal d of the left operand's matrix (FP64, d_i = diag[i * diag_stride]);
+  // the product itself then runs on the off-diagonal part, and the epilogue
+  // adds (d_i - eps_j) b_ij.
+  const double* diag; int64_t diag_stride;
+  // far_krange / farmax_out: the largest |output| over the rows outside the
+  // K range far_krange gives the output's column tile, folded into
+  // *farmax_out (the bits of a non-negative float, atomic max).
+  const int32_t* far_krange; unsigned* farmax_out;
+  // Gate (optional): with m = *gate_far (a float's bits) and the Gershgorin
+  // scalars gate_scal (scal[1], scal[2]: interval; scal[3]: largest
+  // off-diagonal absolute row sum rho), the terms a K-range-restricted product
+  // drops are negligible when rho * m <= 2^-20 max(|scal[1]|, |scal[2]|); the
+  // kernel runs only when that test equals gate_band (NaN: the test fails).
+  // band_count (optional) counts the launches of the band form that ran.
+  const unsigned* gate_far; const double* gate_scal; int gate_band; unsigned* band_count;
 };
 
 constexpr int X3_NUM_CFG = 6;
@@ -74,12 +90,14 @@ size_t x3_split_bytes(int64_t n);
 // column-major with ld; src_double selects FP64 or FP32 storage.
 // PACK_SUB_I packs X - I; PACK_LOWER / PACK_UPPER keep only the lower / upper
 // triangle of X (row >= col / row <= col), zeros elsewhere; PACK_HALF_DIAG
-// halves the diagonal (after PACK_SUB_I).
+// halves the diagonal (after PACK_SUB_I); PACK_OFFDIAG zeroes it.
 // PACK_PLAIN writes the plain layout: row r holds bf16(x) for k = 0 .. K-1
 // contiguously (no lo values), zero-filled to a multiple of 32, row stride at
 // least x3_plain_stride(K).
 enum PackFlags : int { PACK_BY_ROWS = 1, PACK_SUB_I = 2, PACK_LOWER = 4, PACK_UPPER = 8, PACK_HALF_DIAG = 16,
-                       PACK_PLAIN = 32 };
+                       PACK_PLAIN = 32, PACK_OFFDIAG = 64 };
+// Largest dropped-term bound of the band form, relative to the Gershgorin bound.
+constexpr double X3_BAND_TOL = 9.5367431640625e-07;  // 2^-20
 inline int64_t x3_plain_stride(int64_t K) { return 32 * ((K + 31) / 32); }
 hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P, int64_t ldp,
                    hipStream_t s);

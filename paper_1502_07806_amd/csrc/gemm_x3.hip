@@ -94,6 +94,17 @@ __device__ inline void x3_k_range(const X3Args& g, int tn, int64_t m0, int64_t n
   if (g.tiles == X3_KPREFIX) kend = min<int64_t>(kend, n0 + BN);
 }
 
+// Gate of the band / full forms of a folded-spectrum product (see X3Args):
+// true when this launch is not the one that should run.  Every workgroup reads
+// the same words, written by earlier launches, so the whole grid agrees.
+__device__ inline bool x3_gate_closed(const X3Args& g) {
+  if (!g.gate_far) return false;
+  const float m = __uint_as_float(*g.gate_far);
+  const double G = fmax(fabs(g.gate_scal[1]), fabs(g.gate_scal[2]));
+  const bool band_ok = g.gate_scal[3] * (double)m <= X3_BAND_TOL * G;  // false for NaN
+  return band_ok != (g.gate_band != 0);
+}
+
 // Epilogue shared by the split-BF16 kernels: acc[ib][jb][r] is C(i, j) with
 // i = wi0 + 32 ib + lane % 32, j = wj0 + 32 jb + 8 (r / 4) + 4 (lane / 32) + r % 4.
 template <int EPI, int WGR, int WR, int WC>
@@ -137,6 +148,14 @@ __device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t
   }
   double a_eff = g.alpha;
   if (EPI == X3_FSUPD && g.alpha_dev) a_eff = *g.alpha_dev;
+  // rows outside [fk0, fk1) are the far rows of this column tile
+  int64_t fk0 = 0, fk1 = 0;
+  if ((EPI == X3_SHIFT || EPI == X3_FSUPD) && g.farmax_out) {
+    const int64_t tn = n0 / BN;
+    fk0 = g.far_krange[2 * tn];
+    fk1 = g.far_krange[2 * tn + 1];
+  }
+  float farmax = 0.0f;
   // C may alias D (in-place update): the inputs of 8 outputs are gathered
   // before any of them is stored, so 8 loads are in flight instead of one.
   constexpr int GR = 8;
@@ -144,6 +163,8 @@ __device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t
   for (int ib = 0; ib < WR; ++ib) {
     const int64_t gi = m0 + wi0 + ib * 32 + l32;
     if (gi >= g.M) continue;
+    const double dg = ((EPI == X3_SHIFT || EPI == X3_FSUPD) && g.diag) ? g.diag[gi * g.diag_stride] : 0.0;
+    const bool far_row = gi < fk0 || gi >= fk1;
 #pragma unroll
     for (int jb = 0; jb < WC; ++jb)
 #pragma unroll
@@ -180,13 +201,25 @@ __device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t
           const double v = (double)acc[ib][jb][r];
           double outv;
           if (EPI == X3_STORE) outv = g.alpha * v + g.beta * in1[u];
-          else if (EPI == X3_SHIFT) outv = v - in1[u] * ev[u];
-          else if (EPI == X3_FSUPD) outv = in2[u] - a_eff * (v - in1[u] * ev[u]);
+          else if (EPI == X3_SHIFT) outv = v + in1[u] * (dg - ev[u]);
+          else if (EPI == X3_FSUPD) outv = in2[u] - a_eff * (v + in1[u] * (dg - ev[u]));
           else outv = g.alpha * v + in1[u];
           if (g.c_double) ((double*)g.C)[gi + gj * g.ldc] = outv;
           else ((float*)g.C)[gi + gj * g.ldc] = (float)outv;
+          if ((EPI == X3_SHIFT || EPI == X3_FSUPD) && far_row) {
+            const float a = fabsf((float)outv);
+            farmax = (a > farmax || a != a) ? a : farmax;
+          }
         }
       }
+  }
+  if ((EPI == X3_SHIFT || EPI == X3_FSUPD) && g.farmax_out) {
+    // wave maximum, then one atomic per wave (non-negative floats order like
+    // their bits; a NaN's bits exceed every finite value's)
+    unsigned mb = __float_as_uint(farmax);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) mb = max(mb, (unsigned)__shfl_xor((int)mb, off, 64));
+    if (lane == 0 && mb != 0u) atomicMax(g.farmax_out, mb);
   }
 }
 
@@ -198,6 +231,8 @@ __global__ __launch_bounds__(X3Cfg<CFG>::NT, 1) void gemm_x3_kernel(X3Args g, in
   unsigned char* As = lds;                       // [2][BM][ROWB]
   unsigned char* Bs = lds + 2 * TILE_BYTES;      // [2][BN][ROWB]
   __shared__ double red[WGR][BN];
+  if (x3_gate_closed(g)) return;
+  if (g.band_count && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(g.band_count, 1u);
 
   int tm, tn;
   x3_tile_coords(g, tiles_m, tiles_n, tm, tn);
@@ -335,6 +370,8 @@ __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int 
   constexpr int NW = 8, WGR = 4, WR = 2, WC = 4, CPW = 16 / NW;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   __shared__ double red[WGR][BN];
+  if (x3_gate_closed(g)) return;
+  if (g.band_count && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(g.band_count, 1u);
   int tm, tn, unit = -1;  // unit: K-split piece of a tail tile, -1 for a whole tile
   if (g.split_s > 0 && (int)blockIdx.x >= g.split_full) {
     unit = (int)blockIdx.x - g.split_full;
@@ -584,6 +621,7 @@ __global__ __launch_bounds__(256) void k_pack(const void* X, int src_double, int
       v = src_double ? ((const double*)X)[row + col * ldx] : (double)((const float*)X)[row + col * ldx];
       if ((flags & PACK_SUB_I) && row == col) v -= 1.0;
       if ((flags & PACK_HALF_DIAG) && row == col) v *= 0.5;
+      if ((flags & PACK_OFFDIAG) && row == col) v = 0.0;
     }
     tile[rr][kk] = v;
   }
@@ -652,7 +690,7 @@ __global__ __launch_bounds__(256) void k_pack_cols(const void* X, int64_t K, int
       v[u] = k < K ? (DBL ? ((const double*)X)[k + r * ldx] : (double)((const float*)X)[k + r * ldx]) : 0.0;
     }
   }
-  if (flags & (PACK_LOWER | PACK_UPPER | PACK_SUB_I | PACK_HALF_DIAG)) {
+  if (flags & (PACK_LOWER | PACK_UPPER | PACK_SUB_I | PACK_HALF_DIAG | PACK_OFFDIAG)) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t k = k0 + u;  // X(row = k, col = r)
@@ -660,6 +698,7 @@ __global__ __launch_bounds__(256) void k_pack_cols(const void* X, int64_t K, int
       if (k == r && k < K) {
         if (flags & PACK_SUB_I) v[u] -= 1.0;
         if (flags & PACK_HALF_DIAG) v[u] *= 0.5;
+        if (flags & PACK_OFFDIAG) v[u] = 0.0;
       }
     }
   }

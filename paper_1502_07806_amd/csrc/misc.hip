@@ -48,22 +48,25 @@ __global__ __launch_bounds__(NT) void k_gersh_col(const double* At, int64_t n, i
 
 __global__ __launch_bounds__(NT) void k_gersh_final(const double* lo, const double* hi, int64_t n, int q,
                                                      double user_alpha, double* scal, int* info) {
-  __shared__ double slo[NT], shi[NT];
-  double a = DBL_MAX, b = -DBL_MAX;
+  __shared__ double slo[NT], shi[NT], srad[NT];
+  double a = DBL_MAX, b = -DBL_MAX, rad = 0.0;  // rad: largest off-diagonal absolute row sum
   for (int64_t i = threadIdx.x; i < n; i += NT) {
     double x = lo[i], y = hi[i];
     a = (x != x) ? x : fmin(a, x);  // keep NaN visible (fmin would drop it)
     b = (y != y) ? y : fmax(b, y);
-    if (a != a || b != b) { a = b = __builtin_nan(""); break; }
+    rad = fmax(rad, 0.5 * (y - x));
+    if (a != a || b != b) { a = b = rad = __builtin_nan(""); break; }
   }
   slo[threadIdx.x] = a;
   shi[threadIdx.x] = b;
+  srad[threadIdx.x] = rad;
   __syncthreads();
   for (int w = NT / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
-      double a2 = slo[threadIdx.x + w], b2 = shi[threadIdx.x + w];
+      double a2 = slo[threadIdx.x + w], b2 = shi[threadIdx.x + w], r2 = srad[threadIdx.x + w];
       slo[threadIdx.x] = (a2 != a2) ? a2 : fmin(slo[threadIdx.x], a2);
       shi[threadIdx.x] = (b2 != b2) ? b2 : fmax(shi[threadIdx.x], b2);
+      srad[threadIdx.x] = (r2 != r2) ? r2 : fmax(srad[threadIdx.x], r2);
     }
     __syncthreads();
   }
@@ -75,6 +78,7 @@ __global__ __launch_bounds__(NT) void k_gersh_final(const double* lo, const doub
     scal[0] = alpha;
     scal[1] = slo[0];
     scal[2] = shi[0];
+    scal[3] = srad[0];
     // A non-finite entry of A or V_prev spreads over every entry of At.
     if (info && !(isfinite(slo[0]) && isfinite(shi[0]))) atomicCAS(info, 0, -1);
   }

@@ -79,6 +79,7 @@ struct pfsm_plan {
   size_t m_oz;  // digit planes of A and V_new for the refinement product, then 2n exponents
   size_t m_split = 0, split_bytes = 0;  // K-split scratch of the lower-triangle split-BF16 products
   size_t m_gate = 0, m_bcopy = 0;  // orthonormalisation: fallback gate word, Cholesky block copies
+  size_t m_Epk = 0, m_fm = 0;       // band form of the folded-spectrum products: off-diagonal At, far maxima
 };
 
 namespace {
@@ -139,6 +140,13 @@ struct StageClock {
     hipError_t _e = (expr);                     \
     if (_e != hipSuccess) return PFSM_HIP_ERROR; \
   } while (0)
+
+// The mixed path's folded-spectrum products run on plain BF16 operands (q = 2,
+// unless the split is asked for), and then also in the band form.
+bool mixed_band_form(const pfsm_plan* pl) {
+  return pl->precision == PFSM_PREC_MIXED_BF16 && !(pl->flags & PFSM_FLAG_FS_SPLIT) && pl->q == 2 &&
+         pl->iterations > 0;
+}
 
 // Rotation floor of the submatrix eigensolver: the FP64 rounding floor, or the
 // looser one of the mixed path, whose start vectors are stored in FP32.
@@ -350,6 +358,8 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     pl->m_oz = w; w = align256(w + oz);
     pl->m_gate = w; w = align256(w + sizeof(int));
     pl->m_bcopy = w; w = align256(w + (size_t)((n + CHOL_NB - 1) / CHOL_NB) * CHOL_NB * CHOL_NB * sizeof(double));
+    pl->m_Epk = w; w = align256(w + (size_t)n * x3_plain_stride(n) * sizeof(bf16_t));
+    pl->m_fm = w; w = align256(w + (size_t)(2 * pl->iterations + 4) * sizeof(unsigned));
   }
   pl->total = w;
   *out = pl;
@@ -582,7 +592,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   // stride ldq) for those products only.  The refinement against A in FP64
   // removes what the single BF16 product leaves in the vectors (at N = 8192
   // the refined eigenvalues stay 3.3e-10 from an FP64 computation).
-  const bool fs_plain = !(pl->flags & PFSM_FLAG_FS_SPLIT) && pl->q == 2 && pl->iterations > 0;
+  const bool fs_plain = mixed_band_form(pl);
   const int64_t ldq = x3_plain_stride(n);
   double* At64 = (double*)(W + pl->o_At);
   double* B64a = (double*)(W + pl->o_b0);   // X0 (FP64), later Z = A V_new
@@ -642,24 +652,55 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   PFSM_TRY(pack_x3(X32, 0, n, n, n, fs_plain ? PACK_PLAIN : 0, Xpk, fs_plain ? ldq : ldp, s));
   clk.mark(3);
   // (3) folded-spectrum iterations (X master copy in FP32).
+  // Band form (plain operands): (At - eps) B = E B_band + (D - eps) B + E B_far
+  // with D the diagonal of At, E the rest, B_band the rows of the operand
+  // inside the K range of its column tile (the submatrix rows) and B_far the
+  // others.  The first two terms are computed, the product on E restricted to
+  // that K range, the diagonal term exactly in the epilogue; the third is
+  // dropped when its bound, rho max |B_far| (rho: largest off-diagonal
+  // absolute row sum of At), is at most 2^-20 of the Gershgorin bound, far
+  // below the rounding of a plain BF16 product of the whole matrix (2^-9).
+  // Every product is enqueued in both forms behind a device gate on that
+  // bound (the other launch returns at once), and every epilogue records the
+  // largest far-row output for the gate of the next product: a static launch
+  // sequence.  X0 has no far rows (zero padding), so fm[0] = 0.
+  unsigned* fm = (unsigned*)(W + pl->m_fm);
+  const bool band = fs_plain;
+  if (band) {
+    PFSM_TRY(pack_x3(At32, 0, n, n, n, PACK_PLAIN | PACK_OFFDIAG, (bf16_t*)(W + pl->m_Epk), ldq, s));
+    PFSM_TRY(fill_i32((int*)fm, 2 * pl->iterations + 4, 0, s));
+  }
+  // the product in the band and full forms; f_in / f_out: far maxima of operand and output
+  auto fs_gemm = [&](int epi, X3Args g, int f_in, int f_out) -> hipError_t {
+    if (!band) return gemm_x3(epi, g, s);
+    g.far_krange = pl->d_krange_x3; g.farmax_out = fm + f_out;
+    g.gate_far = fm + f_in; g.gate_scal = scal;
+    X3Args b = g;
+    b.Ap = (const bf16_t*)(W + pl->m_Epk); b.krange = pl->d_krange_x3; b.diag = At64; b.diag_stride = n + 1;
+    b.gate_band = 1; b.band_count = fm + 2 * pl->iterations + 3;
+    hipError_t e1 = gemm_x3(epi, b, s);
+    if (e1 != hipSuccess) return e1;
+    g.gate_band = 0;
+    return gemm_x3(epi, g, s);
+  };
   for (int it = 0; it < pl->iterations; ++it) {
     const int32_t* kr = (it == 0) ? pl->d_krange_x3 : nullptr;
     if (pl->q == 2) {
       X3Args g = x3(X3_SHIFT, n, n, n, Atpk, Xpk, Y32, n, 0);
       g.B32 = X32; g.ldb32 = n; g.eps = eps; g.krange = kr;
       if (fs_plain) { g.products = 1; g.ldap = g.ldbp = ldq; }
-      PFSM_TRY(gemm_x3(X3_SHIFT, g, s));  // Y = (At - eps) X
+      PFSM_TRY(fs_gemm(X3_SHIFT, g, 2 * it, 2 * it + 1));  // Y = (At - eps) X
       PFSM_TRY(pack_x3(Y32, 0, n, n, n, fs_plain ? PACK_PLAIN : 0, Ypk, fs_plain ? ldq : ldp, s));
       if (it < 8) clk.mark(4 + 2 * it);
       X3Args h = x3(X3_FSUPD, n, n, n, Atpk, Ypk, X32, n, 0);
       h.B32 = Y32; h.ldb32 = n; h.D = X32; h.ldd = n; h.eps = eps; h.alpha_dev = scal;
       if (fs_plain) { h.products = 1; h.ldap = h.ldbp = ldq; }
-      PFSM_TRY(gemm_x3(X3_FSUPD, h, s));  // X <- X - a (At - eps) Y
+      PFSM_TRY(fs_gemm(X3_FSUPD, h, 2 * it + 1, 2 * it + 2));  // X <- X - a (At - eps) Y
     } else {
       if (it < 8) clk.mark(4 + 2 * it);
       X3Args h = x3(X3_FSUPD, n, n, n, Atpk, Xpk, X32, n, 0);
       h.B32 = X32; h.ldb32 = n; h.D = X32; h.ldd = n; h.eps = eps; h.alpha_dev = scal; h.krange = kr;
-      PFSM_TRY(gemm_x3(X3_FSUPD, h, s));  // X <- X - a (At - eps) X (operand read from the packed copy)
+      PFSM_TRY(fs_gemm(X3_FSUPD, h, 2 * it, 2 * it + 2));  // X <- X - a (At - eps) X (operand read from the packed copy)
     }
     if (it < 8) clk.mark(5 + 2 * it);  // the update stage holds exactly one GEMM launch
     // the next iteration's operand, or the split operand of the overlap
@@ -812,13 +853,13 @@ pfsm_status pfsm_debug_stats(pfsm_plan* pl, const void* dWork, size_t work_bytes
                              int32_t* count) {
   if (!pl || !dWork || !out || !count || work_bytes < pl->total) return PFSM_INVALID_ARG;
   const int64_t n = pl->n;
-  const int32_t need = 2 * pl->P + 3;
+  const int32_t need = 2 * pl->P + 4;
   if (capacity < need) return PFSM_INVALID_ARG;
   if (hipDeviceSynchronize() != hipSuccess) return PFSM_HIP_ERROR;
   if (hipMemcpy(out, (const char*)dWork + pl->o_stats, 2 * pl->P * sizeof(int32_t), hipMemcpyDeviceToHost) !=
       hipSuccess)
     return PFSM_HIP_ERROR;
-  out[2 * pl->P] = out[2 * pl->P + 1] = out[2 * pl->P + 2] = 0;
+  out[2 * pl->P] = out[2 * pl->P + 1] = out[2 * pl->P + 2] = out[2 * pl->P + 3] = 0;
   if (pl->precision == PFSM_PREC_MIXED_BF16) {
     // refinement clusters: count, then the largest cluster size
     const double* rb = (const double*)((const char*)dWork + pl->m_rb);
@@ -837,6 +878,13 @@ pfsm_status pfsm_debug_stats(pfsm_plan* pl, const void* dWork, size_t work_bytes
     out[2 * pl->P] = cnt;
     out[2 * pl->P + 1] = multi;
     out[2 * pl->P + 2] = mx;
+    if (mixed_band_form(pl)) {  // folded-spectrum products that ran in the band form
+      unsigned bc = 0;
+      if (hipMemcpy(&bc, (const char*)dWork + pl->m_fm + (2 * pl->iterations + 3) * sizeof(unsigned), sizeof(bc),
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        return PFSM_HIP_ERROR;
+      out[2 * pl->P + 3] = (int32_t)bc;
+    }
   }
   *count = need;
   return PFSM_OK;
