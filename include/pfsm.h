@@ -290,9 +290,10 @@ pfsm_status pfsm_diagnostics(pfsm_plan* plan, const double* dA, int64_t lda, con
  * device).  out[2p] = sweep at which submatrix p was found converged (0: never),
  * out[2p+1] = pair problems of submatrix p that needed rotations; then, for
  * mixed precision, the number of refinement clusters, of clusters with more
- * than one estimate, the largest cluster, and the number of folded-spectrum
- * products that ran in the band form.  *count = 2P + 4.
- * Errors: INVALID_ARG (capacity < 2P + 4), HIP_ERROR. */
+ * than one estimate, the largest cluster, the number of folded-spectrum
+ * products that ran in the band form, and 1 if the orthonormalisation
+ * correction did (0 otherwise).  *count = 2P + 5.
+ * Errors: INVALID_ARG (capacity < 2P + 5), HIP_ERROR. */
 pfsm_status pfsm_debug_stats(pfsm_plan* plan, const void* dWork, size_t work_bytes, int32_t* out, int32_t capacity,
                              int32_t* count);
 pfsm_status pfsm_timing_begin(pfsm_plan* plan, int32_t max_solves);

@@ -282,7 +282,7 @@ class Plan:
     def debug_stats(self):
         """Counters of the last solve: per-submatrix sweeps and rotating pair problems, refinement clusters."""
         P = len(self.part_offsets) - 1
-        cap = 2 * P + 4
+        cap = 2 * P + 5
         buf = (ctypes.c_int32 * cap)()
         cnt = ctypes.c_int32()
         _check(load_library().pfsm_debug_stats(self._h, self._work.data_ptr(), self.workspace_bytes, buf, cap,
@@ -290,7 +290,7 @@ class Plan:
         v = list(buf)
         return {"converged_sweep": v[0:2 * P:2], "rotating_pairs": v[1:2 * P:2],
                 "clusters": v[2 * P], "multi_clusters": v[2 * P + 1], "max_cluster": v[2 * P + 2],
-                "fs_band_products": v[2 * P + 3]}
+                "fs_band_products": v[2 * P + 3], "correction_band": v[2 * P + 4]}
 
     # -- stage timing (instrumentation for benchmarks)
     TIMING_BOUNDS = 27

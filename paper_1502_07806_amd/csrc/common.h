@@ -11,6 +11,13 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 namespace pfsm {
 
+// Band forms of the mixed path's products (folded-spectrum products and the
+// orthonormalisation correction): the terms a product restricted to the
+// submatrix rows drops must stay below this bound, relative to the scale of
+// the product's output (2^-20, far below the 2^-9 rounding of the plain BF16
+// products of the whole matrix that the full forms compute).
+constexpr double PFSM_BAND_TOL = 9.5367431640625e-07;
+
 // ---------------------------------------------------------------- GEMM (FP64)
 // C = op(A) op(B) with a fused epilogue.  Column-major storage throughout.
 enum GemmEpi : int {

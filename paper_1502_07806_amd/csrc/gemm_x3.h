@@ -67,13 +67,15 @@ struct X3Args {
   // K range far_krange gives the output's column tile, folded into
   // *farmax_out (the bits of a non-negative float, atomic max).
   const int32_t* far_krange; unsigned* farmax_out;
-  // Gate (optional): with m = *gate_far (a float's bits) and the Gershgorin
-  // scalars gate_scal (scal[1], scal[2]: interval; scal[3]: largest
-  // off-diagonal absolute row sum rho), the terms a K-range-restricted product
-  // drops are negligible when rho * m <= 2^-20 max(|scal[1]|, |scal[2]|); the
-  // kernel runs only when that test equals gate_band (NaN: the test fails).
-  // band_count (optional) counts the launches of the band form that ran.
-  const unsigned* gate_far; const double* gate_scal; int gate_band; unsigned* band_count;
+  // Gate (optional): with m = *gate_far (a float's bits) and gate_cl = {c,
+  // limit} (device), the terms a K-range-restricted product drops, bounded by
+  // c m, are negligible when c m <= limit; the kernel runs only when that
+  // test equals gate_band (NaN: the test fails).  band_count (optional)
+  // counts the launches of the band form that ran.
+  const unsigned* gate_far; const double* gate_cl; int gate_band; unsigned* band_count;
+  // Optional [tiles_m][2] K range per row tile of C (multiples of 32),
+  // intersected with the column tiles' range.
+  const int32_t* krange_rows;
 };
 
 constexpr int X3_NUM_CFG = 6;
@@ -96,8 +98,7 @@ size_t x3_split_bytes(int64_t n);
 // least x3_plain_stride(K).
 enum PackFlags : int { PACK_BY_ROWS = 1, PACK_SUB_I = 2, PACK_LOWER = 4, PACK_UPPER = 8, PACK_HALF_DIAG = 16,
                        PACK_PLAIN = 32, PACK_OFFDIAG = 64 };
-// Largest dropped-term bound of the band form, relative to the Gershgorin bound.
-constexpr double X3_BAND_TOL = 9.5367431640625e-07;  // 2^-20
+
 inline int64_t x3_plain_stride(int64_t K) { return 32 * ((K + 31) / 32); }
 hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P, int64_t ldp,
                    hipStream_t s);

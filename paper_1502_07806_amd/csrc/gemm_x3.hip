@@ -82,14 +82,19 @@ __device__ inline void x3_tile_coords(const X3Args& g, int tiles_m, int tiles_n,
   }
 }
 
-// k range of a tile (multiples of 32): the optional per-column-tile range,
-// clipped in the KPREFIX mode (op(B) upper triangular).
-__device__ inline void x3_k_range(const X3Args& g, int tn, int64_t m0, int64_t n0, int64_t& kbeg, int64_t& kend) {
+// k range of a tile (multiples of 32): the optional per-column-tile and
+// per-row-tile ranges, clipped in the KPREFIX mode (op(B) upper triangular).
+__device__ inline void x3_k_range(const X3Args& g, int tm, int tn, int64_t m0, int64_t n0, int64_t& kbeg,
+                                   int64_t& kend) {
   kbeg = 0;
   kend = (g.K + 31) / 32 * 32;
   if (g.krange) {
     kbeg = g.krange[2 * tn];
     kend = g.krange[2 * tn + 1];
+  }
+  if (g.krange_rows) {
+    kbeg = max<int64_t>(kbeg, g.krange_rows[2 * tm]);
+    kend = min<int64_t>(kend, g.krange_rows[2 * tm + 1]);
   }
   if (g.tiles == X3_KPREFIX) kend = min<int64_t>(kend, n0 + BN);
 }
@@ -100,8 +105,7 @@ __device__ inline void x3_k_range(const X3Args& g, int tn, int64_t m0, int64_t n
 __device__ inline bool x3_gate_closed(const X3Args& g) {
   if (!g.gate_far) return false;
   const float m = __uint_as_float(*g.gate_far);
-  const double G = fmax(fabs(g.gate_scal[1]), fabs(g.gate_scal[2]));
-  const bool band_ok = g.gate_scal[3] * (double)m <= X3_BAND_TOL * G;  // false for NaN
+  const bool band_ok = g.gate_cl[0] * (double)m <= g.gate_cl[1];  // false for NaN
   return band_ok != (g.gate_band != 0);
 }
 
@@ -241,7 +245,7 @@ __global__ __launch_bounds__(X3Cfg<CFG>::NT, 1) void gemm_x3_kernel(X3Args g, in
   const int wi0 = (wave % WGR) * (32 * WR), wj0 = (wave / WGR) * (32 * WC);
   const int l32 = lane & 31, lh = lane >> 5;
   int64_t kbeg, kend;
-  x3_k_range(g, tn, m0, n0, kbeg, kend);
+  x3_k_range(g, tm, tn, m0, n0, kbeg, kend);
 
   v16f acc[WR][WC];
 #pragma unroll
@@ -385,7 +389,7 @@ __global__ __launch_bounds__(512, 1) void gemm_x3_dl(X3Args g, int tiles_m, int 
   const int wi0 = (wave % WGR) * (32 * WR), wj0 = (wave / WGR) * (32 * WC);
   const int l32 = lane & 31, lh = lane >> 5;
   int64_t kbeg, kend;
-  x3_k_range(g, tn, m0, n0, kbeg, kend);
+  x3_k_range(g, tm, tn, m0, n0, kbeg, kend);
   if (unit >= 0) {  // piece unit % S of S equal runs of k16 stages
     const int64_t st = kend > kbeg ? (kend - kbeg) / 16 : 0, sl = unit % g.split_s;
     const int64_t b0 = kbeg + 16 * (st * sl / g.split_s), b1 = kbeg + 16 * (st * (sl + 1) / g.split_s);

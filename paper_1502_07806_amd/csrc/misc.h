@@ -9,8 +9,9 @@ hipError_t fill_hash_f32(float* y, int64_t count, uint32_t seed, hipStream_t s);
 // range a per-column-tile product with that krange covers.
 hipError_t zero_krange_rows(float* X, int64_t ldx, int64_t m, int64_t n, const int32_t* krange, int64_t tile_n,
                             hipStream_t s);
-// Gershgorin interval of At (scal[1], scal[2]), the step length alpha (scal[0])
-// and the largest off-diagonal absolute row sum (scal[3]); info = -1 if not finite.
+// Gershgorin interval of At (scal[1], scal[2]), the step length alpha (scal[0]),
+// the largest off-diagonal absolute row sum (scal[3]) and PFSM_BAND_TOL times
+// the Gershgorin bound (scal[4]); info = -1 if not finite.
 hipError_t gershgorin_alpha(const double* At, int64_t n, int64_t ld, int q, double user_alpha,
                             double* part_lo, double* part_hi, double* scal, int* info, hipStream_t s);
 hipError_t rq_reduce(const double* part, int tiles_m, int64_t n, const double* den, double* out, hipStream_t s);

@@ -79,6 +79,8 @@ __global__ __launch_bounds__(NT) void k_gersh_final(const double* lo, const doub
     scal[1] = slo[0];
     scal[2] = shi[0];
     scal[3] = srad[0];
+    // dropped-term limit of the folded-spectrum products' band form
+    scal[4] = PFSM_BAND_TOL * fmax(fabs(slo[0]), fabs(shi[0]));
     // A non-finite entry of A or V_prev spreads over every entry of At.
     if (info && !(isfinite(slo[0]) && isfinite(shi[0]))) atomicCAS(info, 0, -1);
   }

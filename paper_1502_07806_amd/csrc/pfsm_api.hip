@@ -38,6 +38,7 @@ struct pfsm_plan {
   std::vector<int32_t> part_size, wsize, offset;
   std::vector<int32_t> krange;  // [tiles_n][2] K range of the first folded-spectrum product (128-column tiles)
   std::vector<int32_t> krange_x3;  // same for the 256-column tiles of the split-BF16 GEMM
+  std::vector<int32_t> krange_rows;  // [tiles][2] K range of the correction's band form per 256-row tile
   int Mp = 0, nb = 0;
   int device = 0;
   // device table
@@ -48,6 +49,7 @@ struct pfsm_plan {
   int64_t* d_part_start = nullptr;
   int32_t* d_krange = nullptr;
   int32_t* d_krange_x3 = nullptr;
+  int32_t* d_krange_rows = nullptr;
   // workspace layout (byte offsets)
   int x3_cfg = -1;  // split-BF16 GEMM tile configuration (-1: library default), set by pfsm_autotune
   // batched plans: independent sub-plans solved concurrently on internal streams
@@ -80,6 +82,7 @@ struct pfsm_plan {
   size_t m_split = 0, split_bytes = 0;  // K-split scratch of the lower-triangle split-BF16 products
   size_t m_gate = 0, m_bcopy = 0;  // orthonormalisation: fallback gate word, Cholesky block copies
   size_t m_Epk = 0, m_fm = 0;       // band form of the folded-spectrum products: off-diagonal At, far maxima
+  size_t m_gcl = 0;                 // gate scalars of the orthonormalisation correction's band form
 };
 
 namespace {
@@ -270,6 +273,23 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     pl->krange_x3.push_back((int32_t)lo);
     pl->krange_x3.push_back((int32_t)hi);
   }
+  // per 256-row tile: the columns whose tiles' K range (submatrix rows)
+  // meets the tile's rows, i.e. the k for which X(r, k) can lie inside its
+  // submatrix rows (the K range of the orthonormalisation correction's band form)
+  for (int64_t t = 0; t < tiles_x3; ++t) {
+    const int64_t r0 = t * X3_BM, r1 = std::min<int64_t>(n, r0 + X3_BM);
+    int64_t lo = -1, hi = -1;
+    for (int64_t u = 0; u < tiles_x3; ++u) {
+      const int64_t a = pl->krange_x3[2 * u], b = pl->krange_x3[2 * u + 1];
+      if (b <= r0 || a >= r1) continue;
+      if (lo < 0) lo = u;
+      hi = u;
+    }
+    lo = lo < 0 ? 0 : lo * X3_BN;
+    hi = hi < 0 ? 0 : std::min<int64_t>((n + 31) / 32 * 32, (hi + 1) * X3_BN);
+    pl->krange_rows.push_back((int32_t)lo);
+    pl->krange_rows.push_back((int32_t)hi);
+  }
   // device table
   size_t tb = 0;
   size_t o_ws = tb; tb = align256(tb + P * sizeof(int64_t));
@@ -278,6 +298,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   size_t o_ps = tb; tb = align256(tb + P * sizeof(int64_t));
   size_t o_kr = tb; tb = align256(tb + pl->krange.size() * sizeof(int32_t));
   size_t o_k3 = tb; tb = align256(tb + pl->krange_x3.size() * sizeof(int32_t));
+  size_t o_kw = tb; tb = align256(tb + pl->krange_rows.size() * sizeof(int32_t));
   void* sp = nullptr;
   if (hipGetDevice(&pl->device) != hipSuccess || x3_init() != hipSuccess || oz_init() != hipSuccess ||
       scratch_address(&sp) != hipSuccess || hipMalloc(&pl->dtab, tb) != hipSuccess) {
@@ -291,6 +312,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   pl->d_part_start = (int64_t*)(base + o_ps);
   pl->d_krange = (int32_t*)(base + o_kr);
   pl->d_krange_x3 = (int32_t*)(base + o_k3);
+  pl->d_krange_rows = (int32_t*)(base + o_kw);
   bool ok = hipMemcpy(pl->d_wstart, pl->wstart.data(), P * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(pl->d_wsize, pl->wsize.data(), P * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(pl->d_offset, pl->offset.data(), P * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
@@ -299,6 +321,8 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
             hipMemcpy(pl->d_krange, pl->krange.data(), pl->krange.size() * sizeof(int32_t),
                       hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(pl->d_krange_x3, pl->krange_x3.data(), pl->krange_x3.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(pl->d_krange_rows, pl->krange_rows.data(), pl->krange_rows.size() * sizeof(int32_t),
                       hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) {
     hipFree(pl->dtab);
@@ -360,6 +384,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     pl->m_bcopy = w; w = align256(w + (size_t)((n + CHOL_NB - 1) / CHOL_NB) * CHOL_NB * CHOL_NB * sizeof(double));
     pl->m_Epk = w; w = align256(w + (size_t)n * x3_plain_stride(n) * sizeof(bf16_t));
     pl->m_fm = w; w = align256(w + (size_t)(2 * pl->iterations + 4) * sizeof(unsigned));
+    pl->m_gcl = w; w = align256(w + 2 * sizeof(double));
   }
   pl->total = w;
   *out = pl;
@@ -674,7 +699,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   auto fs_gemm = [&](int epi, X3Args g, int f_in, int f_out) -> hipError_t {
     if (!band) return gemm_x3(epi, g, s);
     g.far_krange = pl->d_krange_x3; g.farmax_out = fm + f_out;
-    g.gate_far = fm + f_in; g.gate_scal = scal;
+    g.gate_far = fm + f_in; g.gate_cl = scal + 3;  // {rho, 2^-20 Gershgorin bound}
     X3Args b = g;
     b.Ap = (const bf16_t*)(W + pl->m_Epk); b.krange = pl->d_krange_x3; b.diag = At64; b.diag_stride = n + 1;
     b.gate_band = 1; b.band_count = fm + 2 * pl->iterations + 3;
@@ -733,7 +758,8 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   // sequence does not depend on the data) and replaces X.
   int* gate = (int*)(W + pl->m_gate);
   double* X64 = B64a;  // free until the refinement product
-  PFSM_TRY(lower_minus_identity_check(S64, n, n, ORTHO_FIRST_ORDER_MAX, rb, gate, s));
+  double* gcl = (double*)(W + pl->m_gcl);
+  PFSM_TRY(lower_minus_identity_check(S64, n, n, ORTHO_FIRST_ORDER_MAX, rb, gate, band ? gcl : nullptr, s));
   PFSM_TRY(convert_f32_f64_gated(X32, n, X64, n, n, n, 1, gate, s));
   {
     const int pf = fs_plain ? PACK_PLAIN : 0;
@@ -743,6 +769,18 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     X3Args h = x3(X3_ADD, n, n, n, Rpk, Ypk, X32, n, 0);  // Ypk: columns of Phi(E)^T = rows of Phi(E)
     h.alpha = -1.0; h.D = X32; h.ldd = n; h.d_double = 0; h.tiles = X3_KPREFIX;
     if (fs_plain) { h.products = 1; h.ldap = h.ldbp = ldq; }
+    if (band) {
+      // Band form: X(r, k) lies inside the submatrix rows of column k only for
+      // the k of a contiguous range per row tile (krange_rows); the rest are
+      // far entries of X, at most m = the last update's far maximum, so the
+      // dropped sum is at most n max|E| m (|Phi(E)| <= |E| entrywise), gated
+      // against 2^-20 (the entries of X are at most 1).
+      h.gate_far = fm + 2 * pl->iterations; h.gate_cl = gcl;
+      X3Args b = h;
+      b.krange_rows = pl->d_krange_rows; b.gate_band = 1; b.band_count = fm + 2 * pl->iterations + 2;
+      PFSM_TRY(gemm_x3(X3_ADD, b, s));
+      h.gate_band = 0;
+    }
     PFSM_TRY(gemm_x3(X3_ADD, h, s));  // X <- X - X Phi(E)^T (in place: the operand comes from the packed copy)
   }
   PFSM_TRY(cholesky_qr_gated(S64, n, X64, n, n, n, (double*)(W + pl->o_T), (double*)(W + pl->m_bcopy), info, gate, s));
@@ -853,13 +891,13 @@ pfsm_status pfsm_debug_stats(pfsm_plan* pl, const void* dWork, size_t work_bytes
                              int32_t* count) {
   if (!pl || !dWork || !out || !count || work_bytes < pl->total) return PFSM_INVALID_ARG;
   const int64_t n = pl->n;
-  const int32_t need = 2 * pl->P + 4;
+  const int32_t need = 2 * pl->P + 5;
   if (capacity < need) return PFSM_INVALID_ARG;
   if (hipDeviceSynchronize() != hipSuccess) return PFSM_HIP_ERROR;
   if (hipMemcpy(out, (const char*)dWork + pl->o_stats, 2 * pl->P * sizeof(int32_t), hipMemcpyDeviceToHost) !=
       hipSuccess)
     return PFSM_HIP_ERROR;
-  out[2 * pl->P] = out[2 * pl->P + 1] = out[2 * pl->P + 2] = out[2 * pl->P + 3] = 0;
+  out[2 * pl->P] = out[2 * pl->P + 1] = out[2 * pl->P + 2] = out[2 * pl->P + 3] = out[2 * pl->P + 4] = 0;
   if (pl->precision == PFSM_PREC_MIXED_BF16) {
     // refinement clusters: count, then the largest cluster size
     const double* rb = (const double*)((const char*)dWork + pl->m_rb);
@@ -879,11 +917,12 @@ pfsm_status pfsm_debug_stats(pfsm_plan* pl, const void* dWork, size_t work_bytes
     out[2 * pl->P + 1] = multi;
     out[2 * pl->P + 2] = mx;
     if (mixed_band_form(pl)) {  // folded-spectrum products that ran in the band form
-      unsigned bc = 0;
-      if (hipMemcpy(&bc, (const char*)dWork + pl->m_fm + (2 * pl->iterations + 3) * sizeof(unsigned), sizeof(bc),
+      unsigned bc[2] = {0, 0};  // the correction's count, then the folded-spectrum products'
+      if (hipMemcpy(bc, (const char*)dWork + pl->m_fm + (2 * pl->iterations + 2) * sizeof(unsigned), sizeof(bc),
                     hipMemcpyDeviceToHost) != hipSuccess)
         return PFSM_HIP_ERROR;
-      out[2 * pl->P + 3] = (int32_t)bc;
+      out[2 * pl->P + 3] = (int32_t)bc[1];
+      out[2 * pl->P + 4] = (int32_t)bc[0];
     }
   }
   *count = need;

@@ -48,9 +48,11 @@ hipError_t residuals_from_rq(const double* zz, const double* lam, const int* ran
 // Mixed-path helpers.
 hipError_t f32_mirror_to_f64(float* At32, double* At64, int64_t n, hipStream_t s);   // lower -> both, FP64 copy
 // *gate = 1 when max |L - I| over the lower triangle exceeds limit (or is not
-// a number), else 0; scratch: n doubles.
+// a number), else 0; scratch: n doubles.  cl (optional, 2 doubles): n max |L - I|
+// (a bound on the absolute row sums of the first-order correction) and
+// PFSM_BAND_TOL, the gate of the correction's band form.
 hipError_t lower_minus_identity_check(const double* L, int64_t ldl, int64_t n, double limit, double* scratch,
-                                      int* gate, hipStream_t s);
+                                      int* gate, double* cl, hipStream_t s);
 hipError_t col_sign_f32(float* X, int64_t n, int64_t ldx, double* sgn, hipStream_t s);  // flips in place
 hipError_t permute_f64_cols(const double* X, int64_t ldx, const int* rank, double* Y, int64_t ldy, int64_t m,
                             int64_t n, hipStream_t s);

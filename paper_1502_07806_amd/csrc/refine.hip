@@ -580,7 +580,7 @@ __global__ __launch_bounds__(NT) void k_lmi_col(const double* L, int64_t ldl, in
   }
   if (threadIdx.x == 0) out[j] = sh[0];
 }
-__global__ __launch_bounds__(NT) void k_lmi_final(const double* col, int64_t n, double limit, int* gate) {
+__global__ __launch_bounds__(NT) void k_lmi_final(const double* col, int64_t n, double limit, int* gate, double* cl) {
   __shared__ double sh[NT];
   double m = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += NT) {
@@ -596,7 +596,13 @@ __global__ __launch_bounds__(NT) void k_lmi_final(const double* col, int64_t n, 
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *gate = (sh[0] <= limit) ? 0 : 1;  // NaN: 1
+  if (threadIdx.x == 0) {
+    *gate = (sh[0] <= limit) ? 0 : 1;  // NaN: 1
+    if (cl) {
+      cl[0] = (double)n * sh[0];
+      cl[1] = PFSM_BAND_TOL;
+    }
+  }
 }
 
 __global__ __launch_bounds__(NT) void k_col_sign_f32(float* X, int64_t n, int64_t ldx, double* sgn) {
@@ -674,9 +680,9 @@ hipError_t f32_mirror_to_f64(float* At32, double* At64, int64_t n, hipStream_t s
 }
 
 hipError_t lower_minus_identity_check(const double* L, int64_t ldl, int64_t n, double limit, double* scratch,
-                                      int* gate, hipStream_t s) {
+                                      int* gate, double* cl, hipStream_t s) {
   hipLaunchKernelGGL(k_lmi_col, dim3((unsigned)n), dim3(NT), 0, s, L, ldl, n, scratch);
-  hipLaunchKernelGGL(k_lmi_final, dim3(1), dim3(NT), 0, s, scratch, n, limit, gate);
+  hipLaunchKernelGGL(k_lmi_final, dim3(1), dim3(NT), 0, s, scratch, n, limit, gate, cl);
   return hipGetLastError();
 }
 

@@ -251,10 +251,10 @@ def test_mixed_eigh_floor(pf):
 
 
 def test_mixed_band_form_gate(pf):
-    """Folded-spectrum products in the band form: taken for a basis close to
-    the eigenvectors (every product), refused by the device gate for one far
-    from them (the dropped far terms would not be negligible), and within the
-    mixed bar of the oracle either way."""
+    """Folded-spectrum products (and the orthonormalisation correction) in the
+    band form: taken for a basis close to the eigenvectors (every product),
+    refused by the device gate for one farther from them (the dropped far terms
+    would not be negligible), and within the mixed bar of the oracle either way."""
     n, offs, halo = 1024, uniform_layout(1024, 128), 64
     # kappa = 0.03: the start vectors have no rows outside their submatrices, so
     # the first product takes the band form; the far rows it produces, times the
@@ -265,11 +265,15 @@ def test_mixed_band_form_gate(pf):
         A, V = A.numpy(), V.numpy()
         lam_ref, _, info_ref = pfsm_ref(A, V, offs, halo, 3, 2)
         plan, info, lam, Vo = _run(pf, A, V, offs, halo)
-        nb = plan.debug_stats()["fs_band_products"]
+        st = plan.debug_stats()
+        nb = st["fs_band_products"]
         assert info == info_ref == 0
         assert (nb == 6) if expect_band else (1 <= nb < 6), (kappa, nb)
+        if expect_band:  # the orthonormalisation correction's band form too
+            assert st["correction_band"] == 1
         assert eig_error(lam, lam_ref) <= TOL_MIXED, kappa
         assert orthogonality(Vo) <= 1e-3
     # the split folded-spectrum products have no band form
     plan, info, _, _ = _run(pf, A, V, offs, halo, fs_split=True)
-    assert info == 0 and plan.debug_stats()["fs_band_products"] == 0
+    st = plan.debug_stats()
+    assert info == 0 and st["fs_band_products"] == 0 and st["correction_band"] == 0
