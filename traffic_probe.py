@@ -78,7 +78,7 @@ def summarize(fetch_csv: str, write_csv: str, n: int, out: str):
 
 
 def _short(name: str) -> str:
-    name = name.replace("pfsm::(anonymous namespace)::", "").replace("void ", "")
+    name = name.replace("pfsm::(anonymous namespace)::", "").replace("void ", "").replace("pfsm::", "")
     m = re.match(r"([A-Za-z_0-9]+(<[^()]*>)?)", name)
     return m.group(1) if m else name[:40]
 
