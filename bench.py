@@ -107,14 +107,14 @@ def cpu_baseline(A_dev, V_dev, n: int, slice_size: int, halo: int, small_n: int 
     from pfsm_workloads import prescribed_problem, uniform_layout
 
     A, V = A_dev.cpu().numpy(), V_dev.cpu().numpy()
-    print("cpu baseline: FP64 oracle at N=%d (all BLAS threads)" % n, flush=True)
+    print("cpu baseline: FP64 oracle at N=%d (all BLAS threads)" % n, file=sys.stderr, flush=True)
     total, eigh, info = _timed_oracle(A, V, uniform_layout(n, slice_size), halo)
     assert info == 0
-    print("cpu baseline: %.1f s; FP64 oracle at N=%d, one thread" % (total, small_n), flush=True)
+    print("cpu baseline: %.1f s; FP64 oracle at N=%d, one thread" % (total, small_n), file=sys.stderr, flush=True)
     As, Vs, _, _ = prescribed_problem(small_n, small_n // 4, 5e-3, 3000, clusters=True)
     with threadpool_limits(limits=1, user_api="blas"):
         total1, eigh1, _ = _timed_oracle(As.numpy(), Vs.numpy(), uniform_layout(small_n, slice_size), halo)
-    print("cpu baseline: %.1f s" % total1, flush=True)
+    print("cpu baseline: %.1f s" % total1, file=sys.stderr, flush=True)
     blas = [x for x in threadpool_info() if x.get("user_api") == "blas"]
     threads = max([x.get("num_threads", 1) for x in blas] or [1])
     return {
