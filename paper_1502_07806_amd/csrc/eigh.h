@@ -23,8 +23,8 @@ struct EighBatch {
   double floor_rel;        // rotation floor relative to the Gershgorin bound (0: the FP64 rounding floor)
   double* Bw;              // [P][Mp][Mp] working matrices (column-major)
   double* Uw;              // [P][Mp][Mp] accumulated eigenvectors
-  double* Rw;              // [P][nb/2][2b][2b] pair rotations of the current round
-  int* rflag;              // [P][nb/2] 1 if the pair's rotation is not the identity
+  double* Rw;              // [2][P][nb/2][2b][2b] pair rotations, by round parity
+  int* rflag;              // [2][P][nb/2] 1 if the pair's rotation is not the identity, by round parity
   int* state;              // [P][2] {done, rotated-this-sweep}
   int* stats;              // [P][2] {sweep found converged (0: not), rotating pair problems}
   int* sel;                // [P][Mp] ascending rank -> local index

@@ -59,6 +59,16 @@ __device__ inline bool must_rotate(double apq, double app, double aqq, double fl
   return a > floor_abs && a > TOL * sqrt(fabs(app) * fabs(aqq));
 }
 
+// Pair rotations and their flags of a round: two buffers, by round parity, so
+// that the eigenvector update of round r can run beside the pair problems of
+// round r + 1.
+__device__ inline double* rot_buf(const EighBatch& e, int round) {
+  return e.Rw + (int64_t)(round & 1) * e.P * (e.nb / 2) * B2 * B2;
+}
+__device__ inline int* flag_buf(const EighBatch& e, int round) {
+  return e.rflag + (int64_t)(round & 1) * e.P * (e.nb / 2);
+}
+
 // Circle-method tournament: position -> block index in round r (n even).
 __device__ __host__ inline int rr_index(int pos, int r, int n) {
   if (pos == 0) return 0;
@@ -168,16 +178,23 @@ __device__ inline double rsq_d(double x) {
 // a round needs one barrier; the squared column norms are summed exactly in the first round of
 // each sweep and carried through the rotations in the others.  Padding
 // indices (beyond the submatrix order) never rotate.
-__global__ __launch_bounds__(PS_NT) void pair_solve(EighBatch e, int round) {
+struct SolveLds {
+  double W[B2][LS];  // column-major: W[col][row]
+  double nrm[B2];
+  double cn[B2];     // running squared column norms of W
+  int any_rot;
+  int sweep_rot;
+};
+// Pair problem k of submatrix p in the given round (PS_NT threads).
+__device__ void solve_pair(const EighBatch& e, int round, int p, int k, SolveLds& L) {
   const int npairs = e.nb / 2;
-  const int p = blockIdx.x / npairs, k = blockIdx.x % npairs;
-  int* flagR = e.rflag + (int64_t)p * npairs + k;
+  int* flagR = flag_buf(e, round) + (int64_t)p * npairs + k;
   if (e.state[2 * p]) { if (threadIdx.x == 0) *flagR = 0; return; }
-  __shared__ double W[B2][LS];   // column-major: W[col][row]
-  __shared__ double nrm[B2];
-  __shared__ double cn[B2];      // running squared column norms of W
-  __shared__ int any_rot;
-  __shared__ int sweep_rot;
+  double (*W)[LS] = L.W;
+  double* nrm = L.nrm;
+  double* cn = L.cn;
+  int& any_rot = L.any_rot;
+  int& sweep_rot = L.sweep_rot;
   const int Mp = e.Mp;
   const int msize = e.wsize[p];
   int I, J;
@@ -302,7 +319,7 @@ __global__ __launch_bounds__(PS_NT) void pair_solve(EighBatch e, int round) {
     nrm[tid] = rsq_d(s2);
   }
   __syncthreads();
-  double* Rg = e.Rw + ((int64_t)p * npairs + k) * B2 * B2;
+  double* Rg = rot_buf(e, round) + ((int64_t)p * npairs + k) * B2 * B2;
   for (int idx = tid; idx < B2 * B2; idx += PS_NT) {  // row-major: Rg[r * 2b + c] = R(r, c)
     int r = idx / B2, c = idx % B2;
     Rg[idx] = W[c][r] * nrm[c];
@@ -314,16 +331,30 @@ __global__ __launch_bounds__(PS_NT) void pair_solve(EighBatch e, int round) {
   }
 }
 
-// 64x64x64 products with FP64 MFMA.  Wave w owns rows [32*(w&1), +32) and
-// columns [32*(w>>1), +32) of Z.  The rotation operand R (row-major in global
-// memory, L2-resident) is read straight into registers, all 16 k-steps' worth
-// before the loop; only the tile operand sits in LDS, so a workgroup needs one
-// LDS tile.
+__global__ __launch_bounds__(PS_NT) void pair_solve(EighBatch e, int round) {
+  __shared__ SolveLds L;
+  const int npairs = e.nb / 2;
+  solve_pair(e, round, blockIdx.x / npairs, blockIdx.x % npairs, L);
+}
+
+// 64x64x64 products with FP64 MFMA by NTH / 64 waves: wave w owns rows
+// [32 (w & 1), +32) and JW = 128 * 64 / NTH columns from JW (w >> 1) of Z
+// (32 with four waves, 16 with eight).  The rotation operand R (row-major in
+// global memory, L2-resident) is read straight into registers, all 16
+// k-steps' worth before the loop; only the tile operand sits in LDS, so a
+// workgroup needs one LDS tile.
+template <int NTH> struct Mm64 {
+  static constexpr int JW = 2 * B2 * 64 / NTH;  // columns per wave
+  static constexpr int JB = JW / 16;            // 16-wide MFMA column blocks per wave
+  static_assert(JB >= 1, "at most eight waves");
+};
 // Z = R^T Y: fragment (i, k) of R^T is R(k, i), contiguous over i.
-__device__ inline void mm64_rt_y(const double* __restrict__ R, const double (*Y)[LS], v4d acc[2][2]) {
+template <int NTH>
+__device__ inline void mm64_rt_y(const double* __restrict__ R, const double (*Y)[LS], v4d acc[2][Mm64<NTH>::JB]) {
+  constexpr int JB = Mm64<NTH>::JB;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
-  const int i0 = (wave & 1) * 32, j0 = (wave >> 1) * 32;
+  const int i0 = (wave & 1) * 32, j0 = (wave >> 1) * Mm64<NTH>::JW;
   double af[B2 / 4][2];
 #pragma unroll
   for (int kk = 0; kk < B2 / 4; ++kk)
@@ -332,33 +363,35 @@ __device__ inline void mm64_rt_y(const double* __restrict__ R, const double (*Y)
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < JB; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int kk = 0; kk < B2 / 4; ++kk) {
-    double bf[2];
+    double bf[JB];
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb) bf[jb] = Y[4 * kk + lq][j0 + jb * 16 + l16];
+    for (int jb = 0; jb < JB; ++jb) bf[jb] = Y[4 * kk + lq][j0 + jb * 16 + l16];
 #pragma unroll
     for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb)
+      for (int jb = 0; jb < JB; ++jb)
         acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[jb], af[kk][ib], acc[ib][jb], 0, 0, 0);
   }
 }
 // Z = X R: fragment (k, j) of R is contiguous over j.
-__device__ inline void mm64_x_r(const double (*X)[LS], const double* __restrict__ R, v4d acc[2][2]) {
+template <int NTH>
+__device__ inline void mm64_x_r(const double (*X)[LS], const double* __restrict__ R, v4d acc[2][Mm64<NTH>::JB]) {
+  constexpr int JB = Mm64<NTH>::JB;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
-  const int i0 = (wave & 1) * 32, j0 = (wave >> 1) * 32;
-  double bf[B2 / 4][2];
+  const int i0 = (wave & 1) * 32, j0 = (wave >> 1) * Mm64<NTH>::JW;
+  double bf[B2 / 4][JB];
 #pragma unroll
   for (int kk = 0; kk < B2 / 4; ++kk)
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb) bf[kk][jb] = R[(4 * kk + lq) * B2 + j0 + jb * 16 + l16];
+    for (int jb = 0; jb < JB; ++jb) bf[kk][jb] = R[(4 * kk + lq) * B2 + j0 + jb * 16 + l16];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < JB; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int kk = 0; kk < B2 / 4; ++kk) {
     double af[2];
@@ -367,102 +400,127 @@ __device__ inline void mm64_x_r(const double (*X)[LS], const double* __restrict_
 #pragma unroll
     for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb)
+      for (int jb = 0; jb < JB; ++jb)
         acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[kk][jb], af[ib], acc[ib][jb], 0, 0, 0);
   }
 }
 
-__device__ inline void store_acc(double (*Z)[LS], v4d acc[2][2]) {
+template <int NTH> __device__ inline void store_acc(double (*Z)[LS], v4d acc[2][Mm64<NTH>::JB]) {
+  constexpr int JB = Mm64<NTH>::JB;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
-  const int i0 = (wave & 1) * 32, j0 = (wave >> 1) * 32;
+  const int i0 = (wave & 1) * 32, j0 = (wave >> 1) * Mm64<NTH>::JW;
 #pragma unroll
   for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb)
+    for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) Z[i0 + ib * 16 + l16][j0 + jb * 16 + lq + 4 * r] = acc[ib][jb][r];
 }
 
 // ------------------------------------------------------------------ apply
-// Work items per submatrix: npairs(npairs+1)/2 tiles (k1 <= k2) of B, each also
-// written transposed into (k2, k1) so B stays exactly symmetric, then
-// (Mp/2b)*npairs tiles of U.  One 64 x 64 LDS tile per workgroup (four
-// workgroups fit a CU; the rotations are read from L2 straight into
-// registers); a product with an unrotated pair (identity R) is skipped.
-__global__ __launch_bounds__(NT) void pair_apply(EighBatch e, int round) {
+// B <- J^T B J: per submatrix npairs(npairs+1)/2 tiles (pairs k1 <= k2),
+// each also written transposed into (k2, k1) so B stays exactly symmetric.
+// U <- U J: per submatrix (Mp/2b) * npairs tiles (row tile, pair).  One
+// 64 x 64 LDS tile per workgroup; a product with an unrotated pair (identity
+// R) is skipped.  The B tiles of round r are what the pair problems of round
+// r + 1 read; the U tiles are read by nothing until the next round's U
+// update, so they run in the same launch as the next round's pair problems.
+template <int NTH> __device__ void apply_b_tile(const EighBatch& e, int round, int p, int w, double (*T)[LS]) {
+  if (e.state[2 * p]) return;
+  const int npairs = e.nb / 2;
+  const int Mp = e.Mp;
+  const int* fl = flag_buf(e, round) + (int64_t)p * npairs;
+  const double* Rbase = rot_buf(e, round) + (int64_t)p * npairs * B2 * B2;
+  const int tid = threadIdx.x;
+  v4d acc[2][Mm64<NTH>::JB];
+  int k2 = 0;
+  while ((k2 + 1) * (k2 + 2) / 2 <= w) ++k2;
+  const int k1 = w - k2 * (k2 + 1) / 2;
+  const int f1 = fl[k1], f2 = fl[k2];
+  if (!f1 && !f2) return;
+  int I1, J1, I2, J2;
+  pair_blocks(k1, round, e.nb, I1, J1);
+  pair_blocks(k2, round, e.nb, I2, J2);
+  double* B = e.Bw + (int64_t)p * Mp * Mp;
+  const double* R1 = Rbase + (int64_t)k1 * B2 * B2;
+  const double* R2 = Rbase + (int64_t)k2 * B2 * B2;
+  for (int idx = tid; idx < B2 * B2; idx += NTH) {
+    int r = idx % B2, c = idx / B2;
+    T[r][c] = B[pair_idx(r, I1, J1) + (int64_t)pair_idx(c, I2, J2) * Mp];
+  }
+  __syncthreads();
+  if (f1) {
+    mm64_rt_y<NTH>(R1, T, acc);  // R1^T T
+    __syncthreads();
+    store_acc<NTH>(T, acc);
+    __syncthreads();
+  }
+  if (f2) {
+    mm64_x_r<NTH>(T, R2, acc);  // (R1^T T) R2
+    __syncthreads();
+    store_acc<NTH>(T, acc);
+    __syncthreads();
+  }
+  for (int idx = tid; idx < B2 * B2; idx += NTH) {
+    const int r = idx % B2, c = idx / B2;
+    B[pair_idx(r, I1, J1) + (int64_t)pair_idx(c, I2, J2) * Mp] = T[r][c];
+  }
+  if (k1 != k2) {  // mirror tile, written with consecutive threads along its columns
+    for (int idx = tid; idx < B2 * B2; idx += NTH) {
+      const int c = idx % B2, r = idx / B2;
+      B[pair_idx(c, I2, J2) + (int64_t)pair_idx(r, I1, J1) * Mp] = T[r][c];
+    }
+  }
+}
+
+template <int NTH> __device__ void apply_u_tile(const EighBatch& e, int round, int p, int ww, double (*T)[LS]) {
+  if (e.state[2 * p]) return;
   const int npairs = e.nb / 2;
   const int nrc = e.Mp / B2;
-  const int ntri = npairs * (npairs + 1) / 2;
-  const int per = ntri + nrc * npairs;
-  const int p = blockIdx.x / per, w = blockIdx.x % per;
-  if (e.state[2 * p]) return;
   const int Mp = e.Mp;
-  const int* fl = e.rflag + (int64_t)p * npairs;
-  const double* Rbase = e.Rw + (int64_t)p * npairs * B2 * B2;
-  __shared__ double T[B2][LS];
+  const int rc = ww % nrc, k2 = ww / nrc;
+  if (!flag_buf(e, round)[(int64_t)p * npairs + k2]) return;
+  int I2, J2;
+  pair_blocks(k2, round, e.nb, I2, J2);
+  double* U = e.Uw + (int64_t)p * Mp * Mp;
+  const double* R2 = rot_buf(e, round) + ((int64_t)p * npairs + k2) * B2 * B2;
   const int tid = threadIdx.x;
-  v4d acc[2][2];
-  if (w < ntri) {
-    int k2 = 0;
-    while ((k2 + 1) * (k2 + 2) / 2 <= w) ++k2;
-    const int k1 = w - k2 * (k2 + 1) / 2;
-    const int f1 = fl[k1], f2 = fl[k2];
-    if (!f1 && !f2) return;
-    int I1, J1, I2, J2;
-    pair_blocks(k1, round, e.nb, I1, J1);
-    pair_blocks(k2, round, e.nb, I2, J2);
-    double* B = e.Bw + (int64_t)p * Mp * Mp;
-    const double* R1 = Rbase + (int64_t)k1 * B2 * B2;
-    const double* R2 = Rbase + (int64_t)k2 * B2 * B2;
-    for (int idx = tid; idx < B2 * B2; idx += NT) {
-      int r = idx % B2, c = idx / B2;
-      T[r][c] = B[pair_idx(r, I1, J1) + (int64_t)pair_idx(c, I2, J2) * Mp];
-    }
-    __syncthreads();
-    if (f1) {
-      mm64_rt_y(R1, T, acc);  // R1^T T
-      __syncthreads();
-      store_acc(T, acc);
-      __syncthreads();
-    }
-    if (f2) {
-      mm64_x_r(T, R2, acc);  // (R1^T T) R2
-      __syncthreads();
-      store_acc(T, acc);
-      __syncthreads();
-    }
-    for (int idx = tid; idx < B2 * B2; idx += NT) {
-      const int r = idx % B2, c = idx / B2;
-      B[pair_idx(r, I1, J1) + (int64_t)pair_idx(c, I2, J2) * Mp] = T[r][c];
-    }
-    if (k1 != k2) {  // mirror tile, written with consecutive threads along its columns
-      for (int idx = tid; idx < B2 * B2; idx += NT) {
-        const int c = idx % B2, r = idx / B2;
-        B[pair_idx(c, I2, J2) + (int64_t)pair_idx(r, I1, J1) * Mp] = T[r][c];
-      }
-    }
+  v4d acc[2][Mm64<NTH>::JB];
+  for (int idx = tid; idx < B2 * B2; idx += NTH) {
+    int r = idx % B2, c = idx / B2;
+    T[r][c] = U[(rc * B2 + r) + (int64_t)pair_idx(c, I2, J2) * Mp];
+  }
+  __syncthreads();
+  mm64_x_r<NTH>(T, R2, acc);
+  __syncthreads();
+  store_acc<NTH>(T, acc);
+  __syncthreads();
+  for (int idx = tid; idx < B2 * B2; idx += NTH) {
+    int r = idx % B2, c = idx / B2;
+    U[(rc * B2 + r) + (int64_t)pair_idx(c, I2, J2) * Mp] = T[r][c];
+  }
+}
+
+// B tiles of a round: one workgroup per tile (four fit a CU).
+__global__ __launch_bounds__(NT) void pair_apply_b(EighBatch e, int round) {
+  __shared__ double T[B2][LS];
+  const int npairs = e.nb / 2, ntri = npairs * (npairs + 1) / 2;
+  apply_b_tile<NT>(e, round, blockIdx.x / ntri, blockIdx.x % ntri, T);
+}
+
+// The pair problems of round solve_round (the first P * npairs workgroups;
+// none when solve_round < 0) beside the U tiles of round u_round (the rest).
+__global__ __launch_bounds__(PS_NT) void pair_solve_apply_u(EighBatch e, int solve_round, int u_round) {
+  __shared__ SolveLds L;
+  const int npairs = e.nb / 2;
+  const int ns = solve_round >= 0 ? e.P * npairs : 0;
+  const int b = blockIdx.x;
+  if (b < ns) {
+    solve_pair(e, solve_round, b / npairs, b % npairs, L);
   } else {
-    const int ww = w - ntri;
-    const int rc = ww % nrc, k2 = ww / nrc;
-    if (!fl[k2]) return;
-    int I2, J2;
-    pair_blocks(k2, round, e.nb, I2, J2);
-    double* U = e.Uw + (int64_t)p * Mp * Mp;
-    const double* R2 = Rbase + (int64_t)k2 * B2 * B2;
-    for (int idx = tid; idx < B2 * B2; idx += NT) {
-      int r = idx % B2, c = idx / B2;
-      T[r][c] = U[(rc * B2 + r) + (int64_t)pair_idx(c, I2, J2) * Mp];
-    }
-    __syncthreads();
-    mm64_x_r(T, R2, acc);
-    __syncthreads();
-    store_acc(T, acc);
-    __syncthreads();
-    for (int idx = tid; idx < B2 * B2; idx += NT) {
-      int r = idx % B2, c = idx / B2;
-      U[(rc * B2 + r) + (int64_t)pair_idx(c, I2, J2) * Mp] = T[r][c];
-    }
+    const int per = (e.Mp / B2) * npairs;
+    apply_u_tile<PS_NT>(e, u_round, (b - ns) / per, (b - ns) % per, L.W);
   }
 }
 
@@ -526,9 +584,14 @@ hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, 
   }
   for (int sw = 0; sw < max_sweeps; ++sw) {
     hipLaunchKernelGGL(sweep_begin, dim3((e.P + 63) / 64), dim3(64), 0, s, e, sw);
-    for (int r = 0; r < e.nb - 1; ++r) {
-      hipLaunchKernelGGL(pair_solve, dim3(e.P * npairs), dim3(PS_NT), 0, s, e, r);
-      hipLaunchKernelGGL(pair_apply, dim3(e.P * (npairs * (npairs + 1) / 2 + nrc * npairs)), dim3(NT), 0, s, e, r);
+    // round r: B tiles, then the next round's pair problems beside the U tiles
+    const int rounds = e.nb - 1;
+    hipLaunchKernelGGL(pair_solve, dim3(e.P * npairs), dim3(PS_NT), 0, s, e, 0);
+    for (int r = 0; r < rounds; ++r) {
+      hipLaunchKernelGGL(pair_apply_b, dim3(e.P * (npairs * (npairs + 1) / 2)), dim3(NT), 0, s, e, r);
+      const int next = r + 1 < rounds ? r + 1 : -1;
+      const unsigned grid = (unsigned)((next >= 0 ? e.P * npairs : 0) + e.P * nrc * npairs);
+      hipLaunchKernelGGL(pair_solve_apply_u, dim3(grid), dim3(PS_NT), 0, s, e, next, r);
     }
   }
   hipLaunchKernelGGL(rank_select, dim3(e.P), dim3(NT), e.Mp * sizeof(double), s, e);

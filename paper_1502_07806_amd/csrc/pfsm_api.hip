@@ -339,8 +339,8 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   pl->o_b1 = w; w = align256(w + N2);
   pl->o_Bw = w; w = align256(w + P * Mp2);
   pl->o_Uw = w; w = align256(w + P * Mp2);
-  pl->o_Rw = w; w = align256(w + (size_t)P * (pl->nb / 2) * B2 * B2 * sizeof(double));
-  pl->o_rflag = w; w = align256(w + (size_t)P * (pl->nb / 2) * sizeof(int));
+  pl->o_Rw = w; w = align256(w + 2 * (size_t)P * (pl->nb / 2) * B2 * B2 * sizeof(double));  // two round buffers
+  pl->o_rflag = w; w = align256(w + 2 * (size_t)P * (pl->nb / 2) * sizeof(int));
   pl->o_state = w; w = align256(w + (size_t)P * 2 * sizeof(int));
   pl->o_stats = w; w = align256(w + (size_t)P * 2 * sizeof(int));
   pl->o_sel = w; w = align256(w + (size_t)P * pl->Mp * sizeof(int));
@@ -1023,8 +1023,8 @@ pfsm_status pfsm_plan_create_batched(pfsm_plan** out, const pfsm_desc* descs, in
     const size_t Mp2 = (size_t)g.Mp * g.Mp * sizeof(double);
     g.o_Bw = w; w = align256(w + P * Mp2);
     g.o_Uw = w; w = align256(w + P * Mp2);
-    g.o_Rw = w; w = align256(w + P * (g.nb / 2) * B2 * B2 * sizeof(double));
-    g.o_rflag = w; w = align256(w + P * (g.nb / 2) * sizeof(int));
+    g.o_Rw = w; w = align256(w + 2 * P * (g.nb / 2) * B2 * B2 * sizeof(double));  // two round buffers
+    g.o_rflag = w; w = align256(w + 2 * P * (g.nb / 2) * sizeof(int));
     g.o_state = w; w = align256(w + P * 2 * sizeof(int));
     g.o_stats = w; w = align256(w + P * 2 * sizeof(int));
     g.o_sel = w; w = align256(w + P * g.Mp * sizeof(int));
@@ -1153,8 +1153,8 @@ pfsm_status pfsm_solve_batched(pfsm_plan* pl, const double* const* dA, const int
       v.P = q->P; v.Mp = g.Mp; v.nb = g.nb; v.inner_max_sweeps = EIGH_INNER_SWEEPS; v.floor_rel = g.floor_rel;
       v.Bw = (double*)(W + g.o_Bw) + p0 * g.Mp * g.Mp;
       v.Uw = (double*)(W + g.o_Uw) + p0 * g.Mp * g.Mp;
-      v.Rw = (double*)(W + g.o_Rw) + p0 * (g.nb / 2) * (2 * EIGH_B) * (2 * EIGH_B);
-      v.rflag = (int*)(W + g.o_rflag) + p0 * (g.nb / 2);
+      v.Rw = nullptr;  // the pair rotations are not read after the eigensolver run
+      v.rflag = nullptr;
       v.state = (int*)(W + g.o_state) + 2 * p0;
       v.stats = (int*)(W + g.o_stats) + 2 * p0;
       v.sel = (int*)(W + g.o_sel) + p0 * g.Mp;
