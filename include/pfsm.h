@@ -71,7 +71,8 @@ typedef enum pfsm_precision {
                                BF16 parts (three products), the folded-spectrum products on plain
                                BF16 operands (one product; see PFSM_FLAG_FS_SPLIT); FP64 for the
                                submatrix eigensolver (its rotation floor 2^-24 of the Gershgorin
-                               bound, the unit roundoff of the FP32 start vectors) and the final
+                               bound, the unit roundoff of the FP32 start vectors; its pair
+                               problems stop after a sweep of rotations below 2^-14) and the final
                                Rayleigh quotients / cluster Rayleigh-Ritz against A (from an
                                FP64-accurate int8 digit product).
                                Orthonormalisation: to first order in S - I while max |S - I| <=

@@ -14,6 +14,12 @@ constexpr int EIGH_INNER_SWEEPS = 30;      // sweep limit of the in-LDS pair sol
 // relative) lies far above this floor, and rounds its start vectors to FP32;
 // rotating entries below 2^-24 ||B|| would resolve nothing the inputs hold.
 constexpr double EIGH_FLOOR_MIXED = 5.9604644775390625e-08;  // 2^-24
+// Stopping rule of that path's pair problems: a one-sided Jacobi sweep whose
+// rotations all had |sin| <= 2^-14 ends the iteration.  Cyclic Jacobi
+// converges quadratically, so the column inner products left are of order
+// 2^-28 relative, a sixteenth of the rotation floor above; the FP64 path
+// iterates to its rounding level instead.
+constexpr double EIGH_ANGLE_MIXED = 6.103515625e-05;  // 2^-14
 
 struct EighBatch {
   int P;                   // number of submatrices
@@ -21,6 +27,7 @@ struct EighBatch {
   int nb;                  // Mp / b (even)
   int inner_max_sweeps;    // sweeps of the in-LDS pair solver
   double floor_rel;        // rotation floor relative to the Gershgorin bound (0: the FP64 rounding floor)
+  double angle;            // pair-problem stopping rotation |sin| (0: the FP64 one)
   double* Bw;              // [P][Mp][Mp] working matrices (column-major)
   double* Uw;              // [P][Mp][Mp] accumulated eigenvectors
   double* Rw;              // [2][P][nb/2][2b][2b] pair rotations, by round parity

@@ -230,6 +230,7 @@ __device__ void solve_pair(const EighBatch& e, int round, int p, int k, SolveLds
   }
   __syncthreads();
   const int slot = tid / PL, sub = tid % PL;  // 32 column pairs x PL lanes
+  const double angle = e.angle > 0.0 ? e.angle : ANGLE;
   bool converged = false;
   for (int sweep = 0; sweep < e.inner_max_sweeps; ++sweep) {
     if (tid == 0) sweep_rot = 0;
@@ -290,8 +291,8 @@ __device__ void solve_pair(const EighBatch& e, int round, int p, int k, SolveLds
         const double cs2 = 2.0 * c * sn * ab;
         na = c * c * aa - cs2 + sn * sn * bb;
         nb = sn * sn * aa + cs2 + c * c * bb;
-        // only rotations by more than ANGLE keep the sweep going (see above)
-        if (sub == 0 && fabs(sn) > ANGLE) sweep_rot = 1;
+        // only rotations by more than the stopping angle keep the sweep going (see above)
+        if (sub == 0 && fabs(sn) > angle) sweep_rot = 1;
       }
       if (sub == 0) {
         cn[pc] = na;

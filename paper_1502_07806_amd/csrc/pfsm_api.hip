@@ -63,7 +63,7 @@ struct pfsm_plan {
   struct EighGroup {
     std::vector<int> members, p0;  // instances, and each one's first submatrix in the group
     int P = 0, Mp = 0, nb = 0, max_sweeps = 0;
-    double floor_rel = 0.0;
+    double floor_rel = 0.0, angle = 0.0;
     void* dtab = nullptr;
     int64_t *d_wstart = nullptr, *d_part_start = nullptr, *d_src_off = nullptr, *d_scal_off = nullptr;
     int32_t *d_wsize = nullptr, *d_offset = nullptr, *d_src_ld = nullptr, *d_info_idx = nullptr;
@@ -154,6 +154,8 @@ bool mixed_band_form(const pfsm_plan* pl) {
 // Rotation floor of the submatrix eigensolver: the FP64 rounding floor, or the
 // looser one of the mixed path, whose start vectors are stored in FP32.
 double eigh_floor(const pfsm_plan* pl) { return pl->precision == PFSM_PREC_MIXED_BF16 ? EIGH_FLOOR_MIXED : 0.0; }
+// Stopping rotation of the pair problems: looser with the looser floor.
+double eigh_angle(const pfsm_plan* pl) { return pl->precision == PFSM_PREC_MIXED_BF16 ? EIGH_ANGLE_MIXED : 0.0; }
 
 // Submatrix eigensolver arguments: every pointer into the plan's workspace layout.
 EighBatch eigh_batch(const pfsm_plan* pl, char* W, int* info, const double* scal) {
@@ -166,6 +168,7 @@ EighBatch eigh_batch(const pfsm_plan* pl, char* W, int* info, const double* scal
   e.info = info;
   e.scal = scal;
   e.floor_rel = eigh_floor(pl);
+  e.angle = eigh_angle(pl);
   return e;
 }
 
@@ -953,12 +956,13 @@ pfsm_status pfsm_plan_create_batched(pfsm_plan** out, const pfsm_desc* descs, in
     return PFSM_HIP_ERROR;
   }
   // eigensolver groups: instances with the same padded submatrix order, sweep
-  // limit and rotation floor, their submatrices numbered consecutively
+  // limit, rotation floor and stopping angle, their submatrices numbered consecutively
   for (int32_t i = 0; i < count; ++i) {
     const pfsm_plan* q = pl->sub[i];
     pfsm_plan::EighGroup* g = nullptr;
     for (auto& h : pl->groups)
-      if (h.Mp == q->Mp && h.max_sweeps == q->max_sweeps && h.floor_rel == eigh_floor(q)) g = &h;
+      if (h.Mp == q->Mp && h.max_sweeps == q->max_sweeps && h.floor_rel == eigh_floor(q) && h.angle == eigh_angle(q))
+        g = &h;
     if (!g) {
       pl->groups.emplace_back();
       g = &pl->groups.back();
@@ -966,6 +970,7 @@ pfsm_status pfsm_plan_create_batched(pfsm_plan** out, const pfsm_desc* descs, in
       g->nb = q->nb;
       g->max_sweeps = q->max_sweeps;
       g->floor_rel = eigh_floor(q);
+      g->angle = eigh_angle(q);
     }
     g->members.push_back(i);
     g->p0.push_back(g->P);
@@ -1134,6 +1139,7 @@ pfsm_status pfsm_solve_batched(pfsm_plan* pl, const double* const* dA, const int
     e.wbase = W; e.src_off = g.d_src_off; e.src_ld = g.d_src_ld; e.scal_off = g.d_scal_off;
     e.info_base = dInfo; e.info_idx = g.d_info_idx;
     e.floor_rel = g.floor_rel;
+    e.angle = g.angle;
     PFSM_TRY(eigh_batched_run(e, nullptr, 0, g.max_sweeps, s));
   }
   // 3. every instance from its start vectors on, reading its submatrices'
@@ -1151,6 +1157,7 @@ pfsm_status pfsm_solve_batched(pfsm_plan* pl, const double* const* dA, const int
       EighBatch& v = views[i];
       v = {};
       v.P = q->P; v.Mp = g.Mp; v.nb = g.nb; v.inner_max_sweeps = EIGH_INNER_SWEEPS; v.floor_rel = g.floor_rel;
+      v.angle = g.angle;
       v.Bw = (double*)(W + g.o_Bw) + p0 * g.Mp * g.Mp;
       v.Uw = (double*)(W + g.o_Uw) + p0 * g.Mp * g.Mp;
       v.Rw = nullptr;  // the pair rotations are not read after the eigensolver run
