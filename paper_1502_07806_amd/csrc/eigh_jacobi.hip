@@ -503,11 +503,11 @@ template <int NTH> __device__ void apply_u_tile(const EighBatch& e, int round, i
   }
 }
 
-// B tiles of a round: one workgroup per tile (four fit a CU).
-__global__ __launch_bounds__(NT) void pair_apply_b(EighBatch e, int round) {
+// B tiles of a round: one eight-wave workgroup per tile (four fit a CU).
+__global__ __launch_bounds__(PS_NT) void pair_apply_b(EighBatch e, int round) {
   __shared__ double T[B2][LS];
   const int npairs = e.nb / 2, ntri = npairs * (npairs + 1) / 2;
-  apply_b_tile<NT>(e, round, blockIdx.x / ntri, blockIdx.x % ntri, T);
+  apply_b_tile<PS_NT>(e, round, blockIdx.x / ntri, blockIdx.x % ntri, T);
 }
 
 // The pair problems of round solve_round (the first P * npairs workgroups;
@@ -589,7 +589,7 @@ hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, 
     const int rounds = e.nb - 1;
     hipLaunchKernelGGL(pair_solve, dim3(e.P * npairs), dim3(PS_NT), 0, s, e, 0);
     for (int r = 0; r < rounds; ++r) {
-      hipLaunchKernelGGL(pair_apply_b, dim3(e.P * (npairs * (npairs + 1) / 2)), dim3(NT), 0, s, e, r);
+      hipLaunchKernelGGL(pair_apply_b, dim3(e.P * (npairs * (npairs + 1) / 2)), dim3(PS_NT), 0, s, e, r);
       const int next = r + 1 < rounds ? r + 1 : -1;
       const unsigned grid = (unsigned)((next >= 0 ? e.P * npairs : 0) + e.P * nrc * npairs);
       hipLaunchKernelGGL(pair_solve_apply_u, dim3(grid), dim3(PS_NT), 0, s, e, next, r);
