@@ -109,7 +109,7 @@ def trace_summary(trace_csv: str, out: str):
         if name == "sweep_begin":
             cur = [0.0, 0]
             sweeps.append(cur)
-        if cur is not None and name in ("sweep_begin", "pair_solve", "pair_apply"):
+        if cur is not None and name in ("sweep_begin", "pair_solve", "pair_apply_b", "pair_solve_apply_u"):
             cur[0] += d
             cur[1] += 1
         if name == "rank_select":
