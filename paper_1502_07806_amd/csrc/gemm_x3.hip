@@ -160,9 +160,11 @@ __device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t
     fk1 = g.far_krange[2 * tn + 1];
   }
   float farmax = 0.0f;
-  // C may alias D (in-place update): the inputs of 8 outputs are gathered
-  // before any of them is stored, so 8 loads are in flight instead of one.
-  constexpr int GR = 8;
+  // C may alias D (in-place update): the inputs of GR outputs are gathered
+  // before any of them is stored, so GR loads per input are in flight instead
+  // of one.  The folded-spectrum epilogues (FP32 inputs, the whole tile's
+  // HBM traffic) gather 16: the main loop's registers are free by now.
+  constexpr int GR = (EPI == X3_SHIFT || EPI == X3_FSUPD) ? 16 : 8;
 #pragma unroll
   for (int ib = 0; ib < WR; ++ib) {
     const int64_t gi = m0 + wi0 + ib * 32 + l32;
@@ -175,7 +177,9 @@ __device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t
       for (int r0 = 0; r0 < 16; r0 += GR) {
         // unconditional loads (columns past N read column N - 1), so that no
         // branch separates them and all of them issue before the first use
-        double in1[GR], in2[GR], ev[GR];
+        using In = typename std::conditional<EPI == X3_SHIFT || EPI == X3_FSUPD, float, double>::type;
+        In in1[GR], in2[GR];
+        double ev[GR];
 #pragma unroll
         for (int u = 0; u < GR; ++u) {
           const int r = r0 + u;
@@ -187,12 +191,12 @@ __device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t
             if (g.beta != 0.0)
               in1[u] = g.c_double ? ((const double*)g.C)[gi + gj * g.ldc] : (double)((const float*)g.C)[gi + gj * g.ldc];
           } else if (EPI == X3_SHIFT) {
-            in1[u] = (double)g.B32[gi + gj * g.ldb32];
+            in1[u] = g.B32[gi + gj * g.ldb32];
             ev[u] = g.eps[gj];
           } else if (EPI == X3_FSUPD) {
-            in1[u] = (double)g.B32[gi + gj * g.ldb32];
+            in1[u] = g.B32[gi + gj * g.ldb32];
             ev[u] = g.eps[gj];
-            in2[u] = (double)((const float*)g.D)[gi + gj * g.ldd];
+            in2[u] = ((const float*)g.D)[gi + gj * g.ldd];
           } else {  // X3_ADD
             in1[u] = g.d_double ? ((const double*)g.D)[gi + gj * g.ldd] : (double)((const float*)g.D)[gi + gj * g.ldd];
           }
@@ -205,8 +209,8 @@ __device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t
           const double v = (double)acc[ib][jb][r];
           double outv;
           if (EPI == X3_STORE) outv = g.alpha * v + g.beta * in1[u];
-          else if (EPI == X3_SHIFT) outv = v + in1[u] * (dg - ev[u]);
-          else if (EPI == X3_FSUPD) outv = in2[u] - a_eff * (v + in1[u] * (dg - ev[u]));
+          else if (EPI == X3_SHIFT) outv = v + (double)in1[u] * (dg - ev[u]);
+          else if (EPI == X3_FSUPD) outv = (double)in2[u] - a_eff * (v + (double)in1[u] * (dg - ev[u]));
           else outv = g.alpha * v + in1[u];
           if (g.c_double) ((double*)g.C)[gi + gj * g.ldc] = outv;
           else ((float*)g.C)[gi + gj * g.ldc] = (float)outv;
