@@ -10,9 +10,11 @@
 //             [B_II B_IJ; B_JI B_JJ] is diagonalised in LDS by a scalar
 //             parallel-order cyclic Jacobi, giving an orthogonal R_IJ;
 //     apply   (one workgroup per 2b x 2b tile): B <- J^T B J and U <- U J
-//             with J = diag of the R's, as small MFMA products in LDS.
+//             with J = diag of the R's, as small MFMA products in LDS; the
+//             U tiles of a round run in the same launch as the next round's
+//             pair problems (nothing reads U in between).
 //
-// (The pair problem is solved by a one-sided Jacobi, see pair_solve.)
+// (The pair problem is solved by a one-sided Jacobi, see solve_pair.)
 // A sweep in which no pair needed a rotation marks the submatrix converged;
 // later kernels of that submatrix return immediately.  A pair (p, q) is
 // rotated when |b_pq| > 2^-53 sqrt(|b_pp b_qq|) (relative accuracy) and
