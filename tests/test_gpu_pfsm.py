@@ -344,3 +344,26 @@ def test_residuals_and_threshold(pf, precision):
         l2, V2 = p2.solve(A, V, check=False)
         assert int(p2.info.item()) == code
         assert torch.equal(l2, lam) and torch.equal(V2, Vo)
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_bf16"])
+def test_sweep_limit(pf, precision):
+    """The eigensolver's static launch sequence: the sweeps after convergence
+    change nothing (their launches return at once), so a limit just above the
+    converged sweep gives bitwise the default's results; a limit below what the
+    input needs reports -3 (a submatrix still rotating in its last sweep)."""
+    dev = torch.device("cuda:0")
+    A, V, _, _ = prescribed_problem(512, 256, 1e-2, 4711)
+    A, V = A.to(dev), V.to(dev)
+    offs = uniform_layout(512, 128)
+    plan = pf.Plan(512, offs, halo=64, iterations=2, precision=precision)
+    lam, Vo = plan.solve(A, V)
+    conv = plan.debug_stats()["converged_sweep"]
+    assert min(conv) >= 2  # the first sweep rotated
+    plan_k = pf.Plan(512, offs, halo=64, iterations=2, precision=precision, max_sweeps=max(conv) + 1)
+    lam_k, Vo_k = plan_k.solve(A, V)
+    assert torch.equal(lam, lam_k) and torch.equal(Vo, Vo_k)
+    assert plan_k.debug_stats()["converged_sweep"] == conv
+    plan_1 = pf.Plan(512, offs, halo=64, iterations=2, precision=precision, max_sweeps=1)
+    plan_1.solve(A, V, check=False)
+    torch.cuda.synchronize()
+    assert int(plan_1.info.item()) == -3
