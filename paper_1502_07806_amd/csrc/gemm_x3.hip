@@ -727,6 +727,59 @@ __global__ __launch_bounds__(256) void k_pack_cols(const void* X, int64_t K, int
   *(u32x4*)(dst + 32) = lw;
 }
 
+// Eight consecutive k (a multiple of 8) of FP32 column r as plain BF16, zero
+// past K.
+template <bool VEC>
+__device__ inline void pack_plain_chunk(const float* X, int64_t K, int64_t ldx, int64_t r, int64_t k0, bf16_t* P,
+                                        int64_t ldp) {
+  float v[8];
+  if (VEC && k0 + 8 <= K) {
+    const float4* src = (const float4*)(X + k0 + r * ldx);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const float4 w = src[u];
+      v[4 * u] = w.x;
+      v[4 * u + 1] = w.y;
+      v[4 * u + 2] = w.z;
+      v[4 * u + 3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = k0 + u < K ? X[k0 + u + r * ldx] : 0.0f;
+  }
+  u32x4 hw;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) hw[u] = (uint32_t)f2bf(v[2 * u]) | ((uint32_t)f2bf(v[2 * u + 1]) << 16);
+  *(u32x4*)(P + r * ldp + k0) = hw;
+}
+
+// Band part: grid (band chunks of 128 k, R / 16); 16 threads per column.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_pack_plain_band(const float* X, int64_t K, int64_t R, int64_t ldx,
+                                                         const int32_t* krange, bf16_t* P, int64_t ldp) {
+  const int64_t r = (int64_t)blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (r >= R) return;
+  const int64_t t = r / BN;
+  const int64_t k = krange[2 * t] + (int64_t)blockIdx.x * 128 + 8 * (threadIdx.x & 15);
+  if (k < krange[2 * t + 1]) pack_plain_chunk<VEC>(X, K, ldx, r, k, P, ldp);
+}
+
+// Far part: a fixed grid striding over every (column, chunk of 8 k) outside
+// the band, after the gate test of x3_gate_closed for the band launch.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_pack_plain_far(const float* X, int64_t K, int64_t R, int64_t ldx,
+                                                        const int32_t* krange, bf16_t* P, int64_t ldp,
+                                                        const unsigned* gate_far, const double* gate_cl) {
+  const float m = __uint_as_float(*gate_far);
+  if (gate_cl[0] * (double)m <= gate_cl[1]) return;  // the band form runs (false for NaN)
+  const int64_t nch = (K + 31) / 32 * 4;  // chunks of 8 per column, padding included
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < R * nch; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = c / nch, k = (c % nch) * 8, t = r / BN;
+    if (k >= krange[2 * t] && k < krange[2 * t + 1]) continue;
+    pack_plain_chunk<VEC>(X, K, ldx, r, k, P, ldp);
+  }
+}
+
 template <int CFG>
 hipError_t launch_cfg(int epi, const X3Args& a, int tm, int tn, hipStream_t s) {
   int total = a.tiles == X3_LOWER ? tm * (tm + 1) / 2 : tm * tn;
@@ -906,6 +959,31 @@ hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t 
   }
   dim3 grid((unsigned)((K + 31) / 32), (unsigned)((R + 63) / 64));
   hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, s, X, src_double, m, n, ldx, flags, P, ldp);
+  return hipGetLastError();
+}
+
+hipError_t pack_plain_band(const float* X, int64_t K, int64_t R, int64_t ldx, const int32_t* krange, int band_chunks,
+                           bf16_t* P, int64_t ldp, hipStream_t s) {
+  if (R <= 0 || K <= 0 || band_chunks <= 0) return hipSuccess;
+  if (ldp < x3_plain_stride(K) || ldp % 8 != 0) return hipErrorInvalidValue;
+  const bool vec = ((uintptr_t)X % 16 == 0) && (ldx * 4) % 16 == 0;
+  dim3 grid((unsigned)band_chunks, (unsigned)((R + 15) / 16));
+  if (vec) hipLaunchKernelGGL(k_pack_plain_band<true>, grid, dim3(256), 0, s, X, K, R, ldx, krange, P, ldp);
+  else hipLaunchKernelGGL(k_pack_plain_band<false>, grid, dim3(256), 0, s, X, K, R, ldx, krange, P, ldp);
+  return hipGetLastError();
+}
+
+hipError_t pack_plain_far_gated(const float* X, int64_t K, int64_t R, int64_t ldx, const int32_t* krange, bf16_t* P,
+                                int64_t ldp, const unsigned* gate_far, const double* gate_cl, hipStream_t s) {
+  if (R <= 0 || K <= 0) return hipSuccess;
+  if (ldp < x3_plain_stride(K) || ldp % 8 != 0 || !gate_far || !gate_cl) return hipErrorInvalidValue;
+  const bool vec = ((uintptr_t)X % 16 == 0) && (ldx * 4) % 16 == 0;
+  // a modest grid: when the gate is open (the usual case) every workgroup only reads it
+  const dim3 grid(1024);
+  if (vec)
+    hipLaunchKernelGGL(k_pack_plain_far<true>, grid, dim3(256), 0, s, X, K, R, ldx, krange, P, ldp, gate_far, gate_cl);
+  else
+    hipLaunchKernelGGL(k_pack_plain_far<false>, grid, dim3(256), 0, s, X, K, R, ldx, krange, P, ldp, gate_far, gate_cl);
   return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ struct pfsm_plan {
   std::vector<int32_t> krange;  // [tiles_n][2] K range of the first folded-spectrum product (128-column tiles)
   std::vector<int32_t> krange_x3;  // same for the 256-column tiles of the split-BF16 GEMM
   std::vector<int32_t> krange_rows;  // [tiles][2] K range of the correction's band form per 256-row tile
+  int band_chunks = 0;               // widest krange_x3 range / 128, rounded up
   int Mp = 0, nb = 0;
   int device = 0;
   // device table
@@ -275,6 +276,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     hi = std::min<int64_t>((n + 31) / 32 * 32, (hi + 31) / 32 * 32);
     pl->krange_x3.push_back((int32_t)lo);
     pl->krange_x3.push_back((int32_t)hi);
+    pl->band_chunks = std::max<int>(pl->band_chunks, (int)((std::max<int64_t>(hi - lo, 0) + 127) / 128));
   }
   // per 256-row tile: the columns whose tiles' K range (submatrix rows)
   // meets the tile's rows, i.e. the k for which X(r, k) can lie inside its
@@ -677,7 +679,19 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   const EighBatch e = ext ? *ext : eigh_batch(pl, W, info, scal);
   if (phase == PH_ALL) PFSM_TRY(eigh_batched_run(e, At64, n, pl->max_sweeps, s));
   PFSM_TRY(embed_start_vectors(e, X32, n, eps, n, s));
-  PFSM_TRY(pack_x3(X32, 0, n, n, n, fs_plain ? PACK_PLAIN : 0, Xpk, fs_plain ? ldq : ldp, s));
+  unsigned* fm = (unsigned*)(W + pl->m_fm);
+  const bool band = fs_plain;
+  // Plain operands of the folded-spectrum products: with the band form, the
+  // rows a band-form product reads, then the others only when the product's
+  // gate (fm[gate], the same test) sends it to the full form.
+  auto pack_fs = [&](const float* src, bf16_t* dst, int gate) -> hipError_t {
+    if (!band) return pack_x3(src, 0, n, n, n, fs_plain ? PACK_PLAIN : 0, dst, fs_plain ? ldq : ldp, s);
+    hipError_t err = pack_plain_band(src, n, n, n, pl->d_krange_x3, pl->band_chunks, dst, ldq, s);
+    if (err == hipSuccess) err = pack_plain_far_gated(src, n, n, n, pl->d_krange_x3, dst, ldq, fm + gate, scal + 3, s);
+    return err;
+  };
+  if (band) PFSM_TRY(fill_i32((int*)fm, 2 * pl->iterations + 4, 0, s));
+  PFSM_TRY(pack_fs(X32, Xpk, 0));
   clk.mark(3);
   // (3) folded-spectrum iterations (X master copy in FP32).
   // Band form (plain operands): (At - eps) B = E B_band + (D - eps) B + E B_far
@@ -692,12 +706,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   // bound (the other launch returns at once), and every epilogue records the
   // largest far-row output for the gate of the next product: a static launch
   // sequence.  X0 has no far rows (zero padding), so fm[0] = 0.
-  unsigned* fm = (unsigned*)(W + pl->m_fm);
-  const bool band = fs_plain;
-  if (band) {
-    PFSM_TRY(pack_x3(At32, 0, n, n, n, PACK_PLAIN | PACK_OFFDIAG, (bf16_t*)(W + pl->m_Epk), ldq, s));
-    PFSM_TRY(fill_i32((int*)fm, 2 * pl->iterations + 4, 0, s));
-  }
+  if (band) PFSM_TRY(pack_x3(At32, 0, n, n, n, PACK_PLAIN | PACK_OFFDIAG, (bf16_t*)(W + pl->m_Epk), ldq, s));
   // the product in the band and full forms; f_in / f_out: far maxima of operand and output
   auto fs_gemm = [&](int epi, X3Args g, int f_in, int f_out) -> hipError_t {
     if (!band) return gemm_x3(epi, g, s);
@@ -718,7 +727,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
       g.B32 = X32; g.ldb32 = n; g.eps = eps; g.krange = kr;
       if (fs_plain) { g.products = 1; g.ldap = g.ldbp = ldq; }
       PFSM_TRY(fs_gemm(X3_SHIFT, g, 2 * it, 2 * it + 1));  // Y = (At - eps) X
-      PFSM_TRY(pack_x3(Y32, 0, n, n, n, fs_plain ? PACK_PLAIN : 0, Ypk, fs_plain ? ldq : ldp, s));
+      PFSM_TRY(pack_fs(Y32, Ypk, 2 * it + 1));
       if (it < 8) clk.mark(4 + 2 * it);
       X3Args h = x3(X3_FSUPD, n, n, n, Atpk, Ypk, X32, n, 0);
       h.B32 = Y32; h.ldb32 = n; h.D = X32; h.ldd = n; h.eps = eps; h.alpha_dev = scal;
@@ -733,7 +742,8 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     if (it < 8) clk.mark(5 + 2 * it);  // the update stage holds exactly one GEMM launch
     // the next iteration's operand, or the split operand of the overlap
     const bool plain_next = fs_plain && it + 1 < pl->iterations;
-    PFSM_TRY(pack_x3(X32, 0, n, n, n, plain_next ? PACK_PLAIN : 0, Xpk, plain_next ? ldq : ldp, s));
+    if (plain_next) PFSM_TRY(pack_fs(X32, Xpk, 2 * it + 2));
+    else PFSM_TRY(pack_x3(X32, 0, n, n, n, 0, Xpk, ldp, s));
   }
   clk.mark(19);
   // (4) overlap S = X^T X (FP64 output, lower tiles) and X <- X L^{-T}.
