@@ -103,17 +103,19 @@ inline int64_t x3_plain_stride(int64_t K) { return 32 * ((K + 31) / 32); }
 hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P, int64_t ldp,
                    hipStream_t s);
 
-// The plain layout of the FP32 columns of X (K x R, column-major, ldx) in two
-// parts, split by the K range krange[2 t], krange[2 t + 1] (multiples of 32)
-// of each 256-column tile t: the band part holds the rows inside it, all that
-// a band-form product (X3Args::krange = the same table) reads; the far part
-// the others and the zero padding up to a multiple of 32.  The far part is
-// written only when the gate {gate_far, gate_cl} of X3Args is closed for the
-// band form, i.e. when the full form of the product will run.  band_chunks:
-// at least the widest range / 128.
-hipError_t pack_plain_band(const float* X, int64_t K, int64_t R, int64_t ldx, const int32_t* krange, int band_chunks,
-                           bf16_t* P, int64_t ldp, hipStream_t s);
-hipError_t pack_plain_far_gated(const float* X, int64_t K, int64_t R, int64_t ldx, const int32_t* krange, bf16_t* P,
-                                int64_t ldp, const unsigned* gate_far, const double* gate_cl, hipStream_t s);
+// The same restricted to the K range krange[2 t], krange[2 t + 1] (multiples
+// of 32) of each 256-row tile t of the packed operand (its rows r, t = r / 256):
+// the band part, all that a product with that K range per tile reads
+// (X3Args::krange for a column operand, krange_rows for a row operand).
+// band_chunks: at least the widest range / 32.
+hipError_t pack_x3_band(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P,
+                        int64_t ldp, const int32_t* krange, int band_chunks, hipStream_t s);
+// The far part: every k outside those ranges (zero padding included), written
+// only when the gate {gate_far, gate_cl} of X3Args is closed for the band
+// form, i.e. when the full form of the product will run.  Column operands:
+// plain layout from FP32 only.
+hipError_t pack_x3_far_gated(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P,
+                             int64_t ldp, const int32_t* krange, const unsigned* gate_far, const double* gate_cl,
+                             hipStream_t s);
 
 }  // namespace pfsm

@@ -602,15 +602,50 @@ __device__ inline float bf2f(bf16_t h) { return __builtin_bit_cast(float, (uint3
 
 // One workgroup packs a 32 (k) x 64 (r) block: reads through LDS so that
 // both the column-major source and the packed destination are contiguous.
+// One 64 (r) x 32 (k) block of the packed operand (rows r0 .., chunk kc).
+__device__ void pack_block(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P,
+                           int64_t ldp, int64_t r0, int64_t kc, double (*tile)[33]);
+
+// krange (optional): only the chunks inside [krange[2 t], krange[2 t + 1]) for
+// the rows of P in tile t = r / 256 (band part, the grid's x covering the
+// widest range), or with FAR only the chunks outside it, striding over a
+// fixed grid, and only when the gate {gate_far, gate_cl} of X3Args is closed
+// for the band form.
+template <bool FAR>
 __global__ __launch_bounds__(256) void k_pack(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx,
-                                              int flags, bf16_t* P, int64_t ldp) {
-  const int by_rows = flags & PACK_BY_ROWS;
+                                              int flags, bf16_t* P, int64_t ldp, const int32_t* krange,
+                                              const unsigned* gate_far, const double* gate_cl) {
   __shared__ double tile[64][33];
+  const int by_rows = flags & PACK_BY_ROWS;
+  const int64_t R = by_rows ? m : n;
+  const int64_t K = by_rows ? n : m;
+  if (!FAR) {
+    const int64_t r0 = (int64_t)blockIdx.y * 64;
+    int64_t kc = blockIdx.x;
+    if (krange) {
+      kc += krange[2 * (r0 / BN)] / 32;
+      if (32 * kc >= krange[2 * (r0 / BN) + 1]) return;
+    }
+    pack_block(X, src_double, m, n, ldx, flags, P, ldp, r0, kc, tile);
+    return;
+  }
+  const float gm = __uint_as_float(*gate_far);
+  if (gate_cl[0] * (double)gm <= gate_cl[1]) return;  // the band form runs (false for NaN)
+  const int64_t nkc = (K + 31) / 32, nrb = (R + 63) / 64;
+  for (int64_t b = blockIdx.x; b < nkc * nrb; b += gridDim.x) {  // uniform per workgroup
+    const int64_t r0 = (b / nkc) * 64, kc = b % nkc;
+    if (32 * kc >= krange[2 * (r0 / BN)] && 32 * kc < krange[2 * (r0 / BN) + 1]) continue;
+    pack_block(X, src_double, m, n, ldx, flags, P, ldp, r0, kc, tile);
+    __syncthreads();  // the tile is reused by the next block
+  }
+}
+
+__device__ void pack_block(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P,
+                           int64_t ldp, int64_t r0, int64_t kc, double (*tile)[33]) {
+  const int by_rows = flags & PACK_BY_ROWS;
   // packed operand: rows r in [0, R), k in [0, K); R = by_rows ? m : n, K = by_rows ? n : m
   const int64_t R = by_rows ? m : n;
   const int64_t K = by_rows ? n : m;
-  const int64_t r0 = (int64_t)blockIdx.y * 64;
-  const int64_t kc = blockIdx.x;  // chunk of 32 k values
   const int tid = threadIdx.x;
   // load X values for (r, k) r in [r0, r0+64), k in [32 kc, 32 kc + 32)
   for (int idx = tid; idx < 64 * 32; idx += 256) {
@@ -663,13 +698,20 @@ __global__ __launch_bounds__(256) void k_pack(const void* X, int src_double, int
 // of one column into a 16-byte chunk of each plane; 16 threads cover 128 k of
 // a column (contiguous loads, 128-byte packed chunks).  VEC: X and ldx allow
 // 16-byte loads.
+// krange (optional): only the k in [krange[2 t], krange[2 t + 1]) for the rows
+// r of P in tile t = r / 256, the grid's x covering the widest range.
 template <bool DBL, bool VEC>
 __global__ __launch_bounds__(256) void k_pack_cols(const void* X, int64_t K, int64_t R, int64_t ldx, int flags,
-                                                   bf16_t* P, int64_t ldp) {
+                                                   bf16_t* P, int64_t ldp, const int32_t* krange) {
   const int q = threadIdx.x & 15;
   const int64_t r = (int64_t)blockIdx.y * 16 + (threadIdx.x >> 4);
-  const int64_t k0 = (int64_t)blockIdx.x * 128 + 8 * q;
-  if (r >= R || k0 >= (K + 31) / 32 * 32) return;  // chunks past K are zero-filled
+  if (r >= R) return;
+  int64_t k0 = (int64_t)blockIdx.x * 128 + 8 * q, kend = (K + 31) / 32 * 32;  // chunks past K are zero-filled
+  if (krange) {
+    k0 += krange[2 * (r / BN)];
+    kend = krange[2 * (r / BN) + 1];
+  }
+  if (k0 >= kend) return;
   double v[8];
   if (VEC && k0 + 8 <= K) {
     if (DBL) {
@@ -751,17 +793,6 @@ __device__ inline void pack_plain_chunk(const float* X, int64_t K, int64_t ldx, 
 #pragma unroll
   for (int u = 0; u < 4; ++u) hw[u] = (uint32_t)f2bf(v[2 * u]) | ((uint32_t)f2bf(v[2 * u + 1]) << 16);
   *(u32x4*)(P + r * ldp + k0) = hw;
-}
-
-// Band part: grid (band chunks of 128 k, R / 16); 16 threads per column.
-template <bool VEC>
-__global__ __launch_bounds__(256) void k_pack_plain_band(const float* X, int64_t K, int64_t R, int64_t ldx,
-                                                         const int32_t* krange, bf16_t* P, int64_t ldp) {
-  const int64_t r = (int64_t)blockIdx.y * 16 + (threadIdx.x >> 4);
-  if (r >= R) return;
-  const int64_t t = r / BN;
-  const int64_t k = krange[2 * t] + (int64_t)blockIdx.x * 128 + 8 * (threadIdx.x & 15);
-  if (k < krange[2 * t + 1]) pack_plain_chunk<VEC>(X, K, ldx, r, k, P, ldp);
 }
 
 // Far part: a fixed grid striding over every (column, chunk of 8 k) outside
@@ -938,8 +969,8 @@ hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
   }
 }
 
-hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P, int64_t ldp,
-                   hipStream_t s) {
+hipError_t pack_x3_band(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P,
+                        int64_t ldp, const int32_t* krange, int band_chunks, hipStream_t s) {
   const bool by_rows = flags & PACK_BY_ROWS;
   const int64_t R = by_rows ? m : n;
   const int64_t K = by_rows ? n : m;
@@ -947,43 +978,49 @@ hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t 
   if (!by_rows) {
     const size_t es = src_double ? 8 : 4;
     const bool vec = ((uintptr_t)X % 16 == 0) && ((size_t)ldx * es) % 16 == 0;
-    dim3 grid((unsigned)((K + 127) / 128), (unsigned)((R + 15) / 16));
+    if (krange && band_chunks <= 0) return hipSuccess;
+    dim3 grid((unsigned)(krange ? (band_chunks * 32 + 127) / 128 : (K + 127) / 128), (unsigned)((R + 15) / 16));
+    const int32_t* kr = krange;
     if (src_double) {
-      if (vec) hipLaunchKernelGGL((k_pack_cols<true, true>), grid, dim3(256), 0, s, X, K, R, ldx, flags, P, ldp);
-      else hipLaunchKernelGGL((k_pack_cols<true, false>), grid, dim3(256), 0, s, X, K, R, ldx, flags, P, ldp);
+      if (vec) hipLaunchKernelGGL((k_pack_cols<true, true>), grid, dim3(256), 0, s, X, K, R, ldx, flags, P, ldp, kr);
+      else hipLaunchKernelGGL((k_pack_cols<true, false>), grid, dim3(256), 0, s, X, K, R, ldx, flags, P, ldp, kr);
     } else {
-      if (vec) hipLaunchKernelGGL((k_pack_cols<false, true>), grid, dim3(256), 0, s, X, K, R, ldx, flags, P, ldp);
-      else hipLaunchKernelGGL((k_pack_cols<false, false>), grid, dim3(256), 0, s, X, K, R, ldx, flags, P, ldp);
+      if (vec) hipLaunchKernelGGL((k_pack_cols<false, true>), grid, dim3(256), 0, s, X, K, R, ldx, flags, P, ldp, kr);
+      else hipLaunchKernelGGL((k_pack_cols<false, false>), grid, dim3(256), 0, s, X, K, R, ldx, flags, P, ldp, kr);
     }
     return hipGetLastError();
   }
-  dim3 grid((unsigned)((K + 31) / 32), (unsigned)((R + 63) / 64));
-  hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, s, X, src_double, m, n, ldx, flags, P, ldp);
+  dim3 grid((unsigned)(krange ? band_chunks : (K + 31) / 32), (unsigned)((R + 63) / 64));
+  hipLaunchKernelGGL(k_pack<false>, grid, dim3(256), 0, s, X, src_double, m, n, ldx, flags, P, ldp, krange, nullptr,
+                     nullptr);
   return hipGetLastError();
 }
 
-hipError_t pack_plain_band(const float* X, int64_t K, int64_t R, int64_t ldx, const int32_t* krange, int band_chunks,
-                           bf16_t* P, int64_t ldp, hipStream_t s) {
-  if (R <= 0 || K <= 0 || band_chunks <= 0) return hipSuccess;
-  if (ldp < x3_plain_stride(K) || ldp % 8 != 0) return hipErrorInvalidValue;
-  const bool vec = ((uintptr_t)X % 16 == 0) && (ldx * 4) % 16 == 0;
-  dim3 grid((unsigned)band_chunks, (unsigned)((R + 15) / 16));
-  if (vec) hipLaunchKernelGGL(k_pack_plain_band<true>, grid, dim3(256), 0, s, X, K, R, ldx, krange, P, ldp);
-  else hipLaunchKernelGGL(k_pack_plain_band<false>, grid, dim3(256), 0, s, X, K, R, ldx, krange, P, ldp);
-  return hipGetLastError();
+hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P, int64_t ldp,
+                   hipStream_t s) {
+  return pack_x3_band(X, src_double, m, n, ldx, flags, P, ldp, nullptr, 0, s);
 }
 
-hipError_t pack_plain_far_gated(const float* X, int64_t K, int64_t R, int64_t ldx, const int32_t* krange, bf16_t* P,
-                                int64_t ldp, const unsigned* gate_far, const double* gate_cl, hipStream_t s) {
-  if (R <= 0 || K <= 0) return hipSuccess;
-  if (ldp < x3_plain_stride(K) || ldp % 8 != 0 || !gate_far || !gate_cl) return hipErrorInvalidValue;
-  const bool vec = ((uintptr_t)X % 16 == 0) && (ldx * 4) % 16 == 0;
-  // a modest grid: when the gate is open (the usual case) every workgroup only reads it
-  const dim3 grid(1024);
-  if (vec)
-    hipLaunchKernelGGL(k_pack_plain_far<true>, grid, dim3(256), 0, s, X, K, R, ldx, krange, P, ldp, gate_far, gate_cl);
-  else
-    hipLaunchKernelGGL(k_pack_plain_far<false>, grid, dim3(256), 0, s, X, K, R, ldx, krange, P, ldp, gate_far, gate_cl);
+hipError_t pack_x3_far_gated(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P,
+                             int64_t ldp, const int32_t* krange, const unsigned* gate_far, const double* gate_cl,
+                             hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (!krange || !gate_far || !gate_cl) return hipErrorInvalidValue;
+  if (!(flags & PACK_BY_ROWS)) {
+    if (src_double || flags != PACK_PLAIN || ldp < x3_plain_stride(m) || ldp % 8 != 0) return hipErrorInvalidValue;
+    const bool vec = ((uintptr_t)X % 16 == 0) && (ldx * 4) % 16 == 0;
+    const float* Xf = (const float*)X;
+    // a modest grid: when the gate is open (the usual case) every workgroup only reads it
+    if (vec)
+      hipLaunchKernelGGL(k_pack_plain_far<true>, dim3(1024), dim3(256), 0, s, Xf, m, n, ldx, krange, P, ldp, gate_far,
+                         gate_cl);
+    else
+      hipLaunchKernelGGL(k_pack_plain_far<false>, dim3(1024), dim3(256), 0, s, Xf, m, n, ldx, krange, P, ldp,
+                         gate_far, gate_cl);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_pack<true>, dim3(1024), dim3(256), 0, s, X, src_double, m, n, ldx, flags, P, ldp, krange,
+                     gate_far, gate_cl);
   return hipGetLastError();
 }
 

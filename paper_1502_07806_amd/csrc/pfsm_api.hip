@@ -39,7 +39,7 @@ struct pfsm_plan {
   std::vector<int32_t> krange;  // [tiles_n][2] K range of the first folded-spectrum product (128-column tiles)
   std::vector<int32_t> krange_x3;  // same for the 256-column tiles of the split-BF16 GEMM
   std::vector<int32_t> krange_rows;  // [tiles][2] K range of the correction's band form per 256-row tile
-  int band_chunks = 0;               // widest krange_x3 range / 128, rounded up
+  int band_chunks = 0, band_chunks_rows = 0;  // widest krange_x3 / krange_rows range / 32
   int Mp = 0, nb = 0;
   int device = 0;
   // device table
@@ -276,7 +276,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     hi = std::min<int64_t>((n + 31) / 32 * 32, (hi + 31) / 32 * 32);
     pl->krange_x3.push_back((int32_t)lo);
     pl->krange_x3.push_back((int32_t)hi);
-    pl->band_chunks = std::max<int>(pl->band_chunks, (int)((std::max<int64_t>(hi - lo, 0) + 127) / 128));
+    pl->band_chunks = std::max<int>(pl->band_chunks, (int)((std::max<int64_t>(hi - lo, 0) + 31) / 32));
   }
   // per 256-row tile: the columns whose tiles' K range (submatrix rows)
   // meets the tile's rows, i.e. the k for which X(r, k) can lie inside its
@@ -294,6 +294,7 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
     hi = hi < 0 ? 0 : std::min<int64_t>((n + 31) / 32 * 32, (hi + 1) * X3_BN);
     pl->krange_rows.push_back((int32_t)lo);
     pl->krange_rows.push_back((int32_t)hi);
+    pl->band_chunks_rows = std::max<int>(pl->band_chunks_rows, (int)((std::max<int64_t>(hi - lo, 0) + 31) / 32));
   }
   // device table
   size_t tb = 0;
@@ -686,8 +687,9 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   // gate (fm[gate], the same test) sends it to the full form.
   auto pack_fs = [&](const float* src, bf16_t* dst, int gate) -> hipError_t {
     if (!band) return pack_x3(src, 0, n, n, n, fs_plain ? PACK_PLAIN : 0, dst, fs_plain ? ldq : ldp, s);
-    hipError_t err = pack_plain_band(src, n, n, n, pl->d_krange_x3, pl->band_chunks, dst, ldq, s);
-    if (err == hipSuccess) err = pack_plain_far_gated(src, n, n, n, pl->d_krange_x3, dst, ldq, fm + gate, scal + 3, s);
+    hipError_t err = pack_x3_band(src, 0, n, n, n, PACK_PLAIN, dst, ldq, pl->d_krange_x3, pl->band_chunks, s);
+    if (err == hipSuccess)
+      err = pack_x3_far_gated(src, 0, n, n, n, PACK_PLAIN, dst, ldq, pl->d_krange_x3, fm + gate, scal + 3, s);
     return err;
   };
   if (band) PFSM_TRY(fill_i32((int*)fm, 2 * pl->iterations + 4, 0, s));
@@ -778,7 +780,13 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     const int pf = fs_plain ? PACK_PLAIN : 0;
     const int64_t ldc = fs_plain ? ldq : ldp;
     PFSM_TRY(pack_x3(S64, 1, n, n, n, PACK_SUB_I | PACK_LOWER | PACK_HALF_DIAG | PACK_BY_ROWS | pf, Ypk, ldc, s));
-    PFSM_TRY(pack_x3(X32, 0, n, n, n, PACK_BY_ROWS | pf, Rpk, ldc, s));  // rows of X
+    if (band) {  // rows of X: their band part, and the rest only for the full form (the same gate)
+      PFSM_TRY(pack_x3_band(X32, 0, n, n, n, PACK_BY_ROWS | pf, Rpk, ldc, pl->d_krange_rows, pl->band_chunks_rows, s));
+      PFSM_TRY(pack_x3_far_gated(X32, 0, n, n, n, PACK_BY_ROWS | pf, Rpk, ldc, pl->d_krange_rows,
+                                 fm + 2 * pl->iterations, gcl, s));
+    } else {
+      PFSM_TRY(pack_x3(X32, 0, n, n, n, PACK_BY_ROWS | pf, Rpk, ldc, s));  // rows of X
+    }
     X3Args h = x3(X3_ADD, n, n, n, Rpk, Ypk, X32, n, 0);  // Ypk: columns of Phi(E)^T = rows of Phi(E)
     h.alpha = -1.0; h.D = X32; h.ldd = n; h.d_double = 0; h.tiles = X3_KPREFIX;
     if (fs_plain) { h.products = 1; h.ldap = h.ldbp = ldq; }
@@ -822,7 +830,8 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   // N = 8192), so the plain product's rounding, 2^-9 of those, stays far
   // below the split product's on the first part.  The identity lies inside
   // the first part, so the second is X itself with those rows zeroed.
-  PFSM_TRY(pack_x3(X32, 0, n, n, n, PACK_SUB_I, Xpk, ldp, s));  // columns of X - I
+  // columns of X - I, in the rows the split product reads
+  PFSM_TRY(pack_x3_band(X32, 0, n, n, n, PACK_SUB_I, Xpk, ldp, pl->d_krange_x3, pl->band_chunks, s));
   PFSM_TRY(pack_x3(dV, 1, n, n, ldv, PACK_BY_ROWS, Rpk, ldp, s));  // rows of V
   {
     X3Args g = x3(X3_ADD, n, n, n, Rpk, Xpk, Vn64, n, 1);
