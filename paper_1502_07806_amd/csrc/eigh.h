@@ -47,13 +47,17 @@ struct EighBatch {
   // wbase + scal_off[p], and reports to info_base[info_idx[p]].
   const char* wbase;
   const int64_t* src_off;
+  int src_f32;             // those matrices are FP32 (the mixed path's At)
   const int32_t* src_ld;
   const int64_t* scal_off;
   int* info_base;
   const int32_t* info_idx;
 };
 
+// The submatrices are read from At (FP64, or FP32 widened exactly); with
+// src_off they come from each instance's own matrix, FP32 when src_f32.
 hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, int max_sweeps, hipStream_t s);
+hipError_t eigh_batched_run(const EighBatch& e, const float* At, int64_t ldat, int max_sweeps, hipStream_t s);
 hipError_t embed_start_vectors(const EighBatch& e, double* X, int64_t ldx, double* eps, int64_t n, hipStream_t s);
 // The same with X0 rounded to FP32 (the mixed path's master copy).
 hipError_t embed_start_vectors(const EighBatch& e, float* X, int64_t ldx, double* eps, int64_t n, hipStream_t s);

@@ -85,10 +85,11 @@ __device__ inline void pair_blocks(int k, int r, int nb, int& I, int& J) {
 __device__ inline int pair_idx(int t, int I, int J) { return t < EIGH_B ? I * EIGH_B + t : J * EIGH_B + (t - EIGH_B); }
 
 // ------------------------------------------------------------------ gather
-__global__ void gather_windows(EighBatch e, const double* __restrict__ At, int64_t ldat) {
+template <typename T>
+__global__ void gather_windows(EighBatch e, const T* __restrict__ At, int64_t ldat) {
   const int p = blockIdx.y;
   if (e.src_off) {  // this submatrix's own instance
-    At = (const double*)(e.wbase + e.src_off[p]);
+    At = (const T*)(e.wbase + e.src_off[p]);
     ldat = e.src_ld[p];
   }
   const int Mp = e.Mp;
@@ -100,7 +101,7 @@ __global__ void gather_windows(EighBatch e, const double* __restrict__ At, int64
        idx += (int64_t)gridDim.x * blockDim.x) {
     int r = (int)(idx % Mp), c = (int)(idx / Mp);
     double v;
-    if (r < M && c < M) v = At[(w0 + r) + (w0 + c) * ldat];
+    if (r < M && c < M) v = (double)At[(w0 + r) + (w0 + c) * ldat];
     else v = (r == c) ? EIGH_PAD_DIAG : 0.0;
     B[idx] = v;
     U[idx] = (r == c) ? 1.0 : 0.0;
@@ -578,12 +579,13 @@ __global__ void embed_x0(EighBatch e, T* __restrict__ X, int64_t ldx, double* __
 
 }  // namespace
 
-hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, int max_sweeps, hipStream_t s) {
+template <typename T>
+static hipError_t eigh_run(const EighBatch& e, const T* At, int64_t ldat, int max_sweeps, hipStream_t s) {
   const int npairs = e.nb / 2;
   const int nrc = e.Mp / B2;
   {
     dim3 grid((unsigned)std::min<int64_t>(((int64_t)e.Mp * e.Mp + 255) / 256, 1024), e.P);
-    hipLaunchKernelGGL(gather_windows, grid, dim3(256), 0, s, e, At, ldat);
+    hipLaunchKernelGGL(gather_windows<T>, grid, dim3(256), 0, s, e, At, ldat);
   }
   for (int sw = 0; sw < max_sweeps; ++sw) {
     hipLaunchKernelGGL(sweep_begin, dim3((e.P + 63) / 64), dim3(64), 0, s, e, sw);
@@ -599,6 +601,14 @@ hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, 
   }
   hipLaunchKernelGGL(rank_select, dim3(e.P), dim3(NT), e.Mp * sizeof(double), s, e);
   return hipGetLastError();
+}
+
+hipError_t eigh_batched_run(const EighBatch& e, const double* At, int64_t ldat, int max_sweeps, hipStream_t s) {
+  if (e.src_f32) return eigh_run(e, (const float*)At, ldat, max_sweeps, s);
+  return eigh_run(e, At, ldat, max_sweeps, s);
+}
+hipError_t eigh_batched_run(const EighBatch& e, const float* At, int64_t ldat, int max_sweeps, hipStream_t s) {
+  return eigh_run(e, At, ldat, max_sweeps, s);
 }
 
 hipError_t embed_start_vectors(const EighBatch& e, float* X, int64_t ldx, double* eps, int64_t n, hipStream_t s) {

@@ -14,6 +14,9 @@ hipError_t zero_krange_rows(float* X, int64_t ldx, int64_t m, int64_t n, const i
 // the Gershgorin bound (scal[4]); info = -1 if not finite.
 hipError_t gershgorin_alpha(const double* At, int64_t n, int64_t ld, int q, double user_alpha,
                             double* part_lo, double* part_hi, double* scal, int* info, hipStream_t s);
+// The same from FP32 columns (each entry widened exactly to FP64).
+hipError_t gershgorin_alpha(const float* At, int64_t n, int64_t ld, int q, double user_alpha,
+                            double* part_lo, double* part_hi, double* scal, int* info, hipStream_t s);
 hipError_t rq_reduce(const double* part, int tiles_m, int64_t n, const double* den, double* out, hipStream_t s);
 hipError_t col_norm2(const double* X, int64_t m, int64_t n, int64_t ldx, double* out, hipStream_t s);
 hipError_t finalize_order(const double* lam_u, const double* X, int64_t n, int64_t ldx, double* Xp, int64_t ldxp,

@@ -31,15 +31,16 @@ __global__ void k_fill_i32(int* p, int64_t count, int value) {
 }
 
 // Column j of the symmetric At: radius sum_{i != j} |At_ij| (= row radius by symmetry).
-__global__ __launch_bounds__(NT) void k_gersh_col(const double* At, int64_t n, int64_t ld, double* lo, double* hi) {
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gersh_col(const T* At, int64_t n, int64_t ld, double* lo, double* hi) {
   __shared__ double sh[NT / 64];
   const int64_t j = blockIdx.x;
-  const double* c = At + j * ld;
+  const T* c = At + j * ld;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += NT) s += fabs(c[i]);
+  for (int64_t i = threadIdx.x; i < n; i += NT) s += fabs((double)c[i]);
   s = block_sum(s, sh);
   if (threadIdx.x == 0) {
-    double d = c[j];
+    double d = (double)c[j];
     double r = s - fabs(d);
     lo[j] = d - r;
     hi[j] = d + r;
@@ -368,11 +369,20 @@ hipError_t mirror_lower(double* C, int64_t n, int64_t ldc, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t gershgorin_alpha(const double* At, int64_t n, int64_t ld, int q, double user_alpha, double* part_lo,
-                            double* part_hi, double* scal, int* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_gersh_col, dim3((unsigned)n), dim3(NT), 0, s, At, n, ld, part_lo, part_hi);
+template <typename T>
+static hipError_t gershgorin_alpha_t(const T* At, int64_t n, int64_t ld, int q, double user_alpha, double* part_lo,
+                                     double* part_hi, double* scal, int* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_gersh_col<T>, dim3((unsigned)n), dim3(NT), 0, s, At, n, ld, part_lo, part_hi);
   hipLaunchKernelGGL(k_gersh_final, dim3(1), dim3(NT), 0, s, part_lo, part_hi, n, q, user_alpha, scal, info);
   return hipGetLastError();
+}
+hipError_t gershgorin_alpha(const double* At, int64_t n, int64_t ld, int q, double user_alpha, double* part_lo,
+                            double* part_hi, double* scal, int* info, hipStream_t s) {
+  return gershgorin_alpha_t(At, n, ld, q, user_alpha, part_lo, part_hi, scal, info, s);
+}
+hipError_t gershgorin_alpha(const float* At, int64_t n, int64_t ld, int q, double user_alpha, double* part_lo,
+                            double* part_hi, double* scal, int* info, hipStream_t s) {
+  return gershgorin_alpha_t(At, n, ld, q, user_alpha, part_lo, part_hi, scal, info, s);
 }
 
 hipError_t rq_reduce(const double* part, int tiles_m, int64_t n, const double* den, double* out, hipStream_t s) {

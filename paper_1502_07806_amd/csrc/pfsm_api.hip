@@ -340,7 +340,8 @@ pfsm_status pfsm_plan_create(pfsm_plan** out, const pfsm_desc* d) {
   const int tiles_m = (int)((n + GEMM_BM - 1) / GEMM_BM);
   const size_t Mp2 = (size_t)pl->Mp * pl->Mp * sizeof(double);
   size_t w = 0;
-  pl->o_At = w; w = align256(w + N2);
+  // FP64 path: At; mixed path: the FP64 diagonal of its FP32 At
+  pl->o_At = w; w = align256(w + (d->precision == PFSM_PREC_MIXED_BF16 ? n * sizeof(double) : N2));
   pl->o_b0 = w; w = align256(w + N2);
   pl->o_b1 = w; w = align256(w + N2);
   pl->o_Bw = w; w = align256(w + P * Mp2);
@@ -625,7 +626,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   // the refined eigenvalues stay 3.3e-10 from an FP64 computation).
   const bool fs_plain = mixed_band_form(pl);
   const int64_t ldq = x3_plain_stride(n);
-  double* At64 = (double*)(W + pl->o_At);
+  double* Atd = (double*)(W + pl->o_At);    // diagonal of At (FP64)
   double* B64a = (double*)(W + pl->o_b0);   // X0 (FP64), later Z = A V_new
   double* Vn64 = (double*)(W + pl->o_b1);   // V_new before ordering
   float* At32 = (float*)(W + pl->m_At32);
@@ -667,18 +668,18 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     h.tiles = X3_LOWER;
     h.split_ws = split_ws; h.split_bytes = pl->split_bytes;
     PFSM_TRY(gemm_x3(X3_STORE, h, s));
-    PFSM_TRY(f32_mirror_to_f64(At32, At64, n, s));
+    PFSM_TRY(f32_mirror_lower(At32, Atd, n, s));
     PFSM_TRY(pack_x3(At32, 0, n, n, n, fs_plain ? PACK_PLAIN : 0, Atpk, fs_plain ? ldq : ldp, s));
   }
   clk.mark(1);
-  PFSM_TRY(gershgorin_alpha(At64, n, n, pl->q, pl->alpha, (double*)(W + pl->o_glo), (double*)(W + pl->o_ghi), scal,
+  PFSM_TRY(gershgorin_alpha(At32, n, n, pl->q, pl->alpha, (double*)(W + pl->o_glo), (double*)(W + pl->o_ghi), scal,
                             info, s));
   clk.mark(2);
   }
   if (phase == PH_BEGIN) return hip_status(hipGetLastError());
   // (2) submatrix eigensolver (FP64) and start vectors.
   const EighBatch e = ext ? *ext : eigh_batch(pl, W, info, scal);
-  if (phase == PH_ALL) PFSM_TRY(eigh_batched_run(e, At64, n, pl->max_sweeps, s));
+  if (phase == PH_ALL) PFSM_TRY(eigh_batched_run(e, At32, n, pl->max_sweeps, s));
   PFSM_TRY(embed_start_vectors(e, X32, n, eps, n, s));
   unsigned* fm = (unsigned*)(W + pl->m_fm);
   const bool band = fs_plain;
@@ -715,7 +716,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     g.far_krange = pl->d_krange_x3; g.farmax_out = fm + f_out;
     g.gate_far = fm + f_in; g.gate_cl = scal + 3;  // {rho, 2^-20 Gershgorin bound}
     X3Args b = g;
-    b.Ap = (const bf16_t*)(W + pl->m_Epk); b.krange = pl->d_krange_x3; b.diag = At64; b.diag_stride = n + 1;
+    b.Ap = (const bf16_t*)(W + pl->m_Epk); b.krange = pl->d_krange_x3; b.diag = Atd; b.diag_stride = 1;
     b.gate_band = 1; b.band_count = fm + 2 * pl->iterations + 3;
     hipError_t e1 = gemm_x3(epi, b, s);
     if (e1 != hipSuccess) return e1;
@@ -1007,7 +1008,8 @@ pfsm_status pfsm_plan_create_batched(pfsm_plan** out, const pfsm_desc* descs, in
         ps.push_back(q->part_start[p]);
         wz.push_back(q->wsize[p]);
         of.push_back(q->offset[p]);
-        so.push_back((int64_t)(pl->sub_off[i] + q->o_At));
+        // the instance's At: FP64, or FP32 on the mixed path
+        so.push_back((int64_t)(pl->sub_off[i] + (q->precision == PFSM_PREC_MIXED_BF16 ? q->m_At32 : q->o_At)));
         sl.push_back((int32_t)q->n);
         sc.push_back((int64_t)(pl->sub_off[i] + q->o_scal));
         ii.push_back(i);
@@ -1156,10 +1158,11 @@ pfsm_status pfsm_solve_batched(pfsm_plan* pl, const double* const* dA, const int
     e.sel = (int*)(W + g.o_sel);
     e.wstart = g.d_wstart; e.wsize = g.d_wsize; e.offset = g.d_offset; e.part_start = g.d_part_start;
     e.wbase = W; e.src_off = g.d_src_off; e.src_ld = g.d_src_ld; e.scal_off = g.d_scal_off;
+    e.src_f32 = g.floor_rel > 0.0;  // a mixed-precision group (its instances' At in FP32)
     e.info_base = dInfo; e.info_idx = g.d_info_idx;
     e.floor_rel = g.floor_rel;
     e.angle = g.angle;
-    PFSM_TRY(eigh_batched_run(e, nullptr, 0, g.max_sweeps, s));
+    PFSM_TRY(eigh_batched_run(e, (const double*)nullptr, 0, g.max_sweeps, s));
   }
   // 3. every instance from its start vectors on, reading its submatrices'
   // eigenpairs through a view of its group's arrays

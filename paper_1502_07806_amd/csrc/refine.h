@@ -46,7 +46,7 @@ hipError_t residuals_from_rq(const double* zz, const double* lam, const int* ran
                              hipStream_t s);
 
 // Mixed-path helpers.
-hipError_t f32_mirror_to_f64(float* At32, double* At64, int64_t n, hipStream_t s);   // lower -> both, FP64 copy
+hipError_t f32_mirror_lower(float* At32, double* diag, int64_t n, hipStream_t s);  // lower -> both; diag in FP64
 // *gate = 1 when max |L - I| over the lower triangle exceeds limit (or is not
 // a number), else 0; scratch: n doubles.  cl (optional, 2 doubles): n max |L - I|
 // (a bound on the absolute row sums of the first-order correction) and

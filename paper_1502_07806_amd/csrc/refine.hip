@@ -526,7 +526,7 @@ __device__ inline void tile_pair(int t, int& I, int& J) {  // t -> (I, J), I >= 
   I = r;
   J = t - r * (r + 1) / 2;
 }
-__global__ __launch_bounds__(256) void k_sym_from_lower(float* A32, double* A64, int64_t n) {
+__global__ __launch_bounds__(256) void k_sym_from_lower(float* A32, double* dg, int64_t n) {
   __shared__ float T[TT][TT + 1];
   int I, J;
   tile_pair(blockIdx.x, I, J);
@@ -544,8 +544,8 @@ __global__ __launch_bounds__(256) void k_sym_from_lower(float* A32, double* A64,
       const int64_t i = i0 + a, j = j0 + c;
       if (i < n && j < n) {
         const float v = (i >= j) ? T[a][c] : T[c][a];  // the latter only on the diagonal tile
-        A64[i + j * n] = (double)v;
         if (I == J && i < j) A32[i + j * n] = v;
+        if (i == j) dg[i] = (double)v;
       }
     }
     // mirrored tile (J, I): element (j0 + a, i0 + c) = A(i0 + c, j0 + a)
@@ -553,7 +553,6 @@ __global__ __launch_bounds__(256) void k_sym_from_lower(float* A32, double* A64,
       const int64_t i = j0 + a, j = i0 + c;
       if (i < n && j < n) {
         const float v = T[c][a];
-        A64[i + j * n] = (double)v;
         A32[i + j * n] = v;
       }
     }
@@ -672,10 +671,10 @@ hipError_t residuals_from_rq(const double* zz, const double* lam, const int* ran
   return hipGetLastError();
 }
 
-hipError_t f32_mirror_to_f64(float* At32, double* At64, int64_t n, hipStream_t s) {
+hipError_t f32_mirror_lower(float* At32, double* diag, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t t = (n + TT - 1) / TT;
-  hipLaunchKernelGGL(k_sym_from_lower, dim3((unsigned)(t * (t + 1) / 2)), dim3(256), 0, s, At32, At64, n);
+  hipLaunchKernelGGL(k_sym_from_lower, dim3((unsigned)(t * (t + 1) / 2)), dim3(256), 0, s, At32, diag, n);
   return hipGetLastError();
 }
 
