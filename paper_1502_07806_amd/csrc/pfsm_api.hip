@@ -669,7 +669,7 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     h.split_ws = split_ws; h.split_bytes = pl->split_bytes;
     PFSM_TRY(gemm_x3(X3_STORE, h, s));
     PFSM_TRY(f32_mirror_lower(At32, Atd, n, s));
-    PFSM_TRY(pack_x3(At32, 0, n, n, n, fs_plain ? PACK_PLAIN : 0, Atpk, fs_plain ? ldq : ldp, s));
+    if (!fs_plain) PFSM_TRY(pack_x3(At32, 0, n, n, n, 0, Atpk, ldp, s));  // (the band form packs E instead)
   }
   clk.mark(1);
   PFSM_TRY(gershgorin_alpha(At32, n, n, pl->q, pl->alpha, (double*)(W + pl->o_glo), (double*)(W + pl->o_ghi), scal,
@@ -715,8 +715,11 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
     if (!band) return gemm_x3(epi, g, s);
     g.far_krange = pl->d_krange_x3; g.farmax_out = fm + f_out;
     g.gate_far = fm + f_in; g.gate_cl = scal + 3;  // {rho, 2^-20 Gershgorin bound}
+    // both forms on E with the diagonal term in the epilogue: the full form
+    // adds E B_far, so At itself is never packed
+    g.Ap = (const bf16_t*)(W + pl->m_Epk); g.diag = Atd; g.diag_stride = 1;
     X3Args b = g;
-    b.Ap = (const bf16_t*)(W + pl->m_Epk); b.krange = pl->d_krange_x3; b.diag = Atd; b.diag_stride = 1;
+    b.krange = pl->d_krange_x3;
     b.gate_band = 1; b.band_count = fm + 2 * pl->iterations + 3;
     hipError_t e1 = gemm_x3(epi, b, s);
     if (e1 != hipSuccess) return e1;
