@@ -27,6 +27,7 @@ enum X3Epi : int {
   X3_FSUPD = 2,  // C = D32(i,j) - a*(acc - B32(i,j)*eps[j])    (FP32 out)
   X3_ADD = 3,    // C = alpha*acc + D(i,j)   (D float or double)
   X3_RQ = 4,     // part[tile_m][j] = sum_i acc(i,j) * D32(i,j)
+  X3_STORE_PACK = 5,  // alpha*acc written only as its split BF16 packed copy (pack_split)
 };
 
 // LOWER: only tiles with tile row >= tile column (square C); KPREFIX: the k
@@ -76,6 +77,10 @@ struct X3Args {
   // Optional [tiles_m][2] K range per row tile of C (multiples of 32),
   // intersected with the column tiles' range.
   const int32_t* krange_rows;
+  // STORE_PACK (all tiles, M a multiple of 32): the output of pack_x3
+  // (without PACK_PLAIN) for the FP32-rounded product, row j = column j of the
+  // product, row stride ld_pack_split; C is not written.
+  bf16_t* pack_split; int64_t ld_pack_split;
 };
 
 constexpr int X3_NUM_CFG = 6;

@@ -109,6 +109,15 @@ __device__ inline bool x3_gate_closed(const X3Args& g) {
   return band_ok != (g.gate_band != 0);
 }
 
+__device__ inline bf16_t f2bf(float x) {
+  // round to nearest even (finite inputs; NaN stays NaN)
+  uint32_t b = __builtin_bit_cast(uint32_t, x);
+  if ((b & 0x7f800000u) == 0x7f800000u) return (bf16_t)((b >> 16) | ((b & 0xffffu) ? 0x40u : 0u));
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (bf16_t)(b >> 16);
+}
+__device__ inline float bf2f(bf16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+
 // Epilogue shared by the split-BF16 kernels: acc[ib][jb][r] is C(i, j) with
 // i = wi0 + 32 ib + lane % 32, j = wj0 + 32 jb + 8 (r / 4) + 4 (lane / 32) + r % 4.
 template <int EPI, int WGR, int WR, int WC>
@@ -197,7 +206,7 @@ __device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t
             in1[u] = g.B32[gi + gj * g.ldb32];
             ev[u] = g.eps[gj];
             in2[u] = ((const float*)g.D)[gi + gj * g.ldd];
-          } else {  // X3_ADD
+          } else if (EPI == X3_ADD) {
             in1[u] = g.d_double ? ((const double*)g.D)[gi + gj * g.ldd] : (double)((const float*)g.D)[gi + gj * g.ldd];
           }
         }
@@ -209,11 +218,21 @@ __device__ inline void x3_epilogue(const X3Args& g, v16f (&acc)[WR][WC], int64_t
           const double v = (double)acc[ib][jb][r];
           double outv;
           if (EPI == X3_STORE) outv = g.alpha * v + g.beta * in1[u];
+          else if (EPI == X3_STORE_PACK) outv = g.alpha * v;
           else if (EPI == X3_SHIFT) outv = v + (double)in1[u] * (dg - ev[u]);
           else if (EPI == X3_FSUPD) outv = (double)in2[u] - a_eff * (v + (double)in1[u] * (dg - ev[u]));
           else outv = g.alpha * v + in1[u];
-          if (g.c_double) ((double*)g.C)[gi + gj * g.ldc] = outv;
-          else ((float*)g.C)[gi + gj * g.ldc] = (float)outv;
+          if (EPI == X3_STORE_PACK) {  // the hi / lo parts of the FP32 value, as pack_x3 makes them
+            const float y = (float)outv;
+            const bf16_t h = f2bf(y), l = f2bf((float)((double)y - (double)bf2f(h)));
+            bf16_t* dst = g.pack_split + gj * g.ld_pack_split + (gi >> 5) * 64 + (gi & 31);
+            dst[0] = h;
+            dst[32] = l;
+          } else if (g.c_double) {
+            ((double*)g.C)[gi + gj * g.ldc] = outv;
+          } else {
+            ((float*)g.C)[gi + gj * g.ldc] = (float)outv;
+          }
           if ((EPI == X3_SHIFT || EPI == X3_FSUPD) && far_row) {
             const float a = fabsf((float)outv);
             farmax = (a > farmax || a != a) ? a : farmax;
@@ -591,14 +610,6 @@ __global__ __launch_bounds__(256) void k_x3_split_sum(X3Args g) {
 }
 
 // ---------------------------------------------------------------- packing
-__device__ inline bf16_t f2bf(float x) {
-  // round to nearest even (finite inputs; NaN stays NaN)
-  uint32_t b = __builtin_bit_cast(uint32_t, x);
-  if ((b & 0x7f800000u) == 0x7f800000u) return (bf16_t)((b >> 16) | ((b & 0xffffu) ? 0x40u : 0u));
-  b += 0x7fffu + ((b >> 16) & 1u);
-  return (bf16_t)(b >> 16);
-}
-__device__ inline float bf2f(bf16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
 
 // One workgroup packs a 32 (k) x 64 (r) block: reads through LDS so that
 // both the column-major source and the packed destination are contiguous.
@@ -885,6 +896,7 @@ hipError_t x3_init() {
   X3_DL_ATTR(X3_FSUPD)
   X3_DL_ATTR(X3_ADD)
   X3_DL_ATTR(X3_RQ)
+  X3_DL_ATTR(X3_STORE_PACK)
 #undef X3_DL_ATTR
 #define X3_DL1_ATTR(E)                                                                                            \
   if (e == hipSuccess)                                                                                            \
@@ -913,9 +925,13 @@ hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
   if (tm == 0 || tn == 0) return hipSuccess;
   if (a.tiles == X3_LOWER && tm != tn) return hipErrorInvalidValue;
   if (a.products != 0 && a.products != 1 && a.products != 3) return hipErrorInvalidValue;
+  if (epi == X3_STORE_PACK &&
+      (!a.pack_split || a.tiles == X3_LOWER || a.M % 32 != 0 || a.ld_pack_split < x3_row_stride(a.M) || a.products == 1))
+    return hipErrorInvalidValue;
   const bool one = a.products == 1;
   if (one && ((epi != X3_SHIFT && epi != X3_FSUPD && epi != X3_ADD) || a.tiles == X3_LOWER)) return hipErrorInvalidValue;
-  const int cfg = one ? 5 : (a.cfg >= 0 ? a.cfg : x3_default_cfg);
+  // products on plain operands and the packing epilogue run in the direct-to-LDS configuration
+  const int cfg = (one || epi == X3_STORE_PACK) ? 5 : (a.cfg >= 0 ? a.cfg : x3_default_cfg);
   switch (cfg) {
     case 0: return launch_cfg<0>(epi, a, tm, tn, s);
     case 1: return launch_cfg<1>(epi, a, tm, tn, s);
@@ -954,6 +970,7 @@ hipError_t gemm_x3(int epi, const X3Args& a, hipStream_t s) {
         X3_DL_CASE(X3_FSUPD)
         X3_DL_CASE(X3_ADD)
         X3_DL_CASE(X3_RQ)
+        X3_DL_CASE(X3_STORE_PACK)
 #undef X3_DL_CASE
         default: return hipErrorInvalidValue;
       }

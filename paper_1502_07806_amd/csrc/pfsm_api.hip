@@ -657,13 +657,18 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   if (phase != PH_END) {
   PFSM_TRY(fill_i32(info, 1, 0, s));
   clk.mark(0);
-  // (1) basis change: W = A V, At = V^T W (lower tiles), FP64 copy for the eigensolver.
+  // (1) basis change: W = A V, At = V^T W (lower tiles, then both triangles in FP32 and the diagonal in FP64).
   PFSM_TRY(pack_x3(dA, 1, n, n, lda, 0, Apk, ldp, s));        // rows of A (= columns, A symmetric)
   PFSM_TRY(pack_x3(dV, 1, n, n, ldv, 0, Vpk, ldp, s));        // columns of V
   {
     X3Args g = x3(X3_STORE, n, n, n, Apk, Vpk, Y32, n, 0);
-    PFSM_TRY(gemm_x3(X3_STORE, g, s));
-    PFSM_TRY(pack_x3(Y32, 0, n, n, n, 0, Ypk, ldp, s));       // columns of W
+    if (n % 32 == 0) {  // W only feeds At = V^T W: its epilogue writes the packed copy alone
+      g.pack_split = Ypk; g.ld_pack_split = ldp;
+      PFSM_TRY(gemm_x3(X3_STORE_PACK, g, s));
+    } else {
+      PFSM_TRY(gemm_x3(X3_STORE, g, s));
+      PFSM_TRY(pack_x3(Y32, 0, n, n, n, 0, Ypk, ldp, s));     // columns of W
+    }
     X3Args h = x3(X3_STORE, n, n, n, Vpk, Ypk, At32, n, 0);
     h.tiles = X3_LOWER;
     h.split_ws = split_ws; h.split_bytes = pl->split_bytes;
