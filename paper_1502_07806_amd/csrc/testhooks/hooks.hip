@@ -35,6 +35,16 @@ int pfsm_test_pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64
   return (int)pack_x3(X, src_double, m, n, ldx, flags, (bf16_t*)P, ldp, (hipStream_t)stream);
 }
 
+// The band part (far = 0) or the gated far part (far = 1) of a pack (pack_x3_band, pack_x3_far_gated).
+int pfsm_test_pack_x3_part(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, void* P,
+                           int64_t ldp, const int32_t* krange, int band_chunks, int far, const unsigned* gate_far,
+                           const double* gate_cl, void* stream) {
+  if (far)
+    return (int)pack_x3_far_gated(X, src_double, m, n, ldx, flags, (bf16_t*)P, ldp, krange, gate_far, gate_cl,
+                                  (hipStream_t)stream);
+  return (int)pack_x3_band(X, src_double, m, n, ldx, flags, (bf16_t*)P, ldp, krange, band_chunks, (hipStream_t)stream);
+}
+
 int pfsm_test_gemm_x3_ws(int epi, int cfg, int tiles, int64_t M, int64_t N, int64_t K, const void* Ap, int64_t ldap,
                          const void* Bp, int64_t ldbp, void* C, int64_t ldc, int c_double, double alpha, double beta,
                          const float* B32, int64_t ldb32, const void* D, int64_t ldd, int d_double, const double* eps,

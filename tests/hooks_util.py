@@ -21,6 +21,8 @@ def lib():
         L.pfsm_test_gemm_f64.restype = i32
         L.pfsm_test_pack_x3.argtypes = [vp, i32, i64, i64, i64, i32, vp, i64, vp]
         L.pfsm_test_pack_x3.restype = i32
+        L.pfsm_test_pack_x3_part.argtypes = [vp, i32, i64, i64, i64, i32, vp, i64, vp, i32, i32, vp, vp, vp]
+        L.pfsm_test_pack_x3_part.restype = i32
         L.pfsm_test_gemm_x3.argtypes = [i32, i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, dbl, dbl, vp,
                                         i64, vp, i64, i32, vp, vp, vp]
         L.pfsm_test_gemm_x3.restype = i32

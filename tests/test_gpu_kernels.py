@@ -547,3 +547,62 @@ def test_gemm_oz_multi_matches_fused(dev, M, N, K, s):
         out.append(_np(C))
     assert np.all(np.isfinite(out[1]))
     assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+@pytest.mark.parametrize("n", [512, 700])
+@pytest.mark.parametrize("by_rows,flags", [(False, 32), (False, 2), (True, 32)])
+def test_pack_band_and_gated_far(dev, n, by_rows, flags):
+    """The two-part packs of the band forms: the band part writes exactly the
+    rows of the packed operand inside each 256-row tile's K range, bitwise as
+    the full pack does, and nothing else; the far part writes nothing while
+    the gate lets the band form run, and completes the full pack when it does
+    not.  Plain column packs (the folded-spectrum operands), split column packs
+    (X - I of the back-rotation, band part only) and plain row packs (the
+    correction's operand); n = 700 has zero padding past K."""
+    L = lib()
+    g = np.random.default_rng(n + 10 * flags + by_rows)
+    x = g.standard_normal((n, n)).astype(np.float32)
+    plain = bool(flags & 32)
+    ld = L.pfsm_test_x3_plain_stride(n) if plain else L.pfsm_test_x3_row_stride(n)
+    kpad = (n + 31) // 32 * 32
+    tiles = (n + 255) // 256
+    kr = []
+    for _ in range(tiles):  # a random band per 256-row tile of the packed operand
+        lo = int(g.integers(0, kpad // 32)) * 32
+        hi = min(kpad, lo + 32 * int(g.integers(1, 9)))
+        kr += [lo, hi]
+    chunks = max((kr[2 * t + 1] - kr[2 * t]) // 32 for t in range(tiles))
+    dkr = torch.tensor(kr, dtype=torch.int32, device=dev)
+    dx = torch.from_numpy(x).to(dev).t().contiguous().t()  # column-major FP32
+    fl = flags | (1 if by_rows else 0)
+    full = torch.full((n * ld,), -1, dtype=torch.int16, device=dev)
+    assert L.pfsm_test_pack_x3(_p(dx), 0, n, n, dx.stride(1), fl, _p(full), ld, _stream()) == 0
+    part = torch.full((n * ld,), -1, dtype=torch.int16, device=dev)
+    assert L.pfsm_test_pack_x3_part(_p(dx), 0, n, n, dx.stride(1), fl, _p(part), ld, _p(dkr), chunks, 0, None, None,
+                                    _stream()) == 0
+    torch.cuda.synchronize()
+    F, Pp = full.view(n, ld).cpu().numpy(), part.view(n, ld).cpu().numpy()
+    band = np.zeros((n, ld), dtype=bool)  # packed positions of the k inside each row's band
+    for r in range(n):
+        lo, hi = kr[2 * (r // 256)], kr[2 * (r // 256) + 1]
+        k = np.arange(lo, hi)
+        if plain:
+            band[r, k] = True
+        else:
+            band[r, (k >> 5) * 64 + (k & 31)] = True
+            band[r, (k >> 5) * 64 + (k & 31) + 32] = True
+    assert np.array_equal(Pp[band], F[band])
+    assert np.all(Pp[~band] == -1)
+    if not plain:
+        return  # the split column layout has no far part (the back-rotation's plain product covers those rows)
+    open_gate = torch.tensor([0], dtype=torch.int32, device=dev)  # m = 0: c m <= limit
+    closed_gate = torch.tensor([np.float32(2.0).view(np.int32)], dtype=torch.int32, device=dev)  # m = 2
+    cl = torch.tensor([1.0, 1.0], dtype=torch.float64, device=dev)
+    assert L.pfsm_test_pack_x3_part(_p(dx), 0, n, n, dx.stride(1), fl, _p(part), ld, _p(dkr), chunks, 1,
+                                    _p(open_gate), _p(cl), _stream()) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(part.view(n, ld).cpu().numpy(), Pp)
+    assert L.pfsm_test_pack_x3_part(_p(dx), 0, n, n, dx.stride(1), fl, _p(part), ld, _p(dkr), chunks, 1,
+                                    _p(closed_gate), _p(cl), _stream()) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(part.view(n, ld).cpu().numpy(), F)
