@@ -108,7 +108,11 @@ inline int64_t x3_plain_stride(int64_t K) { return 32 * ((K + 31) / 32); }
 hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P, int64_t ldp,
                    hipStream_t s);
 
-// The same restricted to the K range krange[2 t], krange[2 t + 1] (multiples
+// The split layout into P and the plain one (PACK_PLAIN) into P2 from one
+// read of X (transposing packs: the plain values are the split hi parts).
+hipError_t pack_x3_split_and_plain(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags,
+                                   bf16_t* P, int64_t ldp, bf16_t* P2, int64_t ldp2, hipStream_t s);
+// The same as pack_x3, restricted to the K range krange[2 t], krange[2 t + 1] (multiples
 // of 32) of each 256-row tile t of the packed operand (its rows r, t = r / 256):
 // the band part, all that a product with that K range per tile reads
 // (X3Args::krange for a column operand, krange_rows for a row operand).

@@ -615,7 +615,8 @@ __global__ __launch_bounds__(256) void k_x3_split_sum(X3Args g) {
 // both the column-major source and the packed destination are contiguous.
 // One 64 (r) x 32 (k) block of the packed operand (rows r0 .., chunk kc).
 __device__ void pack_block(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P,
-                           int64_t ldp, int64_t r0, int64_t kc, double (*tile)[33]);
+                           int64_t ldp, int64_t r0, int64_t kc, double (*tile)[33], bf16_t* P2 = nullptr,
+                           int64_t ldp2 = 0);
 
 // krange (optional): only the chunks inside [krange[2 t], krange[2 t + 1]) for
 // the rows of P in tile t = r / 256 (band part, the grid's x covering the
@@ -651,8 +652,15 @@ __global__ __launch_bounds__(256) void k_pack(const void* X, int src_double, int
   }
 }
 
+// Both layouts from one read: P split (flags without PACK_PLAIN), P2 plain.
+__global__ __launch_bounds__(256) void k_pack_dual(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx,
+                                                   int flags, bf16_t* P, int64_t ldp, bf16_t* P2, int64_t ldp2) {
+  __shared__ double tile[64][33];
+  pack_block(X, src_double, m, n, ldx, flags, P, ldp, (int64_t)blockIdx.y * 64, blockIdx.x, tile, P2, ldp2);
+}
+
 __device__ void pack_block(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P,
-                           int64_t ldp, int64_t r0, int64_t kc, double (*tile)[33]) {
+                           int64_t ldp, int64_t r0, int64_t kc, double (*tile)[33], bf16_t* P2, int64_t ldp2) {
   const int by_rows = flags & PACK_BY_ROWS;
   // packed operand: rows r in [0, R), k in [0, K); R = by_rows ? m : n, K = by_rows ? n : m
   const int64_t R = by_rows ? m : n;
@@ -694,6 +702,7 @@ __device__ void pack_block(const void* X, int src_double, int64_t m, int64_t n, 
       hw[u] = (uint32_t)h0 | ((uint32_t)h1 << 16);
       lw[u] = (uint32_t)l0 | ((uint32_t)l1 << 16);
     }
+    if (P2) *(u32x4*)(P2 + r * ldp2 + kc * 32 + 8 * c) = hw;  // the plain layout holds the hi parts
     if (flags & PACK_PLAIN) {  // 64-byte aligned: ldp is a multiple of 32
       *(u32x4*)(P + r * ldp + kc * 32 + 8 * c) = hw;
       return;
@@ -1016,6 +1025,18 @@ hipError_t pack_x3_band(const void* X, int src_double, int64_t m, int64_t n, int
 hipError_t pack_x3(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P, int64_t ldp,
                    hipStream_t s) {
   return pack_x3_band(X, src_double, m, n, ldx, flags, P, ldp, nullptr, 0, s);
+}
+
+hipError_t pack_x3_split_and_plain(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags,
+                                   bf16_t* P, int64_t ldp, bf16_t* P2, int64_t ldp2, hipStream_t s) {
+  const bool by_rows = flags & PACK_BY_ROWS;
+  const int64_t R = by_rows ? m : n, K = by_rows ? n : m;
+  if (R <= 0 || K <= 0) return hipSuccess;
+  if ((flags & PACK_PLAIN) || ldp < x3_row_stride(K) || ldp2 < x3_plain_stride(K) || ldp2 % 32 != 0)
+    return hipErrorInvalidValue;
+  dim3 grid((unsigned)((K + 31) / 32), (unsigned)((R + 63) / 64));
+  hipLaunchKernelGGL(k_pack_dual, grid, dim3(256), 0, s, X, src_double, m, n, ldx, flags, P, ldp, P2, ldp2);
+  return hipGetLastError();
 }
 
 hipError_t pack_x3_far_gated(const void* X, int src_double, int64_t m, int64_t n, int64_t ldx, int flags, bf16_t* P,

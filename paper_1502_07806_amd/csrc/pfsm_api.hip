@@ -841,7 +841,8 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   // the first part, so the second is X itself with those rows zeroed.
   // columns of X - I, in the rows the split product reads
   PFSM_TRY(pack_x3_band(X32, 0, n, n, n, PACK_SUB_I, Xpk, ldp, pl->d_krange_x3, pl->band_chunks, s));
-  PFSM_TRY(pack_x3(dV, 1, n, n, ldv, PACK_BY_ROWS, Rpk, ldp, s));  // rows of V
+  // rows of V, split for the product below and plain (Atpk, free by now) for the second one
+  PFSM_TRY(pack_x3_split_and_plain(dV, 1, n, n, ldv, PACK_BY_ROWS, Rpk, ldp, Atpk, ldq, s));
   {
     X3Args g = x3(X3_ADD, n, n, n, Rpk, Xpk, Vn64, n, 1);
     g.D = dV; g.ldd = ldv; g.d_double = 1; g.krange = pl->d_krange_x3;
@@ -849,7 +850,6 @@ static pfsm_status solve_mixed(pfsm_plan* pl, const double* dA, int64_t lda, con
   }
   PFSM_TRY(zero_krange_rows(X32, n, n, n, pl->d_krange_x3, X3_BN, s));
   PFSM_TRY(pack_x3(X32, 0, n, n, n, PACK_PLAIN, Ypk, ldq, s));                  // columns of X outside those rows
-  PFSM_TRY(pack_x3(dV, 1, n, n, ldv, PACK_BY_ROWS | PACK_PLAIN, Atpk, ldq, s));  // rows of V, plain
   {
     X3Args h = x3(X3_ADD, n, n, n, Atpk, Ypk, Vn64, n, 1);
     h.D = Vn64; h.ldd = n; h.d_double = 1; h.products = 1; h.ldap = h.ldbp = ldq;
