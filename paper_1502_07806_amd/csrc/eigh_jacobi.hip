@@ -209,9 +209,19 @@ __device__ void solve_pair(const EighBatch& e, int round, int p, int k, SolveLds
   if (tid == 0) any_rot = 0;
   __syncthreads();
   int need = 0;
-  for (int idx = tid; idx < B2 * B2; idx += PS_NT) {
-    int r = idx % B2, c = idx / B2;
-    W[c][r] = B[pair_idx(r, I, J) + (int64_t)pair_idx(c, I, J) * Mp];
+  {  // every load in flight before the first store (a loop would wait for each in turn)
+    constexpr int PER = B2 * B2 / PS_NT;
+    double v[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int idx = tid + PS_NT * m, r = idx % B2, c = idx / B2;
+      v[m] = B[pair_idx(r, I, J) + (int64_t)pair_idx(c, I, J) * Mp];
+    }
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int idx = tid + PS_NT * m, r = idx % B2, c = idx / B2;
+      W[c][r] = v[m];
+    }
   }
   __syncthreads();
   for (int idx = tid; idx < B2 * B2; idx += PS_NT) {
@@ -449,9 +459,19 @@ template <int NTH> __device__ void apply_b_tile(const EighBatch& e, int round, i
   double* B = e.Bw + (int64_t)p * Mp * Mp;
   const double* R1 = Rbase + (int64_t)k1 * B2 * B2;
   const double* R2 = Rbase + (int64_t)k2 * B2 * B2;
-  for (int idx = tid; idx < B2 * B2; idx += NTH) {
-    int r = idx % B2, c = idx / B2;
-    T[r][c] = B[pair_idx(r, I1, J1) + (int64_t)pair_idx(c, I2, J2) * Mp];
+  {  // every load in flight before the first store
+    constexpr int PER = B2 * B2 / NTH;
+    double v[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int idx = tid + NTH * m, r = idx % B2, c = idx / B2;
+      v[m] = B[pair_idx(r, I1, J1) + (int64_t)pair_idx(c, I2, J2) * Mp];
+    }
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int idx = tid + NTH * m, r = idx % B2, c = idx / B2;
+      T[r][c] = v[m];
+    }
   }
   __syncthreads();
   if (f1) {
@@ -491,9 +511,19 @@ template <int NTH> __device__ void apply_u_tile(const EighBatch& e, int round, i
   const double* R2 = rot_buf(e, round) + ((int64_t)p * npairs + k2) * B2 * B2;
   const int tid = threadIdx.x;
   v4d acc[2][Mm64<NTH>::JB];
-  for (int idx = tid; idx < B2 * B2; idx += NTH) {
-    int r = idx % B2, c = idx / B2;
-    T[r][c] = U[(rc * B2 + r) + (int64_t)pair_idx(c, I2, J2) * Mp];
+  {  // every load in flight before the first store
+    constexpr int PER = B2 * B2 / NTH;
+    double v[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int idx = tid + NTH * m, r = idx % B2, c = idx / B2;
+      v[m] = U[(rc * B2 + r) + (int64_t)pair_idx(c, I2, J2) * Mp];
+    }
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int idx = tid + NTH * m, r = idx % B2, c = idx / B2;
+      T[r][c] = v[m];
+    }
   }
   __syncthreads();
   mm64_x_r<NTH>(T, R2, acc);
