@@ -561,24 +561,25 @@ __global__ __launch_bounds__(PS_NT) void pair_solve_apply_u(EighBatch e, int sol
 // ------------------------------------------------------------------ select + embed
 // Ascending rank of each diagonal entry (stable), then the slice's ranks
 // [offset, offset + size) become start vectors X0 (zero outside the
-// submatrix rows) and shifts eps.  One workgroup per submatrix for ranking.
-__global__ __launch_bounds__(NT) void rank_select(EighBatch e) {
+// submatrix rows) and shifts eps.  Ranking: one workgroup per 64 entries of a submatrix.
+constexpr int RS_NT = 64;  // entries ranked per workgroup (one per thread)
+__global__ __launch_bounds__(RS_NT) void rank_select(EighBatch e) {
   const int p = blockIdx.x;
   const int Mp = e.Mp;
   const double* B = e.Bw + (int64_t)p * Mp * Mp;
   int* sel = e.sel + (int64_t)p * Mp;
   extern __shared__ double dsh[];
-  for (int i = threadIdx.x; i < Mp; i += NT) dsh[i] = B[i + (int64_t)i * Mp];
+#pragma unroll 8
+  for (int i = threadIdx.x; i < Mp; i += RS_NT) dsh[i] = B[i + (int64_t)i * Mp];
   __syncthreads();
-  for (int i = threadIdx.x; i < Mp; i += NT) {
-    double di = dsh[i];
-    int rank = 0;
-    for (int j = 0; j < Mp; ++j) rank += order_before(dsh[j], j, di, i);
-    sel[rank] = i;  // rank -> local index; ranks are a permutation even with NaN
-  }
+  const int i = blockIdx.y * RS_NT + threadIdx.x;  // Mp is a multiple of RS_NT
+  const double di = dsh[i];
+  int rank = 0;
+  for (int j = 0; j < Mp; ++j) rank += order_before(dsh[j], j, di, i);
+  sel[rank] = i;  // rank -> local index; ranks are a permutation even with NaN
   // not converged: the last sweep still rotated and no sweep was rotation-free
   int* inf = info_of(e, p);
-  if (threadIdx.x == 0 && e.state[2 * p] == 0 && e.state[2 * p + 1] != 0 && inf)
+  if (blockIdx.y == 0 && threadIdx.x == 0 && e.state[2 * p] == 0 && e.state[2 * p + 1] != 0 && inf)
     atomicCAS(inf, 0, PFSM_INFO_EIGH_NOCONV);
 }
 
@@ -629,7 +630,7 @@ static hipError_t eigh_run(const EighBatch& e, const T* At, int64_t ldat, int ma
       hipLaunchKernelGGL(pair_solve_apply_u, dim3(grid), dim3(PS_NT), 0, s, e, next, r);
     }
   }
-  hipLaunchKernelGGL(rank_select, dim3(e.P), dim3(NT), e.Mp * sizeof(double), s, e);
+  hipLaunchKernelGGL(rank_select, dim3(e.P, e.Mp / RS_NT), dim3(RS_NT), e.Mp * sizeof(double), s, e);
   return hipGetLastError();
 }
 
