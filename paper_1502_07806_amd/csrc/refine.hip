@@ -92,19 +92,17 @@ __global__ __launch_bounds__(1024) void k_clusters(const double* lam_s, int64_t 
     bool start = (i == 0) || !(lam_s[i] - lam_s[i - 1] <= thr);
     cnt += start;
   }
+  // inclusive prefix sum of the counts over the 1024 threads (log-step scan)
   scan[threadIdx.x] = cnt;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int t = 0; t < 1024; ++t) {
-      int c = scan[t];
-      scan[t] = acc;
-      acc += c;
-    }
-    *count = acc;  // number of natural clusters (before cutting at KM)
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = (int)threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+    __syncthreads();
+    scan[threadIdx.x] += v;
+    __syncthreads();
   }
-  __syncthreads();
-  int idx = scan[threadIdx.x];
+  if (threadIdx.x == 1023) *count = scan[1023];  // number of natural clusters (before cutting at KM)
+  int idx = scan[threadIdx.x] - cnt;  // first cluster index of my range
   for (int64_t i = b0; i < b1; ++i) {
     bool start = (i == 0) || !(lam_s[i] - lam_s[i - 1] <= thr);
     if (start) {
