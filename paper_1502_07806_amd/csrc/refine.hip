@@ -562,6 +562,7 @@ __global__ __launch_bounds__(NT) void k_lmi_col(const double* L, int64_t ldl, in
   __shared__ double sh[NT];
   const int64_t j = blockIdx.x;
   double m = 0.0;
+#pragma unroll 8  // eight loads in flight per thread
   for (int64_t i = j + threadIdx.x; i < n; i += NT) {
     double v = fabs(L[i + j * ldl] - (i == j ? 1.0 : 0.0));
     m = (v > m || v != v) ? v : m;
@@ -609,6 +610,7 @@ __global__ __launch_bounds__(NT) void k_col_sign_f32(float* X, int64_t n, int64_
   float* c = X + j * ldx;
   float best = -1.f;
   int64_t bi = 0;
+#pragma unroll 8  // eight loads in flight per thread
   for (int64_t i = threadIdx.x; i < n; i += NT) {
     float a = fabsf(c[i]);
     if (a > best) { best = a; bi = i; }
