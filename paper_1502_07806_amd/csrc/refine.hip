@@ -38,6 +38,7 @@ __global__ __launch_bounds__(NT) void k_dots(const double* V, int64_t ldv, const
   __shared__ double sh[NT / 64];
   const int64_t j = blockIdx.x;
   double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll 8  // eight loads of each operand in flight per thread; the sums keep their order
   for (int64_t i = threadIdx.x; i < n; i += NT) {
     const double v = V[i + j * ldv], z = Z[i + j * ldz];
     a += v * z;
