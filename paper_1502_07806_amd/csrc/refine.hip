@@ -531,10 +531,17 @@ __global__ __launch_bounds__(256) void k_sym_from_lower(float* A32, double* dg, 
   tile_pair(blockIdx.x, I, J);
   const int64_t i0 = (int64_t)I * TT, j0 = (int64_t)J * TT;
   const int a = threadIdx.x & 63, b0 = threadIdx.x >> 6;
-  // T[r][c] = A32(i0 + r, j0 + c) where that is in the lower triangle
-  for (int c = b0; c < TT; c += 4) {
-    const int64_t i = i0 + a, j = j0 + c;
-    T[a][c] = (i < n && j < n && i >= j) ? A32[i + j * n] : 0.f;
+  // T[r][c] = A32(i0 + r, j0 + c) where that is in the lower triangle (all
+  // sixteen loads of a thread in flight before the first store)
+  {
+    float v[TT / 4];
+#pragma unroll
+    for (int m = 0; m < TT / 4; ++m) {
+      const int64_t i = i0 + a, j = j0 + b0 + 4 * m;
+      v[m] = (i < n && j < n && i >= j) ? A32[i + j * n] : 0.f;
+    }
+#pragma unroll
+    for (int m = 0; m < TT / 4; ++m) T[a][b0 + 4 * m] = v[m];
   }
   __syncthreads();
   for (int c = b0; c < TT; c += 4) {
